@@ -1,0 +1,191 @@
+"""FP64 oracle: phantom structures and the dose-deposition matrix D.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the library never does.
+
+The paper takes D from a clinical dose engine (Section 2.1: D_ij is the dose
+to voxel j from beamlet i of unit intensity; Section 2.3 stores it in CSR).
+Here D comes from a synthetic pencil-beam model, evaluated by brute force over
+every (voxel, beamlet) pair in float64, with every arithmetic expression
+written in one fixed order so that an independent implementation that follows
+the same formulas (IEEE float64, no fused multiply-add) reproduces the
+sparsity pattern bit for bit:
+
+  voxel centre   p_a = (i_a + 0.5)*h - (n_a*h)/2         (a = x, y, z)
+  beam b         theta = (2*pi*b)/B, c = cos(theta), s = sin(theta)
+                 (host libm cos/sin, computed once per beam)
+  depth          t_a = min((lo_a - p_a)/dir_a, (hi_a - p_a)/dir_a) for the
+                 in-plane axes with dir_a != 0, dir = (c, s); depth = -max t_a
+  lateral        u = (-s)*x + c*y,  v = z
+  beamlet (m,n)  centre (u_c, v_c) = ((m+0.5)*w, (n+0.5)*w)
+  exponent       e = (mu*depth) + (r2/((2*sigma)*sigma)),
+                 r2 = (u-u_c)*(u-u_c) + (v-v_c)*(v-v_c)
+  keep           e <= e_min + L,  L = log(1/tau),  e_min = min over voxels
+                 (equivalent to D >= tau * max_j D, with no exp in the test)
+  value          D = float32(exp(-e))
+
+Voxel j = ix + nx*(iy + ny*iz).  Beamlets are beam-major, then m ascending,
+then n ascending; a beamlet exists if the point of its square closest to the
+beam axis lies within r_ptv + margin.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+import scipy.sparse as sp
+
+from workloads import BLADDER, NORMAL, PTV, RECTUM, PhantomSpec
+
+
+def voxel_centres(spec: PhantomSpec):
+    """Voxel centre coordinates (x, y, z) in mm, float64, voxel order j."""
+    def axis(n):
+        i = np.arange(n, dtype=np.float64)
+        return (i + 0.5) * spec.h - (n * spec.h) / 2.0
+    ax, ay, az = axis(spec.nx), axis(spec.ny), axis(spec.nz)
+    z, y, x = np.meshgrid(az, ay, ax, indexing="ij")
+    return x.ravel(), y.ravel(), z.ravel()
+
+
+def structure_ids(spec: PhantomSpec) -> np.ndarray:
+    """Structure id of every voxel (uint8), priority PTV > rectum > bladder > normal.
+
+    A voxel belongs to a structure when its centre lies inside or on it:
+    PTV sphere at the origin, rectum cylinder along z centred at
+    (0, -(r_ptv + r_rectum)), bladder sphere centred at (0, r_ptv + r_bladder, 0).
+    """
+    x, y, z = voxel_centres(spec)
+    sid = np.full(x.shape, NORMAL, dtype=np.uint8)
+    cb = spec.r_ptv + spec.r_bladder
+    dyb = y - cb
+    in_bladder = (x * x + dyb * dyb) + z * z <= spec.r_bladder * spec.r_bladder
+    cr = -(spec.r_ptv + spec.r_rectum)
+    dyr = y - cr
+    in_rectum = x * x + dyr * dyr <= spec.r_rectum * spec.r_rectum
+    in_ptv = (x * x + y * y) + z * z <= spec.r_ptv * spec.r_ptv
+    sid[in_bladder] = BLADDER
+    sid[in_rectum] = RECTUM
+    sid[in_ptv] = PTV
+    return sid
+
+
+@dataclass
+class Beamlet:
+    beam: int
+    m: int
+    n: int
+    u_c: float
+    v_c: float
+
+
+def beam_directions(spec: PhantomSpec):
+    """(cos, sin) of each beam angle 2*pi*b/B, via the host math library."""
+    out = []
+    for b in range(spec.n_beams):
+        theta = (2.0 * math.pi * b) / spec.n_beams
+        out.append((math.cos(theta), math.sin(theta)))
+    return out
+
+
+def beamlets(spec: PhantomSpec) -> List[Beamlet]:
+    """Beamlets covering the PTV projection plus the margin, in column order."""
+    w = spec.beamlet
+    reach = spec.r_ptv + spec.margin
+    kmax = int(math.ceil(reach / w)) + 1
+    out = []
+    for b in range(spec.n_beams):
+        for m in range(-kmax, kmax):
+            lo_u, hi_u = m * w, (m + 1) * w
+            cu = min(max(0.0, lo_u), hi_u)
+            for n in range(-kmax, kmax):
+                lo_v, hi_v = n * w, (n + 1) * w
+                cv = min(max(0.0, lo_v), hi_v)
+                if cu * cu + cv * cv <= reach * reach:
+                    out.append(Beamlet(b, m, n, (m + 0.5) * w, (n + 0.5) * w))
+    return out
+
+
+def beam_depth_and_u(spec: PhantomSpec, x, y, cos_t: float, sin_t: float):
+    """Depth below the box entry point along the beam, and the lateral u."""
+    hx, hy = (spec.nx * spec.h) / 2.0, (spec.ny * spec.h) / 2.0
+    ts = []
+    if cos_t != 0.0:
+        ts.append(np.minimum((-hx - x) / cos_t, (hx - x) / cos_t))
+    if sin_t != 0.0:
+        ts.append(np.minimum((-hy - y) / sin_t, (hy - y) / sin_t))
+    t_entry = ts[0] if len(ts) == 1 else np.maximum(ts[0], ts[1])
+    depth = -t_entry
+    u = (-sin_t) * x + cos_t * y
+    return depth, u
+
+
+def beamlet_exponent(spec: PhantomSpec, depth, u, z, bl: Beamlet):
+    """Exponent e = mu*depth + r^2/(2 sigma^2) of one beamlet at every voxel."""
+    du = u - bl.u_c
+    dv = z - bl.v_c
+    r2 = du * du + dv * dv
+    return (spec.mu * depth) + (r2 / ((2.0 * spec.sigma) * spec.sigma))
+
+
+@dataclass
+class DoseMatrix:
+    """D (nv x nb) as scipy CSR and CSC, float32 values, int32 indices."""
+    nv: int
+    nb: int
+    csr: sp.csr_matrix
+    csc: sp.csc_matrix
+    struct_id: np.ndarray
+    beamlets: List[Beamlet]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.csr.nnz)
+
+
+def dose_column(spec: PhantomSpec, depth, u, z, bl: Beamlet):
+    """Kept voxel indices (ascending) and float32 values of one beamlet."""
+    e = beamlet_exponent(spec, depth, u, z, bl)
+    keep_limit = e.min() + math.log(1.0 / spec.tau)
+    rows = np.nonzero(e <= keep_limit)[0].astype(np.int32)
+    vals = np.exp(-e[rows]).astype(np.float32)
+    return rows, vals
+
+
+def build_columns(spec: PhantomSpec, which=None):
+    """Columns of D for the beamlet indices ``which`` (all when None).
+
+    Returns (list of beamlets, list of (rows, vals)) in the requested order.
+    """
+    bls = beamlets(spec)
+    dirs = beam_directions(spec)
+    x, y, z = voxel_centres(spec)
+    idx = range(len(bls)) if which is None else which
+    cache = {}
+    cols = []
+    for i in idx:
+        bl = bls[i]
+        if bl.beam not in cache:
+            cache.clear()
+            cache[bl.beam] = beam_depth_and_u(spec, x, y, *dirs[bl.beam])
+        depth, u = cache[bl.beam]
+        cols.append(dose_column(spec, depth, u, z, bl))
+    return bls, cols
+
+
+def build_dose_matrix(spec: PhantomSpec) -> DoseMatrix:
+    """Brute-force D for the whole phantom, in CSC then CSR (indices sorted)."""
+    bls, cols = build_columns(spec)
+    nv, nb = spec.nv, len(bls)
+    lens = np.array([len(r) for r, _ in cols], dtype=np.int64)
+    col_ptr = np.zeros(nb + 1, dtype=np.int64)
+    np.cumsum(lens, out=col_ptr[1:])
+    row_idx = np.concatenate([r for r, _ in cols]) if nb else np.zeros(0, np.int32)
+    vals = np.concatenate([v for _, v in cols]) if nb else np.zeros(0, np.float32)
+    csc = sp.csc_matrix((vals, row_idx, col_ptr), shape=(nv, nb))
+    csc.has_sorted_indices = True
+    csr = csc.tocsr()
+    csr.sort_indices()
+    return DoseMatrix(nv, nb, csr, csc, structure_ids(spec), bls)

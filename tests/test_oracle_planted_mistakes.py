@@ -1,0 +1,95 @@
+"""Planted mistakes: each plausible slip in the oracle must fail a pin.
+
+The mistakes are planted in the oracle only, on the CPU, by monkeypatching;
+the pins are the same checkers the oracle tests use.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import model, phantom, solver
+from oracle_pins import fd_gradient_error, floats, worked_example
+from workloads import TINY, random_csr, random_penalties
+
+
+def _problem():
+    A = random_csr(150, 25, 5, seed=31)
+    D = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.nv, A.nb))
+    pen = model.VoxelPenalties.from_structures(A.struct_id, np.array(
+        [[p.T_under, p.T_over, p.w_under, p.w_over] for p in random_penalties(4, 5, scale=3.0)]))
+    x = np.random.default_rng(1).uniform(0, 1.5, A.nb)
+    return D, pen, x
+
+
+def test_pins_hold_without_mistakes():
+    D, pen, x = _problem()
+    assert fd_gradient_error(D, pen, x, range(25))[0] <= 1e-6
+
+
+def test_dropped_underdose_term_is_caught(monkeypatch):
+    D, pen, x = _problem()
+    monkeypatch.setattr(model, "residual", lambda z, p: p.w_over * np.maximum(z - p.T_over, 0.0))
+    assert fd_gradient_error(D, pen, x, range(25))[0] > 1e-3
+
+
+def test_wrong_residual_sign_is_caught(monkeypatch):
+    D, pen, x = _problem()
+    orig = model.residual
+    monkeypatch.setattr(model, "residual", lambda z, p: -orig(z, p))
+    assert fd_gradient_error(D, pen, x, range(25))[0] > 1e-3
+
+
+def test_missing_factor_two_is_caught(monkeypatch):
+    D, pen, x = _problem()
+    monkeypatch.setattr(model, "gradient",
+                        lambda D_, x_, p: model.adjoint(D_, model.residual(model.dose(D_, x_), p)))
+    assert fd_gradient_error(D, pen, x, range(25))[0] > 1e-3
+
+
+def test_transposed_adjoint_is_caught(monkeypatch):
+    """A square D makes D r type-check; the adjoint identity still fails."""
+    rng = np.random.default_rng(2)
+    Dd = rng.uniform(0, 1, (30, 30)).astype(np.float32)
+    D = sp.csr_matrix(Dd)
+    x, r = rng.uniform(0, 1, 30), rng.standard_normal(30)
+    monkeypatch.setattr(model, "adjoint", lambda D_, r_: model.as_f64_matrix(D_) @ r_)
+    lhs, rhs = model.dose(D, x) @ r, x @ model.adjoint(D, r)
+    assert abs(lhs - rhs) > 1e-6 * abs(lhs)
+
+
+def test_wrong_threshold_in_overdose_is_caught(monkeypatch):
+    """Using T_under in the over-dose term breaks the hand-worked branch case."""
+    g, _, _ = worked_example()
+    monkeypatch.setattr(model, "under_over", lambda z, p: (np.minimum(z - p.T_under, 0.0),
+                                                           np.maximum(z - p.T_under, 0.0)))
+    D = sp.csr_matrix(np.array([[2.0]], dtype=np.float32))
+    lhs, rhs = g["branch_inside"].split("->")
+    tu, to, wu, wo = floats(lhs)
+    pen = model.VoxelPenalties(np.array([tu]), np.array([to]), np.array([wu]), np.array([wo]))
+    assert model.objective(D, np.array([3.0]), pen) != floats(rhs)[0]
+
+
+def test_eps_large_golden_decides_sufficient_decrease():
+    """With eps = 0.45 the sufficient-decrease term (eps/lambda)*s decides the
+    line search (hand-worked); eps*lambda or a missing term gives another count."""
+    g, D, pen = worked_example()
+    res = solver.solve(D, pen, floats(g["x1"]), eps=float(g["eps_large"]), alpha=2.0,
+                       lambda0=1.0, max_iter=1, fixed_iters=True)
+    e = res.trace[0]
+    assert (e.k, e.lam, e.backtracks, e.step_sq, e.G) == tuple(floats(g["eps_large_trace1"]))
+
+
+def test_mirrored_lateral_axis_is_caught(monkeypatch):
+    """Flipping the lateral axis sign moves beam-0 columns off their closed form."""
+    orig = phantom.beam_depth_and_u
+    def bad(spec, x, y, c, s):
+        d, u = orig(spec, x, y, c, s)
+        return d, -u
+    monkeypatch.setattr(phantom, "beam_depth_and_u", bad)
+    bls, cols = phantom.build_columns(TINY, which=[3])
+    x, y, z = phantom.voxel_centres(TINY)
+    b = bls[3]
+    dense = np.exp(-(TINY.mu * (x + TINY.nx * TINY.h / 2)
+                     + ((y - b.u_c) ** 2 + (z - b.v_c) ** 2) / (2 * TINY.sigma ** 2)))
+    rows, _ = cols[0]
+    want = np.nonzero(dense >= TINY.tau * dense.max())[0]
+    assert not np.array_equal(rows, want)
