@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Time-to-plan of the paper-scale phantom on one MI355X.
+
+One step = one plan optimisation with D already resident in HBM: the initial
+step size lambda_0 by 50 power iterations, then gradient projection with
+Armijo's line search from x = 1 until the relative objective change drops
+below 1e-5 (every forward, adjoint, trial, test and update on the GPU).
+
+Prints one JSON line.  --gpus must be 1: the solver runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def forward_bytes(nv, nb, nnz):
+    """Algorithmic bytes of one forward trial pass: CSR (int32 column, float32
+    value, int32 row pointer), structure id, residual out, x_k and g_k in."""
+    return 8 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 8 * nb
+
+
+def adjoint_bytes(nv, nb, nnz):
+    """Algorithmic bytes of one adjoint pass: CSC (int32 row, float32 value,
+    int32 column pointer), every residual once, gradient out."""
+    return 8 * nnz + 4 * (nb + 1) + 4 * nv + 4 * nb
+
+
+def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
+    """The FP64 oracle on the host: lambda_0 estimate plus `sample_iters`
+    iterations, scaled to the GPU's iteration count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import model, phantom, solver
+    from workloads import penalty_table, power_start_vector, start_point
+
+    D = phantom.build_dose_matrix(spec, workers=min(spec.n_beams, os.cpu_count() or 1))
+    pen = model.VoxelPenalties.from_structures(D.struct_id, penalty_table(spec))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        lam_ref, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, spec.seed),
+                                                         st.power_iters)
+        t1 = time.perf_counter()
+        ref = solver.solve(D.csr, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam_ref,
+                           max_iter=sample_iters, max_backtracks=st.max_backtracks, fixed_iters=True,
+                           keep_trace=False)
+        t2 = time.perf_counter()
+    per_iter = (t2 - t1) / max(ref.iterations, 1)
+    est = (t1 - t0) + per_iter * gpu_iterations
+    return {
+        "value": est, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"lambda_0 estimate ({st.power_iters} power iterations, {t1 - t0:.2f} s) plus "
+                   f"{ref.iterations} of the plan's iterations ({t2 - t1:.2f} s), scaled to the GPU's "
+                   f"{gpu_iterations} iterations; scipy.sparse float64, one thread"),
+        "lambda0_matches": lam_ref == lam0,
+        "host_cpu": _cpu_model(),
+        "host_nproc": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "small"])
+    ap.add_argument("--trials-per-pass", type=int, default=1)
+    ap.add_argument("--cpu-sample-iters", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs the solver on exactly one GPU; multi-GPU runs are not part of this build "
+              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0908_4421_amd.imrt import Context, Dose, Plan
+    from workloads import NAMED, PAPER_SCALE_SETTINGS, TINY_SETTINGS, penalty_table, power_start_vector
+
+    spec = NAMED[args.workload]
+    st = TINY_SETTINGS if args.workload == "tiny" else PAPER_SCALE_SETTINGS
+    ctx = Context(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dose = Dose.from_geometry(ctx, spec)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    plan = Plan(ctx, dose)
+    plan.set_structures(None, 4)
+    plan.set_penalties(penalty_table(spec))
+    v0 = torch.as_tensor(power_start_vector(dose.nb, spec.seed).astype(np.float32)).cuda()
+    x = torch.empty(dose.nb, dtype=torch.float32, device="cuda")
+
+    def step(profile=False):
+        lam0, _ = plan.lambda0(v0, st.power_iters)
+        x.fill_(st.x0)
+        res, _ = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=lam0, delta=st.delta,
+                            max_iter=st.max_iter, max_backtracks=st.max_backtracks,
+                            fixed_iters=st.fixed_iters, trials_per_pass=args.trials_per_pass,
+                            profile=profile)
+        return lam0, res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    lam0, res = runs[-1]
+    print(f"[bench] {spec.name}: {res.iterations} iterations, {ms_per_step:.2f} ms per plan", file=sys.stderr,
+          flush=True)
+
+    # one more identical step with HIP events around every forward and adjoint launch
+    _, prof = step(profile=True)
+    nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    kern = {}
+    for name, ms, n, nbytes in (("forward", prof.forward_kernel_ms, prof.forward_passes, forward_bytes(nv, nb, nnz)),
+                                ("adjoint", prof.adjoint_kernel_ms, prof.adjoint_passes, adjoint_bytes(nv, nb, nnz))):
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kern[name] = {"avg_ms": ms, "launches": n, "bytes_per_launch": nbytes, "GB_s": gbs,
+                      "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+
+    out = {
+        "metric": "time-to-plan (s) + SpMV HBM GB/s vs peak, 9-field 2.5mm; p99 served re-plan",
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "nv": nv, "nb": nb, "nnz": nnz, "delta": st.delta,
+                   "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
+                   "trials_per_pass": args.trials_per_pass},
+        "iterations": res.iterations,
+        "iters_per_s": res.iterations / (ms_per_step / 1e3),
+        "forward_passes": res.forward_passes,
+        "adjoint_passes": res.adjoint_passes,
+        "status": res.status,
+        "G_final": res.G_final,
+        "solve_device_ms": res.device_ms,
+        "dose_build_s": build_s,
+        "kernels": kern,
+        "kernel_timing": "HIP events around each launch, one extra identical plan after the timed steps",
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, st, lam0, res.iterations, args.cpu_sample_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

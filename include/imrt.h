@@ -1,0 +1,228 @@
+/*
+ * imrt.h -- C ABI of libimrt, a gfx950 (MI355X) implementation of the
+ * fluence-map optimiser of "GPU-based ultra fast IMRT plan optimization"
+ * (Men, Gu, Choi, Majumdar, Zheng, Mueller, Jiang; arXiv:0908.4421).
+ *
+ * Model (Section 2.1, Eqs. (1)-(4)): voxel dose z = D x over the voxels x
+ * beamlets dose-deposition matrix D; one-sided quadratic penalties
+ *   F_j(z_j) = w_u,j * min(z_j - T_u,j, 0)^2 + w_o,j * max(z_j - T_o,j, 0)^2
+ * summed over voxels into G(x), minimised over x >= 0.
+ * Method (Section 2.2, Eq. (5), steps 1-5): gradient projection
+ *   x_{k+1} = max(0, x_k - lambda grad G(x_k)),  grad G = 2 D^T r,
+ *   r_j = w_u,j * min(z_j - T_u,j, 0) + w_o,j * max(z_j - T_o,j, 0),
+ * with Armijo's rule: accept lambda when
+ *   G(x_{k+1}) < G(x_k) - (eps/lambda) * ||x_{k+1} - x_k||^2,
+ * else lambda <- lambda/alpha; stop when |G_{k+1} - G_k| / G_{k+1} < delta.
+ *
+ * Conventions for every entry point:
+ *  - Return value: IMRT_OK (0) or a negative imrt_error; the message of the
+ *    last error on the calling thread is returned by imrt_last_error().
+ *  - Pointers named *_dev are device memory owned by the caller (for example
+ *    PyTorch tensors); they must stay valid until the call returns.  Every
+ *    other array pointer is host memory read (or written) during the call
+ *    only.  Opaque handles are owned by the library and freed by the
+ *    matching *_destroy; destroying NULL is a no-op.
+ *  - All device work is ordered on the context's stream.  Calls that return
+ *    a host value (objective, step norm, solve result, export) synchronise
+ *    that stream before returning; the others only enqueue work.
+ *  - Dense vectors are float32: x and g have nb entries, dose and residual
+ *    nv entries.  Objective values, step sizes and norms are float64.
+ *  - One context must not be used from two threads at once.
+ */
+#ifndef IMRT_H
+#define IMRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IMRT_API __attribute__((visibility("default")))
+
+typedef struct imrt_ctx imrt_ctx;
+typedef struct imrt_dose imrt_dose;
+typedef struct imrt_plan imrt_plan;
+
+/* Error codes returned by every entry point. */
+typedef enum {
+  IMRT_OK = 0,
+  IMRT_EINVAL = -1,      /* bad argument: null handle, size mismatch, unsorted or out-of-range index, negative weight, ... */
+  IMRT_ENOMEM = -2,      /* device or host allocation failed */
+  IMRT_EHIP = -3,        /* a HIP runtime call failed; the message carries hipGetErrorString */
+  IMRT_ENOTREADY = -4,   /* structures or penalties not set on the plan */
+  IMRT_EUNSUPPORTED = -5 /* valid request outside what this build supports (message says which limit) */
+} imrt_error;
+
+/* Final state of a solve (imrt_solve_result.status). */
+typedef enum {
+  IMRT_CONVERGED = 0,    /* relative objective change below delta, or G == 0 (step 5) */
+  IMRT_MAX_ITER = 1,     /* max_iter accepted iterations done (always the case with fixed_iters) */
+  IMRT_STALLED = 2,      /* a trial equalled x_k (||x_t - x_k|| == 0): x_k is stationary */
+  IMRT_LS_FAIL = 3,      /* more than max_backtracks step reductions in one line search */
+  IMRT_NUMERIC = 4       /* a trial objective was not finite */
+} imrt_solve_status;
+
+/* Storage type of D's values.  Only IMRT_F32 is accepted by this build. */
+typedef enum { IMRT_F32 = 0, IMRT_BF16 = 1, IMRT_F16 = 2 } imrt_dtype;
+
+/* Penalty parameters of one structure (Eq. (1), generalised to separate
+ * under/over thresholds and weights).  Weights must be finite and >= 0. */
+typedef struct {
+  double T_under, T_over, w_under, w_over;
+} imrt_penalty;
+
+/* Synthetic phantom geometry for imrt_build_dose_matrix (all lengths in mm).
+ * Water box of nx*ny*nz voxels at spacing h centred on the isocentre; PTV
+ * sphere of radius r_ptv at the origin, rectum cylinder along z of radius
+ * r_rectum tangent at -y, bladder sphere of radius r_bladder tangent at +y
+ * (structure ids 0 normal, 1 PTV, 2 rectum, 3 bladder, priority
+ * PTV > rectum > bladder > normal).  n_beams coplanar parallel beams at
+ * angles 2*pi*b/n_beams; square beamlets of side `beamlet` whose closest
+ * point to the beam axis lies within r_ptv + margin; D_ij =
+ * float32(exp(-(mu*depth + r^2/(2 sigma^2)))) kept where it is >= tau times
+ * the beamlet's maximum. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+  double r_ptv, r_rectum, r_bladder;
+  int32_t n_beams;
+  double beamlet, sigma, tau, mu, margin;
+} imrt_geometry;
+
+/* Solver settings (Section 2.2). */
+typedef struct {
+  double eps;             /* Armijo sufficient-decrease parameter, 0 < eps < 1 */
+  double alpha;           /* step reduction factor, alpha > 1 */
+  double lambda0;         /* initial step of every line search, > 0 */
+  double delta;           /* relative-change stopping tolerance, >= 0 */
+  int32_t max_iter;       /* cap on accepted iterations, >= 0 */
+  int32_t max_backtracks; /* cap on reductions per line search, >= 0 */
+  int32_t fixed_iters;    /* non-zero: run exactly max_iter iterations, no stopping test */
+  int32_t trials_per_pass;/* trial step sizes evaluated per pass over D: 1, 2 or 4 (0 = 1) */
+  int32_t profile;        /* non-zero: time every forward and adjoint launch with HIP events */
+  int32_t reserved;       /* must be 0 */
+  void* trace;            /* nullable host buffer of max_iter imrt_trace_entry, filled on return */
+} imrt_solve_params;
+
+/* One accepted iteration. */
+typedef struct {
+  int32_t k;              /* accepted iterations so far (1-based) */
+  int32_t backtracks;     /* step reductions in this line search */
+  double lambda;          /* accepted step size */
+  double step_sq;         /* ||x_{k+1} - x_k||^2 */
+  double G;               /* G(x_{k+1}) */
+} imrt_trace_entry;
+
+typedef struct {
+  int32_t iterations;     /* accepted iterations */
+  int32_t forward_passes; /* passes over D in CSR form (including the initial evaluation) */
+  int32_t adjoint_passes; /* passes over D in CSC form */
+  int32_t status;         /* imrt_solve_status */
+  double G_initial;       /* G(x_1) */
+  double G_final;         /* G at the returned x */
+  double device_ms;       /* stream time of the solve, HIP events */
+  /* With params.profile: mean HIP-event duration of the forward pass kernel
+   * and of the adjoint chunk kernel over the launches that did work (the
+   * first forward_passes and adjoint_passes launches; exact when no line
+   * search needed a second pass), else 0. */
+  double forward_kernel_ms;
+  double adjoint_kernel_ms;
+} imrt_solve_result;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  All work is enqueued on
+ * hip_stream (a hipStream_t, borrowed; it must outlive the context).  NULL
+ * selects the device's null stream, which orders with every blocking stream
+ * (PyTorch's default stream is the null stream). */
+IMRT_API int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out);
+IMRT_API int imrt_ctx_destroy(imrt_ctx* ctx);
+/* The stream the context enqueues on (a hipStream_t). */
+IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
+
+/* ---- dose-deposition matrix (Section 2.1; stored as CSR, Section 2.3) ---- */
+
+/* Build the synthetic phantom's structure ids and D on the device (CSR and
+ * CSC, float32 values, int32 indices; columns ascending in each row, rows
+ * ascending in each column).  voxel_struct_out: nullable host array of
+ * nx*ny*nz bytes receiving the structure ids.  Beamlet order: beam-major,
+ * then lateral index, then axial index. */
+IMRT_API int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype storage,
+                           imrt_dose** out, uint8_t* voxel_struct_out);
+
+/* Upload a caller-built D given in CSR form (host arrays, copied).  row_ptr
+ * has nv+1 entries starting at 0 and non-decreasing; col_idx entries lie in
+ * [0, nb) and increase strictly within each row; values are finite and
+ * >= 0.  The CSC copy is derived on the host. */
+IMRT_API int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz,
+                       const int32_t* row_ptr, const int32_t* col_idx, const float* val,
+                       imrt_dtype storage, imrt_dose** out);
+
+IMRT_API int imrt_dose_info(const imrt_dose* dose, int32_t* nv, int32_t* nb, int64_t* nnz);
+
+/* Copy D back to host arrays (each nullable): CSR row_ptr[nv+1],
+ * col_idx[nnz], val[nnz]; CSC col_ptr[nb+1], row_idx[nnz], cval[nnz];
+ * voxel_struct[nv] (only for matrices from imrt_build_dose_matrix). */
+IMRT_API int imrt_dose_export(const imrt_dose* dose, int32_t* row_ptr, int32_t* col_idx, float* val,
+                     int32_t* col_ptr, int32_t* row_idx, float* cval, uint8_t* voxel_struct);
+
+/* d = D x (CSR, voxel-parallel).  x_dev: nb floats; d_dev: nv floats. */
+IMRT_API int imrt_dose_apply(const imrt_dose* dose, const float* x_dev, float* d_dev);
+/* y = D^T r (CSC, beamlet-parallel).  r_dev: nv floats; y_dev: nb floats. */
+IMRT_API int imrt_dose_apply_transpose(const imrt_dose* dose, const float* r_dev, float* y_dev);
+
+IMRT_API int imrt_dose_destroy(imrt_dose* dose);
+
+/* ---- plan: D plus penalties --------------------------------------------- */
+
+/* A plan borrows `dose`, which must outlive it; several plans may share
+ * one dose matrix. */
+IMRT_API int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out);
+
+/* Structure id of every voxel (host, nv bytes, each < nstruct <= 256).
+ * NULL takes the ids computed by imrt_build_dose_matrix. */
+IMRT_API int imrt_set_structures(imrt_plan* plan, const uint8_t* voxel_struct, int32_t nstruct);
+
+/* Penalty table, one entry per structure (host, nstruct entries). */
+IMRT_API int imrt_set_penalties(imrt_plan* plan, const imrt_penalty* table);
+
+/* Optional per-voxel thresholds (host, nv floats each) replacing the
+ * structure thresholds: the paper's T_j, the dose of an original plan.
+ * Weights still come from the structure table.  NULL, NULL clears them. */
+IMRT_API int imrt_set_voxel_targets(imrt_plan* plan, const float* T_under, const float* T_over);
+
+/* G(x) (Eqs. (2)-(4)) in float64, returned in *G_out (host).  dose_dev
+ * (nullable, nv floats) receives D x. */
+IMRT_API int imrt_evaluate_objective(imrt_plan* plan, const float* x_dev, double* G_out, float* dose_dev);
+
+/* g = grad G(x) = 2 D^T r(D x) (nb floats).  G_out (nullable host) receives G(x). */
+IMRT_API int imrt_gradient(imrt_plan* plan, const float* x_dev, float* g_dev, double* G_out);
+
+/* Trial point of step 2/4: x_out = max(0, x - lambda g) (computed in
+ * float64, stored as float32) and *step_sq_out = ||x_out - x||^2 (float64,
+ * host; nullable). */
+IMRT_API int imrt_project(imrt_plan* plan, const float* x_dev, const float* g_dev, double lambda,
+                 float* x_out_dev, double* step_sq_out);
+
+/* Initial step size lambda_0 = smallest power of two >= 2/L, where
+ * L = 2 * (largest penalty weight) * s^2 and s^2 = ||D v||^2 for the unit
+ * vector v reached by `iters` power iterations v <- D^T D v / ||D^T D v||
+ * started from v0_dev (nb floats, not all zero).  Writes lambda_0 and s. */
+IMRT_API int imrt_estimate_lambda0(imrt_plan* plan, const float* v0_dev, int32_t iters,
+                          double* lambda0_out, double* sigma_out);
+
+/* Solve from x_dev (in: x_1 >= 0, finite; out: the final iterate). */
+IMRT_API int imrt_solve(imrt_plan* plan, const imrt_solve_params* params, float* x_dev,
+               imrt_solve_result* result);
+
+IMRT_API int imrt_plan_destroy(imrt_plan* plan);
+
+/* Message of the last error on this thread ("" if none). */
+IMRT_API const char* imrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMRT_H */

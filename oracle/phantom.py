@@ -175,9 +175,27 @@ def build_columns(spec: PhantomSpec, which=None):
     return bls, cols
 
 
-def build_dose_matrix(spec: PhantomSpec) -> DoseMatrix:
-    """Brute-force D for the whole phantom, in CSC then CSR (indices sorted)."""
-    bls, cols = build_columns(spec)
+def _columns_of_beam(args):
+    spec, beam = args
+    bls = beamlets(spec)
+    which = [i for i, b in enumerate(bls) if b.beam == beam]
+    return build_columns(spec, which)[1]
+
+
+def build_dose_matrix(spec: PhantomSpec, workers: int = 1) -> DoseMatrix:
+    """Brute-force D for the whole phantom, in CSC then CSR (indices sorted).
+
+    ``workers`` > 1 evaluates the beams in separate processes; each column is
+    computed by the same code either way.
+    """
+    if workers > 1 and spec.n_beams > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, spec.n_beams)) as pool:
+            per_beam = pool.map(_columns_of_beam, [(spec, b) for b in range(spec.n_beams)])
+        bls = beamlets(spec)
+        cols = [c for group in per_beam for c in group]
+    else:
+        bls, cols = build_columns(spec)
     nv, nb = spec.nv, len(bls)
     lens = np.array([len(r) for r, _ in cols], dtype=np.int64)
     col_ptr = np.zeros(nb + 1, dtype=np.int64)
@@ -189,3 +207,40 @@ def build_dose_matrix(spec: PhantomSpec) -> DoseMatrix:
     csr = csc.tocsr()
     csr.sort_indices()
     return DoseMatrix(nv, nb, csr, csc, structure_ids(spec), bls)
+
+
+def column_minima(spec: PhantomSpec, workers: int = 1) -> np.ndarray:
+    """e_min of every beamlet (float64), by brute force over all voxels."""
+    bls = beamlets(spec)
+    dirs = beam_directions(spec)
+    x, y, z = voxel_centres(spec)
+    out = np.empty(len(bls))
+    cache = {}
+    for i, bl in enumerate(bls):
+        if bl.beam not in cache:
+            cache.clear()
+            cache[bl.beam] = beam_depth_and_u(spec, x, y, *dirs[bl.beam])
+        depth, u = cache[bl.beam]
+        out[i] = beamlet_exponent(spec, depth, u, z, bl).min()
+    return out
+
+
+def dose_rows(spec: PhantomSpec, rows, emin: np.ndarray):
+    """Rows of D (kept beamlet indices ascending, float32 values) for the voxel
+    indices ``rows``, given every beamlet's e_min; same formulas as the columns."""
+    bls = beamlets(spec)
+    dirs = beam_directions(spec)
+    x, y, z = voxel_centres(spec)
+    rows = np.asarray(rows, dtype=np.int64)
+    xs, ys, zs = x[rows], y[rows], z[rows]
+    L = math.log(1.0 / spec.tau)
+    out = []
+    per_beam = [beam_depth_and_u(spec, xs, ys, *dirs[b]) for b in range(spec.n_beams)]
+    e = np.empty((len(rows), len(bls)))
+    for i, bl in enumerate(bls):
+        depth, u = per_beam[bl.beam]
+        e[:, i] = beamlet_exponent(spec, depth, u, zs, bl)
+    for r in range(len(rows)):
+        keep = np.nonzero(e[r] <= emin + L)[0].astype(np.int32)
+        out.append((keep, np.exp(-e[r, keep]).astype(np.float32)))
+    return out

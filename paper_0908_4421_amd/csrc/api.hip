@@ -1,0 +1,864 @@
+// C ABI of libimrt: argument validation, device memory, host preprocessing of
+// D (row blocks and adjoint chunks) and the stream-ordered solve driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "imrt_internal.h"
+
+namespace imrt {
+
+namespace {
+thread_local std::string g_err;
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (v == nullptr || *v == 0) return dflt;
+  const int x = std::atoi(v);
+  return x > 0 ? x : dflt;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+  if (e == hipErrorOutOfMemory) return set_error(IMRT_ENOMEM, "hipMalloc: out of device memory");
+  if (e != hipSuccess) return hip_error(e, "hipMalloc");
+  return IMRT_OK;
+}
+
+template <typename T>
+void dev_free(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int use_device(const imrt_ctx* ctx) {
+  IMRT_HIP(hipSetDevice(ctx->device));
+  return IMRT_OK;
+}
+
+double pow2_at_least(double q) {
+  int ex = 0;
+  const double mant = std::frexp(q, &ex);
+  return mant == 0.5 ? q : std::ldexp(1.0, ex);
+}
+
+}  // namespace
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return IMRT_EHIP;
+}
+
+// Row blocks for the forward pass (at most kFwdNnzMax nonzeros and kFwdRowsMax
+// rows each, or one longer row alone) and nonzero chunks of each CSC column for
+// the adjoint pass (about kAdjChunk nonzeros, split evenly inside a column).
+int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::vector<int32_t>& col_ptr) {
+  std::vector<int32_t> blocks;
+  blocks.push_back(0);
+  int r = 0;
+  while (r < D->nv) {
+    const int start = r;
+    int64_t nz = 0;
+    while (r < D->nv && r - start < kFwdRowsMax) {
+      const int64_t len = row_ptr[r + 1] - row_ptr[r];
+      if (r > start && nz + len > kFwdNnzMax) break;
+      nz += len;
+      ++r;
+      if (nz > kFwdNnzMax) break;
+    }
+    blocks.push_back(r);
+  }
+  std::vector<int32_t> chunk_k, col_chunk(D->nb + 1, 0);
+  chunk_k.push_back(0);
+  for (int i = 0; i < D->nb; ++i) {
+    col_chunk[i] = static_cast<int32_t>(chunk_k.size()) - 1;
+    const int64_t k0 = col_ptr[i], len = col_ptr[i + 1] - col_ptr[i];
+    const int64_t n = std::max<int64_t>(1, (len + kAdjChunk - 1) / kAdjChunk);
+    for (int64_t c = 1; c <= n; ++c) chunk_k.push_back(static_cast<int32_t>(k0 + (len * c) / n));
+  }
+  col_chunk[D->nb] = static_cast<int32_t>(chunk_k.size()) - 1;
+  D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
+  D->nchunks = static_cast<int32_t>(chunk_k.size()) - 1;
+  int rc;
+  if ((rc = dev_alloc(&D->block_row, blocks.size()))) return rc;
+  if ((rc = dev_alloc(&D->chunk_k, chunk_k.size()))) return rc;
+  if ((rc = dev_alloc(&D->col_chunk, col_chunk.size()))) return rc;
+  hipStream_t s = D->ctx->stream;
+  IMRT_HIP(hipMemcpyAsync(D->block_row, blocks.data(), sizeof(int32_t) * blocks.size(), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->chunk_k, chunk_k.data(), sizeof(int32_t) * chunk_k.size(), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->col_chunk, col_chunk.data(), sizeof(int32_t) * col_chunk.size(),
+                          hipMemcpyHostToDevice, s));
+  D->partials_len = std::max(kMaxTrials * forward_grid(D->ctx, D), D->nchunks) + 16;
+  if ((rc = dev_alloc(&D->partials, D->partials_len))) return rc;
+  IMRT_HIP(hipStreamSynchronize(s));
+  return IMRT_OK;
+}
+
+}  // namespace imrt
+
+using namespace imrt;
+
+namespace {
+
+void free_dose(imrt_dose* D) {
+  if (!D) return;
+  (void)hipSetDevice(D->ctx->device);
+  dev_free(D->row_ptr);
+  dev_free(D->col_idx);
+  dev_free(D->val);
+  dev_free(D->col_ptr);
+  dev_free(D->row_idx);
+  dev_free(D->cval);
+  dev_free(D->block_row);
+  dev_free(D->chunk_k);
+  dev_free(D->col_chunk);
+  dev_free(D->sid);
+  dev_free(D->partials);
+  delete D;
+}
+
+void free_plan(imrt_plan* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->ctx->device);
+  dev_free(P->sid);
+  dev_free(P->table);
+  dev_free(P->Tu_vox);
+  dev_free(P->To_vox);
+  for (auto& b : P->rbuf) dev_free(b);
+  dev_free(P->xk);
+  dev_free(P->gk);
+  dev_free(P->vtmp);
+  dev_free(P->fwd_partials);
+  dev_free(P->adj_partials);
+  dev_free(P->misc);
+  dev_free(P->st);
+  dev_free(P->trace);
+  if (P->st_host) (void)hipHostFree(P->st_host);
+  if (P->misc_host) (void)hipHostFree(P->misc_host);
+  delete P;
+}
+
+int plan_ready(const imrt_plan* P) {
+  if (!P) return set_error(IMRT_EINVAL, "plan is NULL");
+  if (!P->have_struct) return set_error(IMRT_ENOTREADY, "structures not set (imrt_set_structures)");
+  if (!P->have_pen) return set_error(IMRT_ENOTREADY, "penalties not set (imrt_set_penalties)");
+  return IMRT_OK;
+}
+
+Penalties plan_penalties(const imrt_plan* P) {
+  return Penalties{P->sid, P->table, P->Tu_vox, P->To_vox};
+}
+
+FwdArgs base_fwd(const imrt_dose* D) {
+  FwdArgs a{};
+  a.row_ptr = D->row_ptr;
+  a.col_idx = D->col_idx;
+  a.val = D->val;
+  a.block_row = D->block_row;
+  a.nblocks = D->nblocks;
+  a.nv = D->nv;
+  a.nb = D->nb;
+  return a;
+}
+
+int ensure_rbuf(imrt_plan* P, int count) {
+  for (int i = 0; i < count; ++i)
+    if (P->rbuf[i] == nullptr) {
+      const int rc = dev_alloc(&P->rbuf[i], P->dose->nv);
+      if (rc) return rc;
+    }
+  return IMRT_OK;
+}
+
+// Objective (and optionally dose/residual) of x on the plan's stream; the
+// float64 total lands in P->misc[slot].
+int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, int slot) {
+  const imrt_dose* D = P->dose;
+  FwdArgs a = base_fwd(D);
+  a.mode = FWD_EVAL;
+  a.pen = plan_penalties(P);
+  a.x = x;
+  a.d_out = dose_out;
+  a.r_out = r_out;
+  a.partials = P->fwd_partials;
+  const int grid = forward_grid(P->ctx, D);
+  int rc = launch_forward(P->ctx, D, a, 1, grid);
+  if (rc) return rc;
+  return launch_sum(P->ctx, P->fwd_partials, grid, P->misc + slot);
+}
+
+int adjoint_into(const imrt_ctx* ctx, const imrt_dose* D, const float* r, double scale, double* partials,
+                 float* out) {
+  AdjArgs a{};
+  a.row_idx = D->row_idx;
+  a.val = D->cval;
+  a.chunk_k = D->chunk_k;
+  a.nchunks = D->nchunks;
+  a.solve = 0;
+  a.r = r;
+  a.partials = partials;
+  AdjFinalArgs f{};
+  f.col_chunk = D->col_chunk;
+  f.nb = D->nb;
+  f.solve = 0;
+  f.scale = scale;
+  f.partials = partials;
+  f.out = out;
+  return launch_adjoint(ctx, D, a, f);
+}
+
+int fetch_misc(imrt_plan* P, int n) {
+  IMRT_HIP(hipMemcpyAsync(P->misc_host, P->misc, sizeof(double) * n, hipMemcpyDeviceToHost, P->ctx->stream));
+  IMRT_HIP(hipStreamSynchronize(P->ctx->stream));
+  return IMRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* imrt_last_error(void) { return imrt::g_err.c_str(); }
+
+int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
+  if (!out) return set_error(IMRT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  IMRT_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return set_error(IMRT_EINVAL, "device index out of range");
+  IMRT_HIP(hipSetDevice(device));
+  auto* c = new (std::nothrow) imrt_ctx();
+  if (!c) return set_error(IMRT_ENOMEM, "host allocation failed");
+  c->device = device;
+  int ncu = 0, lds = 0;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+  (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  if (ncu > 0) c->num_cu = ncu;
+  if (lds > 0) c->max_lds = static_cast<size_t>(lds);
+  c->tune.fwd_grid_per_cu = env_int("IMRT_FWD_WG_PER_CU", c->tune.fwd_grid_per_cu);
+  c->tune.adj_grid_per_cu = env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu);
+  c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
+  c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
+  *out = c;
+  return IMRT_OK;
+}
+
+int imrt_ctx_destroy(imrt_ctx* ctx) {
+  if (!ctx) return IMRT_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return IMRT_OK;
+}
+
+int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out) {
+  if (!ctx || !hip_stream_out) return set_error(IMRT_EINVAL, "ctx or out is NULL");
+  *hip_stream_out = ctx->stream;
+  return IMRT_OK;
+}
+
+int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype storage, imrt_dose** out,
+                           uint8_t* voxel_struct_out) {
+  if (!ctx || !geom || !out) return set_error(IMRT_EINVAL, "ctx, geom or out is NULL");
+  *out = nullptr;
+  if (storage != IMRT_F32) return set_error(IMRT_EUNSUPPORTED, "only IMRT_F32 storage is supported");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  auto* D = new (std::nothrow) imrt_dose();
+  if (!D) return set_error(IMRT_ENOMEM, "host allocation failed");
+  D->ctx = ctx;
+  try {
+    rc = build_phantom(ctx, geom, D);
+  } catch (const std::bad_alloc&) {
+    rc = set_error(IMRT_ENOMEM, "host allocation failed");
+  }
+  if (rc == IMRT_OK && voxel_struct_out) {
+    const hipError_t e = hipMemcpy(voxel_struct_out, D->sid, D->nv, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_error(e, "hipMemcpy(voxel_struct)");
+  }
+  if (rc) {
+    free_dose(D);
+    return rc;
+  }
+  *out = D;
+  return IMRT_OK;
+}
+
+int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const int32_t* row_ptr,
+                       const int32_t* col_idx, const float* val, imrt_dtype storage, imrt_dose** out) {
+  if (!ctx || !out || !row_ptr) return set_error(IMRT_EINVAL, "ctx, out or row_ptr is NULL");
+  *out = nullptr;
+  if (storage != IMRT_F32) return set_error(IMRT_EUNSUPPORTED, "only IMRT_F32 storage is supported");
+  if (nv <= 0 || nb <= 0) return set_error(IMRT_EINVAL, "nv and nb must be positive");
+  if (nnz < 0 || nnz >= (int64_t(1) << 31)) return set_error(IMRT_EINVAL, "nnz must be in [0, 2^31)");
+  if (nnz > 0 && (!col_idx || !val)) return set_error(IMRT_EINVAL, "col_idx or val is NULL");
+  if (row_ptr[0] != 0 || row_ptr[nv] != nnz) return set_error(IMRT_EINVAL, "row_ptr must start at 0 and end at nnz");
+  for (int32_t j = 0; j < nv; ++j) {
+    if (row_ptr[j + 1] < row_ptr[j]) return set_error(IMRT_EINVAL, "row_ptr is decreasing");
+    for (int32_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+      if (col_idx[k] < 0 || col_idx[k] >= nb) return set_error(IMRT_EINVAL, "column index out of range");
+      if (k > row_ptr[j] && col_idx[k] <= col_idx[k - 1])
+        return set_error(IMRT_EINVAL, "column indices must increase strictly within a row");
+      if (!(val[k] >= 0.0f) || !std::isfinite(val[k])) return set_error(IMRT_EINVAL, "values must be finite and >= 0");
+    }
+  }
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  auto* D = new (std::nothrow) imrt_dose();
+  if (!D) return set_error(IMRT_ENOMEM, "host allocation failed");
+  D->ctx = ctx;
+  D->nv = nv;
+  D->nb = nb;
+  D->nnz = nnz;
+  try {
+    // CSC by a stable counting sort over columns: rows stay ascending.
+    std::vector<int32_t> rp(row_ptr, row_ptr + nv + 1), cp(nb + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) cp[col_idx[k] + 1]++;
+    for (int i = 0; i < nb; ++i) cp[i + 1] += cp[i];
+    std::vector<int32_t> ri(static_cast<size_t>(nnz)), fill(cp.begin(), cp.end() - 1);
+    std::vector<float> cv(static_cast<size_t>(nnz));
+    for (int32_t j = 0; j < nv; ++j)
+      for (int32_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
+        const int32_t p = fill[col_idx[k]]++;
+        ri[p] = j;
+        cv[p] = val[k];
+      }
+    hipStream_t s = ctx->stream;
+    if ((rc = dev_alloc(&D->row_ptr, nv + 1)) || (rc = dev_alloc(&D->col_idx, nnz)) ||
+        (rc = dev_alloc(&D->val, nnz)) || (rc = dev_alloc(&D->col_ptr, nb + 1)) ||
+        (rc = dev_alloc(&D->row_idx, nnz)) || (rc = dev_alloc(&D->cval, nnz))) {
+      free_dose(D);
+      return rc;
+    }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(D->row_ptr, row_ptr, sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->val, val, sizeof(float) * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(D->col_ptr, cp.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->row_idx, ri.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->cval, cv.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      free_dose(D);
+      return hip_error(e, "upload of D");
+    }
+    rc = finish_dose(D, rp, cp);
+  } catch (const std::bad_alloc&) {
+    rc = set_error(IMRT_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    free_dose(D);
+    return rc;
+  }
+  *out = D;
+  return IMRT_OK;
+}
+
+int imrt_dose_info(const imrt_dose* dose, int32_t* nv, int32_t* nb, int64_t* nnz) {
+  if (!dose) return set_error(IMRT_EINVAL, "dose is NULL");
+  if (nv) *nv = dose->nv;
+  if (nb) *nb = dose->nb;
+  if (nnz) *nnz = dose->nnz;
+  return IMRT_OK;
+}
+
+int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, float* val, int32_t* col_ptr,
+                     int32_t* row_idx, float* cval, uint8_t* voxel_struct) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  int rc = use_device(D->ctx);
+  if (rc) return rc;
+  hipStream_t s = D->ctx->stream;
+  const size_t nz = static_cast<size_t>(D->nnz);
+  if (voxel_struct && !D->sid) return set_error(IMRT_EINVAL, "this dose matrix has no structure ids");
+  if (row_ptr) IMRT_HIP(hipMemcpyAsync(row_ptr, D->row_ptr, sizeof(int32_t) * (D->nv + 1), hipMemcpyDeviceToHost, s));
+  if (col_idx && nz) IMRT_HIP(hipMemcpyAsync(col_idx, D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+  if (val && nz) IMRT_HIP(hipMemcpyAsync(val, D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
+  if (col_ptr) IMRT_HIP(hipMemcpyAsync(col_ptr, D->col_ptr, sizeof(int32_t) * (D->nb + 1), hipMemcpyDeviceToHost, s));
+  if (row_idx && nz) IMRT_HIP(hipMemcpyAsync(row_idx, D->row_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+  if (cval && nz) IMRT_HIP(hipMemcpyAsync(cval, D->cval, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
+  if (voxel_struct) IMRT_HIP(hipMemcpyAsync(voxel_struct, D->sid, D->nv, hipMemcpyDeviceToHost, s));
+  IMRT_HIP(hipStreamSynchronize(s));
+  return IMRT_OK;
+}
+
+int imrt_dose_apply(const imrt_dose* D, const float* x_dev, float* d_dev) {
+  if (!D || !x_dev || !d_dev) return set_error(IMRT_EINVAL, "dose, x or d is NULL");
+  int rc = use_device(D->ctx);
+  if (rc) return rc;
+  FwdArgs a = base_fwd(D);
+  a.mode = FWD_PLAIN;
+  a.x = x_dev;
+  a.d_out = d_dev;
+  a.partials = D->partials;
+  return launch_forward(D->ctx, D, a, 1, forward_grid(D->ctx, D));
+}
+
+int imrt_dose_apply_transpose(const imrt_dose* D, const float* r_dev, float* y_dev) {
+  if (!D || !r_dev || !y_dev) return set_error(IMRT_EINVAL, "dose, r or y is NULL");
+  int rc = use_device(D->ctx);
+  if (rc) return rc;
+  return adjoint_into(D->ctx, D, r_dev, 1.0, D->partials, y_dev);
+}
+
+int imrt_dose_destroy(imrt_dose* dose) {
+  free_dose(dose);
+  return IMRT_OK;
+}
+
+int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
+  if (!ctx || !dose || !out) return set_error(IMRT_EINVAL, "ctx, dose or out is NULL");
+  *out = nullptr;
+  if (dose->ctx->device != ctx->device) return set_error(IMRT_EINVAL, "dose lives on another device");
+  int rc = use_device(ctx);
+  if (rc) return rc;
+  auto* P = new (std::nothrow) imrt_plan();
+  if (!P) return set_error(IMRT_ENOMEM, "host allocation failed");
+  P->ctx = ctx;
+  P->dose = dose;
+  const int grid = forward_grid(ctx, dose);
+  if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
+      (rc = ensure_rbuf(P, 2)) || (rc = dev_alloc(&P->xk, dose->nb)) || (rc = dev_alloc(&P->gk, dose->nb)) ||
+      (rc = dev_alloc(&P->vtmp, dose->nv)) || (rc = dev_alloc(&P->fwd_partials, kMaxTrials * grid)) ||
+      (rc = dev_alloc(&P->adj_partials, dose->nchunks)) || (rc = dev_alloc(&P->misc, 16)) ||
+      (rc = dev_alloc(&P->st, 1))) {
+    free_plan(P);
+    return rc;
+  }
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->st_host), sizeof(SolverState) * 2);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&P->misc_host), sizeof(double) * 16);
+  if (e != hipSuccess) {
+    free_plan(P);
+    return hip_error(e, "hipHostMalloc");
+  }
+  *out = P;
+  return IMRT_OK;
+}
+
+int imrt_set_structures(imrt_plan* P, const uint8_t* voxel_struct, int32_t nstruct) {
+  if (!P) return set_error(IMRT_EINVAL, "plan is NULL");
+  if (nstruct <= 0 || nstruct > kMaxStruct) return set_error(IMRT_EINVAL, "nstruct must be in [1, 256]");
+  int rc = use_device(P->ctx);
+  if (rc) return rc;
+  const imrt_dose* D = P->dose;
+  std::vector<uint8_t> ids;
+  try {
+    ids.resize(D->nv);
+  } catch (const std::bad_alloc&) {
+    return set_error(IMRT_ENOMEM, "host allocation failed");
+  }
+  if (voxel_struct) {
+    std::memcpy(ids.data(), voxel_struct, D->nv);
+  } else {
+    if (!D->sid) return set_error(IMRT_EINVAL, "NULL structure ids need a dose matrix from imrt_build_dose_matrix");
+    IMRT_HIP(hipMemcpy(ids.data(), D->sid, D->nv, hipMemcpyDeviceToHost));
+  }
+  std::vector<char> present(kMaxStruct, 0);
+  for (int32_t j = 0; j < D->nv; ++j) {
+    if (ids[j] >= nstruct) return set_error(IMRT_EINVAL, "structure id >= nstruct");
+    present[ids[j]] = 1;
+  }
+  IMRT_HIP(hipMemcpy(P->sid, ids.data(), D->nv, hipMemcpyHostToDevice));
+  P->nstruct = nstruct;
+  P->have_struct = true;
+  P->have_pen = false;  // the table must match the new structure count
+  return IMRT_OK;
+}
+
+int imrt_set_penalties(imrt_plan* P, const imrt_penalty* table) {
+  if (!P || !table) return set_error(IMRT_EINVAL, "plan or table is NULL");
+  if (!P->have_struct) return set_error(IMRT_ENOTREADY, "set structures before penalties");
+  int rc = use_device(P->ctx);
+  if (rc) return rc;
+  std::vector<PenaltyDev> t(P->nstruct);
+  for (int s = 0; s < P->nstruct; ++s) {
+    const imrt_penalty& p = table[s];
+    if (!std::isfinite(p.T_under) || !std::isfinite(p.T_over) || !std::isfinite(p.w_under) ||
+        !std::isfinite(p.w_over))
+      return set_error(IMRT_EINVAL, "penalty parameters must be finite");
+    if (p.w_under < 0 || p.w_over < 0) return set_error(IMRT_EINVAL, "penalty weights must be >= 0");
+    t[s] = PenaltyDev{p.T_under, p.T_over, p.w_under, p.w_over};
+  }
+  // largest weight over the structures that occur among the voxels
+  std::vector<uint8_t> ids(P->dose->nv);
+  IMRT_HIP(hipMemcpy(ids.data(), P->sid, P->dose->nv, hipMemcpyDeviceToHost));
+  std::vector<char> present(kMaxStruct, 0);
+  for (uint8_t s : ids) present[s] = 1;
+  double wmax = 0.0;
+  for (int s = 0; s < P->nstruct; ++s)
+    if (present[s]) wmax = std::max(wmax, std::max(t[s].w_u, t[s].w_o));
+  IMRT_HIP(hipMemcpy(P->table, t.data(), sizeof(PenaltyDev) * P->nstruct, hipMemcpyHostToDevice));
+  P->w_max = wmax;
+  P->have_pen = true;
+  return IMRT_OK;
+}
+
+int imrt_set_voxel_targets(imrt_plan* P, const float* T_under, const float* T_over) {
+  if (!P) return set_error(IMRT_EINVAL, "plan is NULL");
+  int rc = use_device(P->ctx);
+  if (rc) return rc;
+  if (!T_under && !T_over) {
+    dev_free(P->Tu_vox);
+    dev_free(P->To_vox);
+    return IMRT_OK;
+  }
+  if (!T_under || !T_over) return set_error(IMRT_EINVAL, "give both T_under and T_over, or neither");
+  const int nv = P->dose->nv;
+  for (int j = 0; j < nv; ++j)
+    if (!std::isfinite(T_under[j]) || !std::isfinite(T_over[j]))
+      return set_error(IMRT_EINVAL, "voxel targets must be finite");
+  if (!P->Tu_vox && (rc = dev_alloc(&P->Tu_vox, nv))) return rc;
+  if (!P->To_vox && (rc = dev_alloc(&P->To_vox, nv))) return rc;
+  IMRT_HIP(hipMemcpy(P->Tu_vox, T_under, sizeof(float) * nv, hipMemcpyHostToDevice));
+  IMRT_HIP(hipMemcpy(P->To_vox, T_over, sizeof(float) * nv, hipMemcpyHostToDevice));
+  return IMRT_OK;
+}
+
+int imrt_evaluate_objective(imrt_plan* P, const float* x_dev, double* G_out, float* dose_dev) {
+  int rc = plan_ready(P);
+  if (rc) return rc;
+  if (!x_dev || !G_out) return set_error(IMRT_EINVAL, "x or G_out is NULL");
+  if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, dose_dev, nullptr, 0)) || (rc = fetch_misc(P, 1)))
+    return rc;
+  *G_out = P->misc_host[0];
+  return IMRT_OK;
+}
+
+int imrt_gradient(imrt_plan* P, const float* x_dev, float* g_dev, double* G_out) {
+  int rc = plan_ready(P);
+  if (rc) return rc;
+  if (!x_dev || !g_dev) return set_error(IMRT_EINVAL, "x or g is NULL");
+  if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, nullptr, P->rbuf[0], 0)) ||
+      (rc = adjoint_into(P->ctx, P->dose, P->rbuf[0], 2.0, P->adj_partials, g_dev)))
+    return rc;
+  if (G_out) {
+    if ((rc = fetch_misc(P, 1))) return rc;
+    *G_out = P->misc_host[0];
+  }
+  return IMRT_OK;
+}
+
+int imrt_project(imrt_plan* P, const float* x_dev, const float* g_dev, double lambda, float* x_out_dev,
+                 double* step_sq_out) {
+  if (!P || !x_dev || !g_dev || !x_out_dev) return set_error(IMRT_EINVAL, "plan, x, g or x_out is NULL");
+  if (!std::isfinite(lambda) || lambda < 0) return set_error(IMRT_EINVAL, "lambda must be finite and >= 0");
+  int rc;
+  if ((rc = use_device(P->ctx)) ||
+      (rc = launch_project(P->ctx, x_dev, g_dev, lambda, P->dose->nb, x_out_dev, P->misc)))
+    return rc;
+  if (step_sq_out) {
+    if ((rc = fetch_misc(P, 1))) return rc;
+    *step_sq_out = P->misc_host[0];
+  }
+  return IMRT_OK;
+}
+
+int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, double* lambda0_out,
+                          double* sigma_out) {
+  int rc = plan_ready(P);
+  if (rc) return rc;
+  if (!v0_dev || iters < 0) return set_error(IMRT_EINVAL, "v0 is NULL or iters < 0");
+  if ((rc = use_device(P->ctx))) return rc;
+  const imrt_dose* D = P->dose;
+  const imrt_ctx* C = P->ctx;
+  float* v = P->xk;
+  float* w = P->gk;
+  if ((rc = launch_normalize(C, v0_dev, D->nb, v, P->misc + 1))) return rc;
+  for (int it = 0; it <= iters; ++it) {
+    FwdArgs a = base_fwd(D);
+    a.mode = FWD_PLAIN;
+    a.x = v;
+    a.d_out = P->vtmp;
+    a.partials = P->fwd_partials;
+    const int grid = forward_grid(C, D);
+    if ((rc = launch_forward(C, D, a, 1, grid))) return rc;
+    if (it == iters) {
+      if ((rc = launch_sum(C, P->fwd_partials, grid, P->misc))) return rc;
+      break;
+    }
+    if ((rc = adjoint_into(C, D, P->vtmp, 1.0, P->adj_partials, w))) return rc;
+    if ((rc = launch_normalize(C, w, D->nb, v, P->misc + 1))) return rc;
+  }
+  if ((rc = fetch_misc(P, 2))) return rc;
+  const double s2 = P->misc_host[0];
+  if (P->misc_host[1] == 0.0 || !(s2 > 0.0)) return set_error(IMRT_EINVAL, "power iteration reached a zero vector");
+  if (!(P->w_max > 0.0)) return set_error(IMRT_EINVAL, "all penalty weights are zero");
+  const double L = 2.0 * P->w_max * s2;
+  if (lambda0_out) *lambda0_out = pow2_at_least(2.0 / L);
+  if (sigma_out) *sigma_out = std::sqrt(s2);
+  return IMRT_OK;
+}
+
+int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_solve_result* res) {
+  int rc = plan_ready(P);
+  if (rc) return rc;
+  if (!prm || !x_dev || !res) return set_error(IMRT_EINVAL, "params, x or result is NULL");
+  if (!(prm->eps > 0.0 && prm->eps < 1.0)) return set_error(IMRT_EINVAL, "eps must lie in (0, 1)");
+  if (!(prm->alpha > 1.0) || !std::isfinite(prm->alpha)) return set_error(IMRT_EINVAL, "alpha must be > 1");
+  if (!(prm->lambda0 > 0.0) || !std::isfinite(prm->lambda0)) return set_error(IMRT_EINVAL, "lambda0 must be > 0");
+  if (!(prm->delta >= 0.0)) return set_error(IMRT_EINVAL, "delta must be >= 0");
+  if (prm->max_iter < 0 || prm->max_backtracks < 0) return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
+  if (prm->reserved != 0) return set_error(IMRT_EINVAL, "reserved must be 0");
+  const int nt = prm->trials_per_pass == 0 ? 1 : prm->trials_per_pass;
+  if (nt != 1 && nt != 2 && nt != 4) return set_error(IMRT_EINVAL, "trials_per_pass must be 0, 1, 2 or 4");
+  if ((rc = use_device(P->ctx))) return rc;
+  const imrt_dose* D = P->dose;
+  imrt_ctx* C = P->ctx;
+  hipStream_t s = C->stream;
+  if (forward_lds_bytes(D->nb, nt) > C->max_lds)
+    return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
+
+  // x_1 >= 0 and finite (step "Initialization")
+  std::vector<float> xh(D->nb);
+  IMRT_HIP(hipMemcpyAsync(xh.data(), x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToHost, s));
+  IMRT_HIP(hipStreamSynchronize(s));
+  for (float v : xh)
+    if (!(v >= 0.0f) || !std::isfinite(v)) return set_error(IMRT_EINVAL, "x_1 must be finite and >= 0");
+  if ((rc = ensure_rbuf(P, nt + 1))) return rc;
+  const int cap = prm->trace ? prm->max_iter : 0;
+  if (cap > P->trace_cap) {
+    dev_free(P->trace);
+    if ((rc = dev_alloc(&P->trace, cap))) return rc;
+    P->trace_cap = cap;
+  }
+
+  SolverState init{};
+  init.phase = PH_INIT;
+  init.status = IMRT_MAX_ITER;
+  init.ntrials = nt;
+  init.max_iter = prm->max_iter;
+  init.max_bt = prm->max_backtracks;
+  init.fixed = prm->fixed_iters ? 1 : 0;
+  init.trace_cap = cap;
+  init.lambda = prm->lambda0;
+  init.eps = prm->eps;
+  init.alpha = prm->alpha;
+  init.lambda0 = prm->lambda0;
+  init.delta = prm->delta;
+  P->st_host[0] = init;
+
+  hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_poll[2] = {nullptr, nullptr};
+  // per-launch timing events (profile mode): pairs for forward and adjoint launches
+  std::vector<hipEvent_t> ev_fwd, ev_adj;
+  auto cleanup = [&]() {
+    if (ev_start) (void)hipEventDestroy(ev_start);
+    if (ev_end) (void)hipEventDestroy(ev_end);
+    for (auto& e : ev_poll)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : ev_fwd) (void)hipEventDestroy(e);
+    for (auto& e : ev_adj) (void)hipEventDestroy(e);
+  };
+  auto event_pair = [&](std::vector<hipEvent_t>& pool, hipEvent_t* a, hipEvent_t* b) -> hipError_t {
+    *a = *b = nullptr;
+    if (!prm->profile) return hipSuccess;
+    hipEvent_t x = nullptr, y = nullptr;
+    hipError_t r = hipEventCreate(&x);
+    if (r == hipSuccess) r = hipEventCreate(&y);
+    if (r != hipSuccess) {
+      if (x) (void)hipEventDestroy(x);
+      return r;
+    }
+    pool.push_back(x);
+    pool.push_back(y);
+    *a = x;
+    *b = y;
+    return hipSuccess;
+  };
+  hipError_t e = hipEventCreate(&ev_start);
+  if (e == hipSuccess) e = hipEventCreate(&ev_end);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_poll[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_poll[1], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev_start, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->st, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->xk, x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_error(e, "solve setup");
+  }
+
+  const int grid = forward_grid(C, D);
+  FwdArgs fa = base_fwd(D);
+  fa.mode = FWD_SOLVE;
+  fa.pen = plan_penalties(P);
+  fa.x = P->xk;
+  fa.g = P->gk;
+  for (int i = 0; i <= kMaxTrials; ++i) fa.rbuf[i] = P->rbuf[i];
+  fa.partials = P->fwd_partials;
+  fa.st = P->st;
+  AdjArgs aa{};
+  aa.row_idx = D->row_idx;
+  aa.val = D->cval;
+  aa.chunk_k = D->chunk_k;
+  aa.nchunks = D->nchunks;
+  aa.solve = 1;
+  for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
+  aa.partials = P->adj_partials;
+  aa.st = P->st;
+  AdjFinalArgs af{};
+  af.col_chunk = D->col_chunk;
+  af.nb = D->nb;
+  af.solve = 1;
+  af.scale = 2.0;
+  af.partials = P->adj_partials;
+  af.out = P->gk;
+  af.st = P->st;
+  DecideArgs da{};
+  da.partials = P->fwd_partials;
+  da.nparts = grid;
+  da.nb = D->nb;
+  da.x = P->xk;
+  da.g = P->gk;
+  da.st = P->st;
+  da.trace = cap > 0 ? P->trace : nullptr;
+
+  // initial evaluation G(x_1)
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((e = event_pair(ev_fwd, &e0, &e1)) != hipSuccess) {
+    cleanup();
+    return hip_error(e, "hipEventCreate");
+  }
+  if ((rc = launch_forward(C, D, fa, nt, grid, e0, e1)) || (rc = launch_decide(C, da, nt))) {
+    cleanup();
+    return rc;
+  }
+  // Iterations are enqueued in batches of (adjoint, forward, decide) groups.
+  // After each batch a copy of the device state is queued; the host waits on
+  // the older of two outstanding copies, so one batch is always in flight and
+  // the device never waits for the host.  Groups enqueued after convergence
+  // exit at once.
+  const long long max_groups =
+      (static_cast<long long>(prm->max_iter) + 1) * (prm->max_backtracks / nt + 2) + 4;
+  struct Poll {
+    int slot;
+    long long enq;
+  };
+  Poll q[2];
+  int nq = 0, next_slot = 0;
+  long long enq = 0, enq_seen = 0;
+  int k_seen = 0;
+  for (;;) {
+    long long batch = C->tune.batch_iters;
+    if (prm->fixed_iters) {
+      const long long need = static_cast<long long>(prm->max_iter) - k_seen - (enq - enq_seen);
+      batch = std::max(0LL, std::min(batch, need));
+      if (batch == 0 && nq == 0) batch = 1;
+    }
+    if (batch > 0 && nq < 2) {
+      for (long long i = 0; i < batch; ++i) {
+        hipEvent_t a0, a1, f0, f1;
+        if ((e = event_pair(ev_adj, &a0, &a1)) != hipSuccess || (e = event_pair(ev_fwd, &f0, &f1)) != hipSuccess) {
+          (void)hipStreamSynchronize(s);
+          cleanup();
+          return hip_error(e, "hipEventCreate");
+        }
+        if ((rc = launch_adjoint(C, D, aa, af, a0, a1)) || (rc = launch_forward(C, D, fa, nt, grid, f0, f1)) ||
+            (rc = launch_decide(C, da, nt))) {
+          (void)hipStreamSynchronize(s);
+          cleanup();
+          return rc;
+        }
+      }
+      enq += batch;
+      const int slot = next_slot;
+      next_slot ^= 1;
+      e = hipMemcpyAsync(&P->st_host[slot], P->st, sizeof(SolverState), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(ev_poll[slot], s);
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        cleanup();
+        return hip_error(e, "solve poll");
+      }
+      q[nq++] = Poll{slot, enq};
+    } else {
+      batch = 0;
+    }
+    if (nq == 2 || (batch == 0 && nq > 0)) {
+      const Poll p = q[0];
+      q[0] = q[1];
+      --nq;
+      e = hipEventSynchronize(ev_poll[p.slot]);
+      if (e != hipSuccess) {
+        cleanup();
+        return hip_error(e, "solve poll wait");
+      }
+      const SolverState seen = P->st_host[p.slot];
+      k_seen = seen.k;
+      enq_seen = p.enq;
+      if (seen.phase == PH_DONE) break;
+    }
+    if (enq > max_groups) {
+      (void)hipStreamSynchronize(s);
+      cleanup();
+      return set_error(IMRT_EINVAL, "internal: solver state machine did not terminate");
+    }
+  }
+  // final state and iterate
+  e = hipMemcpyAsync(&P->st_host[0], P->st, sizeof(SolverState), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(x_dev, P->xk, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(ev_end, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev_start, ev_end);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_error(e, "solve finish");
+  }
+  const SolverState fin = P->st_host[0];
+  res->iterations = fin.k;
+  res->forward_passes = fin.n_fwd;
+  res->adjoint_passes = fin.n_adj;
+  res->status = fin.status;
+  res->G_initial = fin.G_init;
+  res->G_final = fin.G;
+  res->device_ms = ms;
+  res->forward_kernel_ms = 0.0;
+  res->adjoint_kernel_ms = 0.0;
+  if (prm->profile) {
+    auto mean_of = [&](const std::vector<hipEvent_t>& pool, int n, double* out) -> hipError_t {
+      n = std::min<int>(n, static_cast<int>(pool.size() / 2));
+      double tot = 0.0;
+      for (int i = 0; i < n; ++i) {
+        float t = 0.f;
+        const hipError_t r = hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]);
+        if (r != hipSuccess) return r;
+        tot += t;
+      }
+      *out = n > 0 ? tot / n : 0.0;
+      return hipSuccess;
+    };
+    e = mean_of(ev_fwd, fin.n_fwd, &res->forward_kernel_ms);
+    if (e == hipSuccess) e = mean_of(ev_adj, fin.n_adj, &res->adjoint_kernel_ms);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_error(e, "kernel timing");
+    }
+  }
+  if (prm->trace && fin.k > 0) {
+    const int n = std::min(fin.k, cap);
+    e = hipMemcpy(prm->trace, P->trace, sizeof(TraceDev) * n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_error(e, "trace copy");
+    }
+  }
+  cleanup();
+  return IMRT_OK;
+}
+
+int imrt_plan_destroy(imrt_plan* plan) {
+  free_plan(plan);
+  return IMRT_OK;
+}
+
+}  // extern "C"

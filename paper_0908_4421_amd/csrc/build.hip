@@ -1,0 +1,327 @@
+// Synthetic prostate-shaped phantom and its dose-deposition matrix D, built on
+// the device.  D plays the role of the dose deposition coefficients of
+// Section 2.1 (dose to voxel j from beamlet i at unit intensity); the paper
+// takes it from a clinical dose engine, here a pencil-beam model stands in.
+//
+// Every float64 expression is evaluated in one fixed order with contraction
+// off (this file is compiled with -ffp-contract=off as well), so the sparsity
+// pattern is a deterministic function of the geometry:
+//   voxel centre   p_a = (i_a + 0.5)*h - (n_a*h)/2
+//   depth          -max over in-plane axes with dir_a != 0 of
+//                  min((lo_a - p_a)/dir_a, (hi_a - p_a)/dir_a)
+//   lateral        u = (-sin)*x + cos*y,  v = z
+//   exponent       e = (mu*depth) + (((u-u_c)^2 + (v-v_c)^2) / ((2*sigma)*sigma))
+//   kept           e <= e_min(beamlet) + log(1/tau)
+//   value          float32(exp(-e))
+// Beam angles' cosines/sines and log(1/tau) are computed once on the host.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "imrt_internal.h"
+
+namespace imrt {
+namespace {
+
+struct Geo {
+  int nx, ny, nz;
+  double h, hx, hy;            // half extents (n*h)/2 in x and y
+  double r_ptv, r_rectum, r_bladder;
+  double mu, two_sig2;         // (2*sigma)*sigma
+  double keep_log;             // log(1/tau)
+  int nbeam;
+};
+
+struct BeamletDev {
+  int32_t beam;
+  int32_t pad;
+  double u_c, v_c;
+};
+
+__device__ __forceinline__ double centre(int i, int n, double h) {
+  return (static_cast<double>(i) + 0.5) * h - (static_cast<double>(n) * h) / 2.0;
+}
+
+__device__ __forceinline__ void voxel_xyz(const Geo& g, int j, double& x, double& y, double& z) {
+  const int ix = j % g.nx;
+  const int t = j / g.nx;
+  const int iy = t % g.ny;
+  const int iz = t / g.ny;
+  x = centre(ix, g.nx, g.h);
+  y = centre(iy, g.ny, g.h);
+  z = centre(iz, g.nz, g.h);
+}
+
+__device__ __forceinline__ void depth_u(const Geo& g, double x, double y, double c, double s,
+                                        double& depth, double& u) {
+  double t = 0.0;
+  bool have = false;
+  if (c != 0.0) {
+    t = fmin((-g.hx - x) / c, (g.hx - x) / c);
+    have = true;
+  }
+  if (s != 0.0) {
+    const double ty = fmin((-g.hy - y) / s, (g.hy - y) / s);
+    t = have ? fmax(t, ty) : ty;
+  }
+  depth = -t;
+  u = (-s) * x + c * y;
+}
+
+__device__ __forceinline__ double exponent(const Geo& g, double depth, double u, double z,
+                                           double uc, double vc) {
+  const double du = u - uc;
+  const double dv = z - vc;
+  const double r2 = du * du + dv * dv;
+  return (g.mu * depth) + (r2 / g.two_sig2);
+}
+
+__global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, uint8_t* sid) {
+  const int nv = g.nx * g.ny * g.nz;
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= nv) return;
+  double x, y, z;
+  voxel_xyz(g, j, x, y, z);
+  uint8_t s = 0;
+  const double cb = g.r_ptv + g.r_bladder;
+  const double dyb = y - cb;
+  if ((x * x + dyb * dyb) + z * z <= g.r_bladder * g.r_bladder) s = 3;
+  const double cr = -(g.r_ptv + g.r_rectum);
+  const double dyr = y - cr;
+  if (x * x + dyr * dyr <= g.r_rectum * g.r_rectum) s = 2;
+  if ((x * x + y * y) + z * z <= g.r_ptv * g.r_ptv) s = 1;
+  sid[j] = s;
+}
+
+// One workgroup per beamlet: minimum exponent over all voxels (exact; order-free).
+__global__ __launch_bounds__(kThreads) void emin_kernel(Geo g, const BeamletDev* bl, const double2* dirs,
+                                                        double* emin) {
+  const int i = blockIdx.x;
+  const BeamletDev b = bl[i];
+  const double2 d = dirs[b.beam];
+  const int nv = g.nx * g.ny * g.nz;
+  double m = INFINITY;
+  for (int j = threadIdx.x; j < nv; j += kThreads) {
+    double x, y, z, depth, u;
+    voxel_xyz(g, j, x, y, z);
+    depth_u(g, x, y, d.x, d.y, depth, u);
+    m = fmin(m, exponent(g, depth, u, z, b.u_c, b.v_c));
+  }
+  __shared__ double sh[kThreads];
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) emin[i] = sh[0];
+}
+
+// One workgroup per beamlet: ordered compaction of the kept voxels (CSC).
+// With fill == false only the count is produced.
+__global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDev* bl, const double2* dirs,
+                                                          const double* emin, int32_t* counts,
+                                                          const int32_t* col_ptr, int32_t* row_idx,
+                                                          float* cval, int fill) {
+  const int i = blockIdx.x;
+  const BeamletDev b = bl[i];
+  const double2 d = dirs[b.beam];
+  const double limit = emin[i] + g.keep_log;
+  const int nv = g.nx * g.ny * g.nz;
+  __shared__ int wave_cnt[kWaves];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = fill ? col_ptr[i] : 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < nv; j0 += kThreads) {
+    const int j = j0 + threadIdx.x;
+    bool keep = false;
+    double e = 0.0;
+    if (j < nv) {
+      double x, y, z, depth, u;
+      voxel_xyz(g, j, x, y, z);
+      depth_u(g, x, y, d.x, d.y, depth, u);
+      e = exponent(g, depth, u, z, b.u_c, b.v_c);
+      keep = e <= limit;
+    }
+    const unsigned long long mask = __ballot(keep);
+    if (lane == 0) wave_cnt[w] = __popcll(mask);
+    __syncthreads();
+    int before = base;
+    for (int k = 0; k < w; ++k) before += wave_cnt[k];
+    if (keep && fill) {
+      const int pos = before + __popcll(mask & ((1ull << lane) - 1ull));
+      row_idx[pos] = j;
+      cval[pos] = static_cast<float>(exp(-e));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int k = 0; k < kWaves; ++k) tot += wave_cnt[k];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (!fill && threadIdx.x == 0) counts[i] = base;
+}
+
+// One thread per voxel: kept beamlets in ascending column order (CSR).
+__global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const BeamletDev* bl, const int32_t* beam_first,
+                                                       const double2* dirs, const double* emin,
+                                                       int32_t* counts, const int32_t* row_ptr,
+                                                       int32_t* col_idx, float* val, int fill) {
+  const int nv = g.nx * g.ny * g.nz;
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= nv) return;
+  double x, y, z;
+  voxel_xyz(g, j, x, y, z);
+  int pos = fill ? row_ptr[j] : 0;
+  for (int beam = 0; beam < g.nbeam; ++beam) {
+    const double2 d = dirs[beam];
+    double depth, u;
+    depth_u(g, x, y, d.x, d.y, depth, u);
+    for (int i = beam_first[beam]; i < beam_first[beam + 1]; ++i) {
+      const double e = exponent(g, depth, u, z, bl[i].u_c, bl[i].v_c);
+      if (e <= emin[i] + g.keep_log) {
+        if (fill) {
+          col_idx[pos] = i;
+          val[pos] = static_cast<float>(exp(-e));
+        }
+        ++pos;
+      }
+    }
+  }
+  if (!fill) counts[j] = pos;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
+  if (G->nx <= 0 || G->ny <= 0 || G->nz <= 0 || G->n_beams <= 0)
+    return set_error(IMRT_EINVAL, "geometry: grid sizes and beam count must be positive");
+  const int64_t nv64 = static_cast<int64_t>(G->nx) * G->ny * G->nz;
+  if (nv64 >= (int64_t(1) << 31)) return set_error(IMRT_EINVAL, "geometry: too many voxels");
+  if (!(G->h > 0) || !(G->beamlet > 0) || !(G->sigma > 0) || !(G->tau > 0 && G->tau <= 1) ||
+      !(G->mu >= 0) || !(G->r_ptv > 0) || !(G->r_rectum >= 0) || !(G->r_bladder >= 0) || !(G->margin >= 0))
+    return set_error(IMRT_EINVAL, "geometry: lengths, sigma, tau or mu out of range");
+  const int nv = static_cast<int>(nv64);
+
+  // Beam directions and beamlets on the host (libm cos/sin, exact integer scans).
+  std::vector<double2> dirs(G->n_beams);
+  for (int b = 0; b < G->n_beams; ++b) {
+    const double theta = (2.0 * M_PI * b) / G->n_beams;
+    dirs[b] = make_double2(std::cos(theta), std::sin(theta));
+  }
+  const double w = G->beamlet;
+  const double reach = G->r_ptv + G->margin;
+  const int kmax = static_cast<int>(std::ceil(reach / w)) + 1;
+  std::vector<BeamletDev> bls;
+  std::vector<int32_t> beam_first(G->n_beams + 1, 0);
+  for (int b = 0; b < G->n_beams; ++b) {
+    beam_first[b] = static_cast<int32_t>(bls.size());
+    for (int m = -kmax; m < kmax; ++m) {
+      const double lo_u = m * w, hi_u = (m + 1) * w;
+      const double cu = std::min(std::max(0.0, lo_u), hi_u);
+      for (int n = -kmax; n < kmax; ++n) {
+        const double lo_v = n * w, hi_v = (n + 1) * w;
+        const double cv = std::min(std::max(0.0, lo_v), hi_v);
+        if (cu * cu + cv * cv <= reach * reach) bls.push_back({b, 0, (m + 0.5) * w, (n + 0.5) * w});
+      }
+    }
+  }
+  beam_first[G->n_beams] = static_cast<int32_t>(bls.size());
+  const int nb = static_cast<int>(bls.size());
+  if (nb == 0) return set_error(IMRT_EINVAL, "geometry: no beamlets");
+
+  Geo g;
+  g.nx = G->nx; g.ny = G->ny; g.nz = G->nz;
+  g.h = G->h;
+  g.hx = (static_cast<double>(G->nx) * G->h) / 2.0;
+  g.hy = (static_cast<double>(G->ny) * G->h) / 2.0;
+  g.r_ptv = G->r_ptv; g.r_rectum = G->r_rectum; g.r_bladder = G->r_bladder;
+  g.mu = G->mu;
+  g.two_sig2 = (2.0 * G->sigma) * G->sigma;
+  g.keep_log = std::log(1.0 / G->tau);
+  g.nbeam = G->n_beams;
+
+  hipStream_t s = ctx->stream;
+  DevBuf d_bl, d_first, d_dirs, d_emin, d_cnt_c, d_cnt_r;
+  IMRT_HIP(hipMalloc(&d_bl.p, sizeof(BeamletDev) * nb));
+  IMRT_HIP(hipMalloc(&d_first.p, sizeof(int32_t) * (G->n_beams + 1)));
+  IMRT_HIP(hipMalloc(&d_dirs.p, sizeof(double2) * G->n_beams));
+  IMRT_HIP(hipMalloc(&d_emin.p, sizeof(double) * nb));
+  IMRT_HIP(hipMalloc(&d_cnt_c.p, sizeof(int32_t) * nb));
+  IMRT_HIP(hipMalloc(&d_cnt_r.p, sizeof(int32_t) * nv));
+  IMRT_HIP(hipMemcpyAsync(d_bl.p, bls.data(), sizeof(BeamletDev) * nb, hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(d_first.p, beam_first.data(), sizeof(int32_t) * (G->n_beams + 1),
+                          hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(d_dirs.p, dirs.data(), sizeof(double2) * G->n_beams, hipMemcpyHostToDevice, s));
+
+  IMRT_HIP(hipMalloc(&D->sid, nv));
+  const int vgrid = (nv + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(structure_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, D->sid);
+  IMRT_HIP(hipGetLastError());
+  const auto* blp = static_cast<const BeamletDev*>(d_bl.p);
+  const auto* dp = static_cast<const double2*>(d_dirs.p);
+  auto* em = static_cast<double*>(d_emin.p);
+  hipLaunchKernelGGL(emin_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em);
+  IMRT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em,
+                     static_cast<int32_t*>(d_cnt_c.p), nullptr, nullptr, nullptr, 0);
+  IMRT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, blp,
+                     static_cast<const int32_t*>(d_first.p), dp, em, static_cast<int32_t*>(d_cnt_r.p),
+                     nullptr, nullptr, nullptr, 0);
+  IMRT_HIP(hipGetLastError());
+
+  std::vector<int32_t> ccount(nb), rcount(nv);
+  IMRT_HIP(hipMemcpyAsync(ccount.data(), d_cnt_c.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+  IMRT_HIP(hipMemcpyAsync(rcount.data(), d_cnt_r.p, sizeof(int32_t) * nv, hipMemcpyDeviceToHost, s));
+  IMRT_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> col_ptr(nb + 1, 0), row_ptr(nv + 1, 0);
+  int64_t tot_c = 0, tot_r = 0;
+  for (int i = 0; i < nb; ++i) {
+    tot_c += ccount[i];
+    if (tot_c >= (int64_t(1) << 31)) return set_error(IMRT_EUNSUPPORTED, "D has 2^31 or more nonzeros");
+    col_ptr[i + 1] = static_cast<int32_t>(tot_c);
+  }
+  for (int j = 0; j < nv; ++j) {
+    tot_r += rcount[j];
+    if (tot_r >= (int64_t(1) << 31)) return set_error(IMRT_EUNSUPPORTED, "D has 2^31 or more nonzeros");
+    row_ptr[j + 1] = static_cast<int32_t>(tot_r);
+  }
+  if (tot_c != tot_r) return set_error(IMRT_EINVAL, "internal: CSR and CSC nonzero counts differ");
+
+  D->nv = nv;
+  D->nb = nb;
+  D->nnz = tot_r;
+  const size_t nz = static_cast<size_t>(tot_r);
+  IMRT_HIP(hipMalloc(&D->row_ptr, sizeof(int32_t) * (nv + 1)));
+  IMRT_HIP(hipMalloc(&D->col_ptr, sizeof(int32_t) * (nb + 1)));
+  IMRT_HIP(hipMalloc(&D->col_idx, sizeof(int32_t) * std::max<size_t>(nz, 1)));
+  IMRT_HIP(hipMalloc(&D->val, sizeof(float) * std::max<size_t>(nz, 1)));
+  IMRT_HIP(hipMalloc(&D->row_idx, sizeof(int32_t) * std::max<size_t>(nz, 1)));
+  IMRT_HIP(hipMalloc(&D->cval, sizeof(float) * std::max<size_t>(nz, 1)));
+  IMRT_HIP(hipMemcpyAsync(D->row_ptr, row_ptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->col_ptr, col_ptr.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em, nullptr, D->col_ptr,
+                     D->row_idx, D->cval, 1);
+  IMRT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, blp,
+                     static_cast<const int32_t*>(d_first.p), dp, em, nullptr, D->row_ptr, D->col_idx,
+                     D->val, 1);
+  IMRT_HIP(hipGetLastError());
+  IMRT_HIP(hipStreamSynchronize(s));
+  return finish_dose(D, row_ptr, col_ptr);
+}
+
+}  // namespace imrt

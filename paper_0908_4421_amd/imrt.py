@@ -1,0 +1,401 @@
+"""ctypes binding of libimrt (the C ABI declared in include/imrt.h).
+
+Argument marshalling only: every function below calls the C entry point of
+the same name.  Device buffers are passed as raw pointers (``Tensor.data_ptr()``
+of CUDA/HIP tensors); the helper classes at the end manage handle lifetimes
+and take PyTorch tensors.  Loading fails loudly when the HIP library has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimrt.so")
+
+# ---- error / status codes (imrt.h) ------------------------------------------
+IMRT_OK, IMRT_EINVAL, IMRT_ENOMEM, IMRT_EHIP, IMRT_ENOTREADY, IMRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+IMRT_CONVERGED, IMRT_MAX_ITER, IMRT_STALLED, IMRT_LS_FAIL, IMRT_NUMERIC = 0, 1, 2, 3, 4
+IMRT_F32, IMRT_BF16, IMRT_F16 = 0, 1, 2
+STATUS_NAMES = {IMRT_CONVERGED: "converged", IMRT_MAX_ITER: "max_iter", IMRT_STALLED: "stalled",
+                IMRT_LS_FAIL: "line_search_failed", IMRT_NUMERIC: "non_finite"}
+
+
+class imrt_penalty(C.Structure):
+    _fields_ = [("T_under", C.c_double), ("T_over", C.c_double),
+                ("w_under", C.c_double), ("w_over", C.c_double)]
+
+
+class imrt_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
+                ("r_ptv", C.c_double), ("r_rectum", C.c_double), ("r_bladder", C.c_double),
+                ("n_beams", C.c_int32), ("beamlet", C.c_double), ("sigma", C.c_double),
+                ("tau", C.c_double), ("mu", C.c_double), ("margin", C.c_double)]
+
+
+class imrt_solve_params(C.Structure):
+    _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("lambda0", C.c_double),
+                ("delta", C.c_double), ("max_iter", C.c_int32), ("max_backtracks", C.c_int32),
+                ("fixed_iters", C.c_int32), ("trials_per_pass", C.c_int32), ("profile", C.c_int32),
+                ("reserved", C.c_int32), ("trace", C.c_void_p)]
+
+
+class imrt_trace_entry(C.Structure):
+    _fields_ = [("k", C.c_int32), ("backtracks", C.c_int32), ("lambda_", C.c_double),
+                ("step_sq", C.c_double), ("G", C.c_double)]
+
+
+class imrt_solve_result(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("forward_passes", C.c_int32),
+                ("adjoint_passes", C.c_int32), ("status", C.c_int32), ("G_initial", C.c_double),
+                ("G_final", C.c_double), ("device_ms", C.c_double), ("forward_kernel_ms", C.c_double),
+                ("adjoint_kernel_ms", C.c_double)]
+
+
+_vp = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_f32p = C.POINTER(C.c_float)
+_u8p = C.POINTER(C.c_uint8)
+_dp = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); one entry per function of include/imrt.h
+SIGNATURES = {
+    "imrt_ctx_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
+    "imrt_ctx_destroy": (C.c_int, [_vp]),
+    "imrt_ctx_stream": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "imrt_build_dose_matrix": (C.c_int, [_vp, C.POINTER(imrt_geometry), C.c_int, C.POINTER(_vp), _u8p]),
+    "imrt_dose_from_csr": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f32p, C.c_int,
+                                     C.POINTER(_vp)]),
+    "imrt_dose_info": (C.c_int, [_vp, _i32p, _i32p, C.POINTER(C.c_int64)]),
+    "imrt_dose_export": (C.c_int, [_vp, _i32p, _i32p, _f32p, _i32p, _i32p, _f32p, _u8p]),
+    "imrt_dose_apply": (C.c_int, [_vp, _vp, _vp]),
+    "imrt_dose_apply_transpose": (C.c_int, [_vp, _vp, _vp]),
+    "imrt_dose_destroy": (C.c_int, [_vp]),
+    "imrt_plan_create": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
+    "imrt_set_structures": (C.c_int, [_vp, _u8p, C.c_int32]),
+    "imrt_set_penalties": (C.c_int, [_vp, C.POINTER(imrt_penalty)]),
+    "imrt_set_voxel_targets": (C.c_int, [_vp, _f32p, _f32p]),
+    "imrt_evaluate_objective": (C.c_int, [_vp, _vp, _dp, _vp]),
+    "imrt_gradient": (C.c_int, [_vp, _vp, _vp, _dp]),
+    "imrt_project": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _dp]),
+    "imrt_estimate_lambda0": (C.c_int, [_vp, _vp, C.c_int32, _dp, _dp]),
+    "imrt_solve": (C.c_int, [_vp, C.POINTER(imrt_solve_params), _vp, C.POINTER(imrt_solve_result)]),
+    "imrt_plan_destroy": (C.c_int, [_vp]),
+    "imrt_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libimrt.so and bind every entry point (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_0908_4421_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class ImrtError(RuntimeError):
+    def __init__(self, code: int, func: str, msg: str):
+        super().__init__(f"{func} failed ({code}): {msg}")
+        self.code = code
+
+
+def _check(code: int, func: str):
+    if code != IMRT_OK:
+        raise ImrtError(code, func, last_error())
+    return code
+
+
+def last_error() -> str:
+    return load().imrt_last_error().decode(errors="replace")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _host(arr, ctype):
+    return None if arr is None else arr.ctypes.data_as(C.POINTER(ctype))
+
+
+# ---- raw entry points (same names as the C ABI) --------------------------------
+def imrt_ctx_create(device: int, hip_stream: Optional[int]):
+    out = _vp()
+    _check(load().imrt_ctx_create(device, hip_stream, C.byref(out)), "imrt_ctx_create")
+    return out
+
+
+def imrt_ctx_destroy(ctx):
+    return _check(load().imrt_ctx_destroy(ctx), "imrt_ctx_destroy")
+
+
+def imrt_ctx_stream(ctx) -> int:
+    out = _vp()
+    _check(load().imrt_ctx_stream(ctx, C.byref(out)), "imrt_ctx_stream")
+    return out.value or 0
+
+
+def imrt_build_dose_matrix(ctx, geom: imrt_geometry, storage: int = IMRT_F32, voxel_struct_out=None):
+    out = _vp()
+    _check(load().imrt_build_dose_matrix(ctx, C.byref(geom), storage, C.byref(out),
+                                         _host(voxel_struct_out, C.c_uint8)), "imrt_build_dose_matrix")
+    return out
+
+
+def imrt_dose_from_csr(ctx, nv, nb, nnz, row_ptr, col_idx, val, storage: int = IMRT_F32):
+    out = _vp()
+    _check(load().imrt_dose_from_csr(ctx, nv, nb, nnz, _host(row_ptr, C.c_int32), _host(col_idx, C.c_int32),
+                                     _host(val, C.c_float), storage, C.byref(out)), "imrt_dose_from_csr")
+    return out
+
+
+def imrt_dose_info(dose):
+    nv, nb, nnz = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(load().imrt_dose_info(dose, C.byref(nv), C.byref(nb), C.byref(nnz)), "imrt_dose_info")
+    return nv.value, nb.value, nnz.value
+
+
+def imrt_dose_export(dose, row_ptr=None, col_idx=None, val=None, col_ptr=None, row_idx=None, cval=None,
+                     voxel_struct=None):
+    return _check(load().imrt_dose_export(dose, _host(row_ptr, C.c_int32), _host(col_idx, C.c_int32),
+                                          _host(val, C.c_float), _host(col_ptr, C.c_int32),
+                                          _host(row_idx, C.c_int32), _host(cval, C.c_float),
+                                          _host(voxel_struct, C.c_uint8)), "imrt_dose_export")
+
+
+def imrt_dose_apply(dose, x_dev: int, d_dev: int):
+    return _check(load().imrt_dose_apply(dose, x_dev, d_dev), "imrt_dose_apply")
+
+
+def imrt_dose_apply_transpose(dose, r_dev: int, y_dev: int):
+    return _check(load().imrt_dose_apply_transpose(dose, r_dev, y_dev), "imrt_dose_apply_transpose")
+
+
+def imrt_dose_destroy(dose):
+    return _check(load().imrt_dose_destroy(dose), "imrt_dose_destroy")
+
+
+def imrt_plan_create(ctx, dose):
+    out = _vp()
+    _check(load().imrt_plan_create(ctx, dose, C.byref(out)), "imrt_plan_create")
+    return out
+
+
+def imrt_set_structures(plan, voxel_struct, nstruct: int):
+    return _check(load().imrt_set_structures(plan, _host(voxel_struct, C.c_uint8), nstruct), "imrt_set_structures")
+
+
+def imrt_set_penalties(plan, table):
+    arr = (imrt_penalty * len(table))(*[imrt_penalty(*p) for p in table])
+    return _check(load().imrt_set_penalties(plan, arr), "imrt_set_penalties")
+
+
+def imrt_set_voxel_targets(plan, T_under, T_over):
+    return _check(load().imrt_set_voxel_targets(plan, _host(T_under, C.c_float), _host(T_over, C.c_float)),
+                  "imrt_set_voxel_targets")
+
+
+def imrt_evaluate_objective(plan, x_dev: int, dose_dev: Optional[int] = None) -> float:
+    G = C.c_double()
+    _check(load().imrt_evaluate_objective(plan, x_dev, C.byref(G), dose_dev), "imrt_evaluate_objective")
+    return G.value
+
+
+def imrt_gradient(plan, x_dev: int, g_dev: int) -> float:
+    G = C.c_double()
+    _check(load().imrt_gradient(plan, x_dev, g_dev, C.byref(G)), "imrt_gradient")
+    return G.value
+
+
+def imrt_project(plan, x_dev: int, g_dev: int, lam: float, x_out_dev: int) -> float:
+    s = C.c_double()
+    _check(load().imrt_project(plan, x_dev, g_dev, lam, x_out_dev, C.byref(s)), "imrt_project")
+    return s.value
+
+
+def imrt_estimate_lambda0(plan, v0_dev: int, iters: int):
+    lam, sig = C.c_double(), C.c_double()
+    _check(load().imrt_estimate_lambda0(plan, v0_dev, iters, C.byref(lam), C.byref(sig)), "imrt_estimate_lambda0")
+    return lam.value, sig.value
+
+
+def imrt_solve(plan, params: imrt_solve_params, x_dev: int) -> imrt_solve_result:
+    res = imrt_solve_result()
+    _check(load().imrt_solve(plan, C.byref(params), x_dev, C.byref(res)), "imrt_solve")
+    return res
+
+
+def imrt_plan_destroy(plan):
+    return _check(load().imrt_plan_destroy(plan), "imrt_plan_destroy")
+
+
+def imrt_last_error() -> str:
+    return last_error()
+
+
+# ---- helpers over the raw entry points ------------------------------------------
+class Context:
+    """A library context on ``device``, enqueuing on PyTorch's current stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libimrt needs a HIP GPU; none is visible")
+        torch.cuda.set_device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.device = device
+        self.handle = imrt_ctx_create(device, stream)
+
+    def close(self):
+        if self.handle:
+            imrt_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dose:
+    """A device-resident dose-deposition matrix (CSR + CSC)."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        self.nv, self.nb, self.nnz = imrt_dose_info(handle)
+
+    @staticmethod
+    def from_geometry(ctx: Context, spec) -> "Dose":
+        g = geometry_of(spec)
+        return Dose(ctx, imrt_build_dose_matrix(ctx.handle, g))
+
+    @staticmethod
+    def from_csr(ctx: Context, nv, nb, row_ptr, col_idx, val) -> "Dose":
+        import numpy as np
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        return Dose(ctx, imrt_dose_from_csr(ctx.handle, nv, nb, int(row_ptr[-1]), row_ptr, col_idx, val))
+
+    def export(self, structures: bool = False):
+        import numpy as np
+        rp = np.empty(self.nv + 1, np.int32)
+        ci = np.empty(self.nnz, np.int32)
+        v = np.empty(self.nnz, np.float32)
+        cp = np.empty(self.nb + 1, np.int32)
+        ri = np.empty(self.nnz, np.int32)
+        cv = np.empty(self.nnz, np.float32)
+        sid = np.empty(self.nv, np.uint8) if structures else None
+        imrt_dose_export(self.handle, rp, ci, v, cp, ri, cv, sid)
+        return dict(row_ptr=rp, col_idx=ci, val=v, col_ptr=cp, row_idx=ri, cval=cv, struct_id=sid)
+
+    def apply(self, x, out=None):
+        import torch
+        out = torch.empty(self.nv, dtype=torch.float32, device=x.device) if out is None else out
+        imrt_dose_apply(self.handle, x.data_ptr(), out.data_ptr())
+        return out
+
+    def apply_transpose(self, r, out=None):
+        import torch
+        out = torch.empty(self.nb, dtype=torch.float32, device=r.device) if out is None else out
+        imrt_dose_apply_transpose(self.handle, r.data_ptr(), out.data_ptr())
+        return out
+
+    def close(self):
+        if self.handle:
+            imrt_dose_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Dose matrix + structures + penalties; objective, gradient, projection, solve."""
+
+    def __init__(self, ctx: Context, dose: Dose):
+        self.ctx = ctx
+        self.dose = dose
+        self.handle = imrt_plan_create(ctx.handle, dose.handle)
+
+    def set_structures(self, voxel_struct, nstruct: int):
+        import numpy as np
+        arr = None if voxel_struct is None else np.ascontiguousarray(voxel_struct, dtype=np.uint8)
+        imrt_set_structures(self.handle, arr, nstruct)
+
+    def set_penalties(self, table):
+        rows = [tuple(float(v) for v in row) for row in table]
+        imrt_set_penalties(self.handle, rows)
+
+    def set_voxel_targets(self, T_under, T_over):
+        import numpy as np
+        if T_under is None:
+            imrt_set_voxel_targets(self.handle, None, None)
+        else:
+            imrt_set_voxel_targets(self.handle, np.ascontiguousarray(T_under, np.float32),
+                                   np.ascontiguousarray(T_over, np.float32))
+
+    def objective(self, x, dose_out=None) -> float:
+        return imrt_evaluate_objective(self.handle, x.data_ptr(), _ptr(dose_out))
+
+    def gradient(self, x, g=None):
+        import torch
+        g = torch.empty(self.dose.nb, dtype=torch.float32, device=x.device) if g is None else g
+        G = imrt_gradient(self.handle, x.data_ptr(), g.data_ptr())
+        return g, G
+
+    def project(self, x, g, lam: float, out=None):
+        import torch
+        out = torch.empty_like(x) if out is None else out
+        s = imrt_project(self.handle, x.data_ptr(), g.data_ptr(), lam, out.data_ptr())
+        return out, s
+
+    def lambda0(self, v0, iters: int = 50):
+        return imrt_estimate_lambda0(self.handle, v0.data_ptr(), iters)
+
+    def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
+              fixed_iters=False, trials_per_pass=1, trace=False, profile=False):
+        buf = (imrt_trace_entry * max(max_iter, 1))() if trace else None
+        p = imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
+                              trials_per_pass, int(bool(profile)), 0,
+                              C.cast(buf, C.c_void_p) if trace else None)
+        res = imrt_solve(self.handle, p, x.data_ptr())
+        tr = None
+        if trace:
+            tr = [(buf[i].k, buf[i].backtracks, buf[i].lambda_, buf[i].step_sq, buf[i].G)
+                  for i in range(min(res.iterations, max_iter))]
+        return res, tr
+
+    def close(self):
+        if self.handle:
+            imrt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def geometry_of(spec) -> imrt_geometry:
+    """imrt_geometry from a workload PhantomSpec (duck-typed)."""
+    return imrt_geometry(spec.nx, spec.ny, spec.nz, spec.h, spec.r_ptv, spec.r_rectum, spec.r_bladder,
+                         spec.n_beams, spec.beamlet, spec.sigma, spec.tau, spec.mu, spec.margin)

@@ -1,0 +1,126 @@
+"""Paper-scale phantom (9 fields, 2.5 mm voxels, 5 mm beamlets) on the GPU,
+in the launch configuration the benchmark times, against the oracle's stored
+fingerprint and trajectory (tests/golden/paper_scale_oracle.json, written by
+make_paper_scale_fixture.py from the oracle alone) and against oracle rows
+and columns computed here one by one."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import banner, f32_ulp_diff, to_dev, to_host
+from oracle import phantom
+from workloads import PAPER_SCALE, PAPER_SCALE_SETTINGS, penalty_table, power_start_vector, start_point
+
+pytestmark = pytest.mark.gpu
+
+FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_scale_oracle.json")
+
+
+def sha(a, dtype):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
+
+
+@pytest.fixture(scope="module")
+def fx():
+    with open(FIXTURE) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def built():
+    from paper_0908_4421_amd.imrt import Context, Dose, Plan
+    banner("paper-scale build")
+    ctx = Context(0)
+    dose = Dose.from_geometry(ctx, PAPER_SCALE)
+    plan = Plan(ctx, dose)
+    plan.set_structures(None, 4)
+    plan.set_penalties(penalty_table(PAPER_SCALE))
+    return ctx, dose, plan, dose.export(structures=True)
+
+
+def test_sparsity_and_structures_bit_exact(built, fx):
+    ctx, dose, plan, ex = built
+    assert (dose.nv, dose.nb, dose.nnz) == (fx["nv"], fx["nb"], fx["nnz"])
+    assert sha(ex["row_ptr"], "<i4") == fx["sha256_row_ptr"]
+    assert sha(ex["col_idx"], "<i4") == fx["sha256_col_idx"]
+    assert sha(ex["col_ptr"], "<i4") == fx["sha256_col_ptr"]
+    assert sha(ex["row_idx"], "<i4") == fx["sha256_row_idx"]
+    assert sha(ex["struct_id"], "u1") == fx["sha256_struct_id"]
+    v = ex["val"].astype(np.float64)
+    assert abs(v.sum() - fx["val_sum"]) <= 1e-7 * fx["val_sum"]
+    assert abs((v * v).sum() - fx["val_sumsq"]) <= 1e-7 * fx["val_sumsq"]
+
+
+def test_sampled_columns_and_rows_against_oracle(built, fx):
+    ctx, dose, plan, ex = built
+    rng = np.random.default_rng(5)
+    cols = sorted(rng.choice(dose.nb, size=10, replace=False).tolist())
+    _, oc = phantom.build_columns(PAPER_SCALE, cols)
+    for i, (rows, vals) in zip(cols, oc):
+        a, b = ex["col_ptr"][i], ex["col_ptr"][i + 1]
+        assert np.array_equal(ex["row_idx"][a:b], rows)
+        assert f32_ulp_diff(ex["cval"][a:b], vals) <= 1
+    lens = np.diff(ex["row_ptr"])
+    rows = np.concatenate([rng.choice(np.nonzero(lens > 0)[0], 40, replace=False),
+                           rng.choice(dose.nv, 10, replace=False)])
+    orow = phantom.dose_rows(PAPER_SCALE, rows, np.array(fx["emin"]))
+    for j, (c, v) in zip(rows, orow):
+        a, b = ex["row_ptr"][j], ex["row_ptr"][j + 1]
+        assert np.array_equal(ex["col_idx"][a:b], c)
+        assert f32_ulp_diff(ex["val"][a:b], v) <= 1
+
+
+def test_lambda0_matches_oracle(built, fx):
+    ctx, dose, plan, ex = built
+    v0 = power_start_vector(dose.nb, PAPER_SCALE.seed).astype(np.float32)
+    lam, sig = plan.lambda0(to_dev(v0), PAPER_SCALE_SETTINGS.power_iters)
+    assert abs(sig - fx["sigma"]) <= 1e-5 * fx["sigma"]
+    assert lam == fx["lambda0"]
+
+
+def test_full_solve_trajectory(built, fx):
+    """Run to the stopping rule; G at every iteration index agrees with the
+    oracle's trajectory within 1e-6 relative; dose at sampled voxels agrees
+    with the oracle's rows applied to the GPU's plan within 1e-5."""
+    banner("paper-scale solve")
+    ctx, dose, plan, ex = built
+    st = PAPER_SCALE_SETTINGS
+    x = to_dev(start_point(dose.nb, st).astype(np.float32))
+    res, tr = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=fx["lambda0"], delta=st.delta,
+                         max_iter=st.max_iter, max_backtracks=st.max_backtracks, trace=True)
+    banner(f"paper-scale solve: {res.iterations} iterations, {res.device_ms:.1f} ms")
+    assert res.status == 0
+    assert abs(res.G_initial - fx["G_initial"]) <= 1e-6 * fx["G_initial"]
+    ref = fx["trace"]
+    n = min(len(tr), len(ref))
+    assert abs(len(tr) - len(ref)) <= max(5, len(ref) // 50)
+    worst = 0.0
+    for (k, m, lam, s, G), (rk, rlam, rm, rs, rG) in zip(tr[:n], ref[:n]):
+        assert k == rk
+        worst = max(worst, abs(G - rG) / rG)
+    assert worst <= 1e-6, worst
+    # final objective against the oracle's at the same iteration index
+    K = len(tr)
+    if K <= len(ref):
+        assert abs(res.G_final - ref[K - 1][4]) <= 1e-6 * ref[K - 1][4]
+    import torch
+    d = torch.empty(dose.nv, dtype=torch.float32, device="cuda")
+    G_at = plan.objective(x, d)
+    assert G_at == res.G_final
+    d = to_host(d)
+    xg = to_host(x).astype(np.float64)
+    assert np.all(xg >= 0)
+    lens = np.diff(ex["row_ptr"])
+    rng = np.random.default_rng(7)
+    rows = rng.choice(np.nonzero(lens > 0)[0], 200, replace=False)
+    orow = phantom.dose_rows(PAPER_SCALE, rows, np.array(fx["emin"]))
+    zmax = 0.0
+    err = 0.0
+    for j, (c, v) in zip(rows, orow):
+        z = float(v.astype(np.float64) @ xg[c])
+        zmax = max(zmax, abs(z))
+        err = max(err, abs(d[j] - z) / max(abs(z), 1e-30))
+    assert err <= 1e-5

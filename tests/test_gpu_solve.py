@@ -1,0 +1,179 @@
+"""GPU Armijo gradient-projection solve against the FP64 oracle: the
+hand-worked example, the tiny phantom's 200 fixed iterations, forced
+backtracking with 1/2/4 trial steps per pass, stopping statuses and errors."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from gpu_util import banner, to_dev, to_host
+from oracle import model, phantom, solver
+from oracle_pins import floats, worked_example
+from workloads import TINY, TINY_SETTINGS, penalty_table, power_start_vector
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0908_4421_amd.imrt import Context
+    return Context(0)
+
+
+@pytest.fixture(scope="module")
+def tiny(ctx):
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    D = phantom.build_dose_matrix(TINY)
+    lib = Dose.from_geometry(ctx, TINY)
+    plan = Plan(ctx, lib)
+    plan.set_structures(None, 4)
+    plan.set_penalties(penalty_table(TINY))
+    pen = model.VoxelPenalties.from_structures(D.struct_id, penalty_table(TINY))
+    lam0, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, TINY.seed))
+    return D, lib, plan, pen, lam0
+
+
+def _plan_from_csr(ctx, D, sid, table):
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    D = sp.csr_matrix(D)
+    lib = Dose.from_csr(ctx, D.shape[0], D.shape[1], D.indptr, D.indices, D.data)
+    plan = Plan(ctx, lib)
+    plan.set_structures(sid, len(table))
+    plan.set_penalties(table)
+    return lib, plan
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4])
+def test_worked_example_exact(ctx, nt):
+    """The hand-worked three iterations (all values dyadic, exact in float32)."""
+    banner(f"worked example nt={nt}")
+    g, D, pen = worked_example()
+    # voxels 0,1 structure 0 (two-sided 4 Gy), voxel 2 structure 1 (over 1 Gy, w 1/2)
+    table = [(4.0, 4.0, 1.0, 1.0), (0.0, 1.0, 0.0, 0.5)]
+    lib, plan = _plan_from_csr(ctx, D, np.array([0, 0, 1], np.uint8), table)
+    x = to_dev(floats(g["x1"]).astype(np.float32))
+    res, tr = plan.solve(x, eps=float(g["eps"]), alpha=float(g["alpha"]), lambda0=float(g["lambda0"]),
+                         max_iter=3, fixed_iters=True, trials_per_pass=nt, trace=True)
+    assert res.status == 1 and res.iterations == 3
+    assert res.G_initial == float(g["G1"])
+    for e, key in zip(tr, ("trace1", "trace2", "trace3")):
+        assert tuple(e) == tuple(floats(g[key]))
+    assert np.array_equal(to_host(x), floats(g["x4"]).astype(np.float32))
+    assert res.adjoint_passes == int(g["adjoint_products"])
+    # forward passes: 1 initial + ceil((backtracks+1)/nt) per iteration
+    per_iter = [3, 2, 3]
+    assert res.forward_passes == 1 + sum(-(-t // nt) for t in per_iter)
+
+
+def test_worked_example_eps_large(ctx):
+    g, D, pen = worked_example()
+    table = [(4.0, 4.0, 1.0, 1.0), (0.0, 1.0, 0.0, 0.5)]
+    lib, plan = _plan_from_csr(ctx, D, np.array([0, 0, 1], np.uint8), table)
+    x = to_dev(floats(g["x1"]).astype(np.float32))
+    res, tr = plan.solve(x, eps=float(g["eps_large"]), alpha=2.0, lambda0=1.0, max_iter=1,
+                         fixed_iters=True, trace=True)
+    assert tuple(tr[0]) == tuple(floats(g["eps_large_trace1"]))
+
+
+def _compare_traces(tr, ref, rel=1e-6):
+    assert len(tr) == len(ref.trace)
+    for (k, m, lam, s, G), e in zip(tr, ref.trace):
+        assert k == e.k and m == e.backtracks and lam == e.lam, (k, m, e.backtracks)
+        assert abs(G - e.G) <= rel * abs(e.G), (k, G, e.G)
+        assert abs(s - e.step_sq) <= 1e-4 * e.step_sq + 1e-30
+
+
+def test_tiny_phantom_200_iterations(tiny):
+    """The tiny phantom's configuration: exactly 200 iterations from x = 1."""
+    banner("tiny 200 iterations")
+    D, lib, plan, pen, lam0 = tiny
+    st = TINY_SETTINGS
+    x1 = np.ones(D.nb)
+    ref = solver.solve(D.csr, pen, x1, eps=st.eps, alpha=st.alpha, lambda0=lam0, max_iter=st.max_iter,
+                       max_backtracks=st.max_backtracks, fixed_iters=True)
+    x = to_dev(x1.astype(np.float32))
+    res, tr = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=lam0, max_iter=st.max_iter,
+                         max_backtracks=st.max_backtracks, fixed_iters=True, trace=True)
+    assert res.status == 1 and res.iterations == 200
+    assert abs(res.G_initial - ref.G_initial) <= 1e-6 * ref.G_initial
+    _compare_traces(tr, ref)
+    assert abs(res.G_final - ref.G) <= 1e-6 * ref.G
+    # dose of the GPU's own plan against the oracle's product at the same x
+    import torch
+    xg = to_host(x).astype(np.float64)
+    dose = torch.empty(D.nv, dtype=torch.float32, device="cuda")
+    G_at = plan.objective(x, dose)
+    z = model.dose(D.csr, xg)
+    assert np.max(np.abs(to_host(dose) - z)) <= 1e-5 * np.max(np.abs(z))
+    assert abs(G_at - model.objective_from_dose(z, pen)) <= 1e-6 * G_at
+    assert G_at == res.G_final
+    # x agrees with the oracle's iterate
+    assert np.max(np.abs(xg - ref.x)) <= 1e-4 * np.max(np.abs(ref.x))
+    # a second solve is bit-identical
+    x2 = to_dev(x1.astype(np.float32))
+    res2, tr2 = plan.solve(x2, eps=st.eps, alpha=st.alpha, lambda0=lam0, max_iter=st.max_iter,
+                           max_backtracks=st.max_backtracks, fixed_iters=True, trace=True)
+    assert tr2 == tr and np.array_equal(to_host(x2), to_host(x))
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4])
+def test_forced_backtracking(tiny, nt):
+    """A large lambda_0 makes every line search backtrack; 1, 2 or 4 trial
+    steps per pass over D give the same sequence as the oracle."""
+    banner(f"backtracking nt={nt}")
+    D, lib, plan, pen, _ = tiny
+    x1 = np.ones(D.nb)
+    ref = solver.solve(D.csr, pen, x1, eps=1e-4, alpha=2.0, lambda0=0.125, max_iter=15, fixed_iters=True)
+    x = to_dev(x1.astype(np.float32))
+    res, tr = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=0.125, max_iter=15, fixed_iters=True,
+                         trials_per_pass=nt, trace=True)
+    assert sum(e[1] for e in tr) >= 15
+    _compare_traces(tr, ref)
+    passes = sum(-(-(e.backtracks + 1) // nt) for e in ref.trace)
+    assert res.forward_passes == 1 + passes
+
+
+def test_converged_status_tiny(tiny):
+    D, lib, plan, pen, lam0 = tiny
+    x1 = np.ones(D.nb)
+    ref = solver.solve(D.csr, pen, x1, eps=1e-4, alpha=2.0, lambda0=lam0, delta=1e-3, max_iter=5000)
+    x = to_dev(x1.astype(np.float32))
+    res, tr = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=lam0, delta=1e-3, max_iter=5000, trace=True)
+    assert res.status == 0 and ref.status == 0
+    assert res.iterations == ref.iterations
+    _compare_traces(tr, ref)
+
+
+def test_stalled_and_line_search_failure(ctx):
+    rng = np.random.default_rng(23)
+    Dd = rng.uniform(0.0, 1.0, (60, 6))
+    Dd[rng.random((60, 6)) < 0.3] = 0.0
+    # over-dose only, threshold 0: x = 0 is optimal, the first trial equals x_1 = 0
+    lib, plan = _plan_from_csr(ctx, Dd.astype(np.float32), np.zeros(60, np.uint8), [(0.0, 0.0, 0.0, 1.0)])
+    x = to_dev(np.zeros(6, np.float32))
+    res, _ = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=1.0, max_iter=10)
+    assert res.status == 2 and res.iterations == 0
+    g, D, pen = worked_example()
+    table = [(4.0, 4.0, 1.0, 1.0), (0.0, 1.0, 0.0, 0.5)]
+    lib, plan = _plan_from_csr(ctx, D, np.array([0, 0, 1], np.uint8), table)
+    x = to_dev(floats(g["x1"]).astype(np.float32))
+    res, _ = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=1.0, max_iter=10, max_backtracks=1)
+    assert res.status == 3 and res.iterations == 0
+    assert np.array_equal(to_host(x), floats(g["x1"]).astype(np.float32))
+    res, _ = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=1.0, max_iter=0)
+    assert res.status == 1 and res.iterations == 0 and res.G_final == float(g["G1"])
+
+
+def test_invalid_solve_arguments(tiny):
+    from paper_0908_4421_amd import imrt
+    D, lib, plan, pen, lam0 = tiny
+    x = np.ones(D.nb, np.float32)
+    x[3] = -1.0
+    with pytest.raises(imrt.ImrtError) as e:
+        plan.solve(to_dev(x), eps=1e-4, alpha=2.0, lambda0=lam0, max_iter=5)
+    assert e.value.code == imrt.IMRT_EINVAL
+    ok = to_dev(np.ones(D.nb, np.float32))
+    for kw in (dict(eps=1.5, alpha=2.0, lambda0=lam0), dict(eps=1e-4, alpha=1.0, lambda0=lam0),
+               dict(eps=1e-4, alpha=2.0, lambda0=0.0), dict(eps=1e-4, alpha=2.0, lambda0=lam0, trials_per_pass=3)):
+        with pytest.raises(imrt.ImrtError) as e:
+            plan.solve(ok, max_iter=5, **kw)
+        assert e.value.code == imrt.IMRT_EINVAL
