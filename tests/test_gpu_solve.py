@@ -55,8 +55,8 @@ def test_worked_example_exact(ctx, nt):
                          max_iter=3, fixed_iters=True, trials_per_pass=nt, trace=True)
     assert res.status == 1 and res.iterations == 3
     assert res.G_initial == float(g["G1"])
-    for e, key in zip(tr, ("trace1", "trace2", "trace3")):
-        assert tuple(e) == tuple(floats(g[key]))
+    for (k, m, lam, s, G), key in zip(tr, ("trace1", "trace2", "trace3")):
+        assert (k, lam, m, s, G) == tuple(floats(g[key]))
     assert np.array_equal(to_host(x), floats(g["x4"]).astype(np.float32))
     assert res.adjoint_passes == int(g["adjoint_products"])
     # forward passes: 1 initial + ceil((backtracks+1)/nt) per iteration
@@ -71,7 +71,8 @@ def test_worked_example_eps_large(ctx):
     x = to_dev(floats(g["x1"]).astype(np.float32))
     res, tr = plan.solve(x, eps=float(g["eps_large"]), alpha=2.0, lambda0=1.0, max_iter=1,
                          fixed_iters=True, trace=True)
-    assert tuple(tr[0]) == tuple(floats(g["eps_large_trace1"]))
+    k, m, lam, s, G = tr[0]
+    assert (k, lam, m, s, G) == tuple(floats(g["eps_large_trace1"]))
 
 
 def _compare_traces(tr, ref, rel=1e-6):
