@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--trials-per-pass", type=int, default=1)
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,6 +97,21 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps,
+                          "GB_s_read_plus_write": 8 * n / dt / 1e9}), flush=True)
+        return
 
     from paper_0908_4421_amd.imrt import Context, Dose, Plan
     from workloads import NAMED, PAPER_SCALE_SETTINGS, TINY_SETTINGS, penalty_table, power_start_vector
@@ -162,7 +179,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "nv": nv, "nb": nb, "nnz": nnz, "delta": st.delta,
                    "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
-                   "trials_per_pass": args.trials_per_pass},
+                   "trials_per_pass": args.trials_per_pass,
+                   "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz",
+                                                             "batch_iters", "fold")}},
         "iterations": res.iterations,
         "iters_per_s": res.iterations / (ms_per_step / 1e3),
         "forward_passes": res.forward_passes,

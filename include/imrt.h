@@ -141,6 +141,22 @@ IMRT_API int imrt_ctx_destroy(imrt_ctx* ctx);
 /* The stream the context enqueues on (a hipStream_t). */
 IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 
+/* Launch-shape settings of a context, by name:
+ *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1)
+ *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (>= 1)
+ *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
+ *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
+ *   "fold"           1: in a solve, beamlet columns shared by several
+ *                    adjoint workgroups are completed by the next forward
+ *                    pass while it stages the gradient; 0: by a separate
+ *                    kernel after each adjoint pass
+ * "adj_wg_per_cu" and "adj_min_nnz" are read when a dose matrix is created.
+ * Results are deterministic for given settings; the settings change only the
+ * grouping of the float64 partial sums of G and of shared columns.
+ * Unknown names or out-of-range values return IMRT_EINVAL. */
+IMRT_API int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value);
+IMRT_API int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t* value);
+
 /* ---- dose-deposition matrix (Section 2.1; stored as CSR, Section 2.3) ---- */
 
 /* Build the synthetic phantom's structure ids and D on the device (CSR and

@@ -62,11 +62,30 @@ int hip_error(hipError_t e, const char* what) {
   return IMRT_EHIP;
 }
 
-// Row blocks for the forward pass (at most kFwdNnzMax nonzeros and kFwdRowsMax
-// rows each, or one longer row alone) and nonzero chunks of each CSC column for
-// the adjoint pass (about kAdjChunk nonzeros, split evenly inside a column).
+// Device arrays of D: row and column pointers, and the four nonzero arrays,
+// each followed by kPad zeroed entries so that 16-byte vector loads that
+// straddle the end stay in bounds.
+int alloc_nonzeros(imrt_dose* D) {
+  const size_t nz = static_cast<size_t>(D->nnz) + kPad;
+  int rc;
+  if ((rc = dev_alloc(&D->row_ptr, static_cast<size_t>(D->nv) + 1)) ||
+      (rc = dev_alloc(&D->col_ptr, static_cast<size_t>(D->nb) + 1)) || (rc = dev_alloc(&D->col_idx, nz)) ||
+      (rc = dev_alloc(&D->val, nz)) || (rc = dev_alloc(&D->row_idx, nz)) || (rc = dev_alloc(&D->cval, nz)))
+    return rc;
+  hipStream_t s = D->ctx->stream;
+  const size_t off = static_cast<size_t>(D->nnz);
+  IMRT_HIP(hipMemsetAsync(D->col_idx + off, 0, sizeof(int32_t) * kPad, s));
+  IMRT_HIP(hipMemsetAsync(D->val + off, 0, sizeof(float) * kPad, s));
+  IMRT_HIP(hipMemsetAsync(D->row_idx + off, 0, sizeof(int32_t) * kPad, s));
+  IMRT_HIP(hipMemsetAsync(D->cval + off, 0, sizeof(float) * kPad, s));
+  return IMRT_OK;
+}
+
+// Row blocks for the forward pass (at most kFwdPartNnz nonzeros and
+// kFwdRowsMax rows each, or one longer row alone), and the adjoint partition:
+// workgroup w of G owns nonzeros [w*nnz/G, (w+1)*nnz/G) of the CSC arrays.
 int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::vector<int32_t>& col_ptr) {
-  std::vector<int32_t> blocks;
+  std::vector<int32_t> blocks, block_k0;
   blocks.push_back(0);
   int r = 0;
   while (r < D->nv) {
@@ -74,34 +93,70 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
     int64_t nz = 0;
     while (r < D->nv && r - start < kFwdRowsMax) {
       const int64_t len = row_ptr[r + 1] - row_ptr[r];
-      if (r > start && nz + len > kFwdNnzMax) break;
+      if (r > start && nz + len > kFwdPartNnz) break;
       nz += len;
       ++r;
-      if (nz > kFwdNnzMax) break;
+      if (nz > kFwdPartNnz) break;
     }
     blocks.push_back(r);
   }
-  std::vector<int32_t> chunk_k, col_chunk(D->nb + 1, 0);
-  chunk_k.push_back(0);
-  for (int i = 0; i < D->nb; ++i) {
-    col_chunk[i] = static_cast<int32_t>(chunk_k.size()) - 1;
-    const int64_t k0 = col_ptr[i], len = col_ptr[i + 1] - col_ptr[i];
-    const int64_t n = std::max<int64_t>(1, (len + kAdjChunk - 1) / kAdjChunk);
-    for (int64_t c = 1; c <= n; ++c) chunk_k.push_back(static_cast<int32_t>(k0 + (len * c) / n));
+  for (int32_t b : blocks) block_k0.push_back(row_ptr[b]);
+
+  const int G = adjoint_grid_for(D->ctx, D->nnz);
+  const int64_t nnz = D->nnz;
+  auto kw = [&](int64_t w) { return w * nnz / G; };
+  std::vector<int32_t> wg_c0(G, 0), wg_c1(G, 0), col_wlo(D->nb), col_whi(D->nb);
+  for (int w = 0; w < G; ++w) {
+    wg_c0[w] = D->nb;
+    wg_c1[w] = 0;
   }
-  col_chunk[D->nb] = static_cast<int32_t>(chunk_k.size()) - 1;
+  int w = 0;
+  for (int c = 0; c < D->nb; ++c) {
+    const int64_t cs = col_ptr[c], ce = col_ptr[c + 1];
+    int lo, hi;
+    if (ce == cs) {
+      // empty column: the workgroup whose range holds its position (last one at the end)
+      while (w + 1 < G && kw(w + 1) <= cs) ++w;
+      lo = hi = w;
+    } else {
+      while (w + 1 < G && kw(w + 1) <= cs) ++w;
+      lo = w;
+      hi = w;
+      while (hi + 1 < G && kw(hi + 1) < ce) ++hi;
+    }
+    col_wlo[c] = lo;
+    col_whi[c] = hi;
+    for (int v = lo; v <= hi; ++v) {
+      wg_c0[v] = std::min(wg_c0[v], c);
+      wg_c1[v] = std::max(wg_c1[v], c + 1);
+    }
+  }
+  for (int v = 0; v < G; ++v)
+    if (wg_c1[v] == 0) wg_c0[v] = 0;  // no columns
   D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
-  D->nchunks = static_cast<int32_t>(chunk_k.size()) - 1;
+  D->adj_grid = G;
   int rc;
-  if ((rc = dev_alloc(&D->block_row, blocks.size()))) return rc;
-  if ((rc = dev_alloc(&D->chunk_k, chunk_k.size()))) return rc;
-  if ((rc = dev_alloc(&D->col_chunk, col_chunk.size()))) return rc;
+  if ((rc = dev_alloc(&D->block_row, blocks.size())) || (rc = dev_alloc(&D->block_k0, block_k0.size())) ||
+      (rc = dev_alloc(&D->wg_c0, static_cast<size_t>(G))) || (rc = dev_alloc(&D->wg_c1, static_cast<size_t>(G))) ||
+      (rc = dev_alloc(&D->col_wlo, static_cast<size_t>(D->nb))) ||
+      (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
+      (rc = dev_alloc(&D->pieces, 2 * static_cast<size_t>(G))))
+    return rc;
+  std::vector<int4> shared;
+  for (int c = 0; c < D->nb; ++c)
+    if (col_wlo[c] != col_whi[c]) shared.push_back(make_int4(c, col_wlo[c], col_whi[c], 0));
+  D->nshared = static_cast<int32_t>(shared.size());
+  if ((rc = dev_alloc(&D->shared_cols, shared.size()))) return rc;
   hipStream_t s = D->ctx->stream;
   IMRT_HIP(hipMemcpyAsync(D->block_row, blocks.data(), sizeof(int32_t) * blocks.size(), hipMemcpyHostToDevice, s));
-  IMRT_HIP(hipMemcpyAsync(D->chunk_k, chunk_k.data(), sizeof(int32_t) * chunk_k.size(), hipMemcpyHostToDevice, s));
-  IMRT_HIP(hipMemcpyAsync(D->col_chunk, col_chunk.data(), sizeof(int32_t) * col_chunk.size(),
-                          hipMemcpyHostToDevice, s));
-  D->partials_len = std::max(kMaxTrials * forward_grid(D->ctx, D), D->nchunks) + 16;
+  IMRT_HIP(hipMemcpyAsync(D->block_k0, block_k0.data(), sizeof(int32_t) * block_k0.size(), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wg_c0, wg_c0.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wg_c1, wg_c1.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->col_whi, col_whi.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
+  if (!shared.empty())
+    IMRT_HIP(hipMemcpyAsync(D->shared_cols, shared.data(), sizeof(int4) * shared.size(), hipMemcpyHostToDevice, s));
+  D->partials_len = kMaxTrials * (forward_grid(D->ctx, D) + 1) + 16;
   if ((rc = dev_alloc(&D->partials, D->partials_len))) return rc;
   IMRT_HIP(hipStreamSynchronize(s));
   return IMRT_OK;
@@ -115,7 +170,7 @@ namespace {
 
 void free_dose(imrt_dose* D) {
   if (!D) return;
-  (void)hipSetDevice(D->ctx->device);
+  (void)hipSetDevice(D->device);
   dev_free(D->row_ptr);
   dev_free(D->col_idx);
   dev_free(D->val);
@@ -123,8 +178,13 @@ void free_dose(imrt_dose* D) {
   dev_free(D->row_idx);
   dev_free(D->cval);
   dev_free(D->block_row);
-  dev_free(D->chunk_k);
-  dev_free(D->col_chunk);
+  dev_free(D->block_k0);
+  dev_free(D->wg_c0);
+  dev_free(D->wg_c1);
+  dev_free(D->col_wlo);
+  dev_free(D->col_whi);
+  dev_free(D->shared_cols);
+  dev_free(D->pieces);
   dev_free(D->sid);
   dev_free(D->partials);
   delete D;
@@ -132,17 +192,17 @@ void free_dose(imrt_dose* D) {
 
 void free_plan(imrt_plan* P) {
   if (!P) return;
-  (void)hipSetDevice(P->ctx->device);
+  (void)hipSetDevice(P->device);
   dev_free(P->sid);
   dev_free(P->table);
   dev_free(P->Tu_vox);
   dev_free(P->To_vox);
   for (auto& b : P->rbuf) dev_free(b);
-  dev_free(P->xk);
+  for (auto& b : P->xbuf) dev_free(b);
   dev_free(P->gk);
   dev_free(P->vtmp);
   dev_free(P->fwd_partials);
-  dev_free(P->adj_partials);
+  dev_free(P->pieces);
   dev_free(P->misc);
   dev_free(P->st);
   dev_free(P->trace);
@@ -162,24 +222,31 @@ Penalties plan_penalties(const imrt_plan* P) {
   return Penalties{P->sid, P->table, P->Tu_vox, P->To_vox};
 }
 
+void set_plan_penalties(FwdArgs& a, const imrt_plan* P) {
+  a.pen = plan_penalties(P);
+  a.nstruct = P->nstruct;
+}
+
 FwdArgs base_fwd(const imrt_dose* D) {
   FwdArgs a{};
   a.row_ptr = D->row_ptr;
   a.col_idx = D->col_idx;
   a.val = D->val;
   a.block_row = D->block_row;
+  a.block_k0 = D->block_k0;
   a.nblocks = D->nblocks;
   a.nv = D->nv;
   a.nb = D->nb;
   return a;
 }
 
-int ensure_rbuf(imrt_plan* P, int count) {
-  for (int i = 0; i < count; ++i)
-    if (P->rbuf[i] == nullptr) {
-      const int rc = dev_alloc(&P->rbuf[i], P->dose->nv);
-      if (rc) return rc;
-    }
+// Residual (nv) and iterate (nb) buffers 0..count-1.
+int ensure_buffers(imrt_plan* P, int count) {
+  for (int i = 0; i < count; ++i) {
+    int rc;
+    if (P->rbuf[i] == nullptr && (rc = dev_alloc(&P->rbuf[i], P->dose->nv))) return rc;
+    if (P->xbuf[i] == nullptr && (rc = dev_alloc(&P->xbuf[i], P->dose->nb))) return rc;
+  }
   return IMRT_OK;
 }
 
@@ -189,7 +256,7 @@ int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, in
   const imrt_dose* D = P->dose;
   FwdArgs a = base_fwd(D);
   a.mode = FWD_EVAL;
-  a.pen = plan_penalties(P);
+  set_plan_penalties(a, P);
   a.x = x;
   a.d_out = dose_out;
   a.r_out = r_out;
@@ -200,24 +267,31 @@ int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, in
   return launch_sum(P->ctx, P->fwd_partials, grid, P->misc + slot);
 }
 
-int adjoint_into(const imrt_ctx* ctx, const imrt_dose* D, const float* r, double scale, double* partials,
-                 float* out) {
+AdjArgs base_adj(const imrt_dose* D) {
   AdjArgs a{};
   a.row_idx = D->row_idx;
   a.val = D->cval;
-  a.chunk_k = D->chunk_k;
-  a.nchunks = D->nchunks;
+  a.col_ptr = D->col_ptr;
+  a.wg_c0 = D->wg_c0;
+  a.wg_c1 = D->wg_c1;
+  a.col_wlo = D->col_wlo;
+  a.col_whi = D->col_whi;
+  a.nnz = D->nnz;
+  a.nb = D->nb;
+  a.grid = D->adj_grid;
+  a.fold = 0;
+  return a;
+}
+
+// y = scale * D^T r with the dose's own piece scratch.
+int adjoint_into(const imrt_ctx* ctx, const imrt_dose* D, const float* r, double scale, float* out) {
+  AdjArgs a = base_adj(D);
   a.solve = 0;
   a.r = r;
-  a.partials = partials;
-  AdjFinalArgs f{};
-  f.col_chunk = D->col_chunk;
-  f.nb = D->nb;
-  f.solve = 0;
-  f.scale = scale;
-  f.partials = partials;
-  f.out = out;
-  return launch_adjoint(ctx, D, a, f);
+  a.pieces = D->pieces;
+  a.out = out;
+  a.scale = scale;
+  return launch_adjoint(ctx, D, a, 1);
 }
 
 int fetch_misc(imrt_plan* P, int n) {
@@ -250,6 +324,8 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.fwd_grid_per_cu = env_int("IMRT_FWD_WG_PER_CU", c->tune.fwd_grid_per_cu);
   c->tune.adj_grid_per_cu = env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu);
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
+  c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
+  if (const char* f = std::getenv("IMRT_FOLD")) c->tune.fold = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
   return IMRT_OK;
@@ -258,7 +334,6 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
 int imrt_ctx_destroy(imrt_ctx* ctx) {
   if (!ctx) return IMRT_OK;
   (void)hipSetDevice(ctx->device);
-  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return IMRT_OK;
 }
@@ -266,6 +341,46 @@ int imrt_ctx_destroy(imrt_ctx* ctx) {
 int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out) {
   if (!ctx || !hip_stream_out) return set_error(IMRT_EINVAL, "ctx or out is NULL");
   *hip_stream_out = ctx->stream;
+  return IMRT_OK;
+}
+
+namespace {
+int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
+  if (!name) return nullptr;
+  const std::string n(name);
+  *lo = 1;
+  if (n == "fwd_wg_per_cu") return &ctx->tune.fwd_grid_per_cu;
+  if (n == "adj_wg_per_cu") return &ctx->tune.adj_grid_per_cu;
+  if (n == "batch_iters") return &ctx->tune.batch_iters;
+  if (n == "adj_min_nnz") {
+    *lo = 16;
+    return &ctx->tune.adj_min_nnz;
+  }
+  if (n == "fold") {
+    *lo = 0;
+    return &ctx->tune.fold;
+  }
+  return nullptr;
+}
+}  // namespace
+
+int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
+  if (!ctx) return set_error(IMRT_EINVAL, "ctx is NULL");
+  int64_t lo = 0;
+  int* slot = option_slot(ctx, name, &lo);
+  if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
+  const int64_t hi = (std::string(name) == "fold") ? 1 : (int64_t(1) << 30);
+  if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
+  *slot = static_cast<int>(value);
+  return IMRT_OK;
+}
+
+int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t* value) {
+  if (!ctx || !value) return set_error(IMRT_EINVAL, "ctx or value is NULL");
+  int64_t lo = 0;
+  int* slot = option_slot(const_cast<imrt_ctx*>(ctx), name, &lo);
+  if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
+  *value = *slot;
   return IMRT_OK;
 }
 
@@ -279,6 +394,7 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
   auto* D = new (std::nothrow) imrt_dose();
   if (!D) return set_error(IMRT_ENOMEM, "host allocation failed");
   D->ctx = ctx;
+  D->device = ctx->device;
   try {
     rc = build_phantom(ctx, geom, D);
   } catch (const std::bad_alloc&) {
@@ -319,6 +435,7 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
   auto* D = new (std::nothrow) imrt_dose();
   if (!D) return set_error(IMRT_ENOMEM, "host allocation failed");
   D->ctx = ctx;
+  D->device = ctx->device;
   D->nv = nv;
   D->nb = nb;
   D->nnz = nnz;
@@ -336,9 +453,7 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
         cv[p] = val[k];
       }
     hipStream_t s = ctx->stream;
-    if ((rc = dev_alloc(&D->row_ptr, nv + 1)) || (rc = dev_alloc(&D->col_idx, nnz)) ||
-        (rc = dev_alloc(&D->val, nnz)) || (rc = dev_alloc(&D->col_ptr, nb + 1)) ||
-        (rc = dev_alloc(&D->row_idx, nnz)) || (rc = dev_alloc(&D->cval, nnz))) {
+    if ((rc = alloc_nonzeros(D))) {
       free_dose(D);
       return rc;
     }
@@ -409,7 +524,7 @@ int imrt_dose_apply_transpose(const imrt_dose* D, const float* r_dev, float* y_d
   if (!D || !r_dev || !y_dev) return set_error(IMRT_EINVAL, "dose, r or y is NULL");
   int rc = use_device(D->ctx);
   if (rc) return rc;
-  return adjoint_into(D->ctx, D, r_dev, 1.0, D->partials, y_dev);
+  return adjoint_into(D->ctx, D, r_dev, 1.0, y_dev);
 }
 
 int imrt_dose_destroy(imrt_dose* dose) {
@@ -426,13 +541,14 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
   auto* P = new (std::nothrow) imrt_plan();
   if (!P) return set_error(IMRT_ENOMEM, "host allocation failed");
   P->ctx = ctx;
+  P->device = ctx->device;
   P->dose = dose;
   const int grid = forward_grid(ctx, dose);
   if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
-      (rc = ensure_rbuf(P, 2)) || (rc = dev_alloc(&P->xk, dose->nb)) || (rc = dev_alloc(&P->gk, dose->nb)) ||
-      (rc = dev_alloc(&P->vtmp, dose->nv)) || (rc = dev_alloc(&P->fwd_partials, kMaxTrials * grid)) ||
-      (rc = dev_alloc(&P->adj_partials, dose->nchunks)) || (rc = dev_alloc(&P->misc, 16)) ||
-      (rc = dev_alloc(&P->st, 1))) {
+      (rc = ensure_buffers(P, 2)) || (rc = dev_alloc(&P->gk, dose->nb)) || (rc = dev_alloc(&P->vtmp, dose->nv)) ||
+      (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
+      (rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(dose->adj_grid))) || (rc = dev_alloc(&P->misc, 16)) ||
+      (rc = dev_alloc(&P->st, 2))) {
     free_plan(P);
     return rc;
   }
@@ -540,7 +656,7 @@ int imrt_gradient(imrt_plan* P, const float* x_dev, float* g_dev, double* G_out)
   if (rc) return rc;
   if (!x_dev || !g_dev) return set_error(IMRT_EINVAL, "x or g is NULL");
   if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, nullptr, P->rbuf[0], 0)) ||
-      (rc = adjoint_into(P->ctx, P->dose, P->rbuf[0], 2.0, P->adj_partials, g_dev)))
+      (rc = adjoint_into(P->ctx, P->dose, P->rbuf[0], 2.0, g_dev)))
     return rc;
   if (G_out) {
     if ((rc = fetch_misc(P, 1))) return rc;
@@ -572,7 +688,7 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
   if ((rc = use_device(P->ctx))) return rc;
   const imrt_dose* D = P->dose;
   const imrt_ctx* C = P->ctx;
-  float* v = P->xk;
+  float* v = P->xbuf[0];
   float* w = P->gk;
   if ((rc = launch_normalize(C, v0_dev, D->nb, v, P->misc + 1))) return rc;
   for (int it = 0; it <= iters; ++it) {
@@ -587,7 +703,7 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
       if ((rc = launch_sum(C, P->fwd_partials, grid, P->misc))) return rc;
       break;
     }
-    if ((rc = adjoint_into(C, D, P->vtmp, 1.0, P->adj_partials, w))) return rc;
+    if ((rc = adjoint_into(C, D, P->vtmp, 1.0, w))) return rc;
     if ((rc = launch_normalize(C, w, D->nb, v, P->misc + 1))) return rc;
   }
   if ((rc = fetch_misc(P, 2))) return rc;
@@ -608,7 +724,8 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   if (!(prm->alpha > 1.0) || !std::isfinite(prm->alpha)) return set_error(IMRT_EINVAL, "alpha must be > 1");
   if (!(prm->lambda0 > 0.0) || !std::isfinite(prm->lambda0)) return set_error(IMRT_EINVAL, "lambda0 must be > 0");
   if (!(prm->delta >= 0.0)) return set_error(IMRT_EINVAL, "delta must be >= 0");
-  if (prm->max_iter < 0 || prm->max_backtracks < 0) return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
+  if (prm->max_iter < 0 || prm->max_backtracks < 0)
+    return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
   if (prm->reserved != 0) return set_error(IMRT_EINVAL, "reserved must be 0");
   const int nt = prm->trials_per_pass == 0 ? 1 : prm->trials_per_pass;
   if (nt != 1 && nt != 2 && nt != 4) return set_error(IMRT_EINVAL, "trials_per_pass must be 0, 1, 2 or 4");
@@ -616,26 +733,28 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   const imrt_dose* D = P->dose;
   imrt_ctx* C = P->ctx;
   hipStream_t s = C->stream;
-  if (forward_lds_bytes(D->nb, nt) > C->max_lds)
+  if (forward_lds_bytes(D->nb, nt, P->nstruct) > C->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
 
-  // x_1 >= 0 and finite (step "Initialization")
+  // x_1 >= 0 and finite (initialisation of the method)
   std::vector<float> xh(D->nb);
   IMRT_HIP(hipMemcpyAsync(xh.data(), x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToHost, s));
   IMRT_HIP(hipStreamSynchronize(s));
   for (float v : xh)
     if (!(v >= 0.0f) || !std::isfinite(v)) return set_error(IMRT_EINVAL, "x_1 must be finite and >= 0");
-  if ((rc = ensure_rbuf(P, nt + 1))) return rc;
+  if ((rc = ensure_buffers(P, nt + 1))) return rc;
   const int cap = prm->trace ? prm->max_iter : 0;
   if (cap > P->trace_cap) {
     dev_free(P->trace);
+    P->trace_cap = 0;
     if ((rc = dev_alloc(&P->trace, cap))) return rc;
     P->trace_cap = cap;
   }
-
   SolverState init{};
   init.phase = PH_INIT;
   init.status = IMRT_MAX_ITER;
+  init.acc = 0;
+  init.xi = 0;
   init.ntrials = nt;
   init.max_iter = prm->max_iter;
   init.max_bt = prm->max_backtracks;
@@ -681,7 +800,8 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_poll[1], hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev_start, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->st, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(P->xk, x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->st + 1, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(P->xbuf[0], x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) {
     cleanup();
     return hip_error(e, "solve setup");
@@ -690,49 +810,63 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   const int grid = forward_grid(C, D);
   FwdArgs fa = base_fwd(D);
   fa.mode = FWD_SOLVE;
-  fa.pen = plan_penalties(P);
-  fa.x = P->xk;
+  set_plan_penalties(fa, P);
   fa.g = P->gk;
-  for (int i = 0; i <= kMaxTrials; ++i) fa.rbuf[i] = P->rbuf[i];
+  for (int i = 0; i <= kMaxTrials; ++i) {
+    fa.xbuf[i] = P->xbuf[i];
+    fa.rbuf[i] = P->rbuf[i];
+  }
   fa.partials = P->fwd_partials;
-  fa.st = P->st;
-  AdjArgs aa{};
-  aa.row_idx = D->row_idx;
-  aa.val = D->cval;
-  aa.chunk_k = D->chunk_k;
-  aa.nchunks = D->nchunks;
+  if (C->tune.fold) {
+    fa.shared_cols = D->nshared > 0 ? D->shared_cols : nullptr;
+    fa.nshared = D->nshared;
+    fa.g_scale = 2.0;
+    fa.pieces = P->pieces;
+  }
+  AdjArgs aa = base_adj(D);
   aa.solve = 1;
   for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
-  aa.partials = P->adj_partials;
-  aa.st = P->st;
-  AdjFinalArgs af{};
-  af.col_chunk = D->col_chunk;
-  af.nb = D->nb;
-  af.solve = 1;
-  af.scale = 2.0;
-  af.partials = P->adj_partials;
-  af.out = P->gk;
-  af.st = P->st;
-  DecideArgs da{};
-  da.partials = P->fwd_partials;
-  da.nparts = grid;
-  da.nb = D->nb;
-  da.x = P->xk;
-  da.g = P->gk;
-  da.st = P->st;
-  da.trace = cap > 0 ? P->trace : nullptr;
+  aa.pieces = P->pieces;
+  aa.fold = C->tune.fold;
+  aa.out = P->gk;
+  aa.scale = 2.0;
+  aa.fwd_partials = P->fwd_partials;
+  aa.fwd_parts = grid;
+  aa.trace = cap > 0 ? P->trace : nullptr;
+
+  // The two state copies alternate: pass n reads st[n % 2] and writes st[(n + 1) % 2].
+  long long pass = 0;
+  auto state_in = [&]() { return P->st + (pass & 1); };
+  auto state_out = [&]() { return P->st + ((pass + 1) & 1); };
+  auto forward_pass = [&]() -> int {
+    hipEvent_t f0, f1;
+    const hipError_t r = event_pair(ev_fwd, &f0, &f1);
+    if (r != hipSuccess) return hip_error(r, "hipEventCreate");
+    fa.st_in = state_in();
+    fa.st_out = state_out();
+    const int rr = launch_forward(C, D, fa, nt, grid, f0, f1);
+    ++pass;
+    return rr;
+  };
+  auto adjoint_pass = [&]() -> int {
+    hipEvent_t a0, a1;
+    const hipError_t r = event_pair(ev_adj, &a0, &a1);
+    if (r != hipSuccess) return hip_error(r, "hipEventCreate");
+    aa.st_in = state_in();
+    aa.st_out = state_out();
+    const int rr = launch_adjoint(C, D, aa, nt, a0, a1);
+    ++pass;
+    return rr;
+  };
 
   // initial evaluation G(x_1)
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if ((e = event_pair(ev_fwd, &e0, &e1)) != hipSuccess) {
-    cleanup();
-    return hip_error(e, "hipEventCreate");
-  }
-  if ((rc = launch_forward(C, D, fa, nt, grid, e0, e1)) || (rc = launch_decide(C, da, nt))) {
+  if ((rc = forward_pass())) {
+    (void)hipStreamSynchronize(s);
     cleanup();
     return rc;
   }
-  // Iterations are enqueued in batches of (adjoint, forward, decide) groups.
+  // Iterations are enqueued in batches of (adjoint, forward) groups: each
+  // adjoint pass first decides on the forward pass before it.
   // After each batch a copy of the device state is queued; the host waits on
   // the older of two outstanding copies, so one batch is always in flight and
   // the device never waits for the host.  Groups enqueued after convergence
@@ -756,14 +890,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     }
     if (batch > 0 && nq < 2) {
       for (long long i = 0; i < batch; ++i) {
-        hipEvent_t a0, a1, f0, f1;
-        if ((e = event_pair(ev_adj, &a0, &a1)) != hipSuccess || (e = event_pair(ev_fwd, &f0, &f1)) != hipSuccess) {
-          (void)hipStreamSynchronize(s);
-          cleanup();
-          return hip_error(e, "hipEventCreate");
-        }
-        if ((rc = launch_adjoint(C, D, aa, af, a0, a1)) || (rc = launch_forward(C, D, fa, nt, grid, f0, f1)) ||
-            (rc = launch_decide(C, da, nt))) {
+        if ((rc = adjoint_pass()) || (rc = forward_pass())) {
           (void)hipStreamSynchronize(s);
           cleanup();
           return rc;
@@ -772,7 +899,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
       enq += batch;
       const int slot = next_slot;
       next_slot ^= 1;
-      e = hipMemcpyAsync(&P->st_host[slot], P->st, sizeof(SolverState), hipMemcpyDeviceToHost, s);
+      e = hipMemcpyAsync(&P->st_host[slot], state_in(), sizeof(SolverState), hipMemcpyDeviceToHost, s);
       if (e == hipSuccess) e = hipEventRecord(ev_poll[slot], s);
       if (e != hipSuccess) {
         (void)hipStreamSynchronize(s);
@@ -804,8 +931,14 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     }
   }
   // final state and iterate
-  e = hipMemcpyAsync(&P->st_host[0], P->st, sizeof(SolverState), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(x_dev, P->xk, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(&P->st_host[0], state_in(), sizeof(SolverState), hipMemcpyDeviceToHost);
+  const int xi = P->st_host[0].xi;
+  if (e == hipSuccess && (xi < 0 || xi > nt)) {
+    cleanup();
+    return set_error(IMRT_EINVAL, "internal: iterate buffer index out of range");
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(x_dev, P->xbuf[xi], sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(ev_end, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   float ms = 0.f;
@@ -814,13 +947,13 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     cleanup();
     return hip_error(e, "solve finish");
   }
-  const SolverState fin = P->st_host[0];
-  res->iterations = fin.k;
-  res->forward_passes = fin.n_fwd;
-  res->adjoint_passes = fin.n_adj;
-  res->status = fin.status;
-  res->G_initial = fin.G_init;
-  res->G_final = fin.G;
+  const SolverState done_st = P->st_host[0];
+  res->iterations = done_st.k;
+  res->forward_passes = done_st.n_fwd;
+  res->adjoint_passes = done_st.n_adj;
+  res->status = done_st.status;
+  res->G_initial = done_st.G_init;
+  res->G_final = done_st.G;
   res->device_ms = ms;
   res->forward_kernel_ms = 0.0;
   res->adjoint_kernel_ms = 0.0;
@@ -837,15 +970,15 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
       *out = n > 0 ? tot / n : 0.0;
       return hipSuccess;
     };
-    e = mean_of(ev_fwd, fin.n_fwd, &res->forward_kernel_ms);
-    if (e == hipSuccess) e = mean_of(ev_adj, fin.n_adj, &res->adjoint_kernel_ms);
+    e = mean_of(ev_fwd, done_st.n_fwd, &res->forward_kernel_ms);
+    if (e == hipSuccess) e = mean_of(ev_adj, done_st.n_adj, &res->adjoint_kernel_ms);
     if (e != hipSuccess) {
       cleanup();
       return hip_error(e, "kernel timing");
     }
   }
-  if (prm->trace && fin.k > 0) {
-    const int n = std::min(fin.k, cap);
+  if (prm->trace && done_st.k > 0) {
+    const int n = std::min(done_st.k, cap);
     e = hipMemcpy(prm->trace, P->trace, sizeof(TraceDev) * n, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
       cleanup();

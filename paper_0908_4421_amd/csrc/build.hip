@@ -254,6 +254,7 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   g.nbeam = G->n_beams;
 
   hipStream_t s = ctx->stream;
+  (void)hipGetLastError();  // drop an error left by an unrelated earlier call
   DevBuf d_bl, d_first, d_dirs, d_emin, d_cnt_c, d_cnt_r;
   IMRT_HIP(hipMalloc(&d_bl.p, sizeof(BeamletDev) * nb));
   IMRT_HIP(hipMalloc(&d_first.p, sizeof(int32_t) * (G->n_beams + 1)));
@@ -305,12 +306,9 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   D->nb = nb;
   D->nnz = tot_r;
   const size_t nz = static_cast<size_t>(tot_r);
-  IMRT_HIP(hipMalloc(&D->row_ptr, sizeof(int32_t) * (nv + 1)));
-  IMRT_HIP(hipMalloc(&D->col_ptr, sizeof(int32_t) * (nb + 1)));
-  IMRT_HIP(hipMalloc(&D->col_idx, sizeof(int32_t) * std::max<size_t>(nz, 1)));
-  IMRT_HIP(hipMalloc(&D->val, sizeof(float) * std::max<size_t>(nz, 1)));
-  IMRT_HIP(hipMalloc(&D->row_idx, sizeof(int32_t) * std::max<size_t>(nz, 1)));
-  IMRT_HIP(hipMalloc(&D->cval, sizeof(float) * std::max<size_t>(nz, 1)));
+  (void)nz;
+  const int arc = alloc_nonzeros(D);
+  if (arc) return arc;
   IMRT_HIP(hipMemcpyAsync(D->row_ptr, row_ptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_ptr, col_ptr.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em, nullptr, D->col_ptr,

@@ -14,16 +14,18 @@ namespace imrt {
 // ---- launch geometry -------------------------------------------------------
 constexpr int kThreads = 256;          // 4 wave64 per workgroup
 constexpr int kWaves = kThreads / 64;
-constexpr int kFwdNnzMax = 2048;       // nonzeros of one forward row block (staged in LDS)
+constexpr int kFwdNnzMax = 2048;       // LDS product slots of one forward row block
+constexpr int kFwdPartNnz = kFwdNnzMax - 4;  // block limit so that 16-byte aligned loads fit
 constexpr int kFwdRowsMax = 512;       // rows of one forward row block
-constexpr int kAdjChunk = 2048;        // target nonzeros of one adjoint work item
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;
+constexpr int kPad = 16;               // zeroed tail of every nonzero array (aligned vector loads)
+constexpr int kXcds = 8;               // MI355X: 8 accelerator dies, workgroups dealt round-robin
 
 // ---- device-resident solver state -------------------------------------------
-// Phases of the device-side state machine.  Only single-workgroup kernels (or
-// the last workgroup of a kernel) write the state; every other kernel reads it
-// at entry and exits early when there is nothing to do.
+// Phases of the device-side state machine.  Only one workgroup at a time (a
+// one-workgroup kernel, or the last workgroup of a pass) writes the state;
+// every other kernel reads it at entry and exits early when idle.
 enum Phase : int32_t {
   PH_INIT = 0,       // evaluate G(x_1) with the forward pass
   PH_NEED_GRAD = 1,  // gradient of the accepted iterate needed, then a trial pass
@@ -33,8 +35,9 @@ enum Phase : int32_t {
 
 struct SolverState {
   int32_t phase, status, k, m;        // phase, imrt_solve_status, accepted iterations, backtracks
-  int32_t acc, n_fwd, n_adj, ntrials; // residual buffer of x_k, pass counters, trials per pass
-  int32_t max_iter, max_bt, fixed, trace_cap;
+  int32_t acc, xi, n_fwd, n_adj;      // residual and iterate buffers of x_k, pass counters
+  int32_t ntrials, max_iter, max_bt, fixed;
+  int32_t trace_cap, pad;
   double lambda;                      // first trial step of the next forward pass
   double G, G_prev, G_init;
   double eps, alpha, lambda0, delta;
@@ -50,6 +53,8 @@ struct TraceDev {
   double lambda, step_sq, G;
 };
 static_assert(sizeof(TraceDev) == sizeof(imrt_trace_entry), "trace layout");
+static_assert(sizeof(SolverState) % sizeof(int32_t) == 0 && sizeof(SolverState) <= 256 * sizeof(int32_t),
+              "state is copied word by word by one workgroup");
 
 // ---- kernel argument blocks ---------------------------------------------------
 enum FwdMode : int32_t {
@@ -70,45 +75,54 @@ struct FwdArgs {
   const int32_t* col_idx;
   const float* val;
   const int32_t* block_row;  // nblocks + 1 row boundaries
+  const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
+  int32_t nstruct;
   Penalties pen;
-  const float* x;            // x_k (solve) or the input vector
-  const float* g;            // g_k (solve)
-  float* rbuf[kMaxTrials + 1];
+  const float* x;            // eval/plain input vector
+  const float* g;            // solve: g_k
+  float* xbuf[kMaxTrials + 1];  // solve: iterate buffers (x_k = xbuf[st->xi])
+  float* rbuf[kMaxTrials + 1];  // solve: residual buffers (r(x_k) = rbuf[st->acc])
   float* d_out;              // eval/plain: dose (nullable in eval)
   float* r_out;              // eval: residual (nullable)
-  double* partials;          // [trial][gridDim.x]
-  SolverState* st;
+  double* partials;          // [trial][gridDim.x] objective partials, then [trial] step norms
+  const SolverState* st_in;  // solve: state before this pass
+  SolverState* st_out;       // solve: state after it (copied through by workgroup 0)
+  // solve with folded completion: gradient entries of columns shared by
+  // several adjoint workgroups are completed here from the adjoint pieces
+  const int4* shared_cols;   // (column, wlo, whi, 0)
+  int32_t nshared;
+  double g_scale;
+  const double* pieces;
 };
 
+// Adjoint work partition: workgroup w owns nonzeros [w*nnz/G, (w+1)*nnz/G)
+// of the CSC arrays, i.e. columns [wg_c0[w], wg_c1[w]) in part or whole.
+// Column c is shared by workgroups col_wlo[c]..col_whi[c]; a shared column is
+// completed from the per-workgroup pieces (slot 2w: piece of w's first
+// column, slot 2w+1: piece of its last column) in workgroup order.
 struct AdjArgs {
   const int32_t* row_idx;
   const float* val;
-  const int32_t* chunk_k;    // nchunks + 1 nonzero boundaries (each chunk inside one column)
-  int32_t nchunks;
-  int32_t solve;             // read r from rbuf[st->acc] and run only in PH_NEED_GRAD
+  const int32_t* col_ptr;
+  const int32_t* wg_c0;
+  const int32_t* wg_c1;
+  const int32_t* col_wlo;
+  const int32_t* col_whi;
+  int64_t nnz;
+  int32_t nb, grid;
+  int32_t solve;             // decide the previous forward pass first; r from rbuf
+  int32_t fold;              // shared columns completed by the next forward pass (else adj_final)
   const float* r;
   float* rbuf[kMaxTrials + 1];
-  double* partials;          // per chunk
-  SolverState* st;
-};
-
-struct AdjFinalArgs {
-  const int32_t* col_chunk;  // nb + 1 chunk boundaries per column
-  int32_t nb;
-  int32_t solve;
-  double scale;
-  const double* partials;
+  double* pieces;            // 2 * grid
   float* out;
-  SolverState* st;
-};
-
-struct DecideArgs {
-  const double* partials;    // [trial][nparts]
-  int32_t nparts, nb;
-  float* x;                  // x_k, overwritten by the accepted trial
-  const float* g;
-  SolverState* st;
+  double scale;
+  // solve: line-search decision on the previous forward pass
+  const double* fwd_partials;
+  int32_t fwd_parts;
+  const SolverState* st_in;
+  SolverState* st_out;
   TraceDev* trace;
 };
 
@@ -116,7 +130,9 @@ struct DecideArgs {
 struct Tuning {
   int fwd_grid_per_cu = 4;
   int adj_grid_per_cu = 8;
+  int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
+  int fold = 1;                // solve: shared adjoint columns completed by the next forward pass
 };
 
 }  // namespace imrt
@@ -124,7 +140,6 @@ struct Tuning {
 struct imrt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  bool own_stream = false;
   int num_cu = 256;
   size_t max_lds = 65536;
   imrt::Tuning tune;
@@ -132,9 +147,10 @@ struct imrt_ctx {
 
 struct imrt_dose {
   imrt_ctx* ctx = nullptr;
+  int device = 0;
   int32_t nv = 0, nb = 0;
   int64_t nnz = 0;
-  // CSR (forward) and CSC (adjoint) copies of D
+  // CSR (forward) and CSC (adjoint) copies of D, each nonzero array padded by kPad zeros
   int32_t* row_ptr = nullptr;
   int32_t* col_idx = nullptr;
   float* val = nullptr;
@@ -144,9 +160,15 @@ struct imrt_dose {
   // forward row blocks and adjoint chunks
   int32_t nblocks = 0;
   int32_t* block_row = nullptr;
-  int32_t nchunks = 0;
-  int32_t* chunk_k = nullptr;
-  int32_t* col_chunk = nullptr;
+  int32_t* block_k0 = nullptr;
+  int32_t adj_grid = 0;        // workgroups of the adjoint partition
+  int32_t* wg_c0 = nullptr;
+  int32_t* wg_c1 = nullptr;
+  int32_t* col_wlo = nullptr;
+  int32_t* col_whi = nullptr;
+  int4* shared_cols = nullptr; // (column, wlo, whi, 0) of columns shared by several adjoint workgroups
+  int32_t nshared = 0;
+  double* pieces = nullptr;
   // structure ids from the phantom builder (nullable)
   uint8_t* sid = nullptr;
   // scratch for plain products
@@ -156,6 +178,7 @@ struct imrt_dose {
 
 struct imrt_plan {
   imrt_ctx* ctx = nullptr;
+  int device = 0;
   const imrt_dose* dose = nullptr;
   uint8_t* sid = nullptr;
   int32_t nstruct = 0;
@@ -166,13 +189,13 @@ struct imrt_plan {
   float* To_vox = nullptr;
   // workspace
   float* rbuf[imrt::kMaxTrials + 1] = {};
-  float* xk = nullptr;
+  float* xbuf[imrt::kMaxTrials + 1] = {};
   float* gk = nullptr;
   float* vtmp = nullptr;          // nv scratch
-  double* fwd_partials = nullptr; // kMaxTrials * fwd grid
-  double* adj_partials = nullptr; // nchunks
+  double* fwd_partials = nullptr; // kMaxTrials * (fwd grid + 1)
+  double* pieces = nullptr;       // 2 * adjoint grid
   double* misc = nullptr;         // small reduction scratch
-  imrt::SolverState* st = nullptr;
+  imrt::SolverState* st = nullptr;  // 2 states, alternately read and written by consecutive passes
   imrt::TraceDev* trace = nullptr;
   int32_t trace_cap = 0;
   imrt::SolverState* st_host = nullptr;   // pinned, 2 slots
@@ -192,22 +215,24 @@ int hip_error(hipError_t e, const char* what);
   } while (0)
 
 // launchers (kernels.hip)
+int forward_grid(const imrt_ctx* ctx, const imrt_dose* D);
+int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct);
+__host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
-int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, const AdjFinalArgs& f,
+int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
-int launch_decide(const imrt_ctx* ctx, const DecideArgs& a, int ntrials);
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out);
-int forward_grid(const imrt_ctx* ctx, const imrt_dose* D);
-size_t forward_lds_bytes(int nb, int ntrials);
 
 // phantom builder (build.hip)
 int build_phantom(imrt_ctx* ctx, const imrt_geometry* g, imrt_dose* D);
 
 // host preprocessing (api.hip)
+int alloc_nonzeros(imrt_dose* D);
 int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::vector<int32_t>& col_ptr);
 
 }  // namespace imrt

@@ -1,17 +1,25 @@
 // Hot-path kernels of the gradient-projection / Armijo solver for gfx950.
 //
-//  fwd_kernel       trial update + projection (step 2/4), forward dose z = D x
-//                   over CSR (Section 2.1), penalty residual and objective
-//                   partials (Eq. (1)-(2)) fused in one pass over D.
-//  adj_chunk_kernel beamlet-parallel adjoint D^T r over CSC, columns split
-//                   into fixed nonzero chunks; fixed-order float64 sums.
-//  adj_final_kernel per-column sum of the chunk partials, times 2 (gradient).
-//  decide_kernel    one workgroup: objective reduction, Armijo test (Eq. (5)),
-//                   stopping test (step 5), iterate update, trace.
+//  fwd_kernel   trial update + projection (steps 2 and 4) staged in LDS,
+//               forward dose z = D x over CSR (Section 2.1), penalty residual
+//               and objective partials (Eqs. (1)-(2)), in one pass over D.
+//  adj_kernel   line-search decision on the preceding forward pass (Armijo
+//               test of Eq. (5), stopping test of step 5), taken identically
+//               by every workgroup, then the beamlet-parallel adjoint
+//               g = 2 D^T r over CSC for an accepted, unfinished iterate.
+//  adj_final    completes beamlet columns shared by several adjoint
+//               workgroups (outside a solve, or with the completion not
+//               folded into the next forward pass).
 //
-// Every reduction runs in a fixed order, so results are bit-reproducible run
-// to run and independent of which workgroup finishes first; there are no
-// floating-point atomics.
+// The solver state is double-buffered: a pass reads one copy and workgroup 0
+// writes the other, so no workgroup ever sees a state written during its own
+// pass.  Every reduction runs in a fixed order, so results are
+// bit-reproducible and independent of workgroup timing; there are no
+// floating-point atomics.  Work is dealt to workgroups in contiguous ranges,
+// consecutive ranges on the same accelerator die (workgroups are dispatched
+// round-robin over the 8 dies), so neighbouring beamlet columns share that
+// die's L2 for their residual gathers.
+#include <algorithm>
 #include <cmath>
 
 #include "imrt_internal.h"
@@ -60,6 +68,17 @@ __device__ __forceinline__ float* select_buf(float* const (&b)[kMaxTrials + 1], 
   return p;
 }
 
+// Contiguous share [begin, end) of n work items for this workgroup.  With a
+// grid that is a multiple of the die count, workgroup w (on die w % 8) gets
+// logical slot (w % 8) * (grid / 8) + w / 8, so each die owns one contiguous
+// eighth of the items.
+__device__ __forceinline__ void work_range(int n, int& begin, int& end) {
+  const int G = gridDim.x, w = blockIdx.x;
+  const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
+  begin = static_cast<int>(static_cast<long long>(lw) * n / G);
+  end = static_cast<int>(static_cast<long long>(lw + 1) * n / G);
+}
+
 // Lanes cooperating on one row: the largest power of two with lanes*nr <= 256, at most 64.
 __device__ __forceinline__ int lanes_per_row(int nr) {
   int L = 64;
@@ -71,8 +90,11 @@ struct RowPenalty {
   double Tu, To, wu, wo;
 };
 
-__device__ __forceinline__ RowPenalty row_penalty(const Penalties& p, int row) {
-  const PenaltyDev t = p.table[p.sid[row]];
+// Penalty of a row: the structure's entry of the LDS copy of the table, or
+// per-voxel thresholds when given.
+__device__ __forceinline__ RowPenalty row_penalty(const Penalties& p, int row, const PenaltyDev* tab,
+                                                  uint8_t sid) {
+  const PenaltyDev t = tab[sid];
   RowPenalty r{t.T_u, t.T_o, t.w_u, t.w_o};
   if (p.Tu_vox != nullptr) {
     r.Tu = static_cast<double>(p.Tu_vox[row]);
@@ -92,14 +114,15 @@ __device__ __forceinline__ void penalty(const RowPenalty& p, float z, double& F,
 }
 
 template <int NT>
-__device__ __forceinline__ void row_epilogue(const FwdArgs& a, int row, const float (&d)[NT],
-                                             double (&pacc)[NT], float* const (&rout)[NT], int ntr) {
+__device__ __forceinline__ void row_epilogue(const FwdArgs& a, int row, uint8_t sid, const PenaltyDev* tab,
+                                             const float (&d)[NT], double (&pacc)[NT],
+                                             float* const (&rout)[NT], int ntr) {
   if (a.mode == FWD_PLAIN) {
     a.d_out[row] = d[0];
     pacc[0] += static_cast<double>(d[0]) * static_cast<double>(d[0]);
     return;
   }
-  const RowPenalty p = row_penalty(a.pen, row);
+  const RowPenalty p = row_penalty(a.pen, row, tab, sid);
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     if (q < ntr) {
@@ -117,54 +140,348 @@ __device__ __forceinline__ void row_epilogue(const FwdArgs& a, int row, const fl
   }
 }
 
+// ---- line-search decision ----------------------------------------------------------
+// Decision on the forward pass whose objective partials are in `partials`
+// ([trial][nparts], then [trial] step norms), starting from state `in`.  All
+// threads of the workgroup take part (fixed-order reductions); the new state
+// and the accepted trial land in shared memory.  Every workgroup that runs it
+// on the same inputs reaches the same result.
+struct Decision {
+  SolverState st;   // state after the decision
+  int accepted;     // accepted trial, -1 if none
+  int backtracks;   // reductions before the accepted trial
+  double lam, step_sq;
+};
+
+template <int NT>
+__device__ void decide(const SolverState* in, const double* partials, int nparts, Decision& dec, double* red) {
+#pragma clang fp contract(off)
+  __shared__ double Gq[NT];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    dec.st = *in;
+    dec.accepted = -1;
+  }
+  __syncthreads();
+  if (dec.st.phase == PH_DONE) return;
+  const bool init = (dec.st.phase == PH_INIT);
+  const int ntr = init ? 1 : NT;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    if (q < ntr) {
+      double s = 0.0;
+      for (int i = tid; i < nparts; i += kThreads) s += partials[q * nparts + i];
+      s = block_sum(s, red);
+      if (tid == 0) Gq[q] = s;
+    }
+  }
+  if (tid == 0) {
+    SolverState st = dec.st;
+    st.n_fwd += 1;
+    if (init) {
+      const double G0 = Gq[0];
+      st.G = G0;
+      st.G_init = G0;
+      st.G_prev = G0;
+      st.acc = (st.acc + 1) % (NT + 1);
+      st.m = 0;
+      st.lambda = st.lambda0;
+      if (!isfinite(G0)) {
+        st.status = IMRT_NUMERIC;
+        st.phase = PH_DONE;
+      } else if (st.max_iter <= 0) {
+        st.status = IMRT_MAX_ITER;
+        st.phase = PH_DONE;
+      } else {
+        st.phase = PH_NEED_GRAD;
+      }
+    } else {
+      const double* sq = partials + NT * nparts;
+      bool done = false;
+      int accepted = -1;
+      double l = st.lambda;
+      for (int q = 0; q < NT; ++q) {
+        if (q > 0) l = l / st.alpha;
+        const double s = sq[q], Gt = Gq[q];
+        if (s == 0.0) {
+          st.status = IMRT_STALLED;
+          done = true;
+          break;
+        }
+        if (!isfinite(Gt)) {
+          st.status = IMRT_NUMERIC;
+          done = true;
+          break;
+        }
+        const double C = st.G - (st.eps / l) * s;   // Eq. (5)
+        if (Gt < C) {
+          accepted = q;
+          break;
+        }
+        st.m += 1;
+        if (st.m > st.max_bt) {
+          st.status = IMRT_LS_FAIL;
+          done = true;
+          break;
+        }
+      }
+      if (accepted >= 0) {
+        dec.accepted = accepted;
+        dec.backtracks = st.m;
+        dec.lam = l;
+        dec.step_sq = sq[accepted];
+        st.k += 1;
+        st.G_prev = st.G;
+        st.G = Gq[accepted];
+        st.acc = (st.acc + 1 + accepted) % (NT + 1);
+        st.xi = (st.xi + 1 + accepted) % (NT + 1);
+        st.m = 0;
+        st.lambda = st.lambda0;
+        if (st.fixed) {
+          if (st.k >= st.max_iter) {
+            st.status = IMRT_MAX_ITER;
+            done = true;
+          }
+        } else if (st.G == 0.0 || fabs(st.G - st.G_prev) / st.G < st.delta) {
+          st.status = IMRT_CONVERGED;
+          done = true;
+        } else if (st.k >= st.max_iter) {
+          st.status = IMRT_MAX_ITER;
+          done = true;
+        }
+        st.phase = done ? PH_DONE : PH_NEED_GRAD;
+      } else if (done) {
+        st.phase = PH_DONE;
+      } else {
+        st.lambda = l / st.alpha;
+        st.phase = PH_TRIAL;
+      }
+    }
+    if (st.phase == PH_NEED_GRAD) st.n_adj += 1;
+    dec.st = st;
+  }
+  __syncthreads();
+}
+
+// ---- forward pass ---------------------------------------------------------------
+struct BlockMeta {
+  int r0, r1, k0, k1;
+};
+
+__device__ __forceinline__ BlockMeta block_meta(const FwdArgs& a, int b) {
+  BlockMeta m;
+  m.r0 = a.block_row[b];
+  m.r1 = a.block_row[b + 1];
+  m.k0 = a.block_k0[b];
+  m.k1 = a.block_k0[b + 1];
+  return m;
+}
+
+struct VecRegs {
+  int4 c[2];
+  float4 v[2];
+};
+
+// Issue the 16-byte loads covering nonzeros [base, min(base + 8*256, k1)) of
+// an index/value pair of arrays.  base is a multiple of 4 and the arrays carry
+// a zeroed tail, so whole vectors stay in bounds; a lane past k1 loads the
+// first vector instead (never used), which keeps the loads branch-free.
+__device__ __forceinline__ void issue_vec(const int32_t* idx, const float* val, int base, int k1, VecRegs& R) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    int e0 = base + 4 * (threadIdx.x + j * kThreads);
+    e0 = (e0 < k1) ? e0 : 0;
+    R.c[j] = *reinterpret_cast<const int4*>(idx + e0);
+    R.v[j] = *reinterpret_cast<const float4*>(val + e0);
+  }
+}
+
+// Row pointers (relative to the block's aligned start) and structure ids of
+// one block, loaded ahead into registers.
+struct RowRegs {
+  int rp[3];
+  uint8_t sid[2];
+};
+
+__device__ __forceinline__ void issue_rows(const FwdArgs& a, const BlockMeta& m, bool want_sid, RowRegs& Q) {
+  const int nr = m.r1 - m.r0;
+  const int t = threadIdx.x;
+  const int i0 = (t <= nr) ? t : 0;
+  const int i1 = (t + kThreads <= nr) ? t + kThreads : 0;
+  const int i2 = (2 * kThreads <= nr) ? 2 * kThreads : 0;
+  Q.rp[0] = a.row_ptr[m.r0 + i0];
+  Q.rp[1] = a.row_ptr[m.r0 + i1];
+  Q.rp[2] = a.row_ptr[m.r0 + i2];
+  if (want_sid) {
+    const int j0 = (t < nr) ? t : 0;
+    const int j1 = (t + kThreads < nr) ? t + kThreads : 0;
+    Q.sid[0] = a.pen.sid[m.r0 + j0];
+    Q.sid[1] = a.pen.sid[m.r0 + j1];
+  } else {
+    Q.sid[0] = Q.sid[1] = 0;
+  }
+}
+
+__device__ __forceinline__ void stage_rows(const BlockMeta& m, const RowRegs& Q, int32_t* rp, uint8_t* sid) {
+  const int nr = m.r1 - m.r0;
+  const int a0 = m.k0 & ~3;
+  const int t = threadIdx.x;
+  if (t <= nr) rp[t] = Q.rp[0] - a0;
+  if (t + kThreads <= nr) rp[t + kThreads] = Q.rp[1] - a0;
+  if (t == 0 && 2 * kThreads <= nr) rp[2 * kThreads] = Q.rp[2] - a0;
+  if (t < nr) sid[t] = Q.sid[0];
+  if (t + kThreads < nr) sid[t + kThreads] = Q.sid[1];
+}
+
+// Products D_ij * x_t^(q)_j of the block's nonzeros into LDS, written as
+// whole 4-element vectors at their offset from the block's aligned start.
+// Entries outside [k0, k1) (neighbouring rows or the zeroed tail, all valid
+// column indices) are computed too and never read.
+template <int NT>
+__device__ __forceinline__ void fwd_products(const BlockMeta& m, const VecRegs& R, const float* xs, int nbp,
+                                             float* prod) {
+  const int a0 = m.k0 & ~3;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int off = 4 * (threadIdx.x + j * kThreads);
+    if (a0 + off < m.k1) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const float* xq = xs + q * nbp;
+        float4 p;
+        p.x = R.v[j].x * xq[R.c[j].x];
+        p.y = R.v[j].y * xq[R.c[j].y];
+        p.z = R.v[j].z * xq[R.c[j].z];
+        p.w = R.v[j].w * xq[R.c[j].w];
+        *reinterpret_cast<float4*>(prod + q * kFwdNnzMax + off) = p;
+      }
+    }
+  }
+}
+
 // Forward pass.  Each workgroup stages the NT trial vectors
-// x_t^(q) = max(0, x_k - lambda_q g_k) in LDS, then walks row blocks of at
-// most kFwdNnzMax nonzeros: the block's products D_ij x_t^(q)_i go to LDS with
-// fully coalesced loads of col_idx/val, then lanes-per-row groups sum each
-// row and the penalty epilogue writes r and accumulates G.
+// x_t^(q) = max(0, x_k - lambda_q g_k) and the penalty table in LDS
+// (workgroup 0 also stores the trials and their step norms), then walks its
+// contiguous range of row blocks (at most kFwdPartNnz nonzeros each).  The
+// next block's col_idx/val (16-byte loads), row pointers and structure ids are
+// in flight while the current block's rows are summed from LDS by
+// lanes-per-row groups and the penalty epilogue writes r and accumulates G.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  float* xs = reinterpret_cast<float*>(smem);
-  float* prod = xs + NT * a.nb;
+  const int nb = a.nb;
+  const int nbp = pad4(nb);
+  PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
+  float* xs = reinterpret_cast<float*>(tab + a.nstruct);
+  float* gs = xs + NT * nbp;
+  float* prod = gs + nbp;
   int32_t* rp = reinterpret_cast<int32_t*>(prod + NT * kFwdNnzMax);
+  uint8_t* sidl = reinterpret_cast<uint8_t*>(rp + kFwdRowsMax + 1);
   __shared__ double red[kWaves];
   __shared__ float redf[kWaves];
 
   const int tid = threadIdx.x;
-  const int nb = a.nb;
+  const bool solve = (a.mode == FWD_SOLVE);
+  const bool want_sid = (a.mode != FWD_PLAIN);
   int ntr = 1;
   bool direct = true;
   double lam[NT];
   float* rout[NT];
+  float* xout[NT];
+  const float* xk = a.x;
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     lam[q] = 0.0;
     rout[q] = nullptr;
+    xout[q] = nullptr;
   }
-  if (a.mode == FWD_SOLVE) {
-    const SolverState* st = a.st;
+  if (solve) {
+    const SolverState* st = a.st_in;
+    // the state passes through unchanged (word copy by workgroup 0)
+    constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
+    if (blockIdx.x == 0 && tid < kWords)
+      reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
     const int phase = st->phase;
     if (phase == PH_DONE) return;
     direct = (phase == PH_INIT);
     ntr = direct ? 1 : NT;
-    const int acc = st->acc;
+    const int xi = st->xi, acc = st->acc;
+    xk = select_buf(a.xbuf, xi);
     lam[0] = st->lambda;
+    const double alpha = st->alpha;
 #pragma unroll
-    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / st->alpha;
+    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
 #pragma unroll
-    for (int q = 0; q < NT; ++q) rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
+    for (int q = 0; q < NT; ++q) {
+      rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
+      xout[q] = select_buf(a.xbuf, (xi + 1 + q) % (NT + 1));
+    }
   }
 
+  int b0, b1;
+  work_range(a.nblocks, b0, b1);
+  // first block's data in flight while the trial vectors are staged
+  VecRegs R;
+  RowRegs Q;
+  BlockMeta cur{0, 0, 0, 0}, nxt{0, 0, 0, 0};
+  if (b0 < b1) {
+    cur = block_meta(a, b0);
+    if (cur.k1 - cur.k0 <= kFwdPartNnz) {
+      issue_vec(a.col_idx, a.val, cur.k0 & ~3, cur.k1, R);
+      issue_rows(a, cur, want_sid, Q);
+    }
+    if (b0 + 1 < b1) nxt = block_meta(a, b0 + 1);
+  }
+
+  if (want_sid) {
+    const double* src = reinterpret_cast<const double*>(a.pen.table);
+    double* dst = reinterpret_cast<double*>(tab);
+    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = src[i];
+  }
+  const bool lead = solve && !direct && blockIdx.x == 0;
+  if (!direct) {
+    // gradient of x_k; columns shared by several adjoint workgroups are
+    // completed from their pieces in workgroup order
+    for (int i = tid; i < nb; i += kThreads) gs[i] = a.g[i];
+    if (a.shared_cols != nullptr) {
+      __syncthreads();
+      for (int e = tid; e < a.nshared; e += kThreads) {
+        const int4 sc = a.shared_cols[e];
+        double tot = a.pieces[2 * sc.y + 1];
+        for (int w = sc.y + 1; w < sc.z; ++w) tot += a.pieces[2 * w];
+        tot += a.pieces[2 * sc.z];
+        gs[sc.x] = static_cast<float>(a.g_scale * tot);
+      }
+    }
+    __syncthreads();
+  }
+  double sq[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
   for (int i = tid; i < nb; i += kThreads) {
-    const float xi = a.x[i];
+    const float xi = xk[i];
     if (direct) {
 #pragma unroll
-      for (int q = 0; q < NT; ++q) xs[q * nb + i] = xi;
+      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = xi;
     } else {
-      const float gi = a.g[i];
+      const float gi = gs[i];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) xs[q * nb + i] = trial_point(xi, gi, lam[q]);
+      for (int q = 0; q < NT; ++q) {
+        const float t = trial_point(xi, gi, lam[q]);
+        xs[q * nbp + i] = t;
+        if (lead) {
+          xout[q][i] = t;
+          const double dl = static_cast<double>(t) - static_cast<double>(xi);
+          sq[q] += dl * dl;
+        }
+      }
+    }
+  }
+  if (lead) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const double t = block_sum(sq[q], red);
+      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
     }
   }
   __syncthreads();
@@ -173,35 +490,45 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 #pragma unroll
   for (int q = 0; q < NT; ++q) pacc[q] = 0.0;
 
-  for (int b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
-    const int r0 = a.block_row[b], r1 = a.block_row[b + 1];
-    const int nr = r1 - r0;
-    const int k0 = a.row_ptr[r0], k1 = a.row_ptr[r1];
-    const int nz = k1 - k0;
-    if (nz > kFwdNnzMax) {
-      // a single row longer than the LDS block: all lanes stride over it
+  for (int b = b0; b < b1; ++b) {
+    const bool more = (b + 1 < b1);
+    if (cur.k1 - cur.k0 > kFwdPartNnz) {
+      // a single row longer than an LDS block: all lanes stride over it
       float s[NT];
 #pragma unroll
       for (int q = 0; q < NT; ++q) s[q] = 0.f;
-      for (int k = k0 + tid; k < k1; k += kThreads) {
+      for (int k = cur.k0 + tid; k < cur.k1; k += kThreads) {
         const int c = a.col_idx[k];
         const float v = a.val[k];
 #pragma unroll
-        for (int q = 0; q < NT; ++q) s[q] = fmaf(v, xs[q * nb + c], s[q]);
+        for (int q = 0; q < NT; ++q) s[q] = fmaf(v, xs[q * nbp + c], s[q]);
       }
 #pragma unroll
       for (int q = 0; q < NT; ++q) s[q] = block_sum(s[q], redf);
-      if (tid == 0) row_epilogue<NT>(a, r0, s, pacc, rout, ntr);
+      if (tid == 0) row_epilogue<NT>(a, cur.r0, want_sid ? a.pen.sid[cur.r0] : 0, tab, s, pacc, rout, ntr);
+      if (more) {
+        cur = nxt;
+        if (cur.k1 - cur.k0 <= kFwdPartNnz) {
+          issue_vec(a.col_idx, a.val, cur.k0 & ~3, cur.k1, R);
+          issue_rows(a, cur, want_sid, Q);
+        }
+        if (b + 2 < b1) nxt = block_meta(a, b + 2);
+      }
       continue;
     }
-    for (int k = tid; k < nz; k += kThreads) {
-      const int c = a.col_idx[k0 + k];
-      const float v = a.val[k0 + k];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) prod[q * kFwdNnzMax + k] = v * xs[q * nb + c];
-    }
-    for (int i = tid; i <= nr; i += kThreads) rp[i] = a.row_ptr[r0 + i] - k0;
+    const int nr = cur.r1 - cur.r0;
+    fwd_products<NT>(cur, R, xs, nbp, prod);
+    stage_rows(cur, Q, rp, sidl);
     __syncthreads();
+    const BlockMeta blk = cur;
+    if (more) {
+      cur = nxt;
+      if (cur.k1 - cur.k0 <= kFwdPartNnz) {
+        issue_vec(a.col_idx, a.val, cur.k0 & ~3, cur.k1, R);
+        issue_rows(a, cur, want_sid, Q);
+      }
+      if (b + 2 < b1) nxt = block_meta(a, b + 2);
+    }
     const int L = lanes_per_row(nr);
     const int lane = tid & (L - 1);
     for (int row = tid / L; row < nr; row += kThreads / L) {
@@ -209,15 +536,26 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
       float s[NT];
 #pragma unroll
       for (int q = 0; q < NT; ++q) s[q] = 0.f;
-      for (int k = s0 + lane; k < s1; k += L) {
+      // four independent LDS reads per round; slots past the row read as 0
+      for (int k = s0 + lane; k < s1; k += 4 * L) {
 #pragma unroll
-        for (int q = 0; q < NT; ++q) s[q] += prod[q * kFwdNnzMax + k];
+        for (int q = 0; q < NT; ++q) {
+          const float* pq = prod + q * kFwdNnzMax;
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kk = k + u * L;
+            const float t = pq[kk < kFwdNnzMax ? kk : kFwdNnzMax - 1];
+            v[u] = (kk < s1) ? t : 0.0f;
+          }
+          s[q] += (v[0] + v[1]) + (v[2] + v[3]);
+        }
       }
       for (int off = L >> 1; off > 0; off >>= 1) {
 #pragma unroll
         for (int q = 0; q < NT; ++q) s[q] += __shfl_xor(s[q], off, 64);
       }
-      if (lane == 0) row_epilogue<NT>(a, r0 + row, s, pacc, rout, ntr);
+      if (lane == 0) row_epilogue<NT>(a, blk.r0 + row, sidl[row], tab, s, pacc, rout, ntr);
     }
     __syncthreads();
   }
@@ -229,175 +567,130 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
   }
 }
 
-// Adjoint pass, stage 1: one fixed-order float64 partial per nonzero chunk.
-__global__ __launch_bounds__(kThreads) void adj_chunk_kernel(AdjArgs a) {
+// ---- adjoint pass ----------------------------------------------------------------
+// Residual gathers for the nonzeros of R: all eight are issued together
+// (every index held in R is a valid row: a real entry or the zeroed tail).
+struct GatherRegs {
+  float r[8];
+};
+
+__device__ __forceinline__ void adj_gather(const VecRegs& R, const float* r, GatherRegs& Gr) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    Gr.r[4 * j + 0] = r[R.c[j].x];
+    Gr.r[4 * j + 1] = r[R.c[j].y];
+    Gr.r[4 * j + 2] = r[R.c[j].z];
+    Gr.r[4 * j + 3] = r[R.c[j].w];
+  }
+}
+
+// Fixed-order float64 sum of val * r over this thread's nonzeros of the
+// round starting at `base`, counting only [k0, k1).
+__device__ __forceinline__ double adj_accumulate(const VecRegs& R, const GatherRegs& Gr, int base, int k0,
+                                                 int k1) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int e0 = base + 4 * (threadIdx.x + j * kThreads);
+    const float vv[4] = {R.v[j].x, R.v[j].y, R.v[j].z, R.v[j].w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool in = (e0 + i >= k0) && (e0 + i < k1);
+      s += static_cast<double>(in ? vv[i] : 0.0f) * static_cast<double>(Gr.r[4 * j + i]);
+    }
+  }
+  return s;
+}
+
+__device__ __forceinline__ int logical_wg() {
+  const int G = gridDim.x, w = blockIdx.x;
+  return (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
+}
+
+// Adjoint pass: in a solve, first the decision on the preceding forward pass
+// (every workgroup identically; workgroup 0 stores the new state and trace
+// entry), then g = scale * D^T r over this workgroup's share of the nonzeros.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
+  __shared__ double red[kWaves];
+  __shared__ Decision dec;
+  const int tid = threadIdx.x;
+  const int lw = logical_wg();
+  const int64_t k0w = static_cast<int64_t>(lw) * a.nnz / a.grid;
+  const int64_t k1w = static_cast<int64_t>(lw + 1) * a.nnz / a.grid;
+  const int c0 = a.wg_c0[lw], c1 = a.wg_c1[lw];
+  // the first column's first loads do not depend on the decision
+  VecRegs cur, nxt;
+  int s0 = 0, s1 = 0;
+  if (c0 < c1) {
+    s0 = static_cast<int>(max(k0w, static_cast<int64_t>(a.col_ptr[c0])));
+    s1 = static_cast<int>(min(k1w, static_cast<int64_t>(a.col_ptr[c0 + 1])));
+    issue_vec(a.row_idx, a.val, s0 & ~3, s1, cur);
+  }
   const float* r = a.r;
   if (a.solve) {
-    if (a.st->phase != PH_NEED_GRAD) return;
-    r = select_buf(a.rbuf, a.st->acc);
+    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, dec, red);
+    if (blockIdx.x == 0 && tid == 0) {
+      *a.st_out = dec.st;
+      if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
+        TraceDev e;
+        e.k = dec.st.k;
+        e.backtracks = dec.backtracks;
+        e.lambda = dec.lam;
+        e.step_sq = dec.step_sq;
+        e.G = dec.st.G;
+        a.trace[dec.st.k - 1] = e;
+      }
+    }
+    if (dec.st.phase != PH_NEED_GRAD) return;
+    r = select_buf(a.rbuf, dec.st.acc);
   }
-  __shared__ double red[kWaves];
-  const int tid = threadIdx.x;
-  for (int c = blockIdx.x; c < a.nchunks; c += gridDim.x) {
-    const int k0 = a.chunk_k[c], k1 = a.chunk_k[c + 1];
+  constexpr int kStep = 8 * kThreads;   // nonzeros covered by one round of loads
+  for (int c = c0; c < c1; ++c) {
+    if (c > c0) {
+      s0 = static_cast<int>(max(k0w, static_cast<int64_t>(a.col_ptr[c])));
+      s1 = static_cast<int>(min(k1w, static_cast<int64_t>(a.col_ptr[c + 1])));
+      issue_vec(a.row_idx, a.val, s0 & ~3, s1, cur);
+    }
     double s = 0.0;
-    for (int k = k0 + tid; k < k1; k += kThreads)
-      s += static_cast<double>(a.val[k]) * static_cast<double>(r[a.row_idx[k]]);
+    for (int base = s0 & ~3; base < s1; base += kStep) {
+      // gathers of this round first, then the next round's loads, so that
+      // waiting for the gathers does not wait for the prefetch
+      GatherRegs Gr;
+      adj_gather(cur, r, Gr);
+      issue_vec(a.row_idx, a.val, base + kStep, s1, nxt);   // past the end: first vector only
+      s += adj_accumulate(cur, Gr, base, s0, s1);
+      cur = nxt;
+    }
     s = block_sum(s, red);
-    if (tid == 0) a.partials[c] = s;
-  }
-}
-
-// Adjoint pass, stage 2: column sums of the chunk partials, scaled.
-__global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjFinalArgs f) {
-  if (f.solve && f.st->phase != PH_NEED_GRAD) return;
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= f.nb) return;
-  double s = 0.0;
-  for (int c = f.col_chunk[i]; c < f.col_chunk[i + 1]; ++c) s += f.partials[c];
-  f.out[i] = static_cast<float>(f.scale * s);
-}
-
-// Line-search decision (one workgroup).
-template <int NT>
-__global__ __launch_bounds__(kThreads) void decide_kernel(DecideArgs a) {
-#pragma clang fp contract(off)
-  SolverState* st = a.st;
-  const int phase = st->phase;
-  if (phase == PH_DONE) return;
-  __shared__ double red[kWaves];
-  __shared__ double Gq[NT], Sq[NT];
-  __shared__ int acc_q;
-  __shared__ double acc_lam;
-  const int tid = threadIdx.x;
-  const bool init = (phase == PH_INIT);
-  const int ntr = init ? 1 : NT;
-  double lam[NT];
-  lam[0] = st->lambda;
-#pragma unroll
-  for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / st->alpha;
-
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    if (q < ntr) {
-      double s = 0.0;
-      for (int i = tid; i < a.nparts; i += kThreads) s += a.partials[q * a.nparts + i];
-      s = block_sum(s, red);
-      if (tid == 0) Gq[q] = s;
-    }
-  }
-  if (!init) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      double s = 0.0;
-      for (int i = tid; i < a.nb; i += kThreads) {
-        const float xi = a.x[i];
-        const double dl = static_cast<double>(trial_point(xi, a.g[i], lam[q])) - static_cast<double>(xi);
-        s += dl * dl;
-      }
-      s = block_sum(s, red);
-      if (tid == 0) Sq[q] = s;
-    }
-  }
-
-  if (tid == 0) {
-    int accepted = -1;
-    double lam_used = lam[0];
-    if (init) {
-      const double G0 = Gq[0];
-      st->n_fwd += 1;
-      st->G = G0;
-      st->G_init = G0;
-      st->G_prev = G0;
-      st->acc = (st->acc + 1) % (NT + 1);
-      st->m = 0;
-      st->lambda = st->lambda0;
-      if (!isfinite(G0)) {
-        st->status = IMRT_NUMERIC;
-        st->phase = PH_DONE;
-      } else if (st->max_iter <= 0) {
-        st->status = IMRT_MAX_ITER;
-        st->phase = PH_DONE;
+    if (tid == 0) {
+      const int wlo = a.col_wlo[c], whi = a.col_whi[c];
+      if (wlo == whi) {
+        a.out[c] = static_cast<float>(a.scale * s);
       } else {
-        st->phase = PH_NEED_GRAD;
-      }
-    } else {
-      if (phase == PH_NEED_GRAD) st->n_adj += 1;
-      st->n_fwd += 1;
-      bool done = false;
-      double l = st->lambda;
-      for (int q = 0; q < NT; ++q) {
-        if (q > 0) l = l / st->alpha;
-        lam_used = l;
-        const double s = Sq[q], Gt = Gq[q];
-        if (s == 0.0) {
-          st->status = IMRT_STALLED;
-          done = true;
-          break;
-        }
-        if (!isfinite(Gt)) {
-          st->status = IMRT_NUMERIC;
-          done = true;
-          break;
-        }
-        const double C = st->G - (st->eps / l) * s;   // Eq. (5)
-        if (Gt < C) {
-          accepted = q;
-          break;
-        }
-        st->m += 1;
-        if (st->m > st->max_bt) {
-          st->status = IMRT_LS_FAIL;
-          done = true;
-          break;
-        }
-      }
-      if (accepted >= 0) {
-        st->k += 1;
-        st->G_prev = st->G;
-        st->G = Gq[accepted];
-        st->acc = (st->acc + 1 + accepted) % (NT + 1);
-        if (a.trace != nullptr && st->k - 1 < st->trace_cap) {
-          TraceDev e;
-          e.k = st->k;
-          e.backtracks = st->m;
-          e.lambda = lam_used;
-          e.step_sq = Sq[accepted];
-          e.G = st->G;
-          a.trace[st->k - 1] = e;
-        }
-        st->m = 0;
-        st->lambda = st->lambda0;
-        if (st->fixed) {
-          if (st->k >= st->max_iter) {
-            st->status = IMRT_MAX_ITER;
-            done = true;
-          }
-        } else if (st->G == 0.0 || fabs(st->G - st->G_prev) / st->G < st->delta) {
-          st->status = IMRT_CONVERGED;
-          done = true;
-        } else if (st->k >= st->max_iter) {
-          st->status = IMRT_MAX_ITER;
-          done = true;
-        }
-        st->phase = done ? PH_DONE : PH_NEED_GRAD;
-      } else if (done) {
-        st->phase = PH_DONE;
-      } else {
-        st->lambda = l / st->alpha;
-        st->phase = PH_TRIAL;
+        if (c == c0) a.pieces[2 * lw] = s;
+        if (c == c1 - 1) a.pieces[2 * lw + 1] = s;
       }
     }
-    acc_q = init ? -1 : accepted;
-    acc_lam = lam_used;
-  }
-  __syncthreads();
-  if (acc_q >= 0) {
-    const double l = acc_lam;
-    for (int i = tid; i < a.nb; i += kThreads) a.x[i] = trial_point(a.x[i], a.g[i], l);
   }
 }
 
+// Columns shared by several adjoint workgroups (completion not folded): the
+// fixed-order sum of their pieces.  Runs after adj_kernel; in a solve only
+// when that pass computed a gradient (state after the decision in `st`).
+__global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const SolverState* st) {
+  if (st != nullptr && st->phase != PH_NEED_GRAD) return;
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= a.nb) return;
+  const int wlo = a.col_wlo[c], whi = a.col_whi[c];
+  if (wlo == whi) return;
+  double tot = a.pieces[2 * wlo + 1];
+  for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
+  tot += a.pieces[2 * whi];
+  a.out[c] = static_cast<float>(a.scale * tot);
+}
+
+// ---- small utility kernels ----------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void sum_kernel(const double* parts, int n, double* out) {
   __shared__ double red[kWaves];
   double s = 0.0;
@@ -447,21 +740,42 @@ int check_launch(const char* what) {
   return IMRT_OK;
 }
 
+// Drop an error left behind by an unrelated earlier runtime call on this
+// thread, so that check_launch reports only the launch that follows.
+void clear_stale_error() { (void)hipGetLastError(); }
+
+int grid_for(int items, int cap) {
+  if (items <= 0) return 1;
+  if (items <= cap) return items;
+  return cap;
+}
+
 }  // namespace
 
-size_t forward_lds_bytes(int nb, int ntrials) {
-  return static_cast<size_t>(ntrials) * (static_cast<size_t>(nb) + kFwdNnzMax) * sizeof(float) +
-         static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t);
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct) {
+  const size_t nbp = static_cast<size_t>(pad4(nb));
+  return static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
+         (static_cast<size_t>(ntrials) * (nbp + kFwdNnzMax) + nbp) * sizeof(float) +
+         static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
 }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D) {
-  const int cap = ctx->tune.fwd_grid_per_cu * ctx->num_cu;
-  return D->nblocks < cap ? (D->nblocks > 0 ? D->nblocks : 1) : cap;
+  return grid_for(D->nblocks, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+}
+
+int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
+  const int64_t cap = static_cast<int64_t>(ctx->tune.adj_grid_per_cu) * ctx->num_cu;
+  // at least adj_min_nnz nonzeros per workgroup, at least one workgroup
+  const int64_t per = ctx->tune.adj_min_nnz;
+  const int64_t want = (nnz + per - 1) / per;
+  return static_cast<int>(std::max<int64_t>(1, std::min(cap, want)));
 }
 
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before, hipEvent_t after) {
-  const size_t lds = forward_lds_bytes(a.nb, ntrials);
+  (void)D;
+  clear_stale_error();
+  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct);
   if (lds > ctx->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
   if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
@@ -476,45 +790,44 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   return rc;
 }
 
-int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, const AdjFinalArgs& f,
-                   hipEvent_t before, hipEvent_t after) {
-  const int cap = ctx->tune.adj_grid_per_cu * ctx->num_cu;
-  const int grid = a.nchunks < cap ? (a.nchunks > 0 ? a.nchunks : 1) : cap;
+int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials, hipEvent_t before,
+                   hipEvent_t after) {
+  clear_stale_error();
   if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
-  hipLaunchKernelGGL(adj_chunk_kernel, dim3(grid), dim3(kThreads), 0, ctx->stream, a);
-  int rc = check_launch("adj_chunk_kernel");
+  switch (ntrials) {
+    case 1: hipLaunchKernelGGL(adj_kernel<1>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
+    case 2: hipLaunchKernelGGL(adj_kernel<2>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
+    case 4: hipLaunchKernelGGL(adj_kernel<4>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  int rc = check_launch("adj_kernel");
   if (rc) return rc;
   if (after && hipEventRecord(after, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
-  const int g2 = (f.nb + kThreads - 1) / kThreads;
-  if (g2 > 0) {
-    hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, ctx->stream, f);
+  if (!a.fold) {
+    const int g2 = (a.nb + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, ctx->stream, a,
+                       a.solve ? static_cast<const SolverState*>(a.st_out) : nullptr);
     rc = check_launch("adj_final_kernel");
   }
+  (void)D;
   return rc;
 }
 
-int launch_decide(const imrt_ctx* ctx, const DecideArgs& a, int ntrials) {
-  switch (ntrials) {
-    case 1: hipLaunchKernelGGL(decide_kernel<1>, dim3(1), dim3(kThreads), 0, ctx->stream, a); break;
-    case 2: hipLaunchKernelGGL(decide_kernel<2>, dim3(1), dim3(kThreads), 0, ctx->stream, a); break;
-    case 4: hipLaunchKernelGGL(decide_kernel<4>, dim3(1), dim3(kThreads), 0, ctx->stream, a); break;
-    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
-  }
-  return check_launch("decide_kernel");
-}
-
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out) {
+  clear_stale_error();
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, parts, n, out);
   return check_launch("sum_kernel");
 }
 
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out) {
+  clear_stale_error();
   hipLaunchKernelGGL(project_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, x, g, lambda, nb, x_out, s_out);
   return check_launch("project_kernel");
 }
 
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out) {
+  clear_stale_error();
   hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, w, nb, v_out, norm_out);
   return check_launch("normalize_kernel");
 }

@@ -65,6 +65,8 @@ SIGNATURES = {
     "imrt_ctx_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
     "imrt_ctx_destroy": (C.c_int, [_vp]),
     "imrt_ctx_stream": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "imrt_ctx_set_option": (C.c_int, [_vp, C.c_char_p, C.c_int64]),
+    "imrt_ctx_get_option": (C.c_int, [_vp, C.c_char_p, C.POINTER(C.c_int64)]),
     "imrt_build_dose_matrix": (C.c_int, [_vp, C.POINTER(imrt_geometry), C.c_int, C.POINTER(_vp), _u8p]),
     "imrt_dose_from_csr": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f32p, C.c_int,
                                      C.POINTER(_vp)]),
@@ -144,6 +146,16 @@ def imrt_ctx_stream(ctx) -> int:
     out = _vp()
     _check(load().imrt_ctx_stream(ctx, C.byref(out)), "imrt_ctx_stream")
     return out.value or 0
+
+
+def imrt_ctx_set_option(ctx, name: str, value: int):
+    return _check(load().imrt_ctx_set_option(ctx, name.encode(), int(value)), "imrt_ctx_set_option")
+
+
+def imrt_ctx_get_option(ctx, name: str) -> int:
+    out = C.c_int64()
+    _check(load().imrt_ctx_get_option(ctx, name.encode(), C.byref(out)), "imrt_ctx_get_option")
+    return out.value
 
 
 def imrt_build_dose_matrix(ctx, geom: imrt_geometry, storage: int = IMRT_F32, voxel_struct_out=None):
@@ -248,7 +260,7 @@ def imrt_last_error() -> str:
 class Context:
     """A library context on ``device``, enqueuing on PyTorch's current stream."""
 
-    def __init__(self, device: int = 0, stream: Optional[int] = None):
+    def __init__(self, device: int = 0, stream: Optional[int] = None, **options):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libimrt needs a HIP GPU; none is visible")
@@ -257,6 +269,14 @@ class Context:
             stream = torch.cuda.current_stream(device).cuda_stream
         self.device = device
         self.handle = imrt_ctx_create(device, stream)
+        for name, value in options.items():
+            imrt_ctx_set_option(self.handle, name, value)
+
+    def set_option(self, name: str, value: int):
+        imrt_ctx_set_option(self.handle, name, value)
+
+    def get_option(self, name: str) -> int:
+        return imrt_ctx_get_option(self.handle, name)
 
     def close(self):
         if self.handle:

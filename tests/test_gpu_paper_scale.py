@@ -86,6 +86,22 @@ def test_full_solve_trajectory(built, fx):
     oracle's trajectory within 1e-6 relative; dose at sampled voxels agrees
     with the oracle's rows applied to the GPU's plan within 1e-5."""
     banner("paper-scale solve")
+    _check_full_solve(built, fx)
+
+
+def test_full_solve_trajectory_final_kernel(built, fx):
+    """The same with shared adjoint columns completed by the separate kernel."""
+    from paper_0908_4421_amd.imrt import Context, Dose, Plan
+    banner("paper-scale solve, final kernel")
+    ctx = Context(0, fold=0)
+    dose = Dose.from_geometry(ctx, PAPER_SCALE)
+    plan = Plan(ctx, dose)
+    plan.set_structures(None, 4)
+    plan.set_penalties(penalty_table(PAPER_SCALE))
+    _check_full_solve((ctx, dose, plan, built[3]), fx)
+
+
+def _check_full_solve(built, fx):
     ctx, dose, plan, ex = built
     st = PAPER_SCALE_SETTINGS
     x = to_dev(start_point(dose.nb, st).astype(np.float32))

@@ -22,10 +22,12 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1024, 16], ids=["default", "shared_cols"])
+def ctx(request):
+    """Default adjoint partition, or one with many short workgroup ranges so
+    that most columns are shared by several workgroups."""
     from paper_0908_4421_amd.imrt import Context
-    return Context(0)
+    return Context(0, adj_min_nnz=request.param)
 
 
 def _dose(ctx, A):
@@ -97,3 +99,12 @@ def test_invalid_csr_rejected(ctx):
         imrt.imrt_dose_from_csr(ctx.handle, 2, 3, 3, rp, np.array([0, 1, 2], np.int32),
                                 np.array([1, -1, 1], np.float32))
     assert e.value.code == imrt.IMRT_EINVAL
+
+
+def test_context_options(ctx):
+    from paper_0908_4421_amd import imrt
+    assert ctx.get_option("adj_min_nnz") in (1024, 16)
+    for bad in (("no_such_option", 1), ("fold", 2), ("adj_min_nnz", 3), ("fwd_wg_per_cu", 0)):
+        with pytest.raises(imrt.ImrtError) as e:
+            ctx.set_option(*bad)
+        assert e.value.code == imrt.IMRT_EINVAL
