@@ -44,6 +44,17 @@ int use_device(const imrt_ctx* ctx) {
   return IMRT_OK;
 }
 
+// Largest forward grid of either forward variant at the current settings.
+int forward_grid_cap(imrt_ctx* ctx, const imrt_dose* D) {
+  const int saved = ctx->tune.fwd_wave;
+  ctx->tune.fwd_wave = 0;
+  const int g0 = forward_grid(ctx, D);
+  ctx->tune.fwd_wave = 1;
+  const int g1 = forward_grid(ctx, D);
+  ctx->tune.fwd_wave = saved;
+  return std::max(g0, g1);
+}
+
 double pow2_at_least(double q) {
   int ex = 0;
   const double mant = std::frexp(q, &ex);
@@ -101,6 +112,23 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
     blocks.push_back(r);
   }
   for (int32_t b : blocks) block_k0.push_back(row_ptr[b]);
+  // the same for one wave (at most kWavePartNnz nonzeros and kWaveRowsMax rows)
+  std::vector<int32_t> wblocks, wblock_k0;
+  wblocks.push_back(0);
+  r = 0;
+  while (r < D->nv) {
+    const int start = r;
+    int64_t nz = 0;
+    while (r < D->nv && r - start < kWaveRowsMax) {
+      const int64_t len = row_ptr[r + 1] - row_ptr[r];
+      if (r > start && nz + len > kWavePartNnz) break;
+      nz += len;
+      ++r;
+      if (nz > kWavePartNnz) break;
+    }
+    wblocks.push_back(r);
+  }
+  for (int32_t b : wblocks) wblock_k0.push_back(row_ptr[b]);
 
   const int G = adjoint_grid_for(D->ctx, D->nnz);
   const int64_t nnz = D->nnz;
@@ -134,9 +162,11 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   for (int v = 0; v < G; ++v)
     if (wg_c1[v] == 0) wg_c0[v] = 0;  // no columns
   D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
+  D->nwblocks = static_cast<int32_t>(wblocks.size()) - 1;
   D->adj_grid = G;
   int rc;
   if ((rc = dev_alloc(&D->block_row, blocks.size())) || (rc = dev_alloc(&D->block_k0, block_k0.size())) ||
+      (rc = dev_alloc(&D->wblock_row, wblocks.size())) || (rc = dev_alloc(&D->wblock_k0, wblock_k0.size())) ||
       (rc = dev_alloc(&D->wg_c0, static_cast<size_t>(G))) || (rc = dev_alloc(&D->wg_c1, static_cast<size_t>(G))) ||
       (rc = dev_alloc(&D->col_wlo, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
@@ -150,13 +180,17 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   hipStream_t s = D->ctx->stream;
   IMRT_HIP(hipMemcpyAsync(D->block_row, blocks.data(), sizeof(int32_t) * blocks.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->block_k0, block_k0.data(), sizeof(int32_t) * block_k0.size(), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wblock_row, wblocks.data(), sizeof(int32_t) * wblocks.size(), hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wblock_k0, wblock_k0.data(), sizeof(int32_t) * wblock_k0.size(),
+                          hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wg_c0, wg_c0.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wg_c1, wg_c1.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_whi, col_whi.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   if (!shared.empty())
     IMRT_HIP(hipMemcpyAsync(D->shared_cols, shared.data(), sizeof(int4) * shared.size(), hipMemcpyHostToDevice, s));
-  D->partials_len = kMaxTrials * (forward_grid(D->ctx, D) + 1) + 16;
+  D->fwd_cap = forward_grid_cap(D->ctx, D);
+  D->partials_len = kMaxTrials * (D->fwd_cap + 1) + 16;
   if ((rc = dev_alloc(&D->partials, D->partials_len))) return rc;
   IMRT_HIP(hipStreamSynchronize(s));
   return IMRT_OK;
@@ -179,6 +213,8 @@ void free_dose(imrt_dose* D) {
   dev_free(D->cval);
   dev_free(D->block_row);
   dev_free(D->block_k0);
+  dev_free(D->wblock_row);
+  dev_free(D->wblock_k0);
   dev_free(D->wg_c0);
   dev_free(D->wg_c1);
   dev_free(D->col_wlo);
@@ -235,6 +271,9 @@ FwdArgs base_fwd(const imrt_dose* D) {
   a.block_row = D->block_row;
   a.block_k0 = D->block_k0;
   a.nblocks = D->nblocks;
+  a.wblock_row = D->wblock_row;
+  a.wblock_k0 = D->wblock_k0;
+  a.nwblocks = D->nwblocks;
   a.nv = D->nv;
   a.nb = D->nb;
   return a;
@@ -261,7 +300,7 @@ int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, in
   a.d_out = dose_out;
   a.r_out = r_out;
   a.partials = P->fwd_partials;
-  const int grid = forward_grid(P->ctx, D);
+  const int grid = std::min(forward_grid(P->ctx, D), P->fwd_cap);
   int rc = launch_forward(P->ctx, D, a, 1, grid);
   if (rc) return rc;
   return launch_sum(P->ctx, P->fwd_partials, grid, P->misc + slot);
@@ -326,6 +365,7 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
   if (const char* f = std::getenv("IMRT_FOLD")) c->tune.fold = (std::atoi(f) != 0) ? 1 : 0;
+  if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
   return IMRT_OK;
@@ -356,6 +396,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 16;
     return &ctx->tune.adj_min_nnz;
   }
+  if (n == "fwd_wave") {
+    *lo = 0;
+    return &ctx->tune.fwd_wave;
+  }
   if (n == "fold") {
     *lo = 0;
     return &ctx->tune.fold;
@@ -369,7 +413,8 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int64_t lo = 0;
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
-  const int64_t hi = (std::string(name) == "fold") ? 1 : (int64_t(1) << 30);
+  const std::string nm(name);
+  const int64_t hi = (nm == "fold" || nm == "fwd_wave") ? 1 : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
   return IMRT_OK;
@@ -517,7 +562,7 @@ int imrt_dose_apply(const imrt_dose* D, const float* x_dev, float* d_dev) {
   a.x = x_dev;
   a.d_out = d_dev;
   a.partials = D->partials;
-  return launch_forward(D->ctx, D, a, 1, forward_grid(D->ctx, D));
+  return launch_forward(D->ctx, D, a, 1, std::min(forward_grid(D->ctx, D), D->fwd_cap));
 }
 
 int imrt_dose_apply_transpose(const imrt_dose* D, const float* r_dev, float* y_dev) {
@@ -543,7 +588,8 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
   P->ctx = ctx;
   P->device = ctx->device;
   P->dose = dose;
-  const int grid = forward_grid(ctx, dose);
+  const int grid = forward_grid_cap(ctx, dose);
+  P->fwd_cap = grid;
   if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
       (rc = ensure_buffers(P, 2)) || (rc = dev_alloc(&P->gk, dose->nb)) || (rc = dev_alloc(&P->vtmp, dose->nv)) ||
       (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
@@ -697,7 +743,7 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
     a.x = v;
     a.d_out = P->vtmp;
     a.partials = P->fwd_partials;
-    const int grid = forward_grid(C, D);
+    const int grid = std::min(forward_grid(C, D), P->fwd_cap);
     if ((rc = launch_forward(C, D, a, 1, grid))) return rc;
     if (it == iters) {
       if ((rc = launch_sum(C, P->fwd_partials, grid, P->misc))) return rc;
@@ -733,7 +779,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   const imrt_dose* D = P->dose;
   imrt_ctx* C = P->ctx;
   hipStream_t s = C->stream;
-  if (forward_lds_bytes(D->nb, nt, P->nstruct) > C->max_lds)
+  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0) > C->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
 
   // x_1 >= 0 and finite (initialisation of the method)
@@ -807,7 +853,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     return hip_error(e, "solve setup");
   }
 
-  const int grid = forward_grid(C, D);
+  const int grid = std::min(forward_grid(C, D), P->fwd_cap);
   FwdArgs fa = base_fwd(D);
   fa.mode = FWD_SOLVE;
   set_plan_penalties(fa, P);

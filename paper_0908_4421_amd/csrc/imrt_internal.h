@@ -17,6 +17,9 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kFwdNnzMax = 2048;       // LDS product slots of one forward row block
 constexpr int kFwdPartNnz = kFwdNnzMax - 4;  // block limit so that 16-byte aligned loads fit
 constexpr int kFwdRowsMax = 512;       // rows of one forward row block
+constexpr int kWaveNnz = 512;          // LDS product slots of one wave's row block
+constexpr int kWavePartNnz = kWaveNnz - 4;
+constexpr int kWaveRowsMax = 256;      // rows of one wave's row block
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;
 constexpr int kPad = 16;               // zeroed tail of every nonzero array (aligned vector loads)
@@ -77,6 +80,9 @@ struct FwdArgs {
   const int32_t* block_row;  // nblocks + 1 row boundaries
   const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
+  const int32_t* wblock_row; // per-wave row blocks (wave-granular forward)
+  const int32_t* wblock_k0;
+  int32_t nwblocks;
   int32_t nstruct;
   Penalties pen;
   const float* x;            // eval/plain input vector
@@ -133,6 +139,7 @@ struct Tuning {
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
   int fold = 1;                // solve: shared adjoint columns completed by the next forward pass
+  int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
 
 }  // namespace imrt
@@ -161,6 +168,9 @@ struct imrt_dose {
   int32_t nblocks = 0;
   int32_t* block_row = nullptr;
   int32_t* block_k0 = nullptr;
+  int32_t nwblocks = 0;
+  int32_t* wblock_row = nullptr;
+  int32_t* wblock_k0 = nullptr;
   int32_t adj_grid = 0;        // workgroups of the adjoint partition
   int32_t* wg_c0 = nullptr;
   int32_t* wg_c1 = nullptr;
@@ -174,6 +184,7 @@ struct imrt_dose {
   // scratch for plain products
   double* partials = nullptr;
   int32_t partials_len = 0;
+  int32_t fwd_cap = 1;         // forward grids are capped at the partials capacity
 };
 
 struct imrt_plan {
@@ -192,7 +203,8 @@ struct imrt_plan {
   float* xbuf[imrt::kMaxTrials + 1] = {};
   float* gk = nullptr;
   float* vtmp = nullptr;          // nv scratch
-  double* fwd_partials = nullptr; // kMaxTrials * (fwd grid + 1)
+  double* fwd_partials = nullptr; // kMaxTrials * (fwd_cap + 1)
+  int32_t fwd_cap = 1;
   double* pieces = nullptr;       // 2 * adjoint grid
   double* misc = nullptr;         // small reduction scratch
   imrt::SolverState* st = nullptr;  // 2 states, alternately read and written by consecutive passes
@@ -217,7 +229,7 @@ int hip_error(hipError_t e, const char* what);
 // launchers (kernels.hip)
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D);
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct);
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);

@@ -169,8 +169,20 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     if (q < ntr) {
+      // four independent loads per round, summed in index order
       double s = 0.0;
-      for (int i = tid; i < nparts; i += kThreads) s += partials[q * nparts + i];
+      const double* pq = partials + q * nparts;
+      for (int i0 = tid; i0 < nparts; i0 += 4 * kThreads) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * kThreads;
+          v[u] = pq[i < nparts ? i : 0];
+          v[u] = (i < nparts) ? v[u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += v[u];
+      }
       s = block_sum(s, red);
       if (tid == 0) Gq[q] = s;
     }
@@ -359,6 +371,97 @@ __device__ __forceinline__ void fwd_products(const BlockMeta& m, const VecRegs& 
   }
 }
 
+// Stage the inputs of a forward pass in LDS: the penalty table, the gradient
+// (completing shared adjoint columns from their pieces) and the NT trial
+// vectors x_t^(q) = max(0, x_k - lambda_q g_k), or x itself for a direct
+// pass.  The lead workgroup also stores the trials and their step norms.
+// Ends with a workgroup barrier.
+template <int NT>
+__device__ __forceinline__ void stage_inputs(const FwdArgs& a, bool direct, bool lead, const float* xk,
+                                             const double (&lam)[NT], float* const (&xout)[NT],
+                                             PenaltyDev* tab, float* xs, float* gs, double* red,
+                                             bool want_sid) {
+  const int tid = threadIdx.x;
+  const int nb = a.nb;
+  const int nbp = pad4(nb);
+  if (want_sid) {
+    const double* src = reinterpret_cast<const double*>(a.pen.table);
+    double* dst = reinterpret_cast<double*>(tab);
+    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = src[i];
+  }
+  constexpr int kU = 8;   // vector entries loaded per thread per round
+  if (!direct) {
+    // gradient of x_k; columns shared by several adjoint workgroups are
+    // completed from their pieces in workgroup order
+    for (int i0 = tid; i0 < nb; i0 += kU * kThreads) {
+      float v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kThreads;
+        v[u] = a.g[i < nb ? i : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kThreads;
+        if (i < nb) gs[i] = v[u];
+      }
+    }
+    if (a.shared_cols != nullptr) {
+      __syncthreads();
+      for (int e = tid; e < a.nshared; e += kThreads) {
+        const int4 sc = a.shared_cols[e];
+        double tot = a.pieces[2 * sc.y + 1];
+        for (int w = sc.y + 1; w < sc.z; ++w) tot += a.pieces[2 * w];
+        tot += a.pieces[2 * sc.z];
+        gs[sc.x] = static_cast<float>(a.g_scale * tot);
+      }
+    }
+    __syncthreads();
+  }
+  double sq[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
+  for (int i0 = tid; i0 < nb; i0 += kU * kThreads) {
+    float xv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kThreads;
+      xv[u] = xk[i < nb ? i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kThreads;
+      if (i < nb) {
+        if (direct) {
+#pragma unroll
+          for (int q = 0; q < NT; ++q) xs[q * nbp + i] = xv[u];
+        } else {
+          const float gi = gs[i];
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const float t = trial_point(xv[u], gi, lam[q]);
+            xs[q * nbp + i] = t;
+            if (lead) {
+              xout[q][i] = t;
+              const double dl = static_cast<double>(t) - static_cast<double>(xv[u]);
+              sq[q] += dl * dl;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (lead) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const double t = block_sum(sq[q], red);
+      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
+    }
+  }
+  __syncthreads();
+
+}
+
 // Forward pass.  Each workgroup stages the NT trial vectors
 // x_t^(q) = max(0, x_k - lambda_q g_k) and the penalty table in LDS
 // (workgroup 0 also stores the trials and their step norms), then walks its
@@ -433,58 +536,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     if (b0 + 1 < b1) nxt = block_meta(a, b0 + 1);
   }
 
-  if (want_sid) {
-    const double* src = reinterpret_cast<const double*>(a.pen.table);
-    double* dst = reinterpret_cast<double*>(tab);
-    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = src[i];
-  }
-  const bool lead = solve && !direct && blockIdx.x == 0;
-  if (!direct) {
-    // gradient of x_k; columns shared by several adjoint workgroups are
-    // completed from their pieces in workgroup order
-    for (int i = tid; i < nb; i += kThreads) gs[i] = a.g[i];
-    if (a.shared_cols != nullptr) {
-      __syncthreads();
-      for (int e = tid; e < a.nshared; e += kThreads) {
-        const int4 sc = a.shared_cols[e];
-        double tot = a.pieces[2 * sc.y + 1];
-        for (int w = sc.y + 1; w < sc.z; ++w) tot += a.pieces[2 * w];
-        tot += a.pieces[2 * sc.z];
-        gs[sc.x] = static_cast<float>(a.g_scale * tot);
-      }
-    }
-    __syncthreads();
-  }
-  double sq[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
-  for (int i = tid; i < nb; i += kThreads) {
-    const float xi = xk[i];
-    if (direct) {
-#pragma unroll
-      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = xi;
-    } else {
-      const float gi = gs[i];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const float t = trial_point(xi, gi, lam[q]);
-        xs[q * nbp + i] = t;
-        if (lead) {
-          xout[q][i] = t;
-          const double dl = static_cast<double>(t) - static_cast<double>(xi);
-          sq[q] += dl * dl;
-        }
-      }
-    }
-  }
-  if (lead) {
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const double t = block_sum(sq[q], red);
-      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
-    }
-  }
-  __syncthreads();
+  stage_inputs<NT>(a, direct, solve && !direct && blockIdx.x == 0, xk, lam, xout, tab, xs, gs, red, want_sid);
 
   double pacc[NT];
 #pragma unroll
@@ -558,6 +610,223 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
       if (lane == 0) row_epilogue<NT>(a, blk.r0 + row, sidl[row], tab, s, pacc, rout, ntr);
     }
     __syncthreads();
+  }
+
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const double t = block_sum(pacc[q], red);
+    if (tid == 0) a.partials[q * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// ---- wave-granular forward pass --------------------------------------------------
+// Same computation as fwd_kernel, but each of the four waves of a workgroup
+// streams its own range of small row blocks (at most kWavePartNnz nonzeros):
+// the products, row pointers and structure ids of a block live in the wave's
+// own LDS region, so blocks need no workgroup barrier, and sixteen or more
+// independent streams per compute unit keep memory busy.
+struct WaveRows {
+  int rp[5];
+  uint8_t sid[4];
+};
+
+__device__ __forceinline__ void wave_issue(const FwdArgs& a, const BlockMeta& m, bool want_sid, int lane,
+                                           VecRegs& R, WaveRows& Q) {
+  const int a0 = m.k0 & ~3;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    int e0 = a0 + 4 * (lane + 64 * j);
+    e0 = (e0 < m.k1) ? e0 : 0;
+    R.c[j] = *reinterpret_cast<const int4*>(a.col_idx + e0);
+    R.v[j] = *reinterpret_cast<const float4*>(a.val + e0);
+  }
+  const int nr = m.r1 - m.r0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const int i = lane + 64 * j;
+    Q.rp[j] = a.row_ptr[m.r0 + ((i <= nr) ? i : 0)];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = lane + 64 * j;
+    Q.sid[j] = want_sid ? a.pen.sid[m.r0 + ((i < nr) ? i : 0)] : 0;
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nb = a.nb;
+  const int nbp = pad4(nb);
+  PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
+  float* xs = reinterpret_cast<float*>(tab + a.nstruct);
+  float* gs = xs + NT * nbp;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int kWaveBytes = ((NT * kWaveNnz + kWaveRowsMax + 1) * 4 + kWaveRowsMax + 15) & ~15;
+  unsigned char* wbase = reinterpret_cast<unsigned char*>(gs + nbp) + wv * kWaveBytes;
+  float* prod = reinterpret_cast<float*>(wbase);
+  int32_t* rp = reinterpret_cast<int32_t*>(prod + NT * kWaveNnz);
+  uint8_t* sidl = reinterpret_cast<uint8_t*>(rp + kWaveRowsMax + 1);
+  __shared__ double red[kWaves];
+
+  const int tid = threadIdx.x;
+  const bool solve = (a.mode == FWD_SOLVE);
+  const bool want_sid = (a.mode != FWD_PLAIN);
+  int ntr = 1;
+  bool direct = true;
+  double lam[NT];
+  float* rout[NT];
+  float* xout[NT];
+  const float* xk = a.x;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    lam[q] = 0.0;
+    rout[q] = nullptr;
+    xout[q] = nullptr;
+  }
+  if (solve) {
+    const SolverState* st = a.st_in;
+    constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
+    if (blockIdx.x == 0 && tid < kWords)
+      reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
+    const int phase = st->phase;
+    if (phase == PH_DONE) return;
+    direct = (phase == PH_INIT);
+    ntr = direct ? 1 : NT;
+    const int xi = st->xi, acc = st->acc;
+    xk = select_buf(a.xbuf, xi);
+    lam[0] = st->lambda;
+    const double alpha = st->alpha;
+#pragma unroll
+    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
+      xout[q] = select_buf(a.xbuf, (xi + 1 + q) % (NT + 1));
+    }
+  }
+
+  // this wave's contiguous range of row blocks
+  const int G = gridDim.x, w = blockIdx.x;
+  const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
+  const long long W = static_cast<long long>(G) * kWaves, gw = static_cast<long long>(lw) * kWaves + wv;
+  const int b0 = static_cast<int>(gw * a.nwblocks / W), b1 = static_cast<int>((gw + 1) * a.nwblocks / W);
+  auto meta = [&](int b) {
+    BlockMeta m;
+    m.r0 = a.wblock_row[b];
+    m.r1 = a.wblock_row[b + 1];
+    m.k0 = a.wblock_k0[b];
+    m.k1 = a.wblock_k0[b + 1];
+    return m;
+  };
+  VecRegs R;
+  WaveRows Q;
+  BlockMeta cur{0, 0, 0, 0}, nxt{0, 0, 0, 0};
+  if (b0 < b1) {
+    cur = meta(b0);
+    if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
+    if (b0 + 1 < b1) nxt = meta(b0 + 1);
+  }
+
+  stage_inputs<NT>(a, direct, solve && !direct && blockIdx.x == 0, xk, lam, xout, tab, xs, gs, red, want_sid);
+
+  double pacc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) pacc[q] = 0.0;
+
+  for (int b = b0; b < b1; ++b) {
+    const bool more = (b + 1 < b1);
+    if (cur.k1 - cur.k0 > kWavePartNnz) {
+      // a single row longer than a wave block: the wave strides over it
+      float s[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) s[q] = 0.f;
+      for (int k = cur.k0 + lane; k < cur.k1; k += 64) {
+        const int c = a.col_idx[k];
+        const float v = a.val[k];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) s[q] = fmaf(v, xs[q * nbp + c], s[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < NT; ++q) s[q] = wave_sum(s[q]);
+      if (lane == 0) row_epilogue<NT>(a, cur.r0, want_sid ? a.pen.sid[cur.r0] : 0, tab, s, pacc, rout, ntr);
+      if (more) {
+        cur = nxt;
+        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
+        if (b + 2 < b1) nxt = meta(b + 2);
+      }
+      continue;
+    }
+    const int a0 = cur.k0 & ~3;
+    const int nr = cur.r1 - cur.r0;
+    // products and row data of this block into the wave's LDS region
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int off = 4 * (lane + 64 * j);
+      if (a0 + off < cur.k1) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const float* xq = xs + q * nbp;
+          float4 p;
+          p.x = R.v[j].x * xq[R.c[j].x];
+          p.y = R.v[j].y * xq[R.c[j].y];
+          p.z = R.v[j].z * xq[R.c[j].z];
+          p.w = R.v[j].w * xq[R.c[j].w];
+          *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int i = lane + 64 * j;
+      if (i <= nr) rp[i] = Q.rp[j] - a0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = lane + 64 * j;
+      if (i < nr) sidl[i] = Q.sid[j];
+    }
+    // LDS operations of one wave complete in order; the fence only keeps the
+    // compiler from moving the reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const BlockMeta blk = cur;
+    if (more) {
+      cur = nxt;
+      if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
+      if (b + 2 < b1) nxt = meta(b + 2);
+    }
+    int L = 64;
+    while (L > 1 && L * nr > 64) L >>= 1;
+    const int sub = lane & (L - 1);
+    for (int row = lane / L; row < nr; row += 64 / L) {
+      const int s0 = rp[row], s1 = rp[row + 1];
+      float s[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) s[q] = 0.f;
+      for (int k = s0 + sub; k < s1; k += 4 * L) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const float* pq = prod + q * kWaveNnz;
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kk = k + u * L;
+            const float t = pq[kk < kWaveNnz ? kk : kWaveNnz - 1];
+            v[u] = (kk < s1) ? t : 0.0f;
+          }
+          s[q] += (v[0] + v[1]) + (v[2] + v[3]);
+        }
+      }
+      for (int off = L >> 1; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) s[q] += __shfl_xor(s[q], off, 64);
+      }
+      if (sub == 0) row_epilogue<NT>(a, blk.r0 + row, sidl[row], tab, s, pacc, rout, ntr);
+    }
+    // the next block's LDS writes must not overtake this block's reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 
 #pragma unroll
@@ -752,15 +1021,24 @@ int grid_for(int items, int cap) {
 
 }  // namespace
 
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct) {
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
   const size_t nbp = static_cast<size_t>(pad4(nb));
-  return static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
-         (static_cast<size_t>(ntrials) * (nbp + kFwdNnzMax) + nbp) * sizeof(float) +
-         static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
+  size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
+                 (static_cast<size_t>(ntrials) * nbp + nbp) * sizeof(float);
+  if (wave) {
+    const size_t per_wave = ((static_cast<size_t>(ntrials) * kWaveNnz + kWaveRowsMax + 1) * 4 + kWaveRowsMax + 15) &
+                            ~static_cast<size_t>(15);
+    bytes += kWaves * per_wave;
+  } else {
+    bytes += static_cast<size_t>(ntrials) * kFwdNnzMax * sizeof(float) +
+             static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
+  }
+  return bytes;
 }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D) {
-  return grid_for(D->nblocks, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+  const int items = ctx->tune.fwd_wave ? (D->nwblocks + kWaves - 1) / kWaves : D->nblocks;
+  return grid_for(items, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
@@ -775,15 +1053,25 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
                    hipEvent_t before, hipEvent_t after) {
   (void)D;
   clear_stale_error();
-  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct);
+  const bool wave = ctx->tune.fwd_wave != 0;
+  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave);
   if (lds > ctx->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
   if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
-  switch (ntrials) {
-    case 1: hipLaunchKernelGGL(fwd_kernel<1>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-    case 2: hipLaunchKernelGGL(fwd_kernel<2>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-    case 4: hipLaunchKernelGGL(fwd_kernel<4>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  if (wave) {
+    switch (ntrials) {
+      case 1: hipLaunchKernelGGL(fwd_wave_kernel<1>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      case 2: hipLaunchKernelGGL(fwd_wave_kernel<2>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      case 4: hipLaunchKernelGGL(fwd_wave_kernel<4>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+    }
+  } else {
+    switch (ntrials) {
+      case 1: hipLaunchKernelGGL(fwd_kernel<1>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      case 2: hipLaunchKernelGGL(fwd_kernel<2>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      case 4: hipLaunchKernelGGL(fwd_kernel<4>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+    }
   }
   const int rc = check_launch("fwd_kernel");
   if (rc == IMRT_OK && after && hipEventRecord(after, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");

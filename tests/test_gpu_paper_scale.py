@@ -90,10 +90,11 @@ def test_full_solve_trajectory(built, fx):
 
 
 def test_full_solve_trajectory_final_kernel(built, fx):
-    """The same with shared adjoint columns completed by the separate kernel."""
+    """The same with shared adjoint columns completed by the separate kernel
+    and workgroup-wide forward row blocks."""
     from paper_0908_4421_amd.imrt import Context, Dose, Plan
     banner("paper-scale solve, final kernel")
-    ctx = Context(0, fold=0)
+    ctx = Context(0, fold=0, fwd_wave=0)
     dose = Dose.from_geometry(ctx, PAPER_SCALE)
     plan = Plan(ctx, dose)
     plan.set_structures(None, 4)

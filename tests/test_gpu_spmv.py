@@ -22,12 +22,13 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=[1024, 16], ids=["default", "shared_cols"])
+@pytest.fixture(scope="module", params=[(1024, 1), (16, 0)], ids=["default", "shared_cols_block_fwd"])
 def ctx(request):
-    """Default adjoint partition, or one with many short workgroup ranges so
-    that most columns are shared by several workgroups."""
+    """Default launch settings, or many short adjoint workgroup ranges (most
+    columns shared by several workgroups) with workgroup-wide forward blocks."""
     from paper_0908_4421_amd.imrt import Context
-    return Context(0, adj_min_nnz=request.param)
+    min_nnz, wave = request.param
+    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave)
 
 
 def _dose(ctx, A):
