@@ -19,6 +19,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KERNEL_SOURCES = ("paper_0908_4421_amd/csrc/kernels.hip", "paper_0908_4421_amd/csrc/imrt_internal.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_fwd_adj_prostate_160x104x80.txt")
 
 
 def forward_bytes(nv, nb, nnz):
@@ -66,6 +68,69 @@ def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
     }
 
 
+def kernel_source_hash():
+    """sha256 of the kernel sources; recorded with every counter summary."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def summarize_pmc(folder):
+    """Median per dispatch of every counter and kernel in the rocprofv3 CSV
+    counter files under `folder` (dispatches that did no work are skipped: a
+    value below 1 % of the kernel's largest)."""
+    import csv
+    import glob
+    import statistics
+    from collections import defaultdict
+    per = defaultdict(float)
+    for path in sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                key = (row["Dispatch_Id"], row["Kernel_Name"], row["Counter_Name"])
+                per[key] += float(row["Counter_Value"])
+    by = defaultdict(list)
+    for (_, kern, ctr), v in per.items():
+        by[(kern, ctr)].append(v)
+    print(f"kernel_source_sha256 = {kernel_source_hash()}")
+    for (kern, ctr), vals in sorted(by.items()):
+        top = max(vals)
+        work = [v for v in vals if v >= 0.01 * top] or vals
+        print(f"counter | {kern} | {ctr} | dispatches {len(vals)} | working {len(work)} | "
+              f"median {statistics.median(work):.1f} | mean {statistics.fmean(work):.1f}")
+
+
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch of the named kernel from the committed counter
+    summary: FETCH_SIZE and WRITE_SIZE medians (KiB per dispatch), each scaled
+    by the factor a plain device copy of known size gave for the same counter.
+    None when the summary is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    ctr = {}
+    for ln in lines:
+        if ln.startswith("counter | "):
+            parts = [p.strip() for p in ln.split("|")]
+            if kernel_key in parts[1]:
+                ctr[parts[2]] = float(parts[5].split()[1])
+        elif " = " in ln and not ln.startswith("#"):
+            k, v = ln.split(" = ", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if "FETCH_SIZE" not in ctr or "WRITE_SIZE" not in ctr:
+        return None
+    return (ctr["FETCH_SIZE"] * 1024 * float(kv["fetch_factor"]) +
+            ctr["WRITE_SIZE"] * 1024 * float(kv["write_factor"]))
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -86,9 +151,16 @@ def main():
     ap.add_argument("--trials-per-pass", type=int, default=1)
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-every", type=int, default=1, metavar="N",
+                    help="HIP events around every N-th forward and adjoint launch of the timed plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="only print per-kernel medians of the rocprofv3 CSV counter files under DIR")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs the solver on exactly one GPU; multi-GPU runs are not part of this build "
@@ -130,7 +202,7 @@ def main():
     v0 = torch.as_tensor(power_start_vector(dose.nb, spec.seed).astype(np.float32)).cuda()
     x = torch.empty(dose.nb, dtype=torch.float32, device="cuda")
 
-    def step(profile=False):
+    def step(profile=0):
         lam0, _ = plan.lambda0(v0, st.power_iters)
         x.fill_(st.x0)
         res, _ = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=lam0, delta=st.delta,
@@ -141,9 +213,11 @@ def main():
 
     for _ in range(args.warmup):
         step()
+    # the timed plans carry HIP events around every profile_every-th forward
+    # and adjoint launch (recorded on the solver's stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = [step() for _ in range(args.steps)]
+    runs = [step(args.profile_every) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -151,18 +225,21 @@ def main():
     print(f"[bench] {spec.name}: {res.iterations} iterations, {ms_per_step:.2f} ms per plan", file=sys.stderr,
           flush=True)
 
-    # one more identical step with HIP events around every forward and adjoint launch
-    _, prof = step(profile=True)
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    wave = ctx.get_option("fwd_wave")
+    names = {"forward": f"{'fwd_wave_kernel' if wave else 'fwd_kernel'}<{args.trials_per_pass}>(",
+             "adjoint": f"adj_kernel<{args.trials_per_pass}>("}
     kern = {}
-    for name, ms, n, nbytes in (("forward", prof.forward_kernel_ms, prof.forward_passes, forward_bytes(nv, nb, nnz)),
-                                ("adjoint", prof.adjoint_kernel_ms, prof.adjoint_passes, adjoint_bytes(nv, nb, nnz))):
+    for name, nbytes in (("forward", forward_bytes(nv, nb, nnz)), ("adjoint", adjoint_bytes(nv, nb, nnz))):
+        ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)
+        n = res.forward_passes if name == "forward" else res.adjoint_passes
         gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kern[name] = {"avg_ms": ms, "launches": n, "bytes_per_launch": nbytes, "GB_s": gbs,
-                      "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
+        kern[name] = {"kernel": names[name], "avg_ms": ms, "launches": n, "bytes_per_launch": nbytes,
+                      "GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+                "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom]),
+                "kernel": kern[dom]["kernel"]}
 
     out = {
         "metric": "time-to-plan (s) + SpMV HBM GB/s vs peak, 9-field 2.5mm; p99 served re-plan",
@@ -191,7 +268,7 @@ def main():
         "solve_device_ms": res.device_ms,
         "dose_build_s": build_s,
         "kernels": kern,
-        "kernel_timing": "HIP events around each launch, one extra identical plan after the timed steps",
+        "kernel_timing": f"HIP events around every {args.profile_every}-th launch of the timed plans",
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -100,7 +100,8 @@ typedef struct {
   int32_t max_backtracks; /* cap on reductions per line search, >= 0 */
   int32_t fixed_iters;    /* non-zero: run exactly max_iter iterations, no stopping test */
   int32_t trials_per_pass;/* trial step sizes evaluated per pass over D: 1, 2 or 4 (0 = 1) */
-  int32_t profile;        /* non-zero: time every forward and adjoint launch with HIP events */
+  int32_t profile;        /* >= 0; n > 0: time every n-th forward and every n-th adjoint launch
+                           * with HIP events on the context stream (1 = every launch) */
   int32_t reserved;       /* must be 0 */
   void* trace;            /* nullable host buffer of max_iter imrt_trace_entry, filled on return */
 } imrt_solve_params;
@@ -122,10 +123,10 @@ typedef struct {
   double G_initial;       /* G(x_1) */
   double G_final;         /* G at the returned x */
   double device_ms;       /* stream time of the solve, HIP events */
-  /* With params.profile: mean HIP-event duration of the forward pass kernel
-   * and of the adjoint chunk kernel over the launches that did work (the
-   * first forward_passes and adjoint_passes launches; exact when no line
-   * search needed a second pass), else 0. */
+  /* With params.profile: mean HIP-event duration of a forward pass launch
+   * and of an adjoint pass launch (its completion kernel included) over the
+   * timed launches among those that did work (the first forward_passes and
+   * adjoint_passes launches), else 0. */
   double forward_kernel_ms;
   double adjoint_kernel_ms;
 } imrt_solve_result;

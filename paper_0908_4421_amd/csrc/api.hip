@@ -773,6 +773,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   if (prm->max_iter < 0 || prm->max_backtracks < 0)
     return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
   if (prm->reserved != 0) return set_error(IMRT_EINVAL, "reserved must be 0");
+  if (prm->profile < 0) return set_error(IMRT_EINVAL, "profile must be >= 0");
   const int nt = prm->trials_per_pass == 0 ? 1 : prm->trials_per_pass;
   if (nt != 1 && nt != 2 && nt != 4) return set_error(IMRT_EINVAL, "trials_per_pass must be 0, 1, 2 or 4");
   if ((rc = use_device(P->ctx))) return rc;
@@ -814,19 +815,28 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   P->st_host[0] = init;
 
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_poll[2] = {nullptr, nullptr};
-  // per-launch timing events (profile mode): pairs for forward and adjoint launches
-  std::vector<hipEvent_t> ev_fwd, ev_adj;
+  // profile mode: HIP events around every profile-th forward and adjoint launch
+  struct Timed {
+    long long launch;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> ev_fwd, ev_adj;
+  long long n_fwd_launch = 0, n_adj_launch = 0;
   auto cleanup = [&]() {
     if (ev_start) (void)hipEventDestroy(ev_start);
     if (ev_end) (void)hipEventDestroy(ev_end);
     for (auto& e : ev_poll)
       if (e) (void)hipEventDestroy(e);
-    for (auto& e : ev_fwd) (void)hipEventDestroy(e);
-    for (auto& e : ev_adj) (void)hipEventDestroy(e);
+    for (auto* pool : {&ev_fwd, &ev_adj})
+      for (auto& t : *pool) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+      }
   };
-  auto event_pair = [&](std::vector<hipEvent_t>& pool, hipEvent_t* a, hipEvent_t* b) -> hipError_t {
+  auto event_pair = [&](std::vector<Timed>& pool, long long& launch, hipEvent_t* a, hipEvent_t* b) -> hipError_t {
     *a = *b = nullptr;
-    if (!prm->profile) return hipSuccess;
+    const long long idx = launch++;
+    if (prm->profile == 0 || idx % prm->profile != 0) return hipSuccess;
     hipEvent_t x = nullptr, y = nullptr;
     hipError_t r = hipEventCreate(&x);
     if (r == hipSuccess) r = hipEventCreate(&y);
@@ -834,8 +844,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
       if (x) (void)hipEventDestroy(x);
       return r;
     }
-    pool.push_back(x);
-    pool.push_back(y);
+    pool.push_back(Timed{idx, x, y});
     *a = x;
     *b = y;
     return hipSuccess;
@@ -886,7 +895,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   auto state_out = [&]() { return P->st + ((pass + 1) & 1); };
   auto forward_pass = [&]() -> int {
     hipEvent_t f0, f1;
-    const hipError_t r = event_pair(ev_fwd, &f0, &f1);
+    const hipError_t r = event_pair(ev_fwd, n_fwd_launch, &f0, &f1);
     if (r != hipSuccess) return hip_error(r, "hipEventCreate");
     fa.st_in = state_in();
     fa.st_out = state_out();
@@ -896,7 +905,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   };
   auto adjoint_pass = [&]() -> int {
     hipEvent_t a0, a1;
-    const hipError_t r = event_pair(ev_adj, &a0, &a1);
+    const hipError_t r = event_pair(ev_adj, n_adj_launch, &a0, &a1);
     if (r != hipSuccess) return hip_error(r, "hipEventCreate");
     aa.st_in = state_in();
     aa.st_out = state_out();
@@ -1004,16 +1013,19 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   res->forward_kernel_ms = 0.0;
   res->adjoint_kernel_ms = 0.0;
   if (prm->profile) {
-    auto mean_of = [&](const std::vector<hipEvent_t>& pool, int n, double* out) -> hipError_t {
-      n = std::min<int>(n, static_cast<int>(pool.size() / 2));
+    // mean over the sampled launches among those that did work
+    auto mean_of = [&](const std::vector<Timed>& pool, int n, double* out) -> hipError_t {
       double tot = 0.0;
-      for (int i = 0; i < n; ++i) {
-        float t = 0.f;
-        const hipError_t r = hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]);
+      int cnt = 0;
+      for (const Timed& t : pool) {
+        if (t.launch >= n) break;
+        float ms_i = 0.f;
+        const hipError_t r = hipEventElapsedTime(&ms_i, t.a, t.b);
         if (r != hipSuccess) return r;
-        tot += t;
+        tot += ms_i;
+        ++cnt;
       }
-      *out = n > 0 ? tot / n : 0.0;
+      *out = cnt > 0 ? tot / cnt : 0.0;
       return hipSuccess;
     };
     e = mean_of(ev_fwd, done_st.n_fwd, &res->forward_kernel_ms);

@@ -391,10 +391,10 @@ class Plan:
         return imrt_estimate_lambda0(self.handle, v0.data_ptr(), iters)
 
     def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
-              fixed_iters=False, trials_per_pass=1, trace=False, profile=False):
+              fixed_iters=False, trials_per_pass=1, trace=False, profile=0):
         buf = (imrt_trace_entry * max(max_iter, 1))() if trace else None
         p = imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
-                              trials_per_pass, int(bool(profile)), 0,
+                              trials_per_pass, int(profile), 0,
                               C.cast(buf, C.c_void_p) if trace else None)
         res = imrt_solve(self.handle, p, x.data_ptr())
         tr = None
