@@ -151,7 +151,7 @@ def main():
     ap.add_argument("--trials-per-pass", type=int, default=1)
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-every", type=int, default=1, metavar="N",
+    ap.add_argument("--profile-every", type=int, default=32, metavar="N",
                     help="HIP events around every N-th forward and adjoint launch of the timed plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")

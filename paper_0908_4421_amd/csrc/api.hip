@@ -316,6 +316,7 @@ AdjArgs base_adj(const imrt_dose* D) {
   a.col_wlo = D->col_wlo;
   a.col_whi = D->col_whi;
   a.nnz = D->nnz;
+  a.nv = D->nv;
   a.nb = D->nb;
   a.grid = D->adj_grid;
   a.fold = 0;

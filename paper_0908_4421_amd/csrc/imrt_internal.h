@@ -116,7 +116,7 @@ struct AdjArgs {
   const int32_t* col_wlo;
   const int32_t* col_whi;
   int64_t nnz;
-  int32_t nb, grid;
+  int32_t nv, nb, grid;
   int32_t solve;             // decide the previous forward pass first; r from rbuf
   int32_t fold;              // shared columns completed by the next forward pass (else adj_final)
   const float* r;

@@ -35,11 +35,48 @@ __device__ __forceinline__ float trial_point(float x, float g, double lam) {
   return static_cast<float>(t < 0.0 ? 0.0 : t);
 }
 
+// ---- cross-lane sums ----------------------------------------------------------
+// Data-parallel-primitive (DPP) moves within a wave: swaps inside quads, the
+// mirrors of 8- and 16-lane rows, and the row broadcasts of lanes 15 and 31.
+// Lanes a row mask leaves out receive 0.  The order of every sum is fixed.
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int2 w = __builtin_bit_cast(int2, v);
+  int2 o;
+  o.x = __builtin_amdgcn_update_dpp(0, w.x, CTRL, ROWS, 0xF, false);
+  o.y = __builtin_amdgcn_update_dpp(0, w.y, CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, o);
+}
+
+// Sum over each aligned group of L lanes; valid in the group's last lane
+// (lane % L == L - 1).
+template <int L, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if constexpr (L >= 2) v += dpp_move<kDppQuadXor1, 0xF>(v);
+  if constexpr (L >= 4) v += dpp_move<kDppQuadXor2, 0xF>(v);
+  if constexpr (L >= 8) v += dpp_move<kDppRowHalfMirror, 0xF>(v);
+  if constexpr (L >= 16) v += dpp_move<kDppRowMirror, 0xF>(v);
+  if constexpr (L >= 32) v += dpp_move<kDppRowBcast15, 0xA>(v);
+  if constexpr (L >= 64) v += dpp_move<kDppRowBcast31, 0xC>(v);
+  return v;
+}
+
+// Sum over the wave; valid in lane 63.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
+  return group_sum<64>(v);
 }
 
 // Sum of v over the workgroup in a fixed order; the result is valid in thread 0.
@@ -47,7 +84,7 @@ template <typename T>
 __device__ __forceinline__ T block_sum(T v, T* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = v;
+  if (lane == 63) sh[w] = v;
   __syncthreads();
   T t = T(0);
   if (threadIdx.x == 0) {
@@ -58,6 +95,37 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
   __syncthreads();
   return t;
 }
+
+// ---- buffer resources -----------------------------------------------------------
+// A raw buffer descriptor built from a wave-uniform base address and length:
+// loads take 32-bit offsets, and a lane whose offset lies past the length
+// reads zeros without touching memory.  Lengths are kept multiples of the
+// access size, so an access is either wholly inside or wholly outside.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // CDNA descriptor word 3: 32-bit data, no swizzle
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+__device__ __forceinline__ int4 load_i4(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ float4 load_f4(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ int load_i32(rsrc_t r, uint32_t off) {
+  return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ float load_f32(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ uint32_t load_u8(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+__device__ __forceinline__ void store_f32(rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ float* select_buf(float* const (&b)[kMaxTrials + 1], int i) {
   float* p = b[0];
@@ -620,40 +688,136 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 }
 
 // ---- wave-granular forward pass --------------------------------------------------
-// Same computation as fwd_kernel, but each of the four waves of a workgroup
-// streams its own range of small row blocks (at most kWavePartNnz nonzeros):
-// the products, row pointers and structure ids of a block live in the wave's
-// own LDS region, so blocks need no workgroup barrier, and sixteen or more
-// independent streams per compute unit keep memory busy.
-struct WaveRows {
-  int rp[5];
-  uint8_t sid[4];
+// Each of the four waves of a workgroup streams its own contiguous range of
+// small row blocks (at most kWavePartNnz nonzeros and kWaveRowsMax rows).
+// Block bounds come from per-lane copies of the block table read with
+// readlane, so all control flow and every descriptor is wave-uniform.  A
+// block's column indices and values arrive as 16-byte buffer loads (lanes
+// past the block read zeros), its products D_ij x_j go to the wave's LDS
+// region, and groups of L lanes (the largest power of two with L * rows <= 64)
+// sum one row each, reading four products per round and combining the lanes
+// with DPP moves.  Row pointers and structure ids of a row are loaded by the
+// lane that finishes it.  The next block's loads are issued as soon as the
+// products of the current one are in LDS.
+constexpr int kWaveSlack = 256;   // LDS floats after the last wave region (over-reads of masked slots)
+
+struct WaveStage {
+  int4 c[2];
+  float4 v[2];
+  int rlo[4], rhi[4];
+  uint32_t sid[4];
 };
 
-__device__ __forceinline__ void wave_issue(const FwdArgs& a, const BlockMeta& m, bool want_sid, int lane,
-                                           VecRegs& R, WaveRows& Q) {
+struct WaveBlock {
+  int r0, r1, k0, k1;
+};
+
+__device__ __forceinline__ int log2_lanes(int nr) {
+  // largest L = 2^e <= 64 with L * nr <= 64 (L = 1 beyond 64 rows)
+  int e = 6;
+  while (e > 0 && (nr << e) > 64) --e;
+  return e;
+}
+
+template <int MODE>
+__device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m, int lane, WaveStage& S) {
   const int a0 = m.k0 & ~3;
+  const uint32_t bytes = static_cast<uint32_t>((m.k1 - a0) * 4 + 15) & ~15u;
+  const rsrc_t rc = make_rsrc(a.col_idx + a0, bytes);
+  const rsrc_t rv = make_rsrc(a.val + a0, bytes);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    int e0 = a0 + 4 * (lane + 64 * j);
-    e0 = (e0 < m.k1) ? e0 : 0;
-    R.c[j] = *reinterpret_cast<const int4*>(a.col_idx + e0);
-    R.v[j] = *reinterpret_cast<const float4*>(a.val + e0);
+    S.c[j] = load_i4(rc, 16 * lane + 1024 * j);
+    S.v[j] = load_f4(rv, 16 * lane + 1024 * j);
   }
   const int nr = m.r1 - m.r0;
+  const int e = log2_lanes(nr);
+  const int passes = ((nr << e) + 63) >> 6;
+  const rsrc_t rp = make_rsrc(a.row_ptr + m.r0, static_cast<uint32_t>(nr + 1) * 4);
+  const rsrc_t rs = make_rsrc(a.pen.sid + m.r0, static_cast<uint32_t>(nr));
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const int i = lane + 64 * j;
-    Q.rp[j] = a.row_ptr[m.r0 + ((i <= nr) ? i : 0)];
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int i = lane + 64 * j;
-    Q.sid[j] = want_sid ? a.pen.sid[m.r0 + ((i < nr) ? i : 0)] : 0;
+  for (int p = 0; p < 4; ++p) {
+    S.rlo[p] = S.rhi[p] = 0;
+    S.sid[p] = 0;
+    if (p < passes) {
+      const int row = (p << (6 - e)) + (lane >> e);
+      S.rlo[p] = load_i32(rp, 4 * row);
+      S.rhi[p] = load_i32(rp, 4 * row + 4);
+      if (MODE != FWD_PLAIN) S.sid[p] = load_u8(rs, row);
+    }
   }
 }
 
-template <int NT>
+template <int NT, int MODE>
+__device__ __forceinline__ void row_finish(const FwdArgs& a, int row, uint32_t sid, const PenaltyDev* tab,
+                                           const float (&d)[NT], double (&pacc)[NT], const rsrc_t (&rout)[NT],
+                                           const rsrc_t& dout, int ntr) {
+#pragma clang fp contract(off)
+  const uint32_t off = 4u * static_cast<uint32_t>(row);
+  if (MODE == FWD_PLAIN) {
+    store_f32(dout, off, d[0]);
+    pacc[0] += static_cast<double>(d[0]) * static_cast<double>(d[0]);
+    return;
+  }
+  const RowPenalty pen = row_penalty(a.pen, row, tab, static_cast<uint8_t>(sid));
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    if (q < ntr) {
+      double F;
+      float r;
+      penalty(pen, d[q], F, r);
+      pacc[q] += F;
+      if (MODE == FWD_SOLVE) {
+        store_f32(rout[q], off, r);
+      } else if (q == 0) {
+        if (a.r_out) store_f32(rout[0], off, r);
+        if (a.d_out) store_f32(dout, off, d[0]);
+      }
+    }
+  }
+}
+
+// Row sums of one block with L lanes per row.
+template <int L, int NT, int MODE>
+__device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, int lane, const WaveBlock& m,
+                                          const WaveStage& S, const PenaltyDev* tab, double (&pacc)[NT],
+                                          const rsrc_t (&rout)[NT], const rsrc_t& dout, int ntr) {
+  constexpr int kRowsPerPass = 64 / L;
+  const int a0 = m.k0 & ~3;
+  const int nr = m.r1 - m.r0;
+  const int passes = (nr * L + 63) / 64;
+  const int sub = lane & (L - 1);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (p < passes) {
+      const int row = p * kRowsPerPass + lane / L;
+      const int s1 = S.rhi[p] - a0;
+      float acc[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[q] = 0.f;
+      for (int k = S.rlo[p] - a0 + sub; k < s1; k += 4 * L) {
+        const int left = s1 - k;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const float* pq = prod + q * kWaveNnz + k;
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const float t = pq[u * L];   // always in the allocation; masked below
+            v[u] = (u * L < left) ? t : 0.0f;
+          }
+          acc[q] += (v[0] + v[1]) + (v[2] + v[3]);
+        }
+      }
+      float d[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) d[q] = group_sum<L>(acc[q]);
+      if (sub == L - 1 && row < nr) row_finish<NT, MODE>(a, m.r0 + row, S.sid[p], tab, d, pacc, rout, dout, ntr);
+    }
+  }
+}
+
+template <int NT, int MODE>
 __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = a.nb;
@@ -661,29 +825,27 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
   float* xs = reinterpret_cast<float*>(tab + a.nstruct);
   float* gs = xs + NT * nbp;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int kWaveBytes = ((NT * kWaveNnz + kWaveRowsMax + 1) * 4 + kWaveRowsMax + 15) & ~15;
-  unsigned char* wbase = reinterpret_cast<unsigned char*>(gs + nbp) + wv * kWaveBytes;
-  float* prod = reinterpret_cast<float*>(wbase);
-  int32_t* rp = reinterpret_cast<int32_t*>(prod + NT * kWaveNnz);
-  uint8_t* sidl = reinterpret_cast<uint8_t*>(rp + kWaveRowsMax + 1);
+  const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  float* prod = gs + nbp + wv * (NT * kWaveNnz);
   __shared__ double red[kWaves];
 
   const int tid = threadIdx.x;
-  const bool solve = (a.mode == FWD_SOLVE);
-  const bool want_sid = (a.mode != FWD_PLAIN);
+  constexpr bool solve = (MODE == FWD_SOLVE);
+  constexpr bool want_sid = (MODE != FWD_PLAIN);
   int ntr = 1;
   bool direct = true;
   double lam[NT];
-  float* rout[NT];
   float* xout[NT];
+  rsrc_t rout[NT];
   const float* xk = a.x;
+  const uint32_t vbytes = 4u * static_cast<uint32_t>(a.nv);
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     lam[q] = 0.0;
-    rout[q] = nullptr;
     xout[q] = nullptr;
+    rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
   }
+  const rsrc_t dout = make_rsrc(a.d_out, a.d_out ? vbytes : 0u);
   if (solve) {
     const SolverState* st = a.st_in;
     constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
@@ -701,7 +863,7 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
+      rout[q] = make_rsrc(select_buf(a.rbuf, (acc + 1 + q) % (NT + 1)), vbytes);
       xout[q] = select_buf(a.xbuf, (xi + 1 + q) % (NT + 1));
     }
   }
@@ -710,22 +872,34 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   const int G = gridDim.x, w = blockIdx.x;
   const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
   const long long W = static_cast<long long>(G) * kWaves, gw = static_cast<long long>(lw) * kWaves + wv;
-  const int b0 = static_cast<int>(gw * a.nwblocks / W), b1 = static_cast<int>((gw + 1) * a.nwblocks / W);
+  const int b0 = uniform(static_cast<int>(gw * a.nwblocks / W));
+  const int b1 = uniform(static_cast<int>((gw + 1) * a.nwblocks / W));
+  // lane i holds the bounds of block mb + i (63 blocks per refill)
+  const rsrc_t mrow = make_rsrc(a.wblock_row, 4u * static_cast<uint32_t>(a.nwblocks + 1));
+  const rsrc_t mk0 = make_rsrc(a.wblock_k0, 4u * static_cast<uint32_t>(a.nwblocks + 1));
+  int mb = b0;
+  int lrow = load_i32(mrow, 4 * (mb + lane));
+  int lk0 = load_i32(mk0, 4 * (mb + lane));
   auto meta = [&](int b) {
-    BlockMeta m;
-    m.r0 = a.wblock_row[b];
-    m.r1 = a.wblock_row[b + 1];
-    m.k0 = a.wblock_k0[b];
-    m.k1 = a.wblock_k0[b + 1];
+    if (b - mb >= 63) {
+      mb = b;
+      lrow = load_i32(mrow, 4 * (mb + lane));
+      lk0 = load_i32(mk0, 4 * (mb + lane));
+    }
+    const int i = b - mb;
+    WaveBlock m;
+    m.r0 = __builtin_amdgcn_readlane(lrow, i);
+    m.r1 = __builtin_amdgcn_readlane(lrow, i + 1);
+    m.k0 = __builtin_amdgcn_readlane(lk0, i);
+    m.k1 = __builtin_amdgcn_readlane(lk0, i + 1);
     return m;
   };
-  VecRegs R;
-  WaveRows Q;
-  BlockMeta cur{0, 0, 0, 0}, nxt{0, 0, 0, 0};
+
+  WaveStage S;
+  WaveBlock cur{0, 0, 0, 0};
   if (b0 < b1) {
     cur = meta(b0);
-    if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
-    if (b0 + 1 < b1) nxt = meta(b0 + 1);
+    if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
   }
 
   stage_inputs<NT>(a, direct, solve && !direct && blockIdx.x == 0, xk, lam, xout, tab, xs, gs, red, want_sid);
@@ -735,94 +909,75 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   for (int q = 0; q < NT; ++q) pacc[q] = 0.0;
 
   for (int b = b0; b < b1; ++b) {
+    const WaveBlock blk = cur;
     const bool more = (b + 1 < b1);
-    if (cur.k1 - cur.k0 > kWavePartNnz) {
-      // a single row longer than a wave block: the wave strides over it
-      float s[NT];
+    if (more) cur = meta(b + 1);
+    if (blk.k1 - blk.k0 > kWavePartNnz) {
+      // one row longer than a wave block: the wave strides over it
+      float acc[NT];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) s[q] = 0.f;
-      for (int k = cur.k0 + lane; k < cur.k1; k += 64) {
-        const int c = a.col_idx[k];
-        const float v = a.val[k];
+      for (int q = 0; q < NT; ++q) acc[q] = 0.f;
+      for (int base = blk.k0 & ~3; base < blk.k1; base += 512) {
+        const uint32_t bytes = static_cast<uint32_t>((blk.k1 - base) * 4 + 15) & ~15u;
+        const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
+        const rsrc_t rv = make_rsrc(a.val + base, bytes);
 #pragma unroll
-        for (int q = 0; q < NT; ++q) s[q] = fmaf(v, xs[q * nbp + c], s[q]);
+        for (int j = 0; j < 2; ++j) {
+          const int4 c = load_i4(rc, 16 * lane + 1024 * j);
+          const float4 v = load_f4(rv, 16 * lane + 1024 * j);
+          const int e0 = base + 4 * lane + 256 * j;
+          const int cc[4] = {c.x, c.y, c.z, c.w};
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float t = vv[i] * xs[q * nbp + cc[i]];
+              acc[q] += (e0 + i >= blk.k0 && e0 + i < blk.k1) ? t : 0.0f;
+            }
+          }
+        }
       }
+      float d[NT];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) s[q] = wave_sum(s[q]);
-      if (lane == 0) row_epilogue<NT>(a, cur.r0, want_sid ? a.pen.sid[cur.r0] : 0, tab, s, pacc, rout, ntr);
-      if (more) {
-        cur = nxt;
-        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
-        if (b + 2 < b1) nxt = meta(b + 2);
+      for (int q = 0; q < NT; ++q) d[q] = wave_sum(acc[q]);
+      if (lane == 63) {
+        const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
+        row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pacc, rout, dout, ntr);
       }
+      if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
       continue;
     }
-    const int a0 = cur.k0 & ~3;
-    const int nr = cur.r1 - cur.r0;
-    // products and row data of this block into the wave's LDS region
+    // products of this block into the wave's LDS region (lanes past the
+    // block hold zeros and write slots that no row reads)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int off = 4 * (lane + 64 * j);
-      if (a0 + off < cur.k1) {
+      const int off = 4 * lane + 256 * j;
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          const float* xq = xs + q * nbp;
-          float4 p;
-          p.x = R.v[j].x * xq[R.c[j].x];
-          p.y = R.v[j].y * xq[R.c[j].y];
-          p.z = R.v[j].z * xq[R.c[j].z];
-          p.w = R.v[j].w * xq[R.c[j].w];
-          *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
-        }
+      for (int q = 0; q < NT; ++q) {
+        const float* xq = xs + q * nbp;
+        float4 p;
+        p.x = S.v[j].x * xq[S.c[j].x];
+        p.y = S.v[j].y * xq[S.c[j].y];
+        p.z = S.v[j].z * xq[S.c[j].z];
+        p.w = S.v[j].w * xq[S.c[j].w];
+        *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
       }
-    }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      const int i = lane + 64 * j;
-      if (i <= nr) rp[i] = Q.rp[j] - a0;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int i = lane + 64 * j;
-      if (i < nr) sidl[i] = Q.sid[j];
     }
     // LDS operations of one wave complete in order; the fence only keeps the
-    // compiler from moving the reads above the writes
+    // compiler from moving the row reads above the product writes
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const BlockMeta blk = cur;
-    if (more) {
-      cur = nxt;
-      if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue(a, cur, want_sid, lane, R, Q);
-      if (b + 2 < b1) nxt = meta(b + 2);
-    }
-    int L = 64;
-    while (L > 1 && L * nr > 64) L >>= 1;
-    const int sub = lane & (L - 1);
-    for (int row = lane / L; row < nr; row += 64 / L) {
-      const int s0 = rp[row], s1 = rp[row + 1];
-      float s[NT];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) s[q] = 0.f;
-      for (int k = s0 + sub; k < s1; k += 4 * L) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          const float* pq = prod + q * kWaveNnz;
-          float v[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int kk = k + u * L;
-            const float t = pq[kk < kWaveNnz ? kk : kWaveNnz - 1];
-            v[u] = (kk < s1) ? t : 0.0f;
-          }
-          s[q] += (v[0] + v[1]) + (v[2] + v[3]);
-        }
-      }
-      for (int off = L >> 1; off > 0; off >>= 1) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) s[q] += __shfl_xor(s[q], off, 64);
-      }
-      if (sub == 0) row_epilogue<NT>(a, blk.r0 + row, sidl[row], tab, s, pacc, rout, ntr);
+    const WaveStage R = S;   // this block's row pointers and ids (loads already waited on)
+    if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+    switch (log2_lanes(blk.r1 - blk.r0)) {
+      case 0: wave_rows<1, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      case 1: wave_rows<2, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      case 2: wave_rows<4, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      case 3: wave_rows<8, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      case 4: wave_rows<16, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      case 5: wave_rows<32, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
+      default: wave_rows<64, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
     }
     // the next block's LDS writes must not overtake this block's reads
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -837,43 +992,71 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
 }
 
 // ---- adjoint pass ----------------------------------------------------------------
-// Residual gathers for the nonzeros of R: all eight are issued together
-// (every index held in R is a valid row: a real entry or the zeroed tail).
-struct GatherRegs {
-  float r[8];
+// Workgroup w owns nonzeros [k0w, k1w) of the CSC arrays and walks them in
+// rounds of 2048 (eight per thread: two 16-byte loads each of row indices and
+// values, lanes past the range read zeros).  A round's residual gathers are
+// issued before the next round's loads, which go to the other of two register
+// stages, so one round is always in flight.  A round inside one column adds
+// all its products; a round that meets a column boundary adds each column's
+// share under a mask and closes every column that ends in it.
+struct AdjStage {
+  int4 c[2];
+  float4 v[2];
 };
 
-__device__ __forceinline__ void adj_gather(const VecRegs& R, const float* r, GatherRegs& Gr) {
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    Gr.r[4 * j + 0] = r[R.c[j].x];
-    Gr.r[4 * j + 1] = r[R.c[j].y];
-    Gr.r[4 * j + 2] = r[R.c[j].z];
-    Gr.r[4 * j + 3] = r[R.c[j].w];
-  }
-}
-
-// Fixed-order float64 sum of val * r over this thread's nonzeros of the
-// round starting at `base`, counting only [k0, k1).
-__device__ __forceinline__ double adj_accumulate(const VecRegs& R, const GatherRegs& Gr, int base, int k0,
-                                                 int k1) {
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int e0 = base + 4 * (threadIdx.x + j * kThreads);
-    const float vv[4] = {R.v[j].x, R.v[j].y, R.v[j].z, R.v[j].w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const bool in = (e0 + i >= k0) && (e0 + i < k1);
-      s += static_cast<double>(in ? vv[i] : 0.0f) * static_cast<double>(Gr.r[4 * j + i]);
-    }
-  }
-  return s;
-}
+constexpr int kAdjStep = 8 * kThreads;   // nonzeros per round
 
 __device__ __forceinline__ int logical_wg() {
   const int G = gridDim.x, w = blockIdx.x;
   return (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
+}
+
+__device__ __forceinline__ void adj_issue(rsrc_t ri, rsrc_t rv, int round, AdjStage& S) {
+  const uint32_t t = 16u * threadIdx.x;
+  const uint32_t base = static_cast<uint32_t>(round) * (kAdjStep * 4u);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    S.c[j] = load_i4(ri, base + t + 4096u * j);
+    S.v[j] = load_f4(rv, base + t + 4096u * j);
+  }
+}
+
+__device__ __forceinline__ void adj_gather(rsrc_t rr, const AdjStage& S, float (&g)[8]) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    g[4 * j + 0] = load_f32(rr, 4u * S.c[j].x);
+    g[4 * j + 1] = load_f32(rr, 4u * S.c[j].y);
+    g[4 * j + 2] = load_f32(rr, 4u * S.c[j].z);
+    g[4 * j + 3] = load_f32(rr, 4u * S.c[j].w);
+  }
+}
+
+// Float64 sum of this thread's eight products, in element order.
+__device__ __forceinline__ double adj_dot(const AdjStage& S, const float (&g)[8]) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s += static_cast<double>(vv[i]) * static_cast<double>(g[4 * j + i]);
+  }
+  return s;
+}
+
+// The same over the elements with index in [lo, hi) (first element e0).
+__device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float (&g)[8], int e0, int lo, int hi) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = e0 + 1024 * j + i;
+      const float r = (e >= lo && e < hi) ? g[4 * j + i] : 0.0f;
+      s += static_cast<double>(vv[i]) * static_cast<double>(r);
+    }
+  }
+  return s;
 }
 
 // Adjoint pass: in a solve, first the decision on the preceding forward pass
@@ -885,17 +1068,17 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   __shared__ Decision dec;
   const int tid = threadIdx.x;
   const int lw = logical_wg();
-  const int64_t k0w = static_cast<int64_t>(lw) * a.nnz / a.grid;
-  const int64_t k1w = static_cast<int64_t>(lw + 1) * a.nnz / a.grid;
-  const int c0 = a.wg_c0[lw], c1 = a.wg_c1[lw];
-  // the first column's first loads do not depend on the decision
-  VecRegs cur, nxt;
-  int s0 = 0, s1 = 0;
-  if (c0 < c1) {
-    s0 = static_cast<int>(max(k0w, static_cast<int64_t>(a.col_ptr[c0])));
-    s1 = static_cast<int>(min(k1w, static_cast<int64_t>(a.col_ptr[c0 + 1])));
-    issue_vec(a.row_idx, a.val, s0 & ~3, s1, cur);
-  }
+  const int k0w = static_cast<int>(static_cast<int64_t>(lw) * a.nnz / a.grid);
+  const int k1w = static_cast<int>(static_cast<int64_t>(lw + 1) * a.nnz / a.grid);
+  const int c0 = uniform(a.wg_c0[lw]), c1 = uniform(a.wg_c1[lw]);
+  const int kb = k0w & ~3;
+  const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
+  const uint32_t bytes = static_cast<uint32_t>((k1w - kb) * 4 + 15) & ~15u;
+  const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
+  const rsrc_t rv = make_rsrc(a.val + kb, bytes);
+  // the first round's loads do not depend on the decision
+  AdjStage A, B;
+  if (nrounds > 0) adj_issue(ri, rv, 0, A);
   const float* r = a.r;
   if (a.solve) {
     decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, dec, red);
@@ -914,34 +1097,57 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
     if (dec.st.phase != PH_NEED_GRAD) return;
     r = select_buf(a.rbuf, dec.st.acc);
   }
-  constexpr int kStep = 8 * kThreads;   // nonzeros covered by one round of loads
-  for (int c = c0; c < c1; ++c) {
-    if (c > c0) {
-      s0 = static_cast<int>(max(k0w, static_cast<int64_t>(a.col_ptr[c])));
-      s1 = static_cast<int>(min(k1w, static_cast<int64_t>(a.col_ptr[c + 1])));
-      issue_vec(a.row_idx, a.val, s0 & ~3, s1, cur);
-    }
-    double s = 0.0;
-    for (int base = s0 & ~3; base < s1; base += kStep) {
-      // gathers of this round first, then the next round's loads, so that
-      // waiting for the gathers does not wait for the prefetch
-      GatherRegs Gr;
-      adj_gather(cur, r, Gr);
-      issue_vec(a.row_idx, a.val, base + kStep, s1, nxt);   // past the end: first vector only
-      s += adj_accumulate(cur, Gr, base, s0, s1);
-      cur = nxt;
-    }
-    s = block_sum(s, red);
+  const rsrc_t rr = make_rsrc(r, 4u * static_cast<uint32_t>(a.nv));
+
+  int c = c0, lo = 0, hi = 0;
+  auto bounds = [&]() {
+    lo = max(uniform(a.col_ptr[c]), k0w);
+    hi = min(uniform(a.col_ptr[c + 1]), k1w);
+  };
+  if (c < c1) bounds();
+  double s = 0.0;
+  auto close = [&]() {
+    const double t = block_sum(s, red);
     if (tid == 0) {
       const int wlo = a.col_wlo[c], whi = a.col_whi[c];
       if (wlo == whi) {
-        a.out[c] = static_cast<float>(a.scale * s);
+        a.out[c] = static_cast<float>(a.scale * t);
       } else {
-        if (c == c0) a.pieces[2 * lw] = s;
-        if (c == c1 - 1) a.pieces[2 * lw + 1] = s;
+        if (c == c0) a.pieces[2 * lw] = t;
+        if (c == c1 - 1) a.pieces[2 * lw + 1] = t;
       }
     }
+    s = 0.0;
+    ++c;
+    if (c < c1) bounds();
+  };
+  int round = 0;
+  auto step = [&](const AdjStage& cur, AdjStage& nxt) {
+    float g[8];
+    adj_gather(rr, cur, g);
+    if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+    const int base = kb + round * kAdjStep, end = base + kAdjStep;
+    while (c < c1 && lo < end) {
+      if (lo <= base && hi >= end) {
+        s += adj_dot(cur, g);
+        if (hi == end) close();
+        break;
+      }
+      s += adj_dot_masked(cur, g, base + 4 * tid, lo, hi);
+      if (hi > end) break;
+      close();
+    }
+    ++round;
+    return round < nrounds;
+  };
+  if (nrounds > 0) {
+    for (;;) {
+      if (!step(A, B)) break;
+      if (!step(B, A)) break;
+    }
   }
+  // empty columns at the end of the range
+  while (c < c1) close();
 }
 
 // Columns shared by several adjoint workgroups (completion not folded): the
@@ -1026,9 +1232,7 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
                  (static_cast<size_t>(ntrials) * nbp + nbp) * sizeof(float);
   if (wave) {
-    const size_t per_wave = ((static_cast<size_t>(ntrials) * kWaveNnz + kWaveRowsMax + 1) * 4 + kWaveRowsMax + 15) &
-                            ~static_cast<size_t>(15);
-    bytes += kWaves * per_wave;
+    bytes += (static_cast<size_t>(kWaves) * ntrials * kWaveNnz + kWaveSlack) * sizeof(float);
   } else {
     bytes += static_cast<size_t>(ntrials) * kFwdNnzMax * sizeof(float) +
              static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
@@ -1059,11 +1263,20 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
   if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
   if (wave) {
-    switch (ntrials) {
-      case 1: hipLaunchKernelGGL(fwd_wave_kernel<1>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-      case 2: hipLaunchKernelGGL(fwd_wave_kernel<2>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-      case 4: hipLaunchKernelGGL(fwd_wave_kernel<4>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-      default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+    const dim3 gd(grid), bd(kThreads);
+    if (a.mode == FWD_SOLVE) {
+      switch (ntrials) {
+        case 1: hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
+        case 2: hipLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
+        case 4: hipLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
+        default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+      }
+    } else if (ntrials != 1) {
+      return set_error(IMRT_EINVAL, "evaluation passes take one trial");
+    } else if (a.mode == FWD_EVAL) {
+      hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL>), gd, bd, lds, ctx->stream, a);
+    } else {
+      hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN>), gd, bd, lds, ctx->stream, a);
     }
   } else {
     switch (ntrials) {
