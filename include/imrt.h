@@ -123,10 +123,9 @@ typedef struct {
   double G_initial;       /* G(x_1) */
   double G_final;         /* G at the returned x */
   double device_ms;       /* stream time of the solve, HIP events */
-  /* With params.profile: mean HIP-event duration of a forward pass launch
-   * and of an adjoint pass launch (its completion kernel included) over the
-   * timed launches among those that did work (the first forward_passes and
-   * adjoint_passes launches), else 0. */
+  /* With params.profile: mean HIP-event duration of a forward pass kernel
+   * and of an adjoint pass kernel over the timed launches among those that
+   * did work (the first forward_passes and adjoint_passes launches), else 0. */
   double forward_kernel_ms;
   double adjoint_kernel_ms;
 } imrt_solve_result;
@@ -149,10 +148,6 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
- *   "fold"           1: in a solve, beamlet columns shared by several
- *                    adjoint workgroups are completed by the next forward
- *                    pass while it stages the gradient; 0: by a separate
- *                    kernel after each adjoint pass
  * "adj_wg_per_cu" and "adj_min_nnz" are read when a dose matrix is created.
  * Results are deterministic for given settings; the settings change only the
  * grouping of the float64 partial sums of G and of shared columns.

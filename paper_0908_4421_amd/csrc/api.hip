@@ -172,11 +172,6 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
       (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->pieces, 2 * static_cast<size_t>(G))))
     return rc;
-  std::vector<int4> shared;
-  for (int c = 0; c < D->nb; ++c)
-    if (col_wlo[c] != col_whi[c]) shared.push_back(make_int4(c, col_wlo[c], col_whi[c], 0));
-  D->nshared = static_cast<int32_t>(shared.size());
-  if ((rc = dev_alloc(&D->shared_cols, shared.size()))) return rc;
   hipStream_t s = D->ctx->stream;
   IMRT_HIP(hipMemcpyAsync(D->block_row, blocks.data(), sizeof(int32_t) * blocks.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->block_k0, block_k0.data(), sizeof(int32_t) * block_k0.size(), hipMemcpyHostToDevice, s));
@@ -187,8 +182,6 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   IMRT_HIP(hipMemcpyAsync(D->wg_c1, wg_c1.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_whi, col_whi.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
-  if (!shared.empty())
-    IMRT_HIP(hipMemcpyAsync(D->shared_cols, shared.data(), sizeof(int4) * shared.size(), hipMemcpyHostToDevice, s));
   D->fwd_cap = forward_grid_cap(D->ctx, D);
   D->partials_len = kMaxTrials * (D->fwd_cap + 1) + 16;
   if ((rc = dev_alloc(&D->partials, D->partials_len))) return rc;
@@ -219,7 +212,6 @@ void free_dose(imrt_dose* D) {
   dev_free(D->wg_c1);
   dev_free(D->col_wlo);
   dev_free(D->col_whi);
-  dev_free(D->shared_cols);
   dev_free(D->pieces);
   dev_free(D->sid);
   dev_free(D->partials);
@@ -236,6 +228,8 @@ void free_plan(imrt_plan* P) {
   for (auto& b : P->rbuf) dev_free(b);
   for (auto& b : P->xbuf) dev_free(b);
   dev_free(P->gk);
+  dev_free(P->xstage);
+  dev_free(P->step_partials);
   dev_free(P->vtmp);
   dev_free(P->fwd_partials);
   dev_free(P->pieces);
@@ -319,7 +313,6 @@ AdjArgs base_adj(const imrt_dose* D) {
   a.nv = D->nv;
   a.nb = D->nb;
   a.grid = D->adj_grid;
-  a.fold = 0;
   return a;
 }
 
@@ -365,7 +358,6 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.adj_grid_per_cu = env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu);
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
-  if (const char* f = std::getenv("IMRT_FOLD")) c->tune.fold = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
@@ -401,10 +393,6 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.fwd_wave;
   }
-  if (n == "fold") {
-    *lo = 0;
-    return &ctx->tune.fold;
-  }
   return nullptr;
 }
 }  // namespace
@@ -415,7 +403,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fold" || nm == "fwd_wave") ? 1 : (int64_t(1) << 30);
+  const int64_t hi = (nm == "fwd_wave") ? 1 : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
   return IMRT_OK;
@@ -593,6 +581,8 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
   P->fwd_cap = grid;
   if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
       (rc = ensure_buffers(P, 2)) || (rc = dev_alloc(&P->gk, dose->nb)) || (rc = dev_alloc(&P->vtmp, dose->nv)) ||
+      (rc = dev_alloc(&P->xstage, static_cast<size_t>(kMaxTrials) * pad4(dose->nb))) ||
+      (rc = dev_alloc(&P->step_partials, static_cast<size_t>(kMaxTrials) * step_grid(dose->nb))) ||
       (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
       (rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(dose->adj_grid))) || (rc = dev_alloc(&P->misc, 16)) ||
       (rc = dev_alloc(&P->st, 2))) {
@@ -858,6 +848,10 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   if (e == hipSuccess) e = hipMemcpyAsync(P->st, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->st + 1, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->xbuf[0], x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
+  // the initial evaluation multiplies by x_1 in every trial row
+  for (int q = 0; q < nt && e == hipSuccess; ++q)
+    e = hipMemcpyAsync(P->xstage + static_cast<size_t>(q) * pad4(D->nb), x_dev, sizeof(float) * D->nb,
+                       hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) {
     cleanup();
     return hip_error(e, "solve setup");
@@ -867,28 +861,30 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   FwdArgs fa = base_fwd(D);
   fa.mode = FWD_SOLVE;
   set_plan_penalties(fa, P);
-  fa.g = P->gk;
-  for (int i = 0; i <= kMaxTrials; ++i) {
-    fa.xbuf[i] = P->xbuf[i];
-    fa.rbuf[i] = P->rbuf[i];
-  }
+  fa.x = P->xstage;
+  for (int i = 0; i <= kMaxTrials; ++i) fa.rbuf[i] = P->rbuf[i];
   fa.partials = P->fwd_partials;
-  if (C->tune.fold) {
-    fa.shared_cols = D->nshared > 0 ? D->shared_cols : nullptr;
-    fa.nshared = D->nshared;
-    fa.g_scale = 2.0;
-    fa.pieces = P->pieces;
-  }
   AdjArgs aa = base_adj(D);
   aa.solve = 1;
   for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
   aa.pieces = P->pieces;
-  aa.fold = C->tune.fold;
   aa.out = P->gk;
   aa.scale = 2.0;
   aa.fwd_partials = P->fwd_partials;
   aa.fwd_parts = grid;
+  aa.step_partials = P->step_partials;
+  aa.step_parts = step_grid(D->nb);
   aa.trace = cap > 0 ? P->trace : nullptr;
+  StepArgs sa{};
+  sa.col_wlo = D->col_wlo;
+  sa.col_whi = D->col_whi;
+  sa.pieces = P->pieces;
+  sa.g = P->gk;
+  sa.scale = 2.0;
+  for (int i = 0; i <= kMaxTrials; ++i) sa.xbuf[i] = P->xbuf[i];
+  sa.xstage = P->xstage;
+  sa.step_partials = P->step_partials;
+  sa.nb = D->nb;
 
   // The two state copies alternate: pass n reads st[n % 2] and writes st[(n + 1) % 2].
   long long pass = 0;
@@ -910,9 +906,13 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     if (r != hipSuccess) return hip_error(r, "hipEventCreate");
     aa.st_in = state_in();
     aa.st_out = state_out();
-    const int rr = launch_adjoint(C, D, aa, nt, a0, a1);
+    int rr = launch_adjoint(C, D, aa, nt, a0, a1);
     ++pass;
-    return rr;
+    if (rr) return rr;
+    // gradient completion and trial points for the next forward pass, from
+    // the state the adjoint pass wrote (the forward pass reads it too)
+    sa.st = state_in();
+    return launch_step(C, sa, nt);
   };
 
   // initial evaluation G(x_1)

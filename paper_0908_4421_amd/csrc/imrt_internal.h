@@ -85,21 +85,13 @@ struct FwdArgs {
   int32_t nwblocks;
   int32_t nstruct;
   Penalties pen;
-  const float* x;            // eval/plain input vector
-  const float* g;            // solve: g_k
-  float* xbuf[kMaxTrials + 1];  // solve: iterate buffers (x_k = xbuf[st->xi])
+  const float* x;            // eval/plain input vector; solve: trial vectors [trial][pad4(nb)]
   float* rbuf[kMaxTrials + 1];  // solve: residual buffers (r(x_k) = rbuf[st->acc])
   float* d_out;              // eval/plain: dose (nullable in eval)
   float* r_out;              // eval: residual (nullable)
-  double* partials;          // [trial][gridDim.x] objective partials, then [trial] step norms
+  double* partials;          // [trial][gridDim.x] objective partials
   const SolverState* st_in;  // solve: state before this pass
   SolverState* st_out;       // solve: state after it (copied through by workgroup 0)
-  // solve with folded completion: gradient entries of columns shared by
-  // several adjoint workgroups are completed here from the adjoint pieces
-  const int4* shared_cols;   // (column, wlo, whi, 0)
-  int32_t nshared;
-  double g_scale;
-  const double* pieces;
 };
 
 // Adjoint work partition: workgroup w owns nonzeros [w*nnz/G, (w+1)*nnz/G)
@@ -118,27 +110,43 @@ struct AdjArgs {
   int64_t nnz;
   int32_t nv, nb, grid;
   int32_t solve;             // decide the previous forward pass first; r from rbuf
-  int32_t fold;              // shared columns completed by the next forward pass (else adj_final)
   const float* r;
   float* rbuf[kMaxTrials + 1];
   double* pieces;            // 2 * grid
   float* out;
   double scale;
   // solve: line-search decision on the previous forward pass
-  const double* fwd_partials;
+  const double* fwd_partials;   // [trial][fwd_parts]
   int32_t fwd_parts;
+  const double* step_partials;  // [trial][step_parts] step norms ||x_t - x_k||^2
+  int32_t step_parts;
   const SolverState* st_in;
   SolverState* st_out;
   TraceDev* trace;
 };
 
+// Between an adjoint pass and the next forward pass of a solve: gradient
+// entries of shared columns completed from the adjoint pieces, then the trial
+// points x_t^(q) = max(0, x_k - lambda_q g) and their step norms.
+struct StepArgs {
+  const SolverState* st;     // state after the adjoint pass (read by the next forward pass too)
+  const int32_t* col_wlo;
+  const int32_t* col_whi;
+  const double* pieces;
+  float* g;                  // gradient: complete for unshared columns, completed here for shared ones
+  double scale;
+  float* xbuf[kMaxTrials + 1];  // iterate buffers; trial q goes to xbuf[(xi + 1 + q) % (NT + 1)]
+  float* xstage;             // trial vectors for the forward pass, [trial][pad4(nb)]
+  double* step_partials;     // [trial][gridDim.x]
+  int32_t nb;
+};
+
 // ---- host-side objects ------------------------------------------------------------
 struct Tuning {
   int fwd_grid_per_cu = 4;
-  int adj_grid_per_cu = 8;
+  int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
-  int fold = 1;                // solve: shared adjoint columns completed by the next forward pass
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
 
@@ -176,8 +184,6 @@ struct imrt_dose {
   int32_t* wg_c1 = nullptr;
   int32_t* col_wlo = nullptr;
   int32_t* col_whi = nullptr;
-  int4* shared_cols = nullptr; // (column, wlo, whi, 0) of columns shared by several adjoint workgroups
-  int32_t nshared = 0;
   double* pieces = nullptr;
   // structure ids from the phantom builder (nullable)
   uint8_t* sid = nullptr;
@@ -202,6 +208,8 @@ struct imrt_plan {
   float* rbuf[imrt::kMaxTrials + 1] = {};
   float* xbuf[imrt::kMaxTrials + 1] = {};
   float* gk = nullptr;
+  float* xstage = nullptr;        // kMaxTrials * pad4(nb) trial vectors of the next forward pass
+  double* step_partials = nullptr;  // kMaxTrials * step grid
   float* vtmp = nullptr;          // nv scratch
   double* fwd_partials = nullptr; // kMaxTrials * (fwd_cap + 1)
   int32_t fwd_cap = 1;
@@ -235,6 +243,8 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+int step_grid(int nb);
+int launch_step(const imrt_ctx* ctx, const StepArgs& a, int ntrials);
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);

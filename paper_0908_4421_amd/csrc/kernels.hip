@@ -1,15 +1,17 @@
 // Hot-path kernels of the gradient-projection / Armijo solver for gfx950.
 //
-//  fwd_kernel   trial update + projection (steps 2 and 4) staged in LDS,
-//               forward dose z = D x over CSR (Section 2.1), penalty residual
-//               and objective partials (Eqs. (1)-(2)), in one pass over D.
+//  fwd_kernel / fwd_wave_kernel
+//               trial vectors staged in LDS, forward dose z = D x over CSR
+//               (Section 2.1), penalty residual and objective partials
+//               (Eqs. (1)-(2)), in one pass over D.
 //  adj_kernel   line-search decision on the preceding forward pass (Armijo
 //               test of Eq. (5), stopping test of step 5), taken identically
 //               by every workgroup, then the beamlet-parallel adjoint
 //               g = 2 D^T r over CSC for an accepted, unfinished iterate.
-//  adj_final    completes beamlet columns shared by several adjoint
-//               workgroups (outside a solve, or with the completion not
-//               folded into the next forward pass).
+//  step_kernel  between the adjoint and the forward pass of a solve:
+//               completes beamlet columns shared by several adjoint
+//               workgroups and writes the trial points and step norms.
+//  adj_final    completes shared columns outside a solve.
 //
 // The solver state is double-buffered: a pass reads one copy and workgroup 0
 // writes the other, so no workgroup ever sees a state written during its own
@@ -222,39 +224,41 @@ struct Decision {
 };
 
 template <int NT>
-__device__ void decide(const SolverState* in, const double* partials, int nparts, Decision& dec, double* red) {
+__device__ void decide(const SolverState* in, const double* partials, int nparts, const double* steps, int nsteps,
+                       Decision& dec, double* red) {
 #pragma clang fp contract(off)
   __shared__ double Gq[NT];
   const int tid = threadIdx.x;
+  // the partial loads do not depend on the state: all are issued at once
+  double s[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    // four independent loads per round, summed in index order
+    s[q] = 0.0;
+    const double* pq = partials + q * nparts;
+    for (int i0 = tid; i0 < nparts; i0 += 4 * kThreads) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kThreads;
+        v[u] = pq[i < nparts ? i : 0];
+        v[u] = (i < nparts) ? v[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[q] += v[u];
+    }
+  }
   if (tid == 0) {
     dec.st = *in;
     dec.accepted = -1;
   }
-  __syncthreads();
-  if (dec.st.phase == PH_DONE) return;
-  const bool init = (dec.st.phase == PH_INIT);
-  const int ntr = init ? 1 : NT;
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    if (q < ntr) {
-      // four independent loads per round, summed in index order
-      double s = 0.0;
-      const double* pq = partials + q * nparts;
-      for (int i0 = tid; i0 < nparts; i0 += 4 * kThreads) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + u * kThreads;
-          v[u] = pq[i < nparts ? i : 0];
-          v[u] = (i < nparts) ? v[u] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s += v[u];
-      }
-      s = block_sum(s, red);
-      if (tid == 0) Gq[q] = s;
-    }
+    const double t = block_sum(s[q], red);
+    if (tid == 0) Gq[q] = t;
   }
+  if (dec.st.phase == PH_DONE) return;
+  const bool init = (dec.st.phase == PH_INIT);
   if (tid == 0) {
     SolverState st = dec.st;
     st.n_fwd += 1;
@@ -276,7 +280,12 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
         st.phase = PH_NEED_GRAD;
       }
     } else {
-      const double* sq = partials + NT * nparts;
+      double sq[NT];
+      for (int q = 0; q < NT; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < nsteps; ++w) t += steps[q * nsteps + w];
+        sq[q] = t;
+      }
       bool done = false;
       int accepted = -1;
       double l = st.lambda;
@@ -439,95 +448,41 @@ __device__ __forceinline__ void fwd_products(const BlockMeta& m, const VecRegs& 
   }
 }
 
-// Stage the inputs of a forward pass in LDS: the penalty table, the gradient
-// (completing shared adjoint columns from their pieces) and the NT trial
-// vectors x_t^(q) = max(0, x_k - lambda_q g_k), or x itself for a direct
-// pass.  The lead workgroup also stores the trials and their step norms.
-// Ends with a workgroup barrier.
+// Stage the inputs of a forward pass in LDS: the penalty table and the NT
+// vectors the pass multiplies by (row q of `src`, stride pad4(nb)).  All
+// loads are issued before any is used.  Ends with a workgroup barrier.
 template <int NT>
-__device__ __forceinline__ void stage_inputs(const FwdArgs& a, bool direct, bool lead, const float* xk,
-                                             const double (&lam)[NT], float* const (&xout)[NT],
-                                             PenaltyDev* tab, float* xs, float* gs, double* red,
+__device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src, PenaltyDev* tab, float* xs,
                                              bool want_sid) {
   const int tid = threadIdx.x;
   const int nb = a.nb;
   const int nbp = pad4(nb);
   if (want_sid) {
-    const double* src = reinterpret_cast<const double*>(a.pen.table);
+    const double* tsrc = reinterpret_cast<const double*>(a.pen.table);
     double* dst = reinterpret_cast<double*>(tab);
-    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = src[i];
+    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = tsrc[i];
   }
-  constexpr int kU = 8;   // vector entries loaded per thread per round
-  if (!direct) {
-    // gradient of x_k; columns shared by several adjoint workgroups are
-    // completed from their pieces in workgroup order
-    for (int i0 = tid; i0 < nb; i0 += kU * kThreads) {
-      float v[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int i = i0 + u * kThreads;
-        v[u] = a.g[i < nb ? i : 0];
-      }
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int i = i0 + u * kThreads;
-        if (i < nb) gs[i] = v[u];
-      }
-    }
-    if (a.shared_cols != nullptr) {
-      __syncthreads();
-      for (int e = tid; e < a.nshared; e += kThreads) {
-        const int4 sc = a.shared_cols[e];
-        double tot = a.pieces[2 * sc.y + 1];
-        for (int w = sc.y + 1; w < sc.z; ++w) tot += a.pieces[2 * w];
-        tot += a.pieces[2 * sc.z];
-        gs[sc.x] = static_cast<float>(a.g_scale * tot);
-      }
-    }
-    __syncthreads();
-  }
-  double sq[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
+  constexpr int kU = 8;   // entries loaded per thread per round and vector
   for (int i0 = tid; i0 < nb; i0 += kU * kThreads) {
-    float xv[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * kThreads;
-      xv[u] = xk[i < nb ? i : 0];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = i0 + u * kThreads;
-      if (i < nb) {
-        if (direct) {
-#pragma unroll
-          for (int q = 0; q < NT; ++q) xs[q * nbp + i] = xv[u];
-        } else {
-          const float gi = gs[i];
-#pragma unroll
-          for (int q = 0; q < NT; ++q) {
-            const float t = trial_point(xv[u], gi, lam[q]);
-            xs[q * nbp + i] = t;
-            if (lead) {
-              xout[q][i] = t;
-              const double dl = static_cast<double>(t) - static_cast<double>(xv[u]);
-              sq[q] += dl * dl;
-            }
-          }
-        }
-      }
-    }
-  }
-  if (lead) {
+    float v[NT][kU];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      const double t = block_sum(sq[q], red);
-      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kThreads;
+        v[q][u] = src[q * nbp + (i < nb ? i : 0)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kThreads;
+        if (i < nb) xs[q * nbp + i] = v[q][u];
+      }
     }
   }
   __syncthreads();
-
 }
 
 // Forward pass.  Each workgroup stages the NT trial vectors
@@ -544,8 +499,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
   const int nbp = pad4(nb);
   PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
   float* xs = reinterpret_cast<float*>(tab + a.nstruct);
-  float* gs = xs + NT * nbp;
-  float* prod = gs + nbp;
+  float* prod = xs + NT * nbp;
   int32_t* rp = reinterpret_cast<int32_t*>(prod + NT * kFwdNnzMax);
   uint8_t* sidl = reinterpret_cast<uint8_t*>(rp + kFwdRowsMax + 1);
   __shared__ double red[kWaves];
@@ -555,17 +509,9 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
   const bool solve = (a.mode == FWD_SOLVE);
   const bool want_sid = (a.mode != FWD_PLAIN);
   int ntr = 1;
-  bool direct = true;
-  double lam[NT];
   float* rout[NT];
-  float* xout[NT];
-  const float* xk = a.x;
 #pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    lam[q] = 0.0;
-    rout[q] = nullptr;
-    xout[q] = nullptr;
-  }
+  for (int q = 0; q < NT; ++q) rout[q] = nullptr;
   if (solve) {
     const SolverState* st = a.st_in;
     // the state passes through unchanged (word copy by workgroup 0)
@@ -574,19 +520,10 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
       reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
     const int phase = st->phase;
     if (phase == PH_DONE) return;
-    direct = (phase == PH_INIT);
-    ntr = direct ? 1 : NT;
-    const int xi = st->xi, acc = st->acc;
-    xk = select_buf(a.xbuf, xi);
-    lam[0] = st->lambda;
-    const double alpha = st->alpha;
+    ntr = (phase == PH_INIT) ? 1 : NT;
+    const int acc = st->acc;
 #pragma unroll
-    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
-      xout[q] = select_buf(a.xbuf, (xi + 1 + q) % (NT + 1));
-    }
+    for (int q = 0; q < NT; ++q) rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
   }
 
   int b0, b1;
@@ -604,7 +541,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     if (b0 + 1 < b1) nxt = block_meta(a, b0 + 1);
   }
 
-  stage_inputs<NT>(a, direct, solve && !direct && blockIdx.x == 0, xk, lam, xout, tab, xs, gs, red, want_sid);
+  stage_inputs<NT>(a, a.x, tab, xs, want_sid);
 
   double pacc[NT];
 #pragma unroll
@@ -824,27 +761,18 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   const int nbp = pad4(nb);
   PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
   float* xs = reinterpret_cast<float*>(tab + a.nstruct);
-  float* gs = xs + NT * nbp;
   const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  float* prod = gs + nbp + wv * (NT * kWaveNnz);
+  float* prod = xs + NT * nbp + wv * (NT * kWaveNnz);
   __shared__ double red[kWaves];
 
   const int tid = threadIdx.x;
   constexpr bool solve = (MODE == FWD_SOLVE);
   constexpr bool want_sid = (MODE != FWD_PLAIN);
   int ntr = 1;
-  bool direct = true;
-  double lam[NT];
-  float* xout[NT];
   rsrc_t rout[NT];
-  const float* xk = a.x;
   const uint32_t vbytes = 4u * static_cast<uint32_t>(a.nv);
 #pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    lam[q] = 0.0;
-    xout[q] = nullptr;
-    rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
-  }
+  for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
   const rsrc_t dout = make_rsrc(a.d_out, a.d_out ? vbytes : 0u);
   if (solve) {
     const SolverState* st = a.st_in;
@@ -853,19 +781,10 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
       reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
     const int phase = st->phase;
     if (phase == PH_DONE) return;
-    direct = (phase == PH_INIT);
-    ntr = direct ? 1 : NT;
-    const int xi = st->xi, acc = st->acc;
-    xk = select_buf(a.xbuf, xi);
-    lam[0] = st->lambda;
-    const double alpha = st->alpha;
+    ntr = (phase == PH_INIT) ? 1 : NT;
+    const int acc = st->acc;
 #pragma unroll
-    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      rout[q] = make_rsrc(select_buf(a.rbuf, (acc + 1 + q) % (NT + 1)), vbytes);
-      xout[q] = select_buf(a.xbuf, (xi + 1 + q) % (NT + 1));
-    }
+    for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(select_buf(a.rbuf, (acc + 1 + q) % (NT + 1)), vbytes);
   }
 
   // this wave's contiguous range of row blocks
@@ -902,7 +821,7 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
   }
 
-  stage_inputs<NT>(a, direct, solve && !direct && blockIdx.x == 0, xk, lam, xout, tab, xs, gs, red, want_sid);
+  stage_inputs<NT>(a, a.x, tab, xs, want_sid);
 
   double pacc[NT];
 #pragma unroll
@@ -1081,7 +1000,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   if (nrounds > 0) adj_issue(ri, rv, 0, A);
   const float* r = a.r;
   if (a.solve) {
-    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, dec, red);
+    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, dec, red);
     if (blockIdx.x == 0 && tid == 0) {
       *a.st_out = dec.st;
       if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
@@ -1165,6 +1084,52 @@ __global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const So
   a.out[c] = static_cast<float>(a.scale * tot);
 }
 
+// Step kernel of a solve, between the adjoint pass and the next forward pass
+// (steps 2 and 4): for a fresh gradient, the entries of columns shared by
+// several adjoint workgroups are completed (fixed-order sum of the pieces);
+// then every trial point x_t^(q) = max(0, x_k - lambda_q g) is written to its
+// iterate buffer and to the forward pass's staging rows, with per-workgroup
+// partial sums of ||x_t^(q) - x_k||^2.  Idle unless the state asks for a
+// trial pass.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
+  __shared__ double red[kWaves];
+  const SolverState* st = a.st;
+  const int phase = st->phase;
+  if (phase != PH_NEED_GRAD && phase != PH_TRIAL) return;
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  const bool in = c < a.nb;
+  const int cc = in ? c : 0;
+  const int xi = st->xi;
+  const float x = select_buf(a.xbuf, xi)[cc];
+  float g = a.g[cc];
+  if (phase == PH_NEED_GRAD && in) {
+    const int wlo = a.col_wlo[c], whi = a.col_whi[c];
+    if (wlo != whi) {
+      double tot = a.pieces[2 * wlo + 1];
+      for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
+      tot += a.pieces[2 * whi];
+      g = static_cast<float>(a.scale * tot);
+      a.g[c] = g;
+    }
+  }
+  const int nbp = pad4(a.nb);
+  double lam = st->lambda;
+  const double alpha = st->alpha;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    if (q > 0) lam = lam / alpha;
+    const float t = trial_point(x, g, lam);
+    if (in) {
+      select_buf(a.xbuf, (xi + 1 + q) % (NT + 1))[c] = t;
+      a.xstage[q * nbp + c] = t;
+    }
+    const double dl = in ? static_cast<double>(t) - static_cast<double>(x) : 0.0;
+    const double sq = block_sum(dl * dl, red);
+    if (threadIdx.x == 0) a.step_partials[q * gridDim.x + blockIdx.x] = sq;
+  }
+}
+
 // ---- small utility kernels ----------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void sum_kernel(const double* parts, int n, double* out) {
   __shared__ double red[kWaves];
@@ -1230,7 +1195,7 @@ int grid_for(int items, int cap) {
 size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
   const size_t nbp = static_cast<size_t>(pad4(nb));
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
-                 (static_cast<size_t>(ntrials) * nbp + nbp) * sizeof(float);
+                 static_cast<size_t>(ntrials) * nbp * sizeof(float);
   if (wave) {
     bytes += (static_cast<size_t>(kWaves) * ntrials * kWaveNnz + kWaveSlack) * sizeof(float);
   } else {
@@ -1304,14 +1269,29 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
   int rc = check_launch("adj_kernel");
   if (rc) return rc;
   if (after && hipEventRecord(after, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
-  if (!a.fold) {
+  if (!a.solve) {
+    // shared columns completed here (a solve completes them in its step kernel)
     const int g2 = (a.nb + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, ctx->stream, a,
-                       a.solve ? static_cast<const SolverState*>(a.st_out) : nullptr);
+                       static_cast<const SolverState*>(nullptr));
     rc = check_launch("adj_final_kernel");
   }
   (void)D;
   return rc;
+}
+
+int step_grid(int nb) { return std::max(1, (nb + kThreads - 1) / kThreads); }
+
+int launch_step(const imrt_ctx* ctx, const StepArgs& a, int ntrials) {
+  clear_stale_error();
+  const dim3 gd(step_grid(a.nb)), bd(kThreads);
+  switch (ntrials) {
+    case 1: hipLaunchKernelGGL(step_kernel<1>, gd, bd, 0, ctx->stream, a); break;
+    case 2: hipLaunchKernelGGL(step_kernel<2>, gd, bd, 0, ctx->stream, a); break;
+    case 4: hipLaunchKernelGGL(step_kernel<4>, gd, bd, 0, ctx->stream, a); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return check_launch("step_kernel");
 }
 
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out) {

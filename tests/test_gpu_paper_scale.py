@@ -89,12 +89,12 @@ def test_full_solve_trajectory(built, fx):
     _check_full_solve(built, fx)
 
 
-def test_full_solve_trajectory_final_kernel(built, fx):
-    """The same with shared adjoint columns completed by the separate kernel
-    and workgroup-wide forward row blocks."""
+def test_full_solve_trajectory_block_forward(built, fx):
+    """The same with workgroup-wide forward row blocks and eight adjoint
+    workgroups per compute unit."""
     from paper_0908_4421_amd.imrt import Context, Dose, Plan
-    banner("paper-scale solve, final kernel")
-    ctx = Context(0, fold=0, fwd_wave=0)
+    banner("paper-scale solve, workgroup forward blocks")
+    ctx = Context(0, fwd_wave=0, adj_wg_per_cu=8)
     dose = Dose.from_geometry(ctx, PAPER_SCALE)
     plan = Plan(ctx, dose)
     plan.set_structures(None, 4)

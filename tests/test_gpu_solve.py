@@ -13,15 +13,15 @@ from workloads import TINY, TINY_SETTINGS, penalty_table, power_start_vector
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=[(1, 1024, 1), (1, 16, 0), (0, 16, 1)],
-                ids=["default", "shared_cols_folded_block_fwd", "shared_cols_final_kernel"])
+@pytest.fixture(scope="module", params=[(1024, 1), (16, 0), (16, 1)],
+                ids=["default", "shared_cols_block_fwd", "shared_cols_wave_fwd"])
 def ctx(request):
-    """Default launch settings; many short adjoint workgroup ranges whose
-    shared columns are completed while the next forward pass stages the
-    gradient (with workgroup-wide forward blocks); or by the final kernel."""
+    """Default launch settings, or many short adjoint workgroup ranges (most
+    beamlet columns shared by several workgroups) with workgroup-wide or
+    wave-wide forward row blocks."""
     from paper_0908_4421_amd.imrt import Context
-    fold, min_nnz, wave = request.param
-    return Context(0, fold=fold, adj_min_nnz=min_nnz, fwd_wave=wave)
+    min_nnz, wave = request.param
+    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave)
 
 
 @pytest.fixture(scope="module")

@@ -105,7 +105,7 @@ def test_invalid_csr_rejected(ctx):
 def test_context_options(ctx):
     from paper_0908_4421_amd import imrt
     assert ctx.get_option("adj_min_nnz") in (1024, 16)
-    for bad in (("no_such_option", 1), ("fold", 2), ("adj_min_nnz", 3), ("fwd_wg_per_cu", 0)):
+    for bad in (("no_such_option", 1), ("fwd_wave", 2), ("adj_min_nnz", 3), ("fwd_wg_per_cu", 0)):
         with pytest.raises(imrt.ImrtError) as e:
             ctx.set_option(*bad)
         assert e.value.code == imrt.IMRT_EINVAL
