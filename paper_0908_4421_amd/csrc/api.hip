@@ -78,17 +78,20 @@ int hip_error(hipError_t e, const char* what) {
 // straddle the end stay in bounds.
 int alloc_nonzeros(imrt_dose* D) {
   const size_t nz = static_cast<size_t>(D->nnz) + kPad;
+  const size_t nzc = csc_alloc(D->nnz);
   int rc;
   if ((rc = dev_alloc(&D->row_ptr, static_cast<size_t>(D->nv) + 1)) ||
       (rc = dev_alloc(&D->col_ptr, static_cast<size_t>(D->nb) + 1)) || (rc = dev_alloc(&D->col_idx, nz)) ||
-      (rc = dev_alloc(&D->val, nz)) || (rc = dev_alloc(&D->row_idx, nz)) || (rc = dev_alloc(&D->cval, nz)))
+      (rc = dev_alloc(&D->val, nz)) || (rc = dev_alloc(&D->row_idx, nzc)) || (rc = dev_alloc(&D->cval, nzc)))
     return rc;
   hipStream_t s = D->ctx->stream;
   const size_t off = static_cast<size_t>(D->nnz);
   IMRT_HIP(hipMemsetAsync(D->col_idx + off, 0, sizeof(int32_t) * kPad, s));
   IMRT_HIP(hipMemsetAsync(D->val + off, 0, sizeof(float) * kPad, s));
-  IMRT_HIP(hipMemsetAsync(D->row_idx + off, 0, sizeof(int32_t) * kPad, s));
-  IMRT_HIP(hipMemsetAsync(D->cval + off, 0, sizeof(float) * kPad, s));
+  // the CSC tile holding the last nonzero and everything after it start as zeros
+  const size_t t0 = off & ~static_cast<size_t>(kTile - 1);
+  IMRT_HIP(hipMemsetAsync(D->row_idx + t0, 0, sizeof(int32_t) * (nzc - t0), s));
+  IMRT_HIP(hipMemsetAsync(D->cval + t0, 0, sizeof(float) * (nzc - t0), s));
   return IMRT_OK;
 }
 
@@ -313,6 +316,7 @@ AdjArgs base_adj(const imrt_dose* D) {
   a.nv = D->nv;
   a.nb = D->nb;
   a.grid = D->adj_grid;
+  a.xcd_map = D->ctx->tune.adj_xcd;
   return a;
 }
 
@@ -359,6 +363,7 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
+  if (const char* f = std::getenv("IMRT_ADJ_XCD")) c->tune.adj_xcd = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
   return IMRT_OK;
@@ -393,6 +398,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.fwd_wave;
   }
+  if (n == "adj_xcd") {
+    *lo = 0;
+    return &ctx->tune.adj_xcd;
+  }
   return nullptr;
 }
 }  // namespace
@@ -403,7 +412,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fwd_wave") ? 1 : (int64_t(1) << 30);
+  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd") ? 1 : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
   return IMRT_OK;
@@ -478,11 +487,13 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
     std::vector<int32_t> rp(row_ptr, row_ptr + nv + 1), cp(nb + 1, 0);
     for (int64_t k = 0; k < nnz; ++k) cp[col_idx[k] + 1]++;
     for (int i = 0; i < nb; ++i) cp[i + 1] += cp[i];
-    std::vector<int32_t> ri(static_cast<size_t>(nnz)), fill(cp.begin(), cp.end() - 1);
-    std::vector<float> cv(static_cast<size_t>(nnz));
+    // (stored in the tiled slot order of the CSC arrays; unused slots zero)
+    const size_t nzc = csc_alloc(nnz);
+    std::vector<int32_t> ri(nzc, 0), fill(cp.begin(), cp.end() - 1);
+    std::vector<float> cv(nzc, 0.0f);
     for (int32_t j = 0; j < nv; ++j)
       for (int32_t k = row_ptr[j]; k < row_ptr[j + 1]; ++k) {
-        const int32_t p = fill[col_idx[k]]++;
+        const int64_t p = csc_slot(fill[col_idx[k]]++);
         ri[p] = j;
         cv[p] = val[k];
       }
@@ -496,8 +507,8 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
     if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s);
     if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->val, val, sizeof(float) * nnz, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(D->col_ptr, cp.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->row_idx, ri.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && nnz) e = hipMemcpyAsync(D->cval, cv.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(D->row_idx, ri.data(), sizeof(int32_t) * nzc, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(D->cval, cv.data(), sizeof(float) * nzc, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       free_dose(D);
@@ -535,9 +546,25 @@ int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, flo
   if (col_idx && nz) IMRT_HIP(hipMemcpyAsync(col_idx, D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
   if (val && nz) IMRT_HIP(hipMemcpyAsync(val, D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
   if (col_ptr) IMRT_HIP(hipMemcpyAsync(col_ptr, D->col_ptr, sizeof(int32_t) * (D->nb + 1), hipMemcpyDeviceToHost, s));
-  if (row_idx && nz) IMRT_HIP(hipMemcpyAsync(row_idx, D->row_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
-  if (cval && nz) IMRT_HIP(hipMemcpyAsync(cval, D->cval, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
   if (voxel_struct) IMRT_HIP(hipMemcpyAsync(voxel_struct, D->sid, D->nv, hipMemcpyDeviceToHost, s));
+  if ((row_idx || cval) && nz) {
+    // CSC arrays come back in plain column-major order
+    try {
+      const size_t nzc = csc_alloc(D->nnz);
+      std::vector<int32_t> ri(row_idx ? nzc : 0);
+      std::vector<float> cv(cval ? nzc : 0);
+      if (row_idx) IMRT_HIP(hipMemcpyAsync(ri.data(), D->row_idx, sizeof(int32_t) * nzc, hipMemcpyDeviceToHost, s));
+      if (cval) IMRT_HIP(hipMemcpyAsync(cv.data(), D->cval, sizeof(float) * nzc, hipMemcpyDeviceToHost, s));
+      IMRT_HIP(hipStreamSynchronize(s));
+      for (size_t k = 0; k < nz; ++k) {
+        const int64_t p = csc_slot(static_cast<int64_t>(k));
+        if (row_idx) row_idx[k] = ri[p];
+        if (cval) cval[k] = cv[p];
+      }
+    } catch (const std::bad_alloc&) {
+      return set_error(IMRT_ENOMEM, "host allocation failed");
+    }
+  }
   IMRT_HIP(hipStreamSynchronize(s));
   return IMRT_OK;
 }

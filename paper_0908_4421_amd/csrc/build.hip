@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDe
     int before = base;
     for (int k = 0; k < w; ++k) before += wave_cnt[k];
     if (keep && fill) {
-      const int pos = before + __popcll(mask & ((1ull << lane) - 1ull));
+      const int64_t pos = csc_slot(before + __popcll(mask & ((1ull << lane) - 1ull)));
       row_idx[pos] = j;
       cval[pos] = static_cast<float>(exp(-e));
     }

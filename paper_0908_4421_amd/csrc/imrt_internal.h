@@ -109,6 +109,7 @@ struct AdjArgs {
   const int32_t* col_whi;
   int64_t nnz;
   int32_t nv, nb, grid;
+  int32_t xcd_map;           // workgroup ranges contiguous per accelerator die (else dispatch order)
   int32_t solve;             // decide the previous forward pass first; r from rbuf
   const float* r;
   float* rbuf[kMaxTrials + 1];
@@ -147,6 +148,7 @@ struct Tuning {
   int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
+  int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
 
@@ -236,9 +238,25 @@ int hip_error(hipError_t e, const char* what);
 
 // launchers (kernels.hip)
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D);
+int wave_grid(const imrt_ctx* ctx, int nwblocks);
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
 size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
+
+// CSC nonzero k is stored at slot csc_slot(k): within every aligned tile of
+// 256 entries, entry 64u + i (i < 64, u < 4) sits at 4i + u, so one 16-byte
+// load by lane i brings entries i, i + 64, i + 128, i + 192 of its tile and
+// each of the four components is a run of 64 consecutive entries across the
+// wave (consecutive rows of a column: their residual gathers coalesce).
+constexpr int kTile = 256;
+__host__ __device__ inline int64_t csc_slot(int64_t k) {
+  return (k & ~static_cast<int64_t>(kTile - 1)) | ((k & 63) << 2) | ((k >> 6) & 3);
+}
+__host__ __device__ inline int64_t csc_entry(int64_t slot) {
+  return (slot & ~static_cast<int64_t>(kTile - 1)) | ((slot & 3) << 6) | ((slot >> 2) & 63);
+}
+// Entries allocated for the CSC arrays of nnz nonzeros (whole tiles plus one).
+inline size_t csc_alloc(int64_t nnz) { return static_cast<size_t>(((nnz + kTile - 1) / kTile + 1) * kTile); }
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials,

@@ -448,27 +448,58 @@ __device__ __forceinline__ void fwd_products(const BlockMeta& m, const VecRegs& 
   }
 }
 
-// Stage the inputs of a forward pass in LDS: the penalty table and the NT
-// vectors the pass multiplies by (row q of `src`, stride pad4(nb)).  All
-// loads are issued before any is used.  Ends with a workgroup barrier.
+// Staging of a forward pass's inputs in LDS: the penalty table and the NT
+// vectors the pass multiplies by (row q of `src`, stride pad4(nb)).  The
+// first round of loads (2048 entries per vector, and the table) goes to
+// registers so that a caller can issue further loads before it waits for
+// them; stage_finish stores them, stages the rest and ends with a barrier.
+constexpr int kStageU = 8;   // entries per thread per round and vector
+
 template <int NT>
-__device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src, PenaltyDev* tab, float* xs,
-                                             bool want_sid) {
-  const int tid = threadIdx.x;
-  const int nb = a.nb;
-  const int nbp = pad4(nb);
-  if (want_sid) {
-    const double* tsrc = reinterpret_cast<const double*>(a.pen.table);
-    double* dst = reinterpret_cast<double*>(tab);
-    for (int i = tid; i < 4 * a.nstruct; i += kThreads) dst[i] = tsrc[i];
+struct StageRegs {
+  float v[NT][kStageU];
+  double tab;
+};
+
+template <int NT>
+__device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, bool want_sid, StageRegs<NT>& R) {
+  const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int i = tid + u * kThreads;
+      R.v[q][u] = src[q * nbp + (i < nb ? i : 0)];
+    }
   }
-  constexpr int kU = 8;   // entries loaded per thread per round and vector
-  for (int i0 = tid; i0 < nb; i0 += kU * kThreads) {
-    float v[NT][kU];
+  // first kThreads doubles of the table (4 per structure); the rest in stage_finish
+  R.tab = (want_sid && tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
+}
+
+template <int NT>
+__device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src, bool want_sid,
+                                             const StageRegs<NT>& R, PenaltyDev* tab, float* xs) {
+  const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
+  if (want_sid) {
+    double* dst = reinterpret_cast<double*>(tab);
+    if (tid < 4 * a.nstruct) dst[tid] = R.tab;
+    for (int i = tid + kThreads; i < 4 * a.nstruct; i += kThreads)
+      dst[i] = reinterpret_cast<const double*>(a.pen.table)[i];
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int i = tid + u * kThreads;
+      if (i < nb) xs[q * nbp + i] = R.v[q][u];
+    }
+  }
+  for (int i0 = tid + kStageU * kThreads; i0 < nb; i0 += kStageU * kThreads) {
+    float v[NT][kStageU];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < kStageU; ++u) {
         const int i = i0 + u * kThreads;
         v[q][u] = src[q * nbp + (i < nb ? i : 0)];
       }
@@ -476,13 +507,21 @@ __device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src,
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < kStageU; ++u) {
         const int i = i0 + u * kThreads;
         if (i < nb) xs[q * nbp + i] = v[q][u];
       }
     }
   }
   __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src, PenaltyDev* tab, float* xs,
+                                             bool want_sid) {
+  StageRegs<NT> R;
+  stage_start<NT>(a, src, want_sid, R);
+  stage_finish<NT>(a, src, want_sid, R, tab, xs);
 }
 
 // Forward pass.  Each workgroup stages the NT trial vectors
@@ -626,7 +665,9 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 
 // ---- wave-granular forward pass --------------------------------------------------
 // Each of the four waves of a workgroup streams its own contiguous range of
-// small row blocks (at most kWavePartNnz nonzeros and kWaveRowsMax rows).
+// small row blocks (at most kWavePartNnz nonzeros and kWaveRowsMax rows),
+// an even split of the block count (a block's time is mostly latency, so
+// equal counts balance better than equal bytes).
 // Block bounds come from per-lane copies of the block table read with
 // readlane, so all control flow and every descriptor is wave-uniform.  A
 // block's column indices and values arrive as 16-byte buffer loads (lanes
@@ -814,14 +855,18 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     return m;
   };
 
+  // Load order: block bounds (above), staging loads, then the first block's
+  // loads, so that waiting for the staging loads does not wait for the
+  // block (the wait counter drains in issue order).
+  StageRegs<NT> SR;
+  stage_start<NT>(a, a.x, want_sid, SR);
   WaveStage S;
   WaveBlock cur{0, 0, 0, 0};
   if (b0 < b1) {
     cur = meta(b0);
     if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
   }
-
-  stage_inputs<NT>(a, a.x, tab, xs, want_sid);
+  stage_finish<NT>(a, a.x, want_sid, SR, tab, xs);
 
   double pacc[NT];
 #pragma unroll
@@ -911,13 +956,16 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
 }
 
 // ---- adjoint pass ----------------------------------------------------------------
-// Workgroup w owns nonzeros [k0w, k1w) of the CSC arrays and walks them in
-// rounds of 2048 (eight per thread: two 16-byte loads each of row indices and
-// values, lanes past the range read zeros).  A round's residual gathers are
-// issued before the next round's loads, which go to the other of two register
-// stages, so one round is always in flight.  A round inside one column adds
-// all its products; a round that meets a column boundary adds each column's
-// share under a mask and closes every column that ends in it.
+// Workgroup w owns nonzeros [k0w, k1w) of the CSC arrays and walks the tiles
+// covering them in rounds of 2048 entries: each thread loads two 16-byte
+// vectors of row indices and of values, i.e. entries e0 + 1024 j + 64 u
+// (j < 2, u < 4) of the round, where e0 = 256 * wave + lane (the tiled slot
+// order of the CSC arrays); lanes past the range read zeros.  A round's
+// residual gathers (each a run of 64 consecutive entries of a column across
+// the wave) are issued before the next round's loads, which go to the other
+// of two register stages, so one round is always in flight.  A round inside
+// one column adds all its products; a round that meets a column boundary adds
+// each column's share under a mask and closes every column that ends in it.
 struct AdjStage {
   int4 c[2];
   float4 v[2];
@@ -925,9 +973,12 @@ struct AdjStage {
 
 constexpr int kAdjStep = 8 * kThreads;   // nonzeros per round
 
-__device__ __forceinline__ int logical_wg() {
+// Logical workgroup of this dispatch slot.  With xcd_map and a grid that is a
+// multiple of the die count, workgroup w (on die w % 8) gets logical slot
+// (w % 8) * (grid / 8) + w / 8, so each die owns one contiguous eighth.
+__device__ __forceinline__ int logical_wg(bool xcd_map) {
   const int G = gridDim.x, w = blockIdx.x;
-  return (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
+  return (xcd_map && G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
 }
 
 __device__ __forceinline__ void adj_issue(rsrc_t ri, rsrc_t rv, int round, AdjStage& S) {
@@ -950,55 +1001,79 @@ __device__ __forceinline__ void adj_gather(rsrc_t rr, const AdjStage& S, float (
   }
 }
 
-// Float64 sum of this thread's eight products, in element order.
+// Float64 sum of this thread's eight products, in a fixed order.
 __device__ __forceinline__ double adj_dot(const AdjStage& S, const float (&g)[8]) {
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s += static_cast<double>(vv[i]) * static_cast<double>(g[4 * j + i]);
+    for (int u = 0; u < 4; ++u) s += static_cast<double>(vv[u]) * static_cast<double>(g[4 * j + u]);
   }
   return s;
 }
 
-// The same over the elements with index in [lo, hi) (first element e0).
+// The same over the entries with index in [lo, hi) (e0 as above).
 __device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float (&g)[8], int e0, int lo, int hi) {
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = e0 + 1024 * j + i;
-      const float r = (e >= lo && e < hi) ? g[4 * j + i] : 0.0f;
-      s += static_cast<double>(vv[i]) * static_cast<double>(r);
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + 1024 * j + 64 * u;
+      const float r = (e >= lo && e < hi) ? g[4 * j + u] : 0.0f;
+      s += static_cast<double>(vv[u]) * static_cast<double>(r);
     }
   }
   return s;
 }
 
-// Adjoint pass: in a solve, first the decision on the preceding forward pass
+// Adjoint pass: in a solve, the decision on the preceding forward pass
 // (every workgroup identically; workgroup 0 stores the new state and trace
-// entry), then g = scale * D^T r over this workgroup's share of the nonzeros.
+// entry), and g = scale * D^T r over this workgroup's share of the nonzeros.
+// The first round's residual gathers are issued before the decision is
+// known, from the residual of the pass's first trial (the one an accepted
+// step of a single-trial pass always lands in); if another trial is
+// accepted they are issued again.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   __shared__ double red[kWaves];
   __shared__ Decision dec;
   const int tid = threadIdx.x;
-  const int lw = logical_wg();
+  const float* r = a.r;
+  int spec = 0;
+  if (a.solve) {
+    const SolverState* st = a.st_in;
+    if (st->phase == PH_DONE) {
+      // finished: the state passes through
+      constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
+      if (blockIdx.x == 0 && tid < kWords)
+        reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
+      return;
+    }
+    spec = (st->acc + 1) % (NT + 1);
+    r = select_buf(a.rbuf, spec);
+  }
+  const int lw = logical_wg(a.xcd_map != 0);
   const int k0w = static_cast<int>(static_cast<int64_t>(lw) * a.nnz / a.grid);
   const int k1w = static_cast<int>(static_cast<int64_t>(lw + 1) * a.nnz / a.grid);
   const int c0 = uniform(a.wg_c0[lw]), c1 = uniform(a.wg_c1[lw]);
-  const int kb = k0w & ~3;
+  const int kb = k0w & ~(kTile - 1);
   const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
-  const uint32_t bytes = static_cast<uint32_t>((k1w - kb) * 4 + 15) & ~15u;
+  // whole tiles: entries of a partial tile sit anywhere in it
+  const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
   const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
   const rsrc_t rv = make_rsrc(a.val + kb, bytes);
-  // the first round's loads do not depend on the decision
+  const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
+  rsrc_t rr = make_rsrc(r, rbytes);
   AdjStage A, B;
-  if (nrounds > 0) adj_issue(ri, rv, 0, A);
-  const float* r = a.r;
+  float g[8];
+  if (nrounds > 0) {
+    adj_issue(ri, rv, 0, A);
+    adj_gather(rr, A, g);
+    if (nrounds > 1) adj_issue(ri, rv, 1, B);
+  }
   if (a.solve) {
     decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, dec, red);
     if (blockIdx.x == 0 && tid == 0) {
@@ -1014,9 +1089,11 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
       }
     }
     if (dec.st.phase != PH_NEED_GRAD) return;
-    r = select_buf(a.rbuf, dec.st.acc);
+    if (dec.st.acc != spec) {
+      rr = make_rsrc(select_buf(a.rbuf, dec.st.acc), rbytes);
+      if (nrounds > 0) adj_gather(rr, A, g);
+    }
   }
-  const rsrc_t rr = make_rsrc(r, 4u * static_cast<uint32_t>(a.nv));
 
   int c = c0, lo = 0, hi = 0;
   auto bounds = [&]() {
@@ -1040,29 +1117,37 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
     ++c;
     if (c < c1) bounds();
   };
-  int round = 0;
-  auto step = [&](const AdjStage& cur, AdjStage& nxt) {
-    float g[8];
-    adj_gather(rr, cur, g);
-    if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+  // distribute one round's products over the columns it meets
+  auto consume = [&](const AdjStage& cur, const float (&gv)[8], int round) {
     const int base = kb + round * kAdjStep, end = base + kAdjStep;
     while (c < c1 && lo < end) {
       if (lo <= base && hi >= end) {
-        s += adj_dot(cur, g);
+        s += adj_dot(cur, gv);
         if (hi == end) close();
         break;
       }
-      s += adj_dot_masked(cur, g, base + 4 * tid, lo, hi);
+      s += adj_dot_masked(cur, gv, base + 256 * (tid >> 6) + (tid & 63), lo, hi);
       if (hi > end) break;
       close();
     }
-    ++round;
-    return round < nrounds;
   };
+  // round 0 (gathers and round 1's loads already issued), then the rest
+  // alternating between the two register stages
+  int round = 0;
   if (nrounds > 0) {
-    for (;;) {
-      if (!step(A, B)) break;
+    consume(A, g, 0);
+    round = 1;
+    auto step = [&](const AdjStage& cur, AdjStage& nxt) {
+      float gv[8];
+      adj_gather(rr, cur, gv);
+      if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+      consume(cur, gv, round);
+      ++round;
+      return round < nrounds;
+    };
+    while (round < nrounds) {
       if (!step(B, A)) break;
+      if (!step(A, B)) break;
     }
   }
   // empty columns at the end of the range
@@ -1206,8 +1291,11 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
 }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D) {
-  const int items = ctx->tune.fwd_wave ? (D->nwblocks + kWaves - 1) / kWaves : D->nblocks;
-  return grid_for(items, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+  return ctx->tune.fwd_wave ? wave_grid(ctx, D->nwblocks) : grid_for(D->nblocks, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+}
+
+int wave_grid(const imrt_ctx* ctx, int nwblocks) {
+  return grid_for((nwblocks + kWaves - 1) / kWaves, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {

@@ -13,7 +13,9 @@ import os
 from typing import Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libimrt.so")
+# IMRT_LIBRARY names another build of the same library (e.g. one compiled with
+# different constants); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("IMRT_LIBRARY") or os.path.join(_HERE, "libimrt.so")
 
 # ---- error / status codes (imrt.h) ------------------------------------------
 IMRT_OK, IMRT_EINVAL, IMRT_ENOMEM, IMRT_EHIP, IMRT_ENOTREADY, IMRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
