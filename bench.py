@@ -258,7 +258,7 @@ def main():
                    "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
                    "trials_per_pass": args.trials_per_pass,
                    "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz",
-                                                             "batch_iters", "fwd_wave")}},
+                                                             "batch_iters", "fwd_wave", "adj_xcd")}},
         "iterations": res.iterations,
         "iters_per_s": res.iterations / (ms_per_step / 1e3),
         "forward_passes": res.forward_passes,

@@ -145,6 +145,9 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1)
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (>= 1)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
+ *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die
+ *                    (shared L2 for residual gathers); 0: dispatch order, so
+ *                    every die gets a mix of beams (default)
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)

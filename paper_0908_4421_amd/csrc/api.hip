@@ -236,6 +236,7 @@ void free_plan(imrt_plan* P) {
   dev_free(P->vtmp);
   dev_free(P->fwd_partials);
   dev_free(P->pieces);
+  dev_free(P->pieces_col);
   dev_free(P->misc);
   dev_free(P->st);
   dev_free(P->trace);
@@ -611,7 +612,8 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
       (rc = dev_alloc(&P->xstage, static_cast<size_t>(kMaxTrials) * pad4(dose->nb))) ||
       (rc = dev_alloc(&P->step_partials, static_cast<size_t>(kMaxTrials) * step_grid(dose->nb))) ||
       (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
-      (rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(dose->adj_grid))) || (rc = dev_alloc(&P->misc, 16)) ||
+      (rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(dose->adj_grid))) ||
+      (rc = dev_alloc(&P->pieces_col, 2 * static_cast<size_t>(dose->nb))) || (rc = dev_alloc(&P->misc, 16)) ||
       (rc = dev_alloc(&P->st, 2))) {
     free_plan(P);
     return rc;
@@ -895,6 +897,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   aa.solve = 1;
   for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
   aa.pieces = P->pieces;
+  aa.pieces_col = P->pieces_col;
   aa.out = P->gk;
   aa.scale = 2.0;
   aa.fwd_partials = P->fwd_partials;
@@ -906,6 +909,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   sa.col_wlo = D->col_wlo;
   sa.col_whi = D->col_whi;
   sa.pieces = P->pieces;
+  sa.pieces_col = P->pieces_col;
   sa.g = P->gk;
   sa.scale = 2.0;
   for (int i = 0; i <= kMaxTrials; ++i) sa.xbuf[i] = P->xbuf[i];

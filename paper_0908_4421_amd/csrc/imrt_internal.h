@@ -38,7 +38,7 @@ enum Phase : int32_t {
 
 struct SolverState {
   int32_t phase, status, k, m;        // phase, imrt_solve_status, accepted iterations, backtracks
-  int32_t acc, xi, n_fwd, n_adj;      // residual and iterate buffers of x_k, pass counters
+  int32_t acc, xi, n_fwd, n_adj;      // trial whose residual buffer holds r(x_k), iterate buffer of x_k, pass counters
   int32_t ntrials, max_iter, max_bt, fixed;
   int32_t trace_cap, pad;
   double lambda;                      // first trial step of the next forward pass
@@ -86,7 +86,7 @@ struct FwdArgs {
   int32_t nstruct;
   Penalties pen;
   const float* x;            // eval/plain input vector; solve: trial vectors [trial][pad4(nb)]
-  float* rbuf[kMaxTrials + 1];  // solve: residual buffers (r(x_k) = rbuf[st->acc])
+  float* rbuf[kMaxTrials + 1];  // solve: residual of trial q into rbuf[q] (r(x_k) = rbuf[st->acc])
   float* d_out;              // eval/plain: dose (nullable in eval)
   float* r_out;              // eval: residual (nullable)
   double* partials;          // [trial][gridDim.x] objective partials
@@ -114,6 +114,7 @@ struct AdjArgs {
   const float* r;
   float* rbuf[kMaxTrials + 1];
   double* pieces;            // 2 * grid
+  double* pieces_col;        // nullable, 2 * nb: pieces of columns shared by two workgroups, by column
   float* out;
   double scale;
   // solve: line-search decision on the previous forward pass
@@ -134,6 +135,7 @@ struct StepArgs {
   const int32_t* col_wlo;
   const int32_t* col_whi;
   const double* pieces;
+  const double* pieces_col;  // 2 * nb: pieces of columns shared by exactly two workgroups
   float* g;                  // gradient: complete for unshared columns, completed here for shared ones
   double scale;
   float* xbuf[kMaxTrials + 1];  // iterate buffers; trial q goes to xbuf[(xi + 1 + q) % (NT + 1)]
@@ -148,7 +150,7 @@ struct Tuning {
   int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
-  int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
+  int adj_xcd = 0;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
 
@@ -216,6 +218,7 @@ struct imrt_plan {
   double* fwd_partials = nullptr; // kMaxTrials * (fwd_cap + 1)
   int32_t fwd_cap = 1;
   double* pieces = nullptr;       // 2 * adjoint grid
+  double* pieces_col = nullptr;   // 2 * nb
   double* misc = nullptr;         // small reduction scratch
   imrt::SolverState* st = nullptr;  // 2 states, alternately read and written by consecutive passes
   imrt::TraceDev* trace = nullptr;

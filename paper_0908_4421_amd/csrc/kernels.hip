@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "imrt_internal.h"
 
 namespace imrt {
@@ -223,20 +225,43 @@ struct Decision {
   double lam, step_sq;
 };
 
+// The first round of partial loads (four per thread and trial) is issued by
+// decide_start, before anything that does not need it, so that waiting for
+// it does not wait for later loads.
+template <int NT>
+struct DecideLoads {
+  double v[NT][4];
+};
+
+template <int NT>
+__device__ __forceinline__ void decide_start(const double* partials, int nparts, DecideLoads<NT>& L) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = tid + u * kThreads;
+      const double t = partials[q * nparts + (i < nparts ? i : 0)];
+      L.v[q][u] = (i < nparts) ? t : 0.0;
+    }
+  }
+}
+
 template <int NT>
 __device__ void decide(const SolverState* in, const double* partials, int nparts, const double* steps, int nsteps,
-                       Decision& dec, double* red) {
+                       const DecideLoads<NT>& L, Decision& dec, double* red) {
 #pragma clang fp contract(off)
   __shared__ double Gq[NT];
   const int tid = threadIdx.x;
-  // the partial loads do not depend on the state: all are issued at once
   double s[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    // four independent loads per round, summed in index order
+    // four values per round, summed in index order
     s[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[q] += L.v[q][u];
     const double* pq = partials + q * nparts;
-    for (int i0 = tid; i0 < nparts; i0 += 4 * kThreads) {
+    for (int i0 = tid + 4 * kThreads; i0 < nparts; i0 += 4 * kThreads) {
       double v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -267,7 +292,7 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
       st.G = G0;
       st.G_init = G0;
       st.G_prev = G0;
-      st.acc = (st.acc + 1) % (NT + 1);
+      st.acc = 0;
       st.m = 0;
       st.lambda = st.lambda0;
       if (!isfinite(G0)) {
@@ -322,7 +347,7 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
         st.k += 1;
         st.G_prev = st.G;
         st.G = Gq[accepted];
-        st.acc = (st.acc + 1 + accepted) % (NT + 1);
+        st.acc = accepted;
         st.xi = (st.xi + 1 + accepted) % (NT + 1);
         st.m = 0;
         st.lambda = st.lambda0;
@@ -560,9 +585,8 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     const int phase = st->phase;
     if (phase == PH_DONE) return;
     ntr = (phase == PH_INIT) ? 1 : NT;
-    const int acc = st->acc;
 #pragma unroll
-    for (int q = 0; q < NT; ++q) rout[q] = select_buf(a.rbuf, (acc + 1 + q) % (NT + 1));
+    for (int q = 0; q < NT; ++q) rout[q] = a.rbuf[q];
   }
 
   int b0, b1;
@@ -823,9 +847,8 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     const int phase = st->phase;
     if (phase == PH_DONE) return;
     ntr = (phase == PH_INIT) ? 1 : NT;
-    const int acc = st->acc;
 #pragma unroll
-    for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(select_buf(a.rbuf, (acc + 1 + q) % (NT + 1)), vbytes);
+    for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
 
   // this wave's contiguous range of row blocks
@@ -1032,17 +1055,32 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float 
 // Adjoint pass: in a solve, the decision on the preceding forward pass
 // (every workgroup identically; workgroup 0 stores the new state and trace
 // entry), and g = scale * D^T r over this workgroup's share of the nonzeros.
-// The first round's residual gathers are issued before the decision is
-// known, from the residual of the pass's first trial (the one an accepted
-// step of a single-trial pass always lands in); if another trial is
-// accepted they are issued again.
+// The first two rounds' loads are issued on entry and the first round's
+// residual gathers before the decision is known, from the residual buffer of
+// the pass's first trial (the one an accepted step of a single-trial pass
+// always lands in); if another trial is accepted they are issued again.
 template <int NT>
 __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   __shared__ double red[kWaves];
   __shared__ Decision dec;
   const int tid = threadIdx.x;
+  const int lw = logical_wg(a.xcd_map != 0);
+  const int k0w = static_cast<int>(static_cast<int64_t>(lw) * a.nnz / a.grid);
+  const int k1w = static_cast<int>(static_cast<int64_t>(lw + 1) * a.nnz / a.grid);
+  const int kb = k0w & ~(kTile - 1);
+  const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
+  // whole tiles: entries of a partial tile sit anywhere in it
+  const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
+  const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
+  const rsrc_t rv = make_rsrc(a.val + kb, bytes);
+  // the decision's partials first, then the first two rounds' loads: none
+  // depends on anything computed
+  DecideLoads<NT> DL;
+  if (a.solve) decide_start<NT>(a.fwd_partials, a.fwd_parts, DL);
+  AdjStage A, B;
+  if (nrounds > 0) adj_issue(ri, rv, 0, A);
+  if (nrounds > 1) adj_issue(ri, rv, 1, B);
   const float* r = a.r;
-  int spec = 0;
   if (a.solve) {
     const SolverState* st = a.st_in;
     if (st->phase == PH_DONE) {
@@ -1052,30 +1090,15 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
         reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
       return;
     }
-    spec = (st->acc + 1) % (NT + 1);
-    r = select_buf(a.rbuf, spec);
+    r = a.rbuf[0];   // residual of the first trial: the accepted one unless a later trial wins
   }
-  const int lw = logical_wg(a.xcd_map != 0);
-  const int k0w = static_cast<int>(static_cast<int64_t>(lw) * a.nnz / a.grid);
-  const int k1w = static_cast<int>(static_cast<int64_t>(lw + 1) * a.nnz / a.grid);
   const int c0 = uniform(a.wg_c0[lw]), c1 = uniform(a.wg_c1[lw]);
-  const int kb = k0w & ~(kTile - 1);
-  const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
-  // whole tiles: entries of a partial tile sit anywhere in it
-  const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
-  const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
-  const rsrc_t rv = make_rsrc(a.val + kb, bytes);
   const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
   rsrc_t rr = make_rsrc(r, rbytes);
-  AdjStage A, B;
   float g[8];
-  if (nrounds > 0) {
-    adj_issue(ri, rv, 0, A);
-    adj_gather(rr, A, g);
-    if (nrounds > 1) adj_issue(ri, rv, 1, B);
-  }
+  if (nrounds > 0) adj_gather(rr, A, g);
   if (a.solve) {
-    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, dec, red);
+    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red);
     if (blockIdx.x == 0 && tid == 0) {
       *a.st_out = dec.st;
       if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
@@ -1089,7 +1112,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
       }
     }
     if (dec.st.phase != PH_NEED_GRAD) return;
-    if (dec.st.acc != spec) {
+    if (dec.st.acc != 0) {
       rr = make_rsrc(select_buf(a.rbuf, dec.st.acc), rbytes);
       if (nrounds > 0) adj_gather(rr, A, g);
     }
@@ -1111,6 +1134,8 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
       } else {
         if (c == c0) a.pieces[2 * lw] = t;
         if (c == c1 - 1) a.pieces[2 * lw + 1] = t;
+        // a column shared by two workgroups also keeps its pieces side by side
+        if (whi - wlo == 1 && a.pieces_col != nullptr) a.pieces_col[2 * c + (lw - wlo)] = t;
       }
     }
     s = 0.0;
@@ -1131,7 +1156,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
       close();
     }
   };
-  // round 0 (gathers and round 1's loads already issued), then the rest
+  // round 0 (its gathers and round 1's loads already issued), then the rest
   // alternating between the two register stages
   int round = 0;
   if (nrounds > 0) {
@@ -1179,24 +1204,34 @@ __global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const So
 template <int NT>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
   __shared__ double red[kWaves];
-  const SolverState* st = a.st;
-  const int phase = st->phase;
-  if (phase != PH_NEED_GRAD && phase != PH_TRIAL) return;
   const int c = blockIdx.x * kThreads + threadIdx.x;
   const bool in = c < a.nb;
   const int cc = in ? c : 0;
-  const int xi = st->xi;
-  const float x = select_buf(a.xbuf, xi)[cc];
+  // loads that do not wait for the state: every iterate buffer's entry
+  float xc[NT + 1];
+#pragma unroll
+  for (int i = 0; i <= NT; ++i) xc[i] = a.xbuf[i][cc];
   float g = a.g[cc];
-  if (phase == PH_NEED_GRAD && in) {
-    const int wlo = a.col_wlo[c], whi = a.col_whi[c];
-    if (wlo != whi) {
-      double tot = a.pieces[2 * wlo + 1];
+  const int wlo = a.col_wlo[cc], whi = a.col_whi[cc];
+  const double p0 = a.pieces_col[2 * cc], p1 = a.pieces_col[2 * cc + 1];
+  const SolverState* st = a.st;
+  const int phase = st->phase;
+  if (phase != PH_NEED_GRAD && phase != PH_TRIAL) return;
+  const int xi = st->xi;
+  float x = xc[0];
+#pragma unroll
+  for (int i = 1; i <= NT; ++i) x = (xi == i) ? xc[i] : x;
+  if (phase == PH_NEED_GRAD && in && wlo != whi) {
+    double tot;
+    if (whi - wlo == 1) {
+      tot = p0 + p1;
+    } else {
+      tot = a.pieces[2 * wlo + 1];
       for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
       tot += a.pieces[2 * whi];
-      g = static_cast<float>(a.scale * tot);
-      a.g[c] = g;
     }
+    g = static_cast<float>(a.scale * tot);
+    a.g[c] = g;
   }
   const int nbp = pad4(a.nb);
   double lam = st->lambda;
@@ -1306,6 +1341,9 @@ int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
   return static_cast<int>(std::max<int64_t>(1, std::min(cap, want)));
 }
 
+// Launches take optional start/stop events, recorded by the dispatch itself
+// around the kernel (hipExtLaunchKernelGGL), so their elapsed time is the
+// kernel's own duration.
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before, hipEvent_t after) {
   (void)D;
@@ -1314,54 +1352,51 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave);
   if (lds > ctx->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
-  if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
+  const dim3 gd(grid), bd(kThreads);
+  hipStream_t s = ctx->stream;
   if (wave) {
-    const dim3 gd(grid), bd(kThreads);
     if (a.mode == FWD_SOLVE) {
       switch (ntrials) {
-        case 1: hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
-        case 2: hipLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
-        case 4: hipLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE>), gd, bd, lds, ctx->stream, a); break;
+        case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
+        case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
+        case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
         default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
       }
     } else if (ntrials != 1) {
       return set_error(IMRT_EINVAL, "evaluation passes take one trial");
     } else if (a.mode == FWD_EVAL) {
-      hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL>), gd, bd, lds, ctx->stream, a);
+      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL>), gd, bd, lds, s, before, after, 0, a);
     } else {
-      hipLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN>), gd, bd, lds, ctx->stream, a);
+      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN>), gd, bd, lds, s, before, after, 0, a);
     }
   } else {
     switch (ntrials) {
-      case 1: hipLaunchKernelGGL(fwd_kernel<1>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-      case 2: hipLaunchKernelGGL(fwd_kernel<2>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
-      case 4: hipLaunchKernelGGL(fwd_kernel<4>, dim3(grid), dim3(kThreads), lds, ctx->stream, a); break;
+      case 1: hipExtLaunchKernelGGL(fwd_kernel<1>, gd, bd, lds, s, before, after, 0, a); break;
+      case 2: hipExtLaunchKernelGGL(fwd_kernel<2>, gd, bd, lds, s, before, after, 0, a); break;
+      case 4: hipExtLaunchKernelGGL(fwd_kernel<4>, gd, bd, lds, s, before, after, 0, a); break;
       default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
     }
   }
-  const int rc = check_launch("fwd_kernel");
-  if (rc == IMRT_OK && after && hipEventRecord(after, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
-  return rc;
+  return check_launch("fwd_kernel");
 }
 
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials, hipEvent_t before,
                    hipEvent_t after) {
   clear_stale_error();
-  if (before && hipEventRecord(before, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
+  const dim3 gd(a.grid), bd(kThreads);
+  hipStream_t s = ctx->stream;
   switch (ntrials) {
-    case 1: hipLaunchKernelGGL(adj_kernel<1>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
-    case 2: hipLaunchKernelGGL(adj_kernel<2>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
-    case 4: hipLaunchKernelGGL(adj_kernel<4>, dim3(a.grid), dim3(kThreads), 0, ctx->stream, a); break;
+    case 1: hipExtLaunchKernelGGL(adj_kernel<1>, gd, bd, 0, s, before, after, 0, a); break;
+    case 2: hipExtLaunchKernelGGL(adj_kernel<2>, gd, bd, 0, s, before, after, 0, a); break;
+    case 4: hipExtLaunchKernelGGL(adj_kernel<4>, gd, bd, 0, s, before, after, 0, a); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
   int rc = check_launch("adj_kernel");
   if (rc) return rc;
-  if (after && hipEventRecord(after, ctx->stream) != hipSuccess) return check_launch("hipEventRecord");
   if (!a.solve) {
     // shared columns completed here (a solve completes them in its step kernel)
     const int g2 = (a.nb + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, ctx->stream, a,
-                       static_cast<const SolverState*>(nullptr));
+    hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, s, a, static_cast<const SolverState*>(nullptr));
     rc = check_launch("adj_final_kernel");
   }
   (void)D;
