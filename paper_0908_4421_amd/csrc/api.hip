@@ -131,6 +131,47 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
     }
     wblocks.push_back(r);
   }
+  // A wave's time is mostly a per-block latency, so every wave of the
+  // default grid gets the same number of blocks: the blocks with the most
+  // nonzeros are halved (by rows) until the count is a multiple of the waves.
+  {
+    const int nwb = static_cast<int>(wblocks.size()) - 1;
+    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb)) * kWaves;
+    const int64_t target = (nwb + waves - 1) / waves * waves;
+    if (nwb > waves && target > nwb) {
+      // max-heap of (nonzeros, block start row) over splittable blocks
+      std::vector<std::pair<int64_t, int32_t>> heap;
+      for (int b = 0; b < nwb; ++b)
+        if (wblocks[b + 1] - wblocks[b] > 1)
+          heap.emplace_back(int64_t(row_ptr[wblocks[b + 1]]) - row_ptr[wblocks[b]], wblocks[b]);
+      std::make_heap(heap.begin(), heap.end());
+      std::vector<int32_t> cuts;
+      std::vector<int32_t> end_of(static_cast<size_t>(D->nv) + 1, -1);
+      for (int b = 0; b < nwb; ++b) end_of[wblocks[b]] = wblocks[b + 1];
+      for (int64_t extra = target - nwb; extra > 0 && !heap.empty(); --extra) {
+        std::pop_heap(heap.begin(), heap.end());
+        const int32_t r0 = heap.back().second;
+        heap.pop_back();
+        const int32_t r1 = end_of[r0];
+        const int64_t half = (int64_t(row_ptr[r0]) + row_ptr[r1]) / 2;
+        int32_t m = r0 + 1;
+        while (m < r1 - 1 && row_ptr[m] < half) ++m;
+        end_of[r0] = m;
+        end_of[m] = r1;
+        cuts.push_back(m);
+        if (m - r0 > 1) {
+          heap.emplace_back(int64_t(row_ptr[m]) - row_ptr[r0], r0);
+          std::push_heap(heap.begin(), heap.end());
+        }
+        if (r1 - m > 1) {
+          heap.emplace_back(int64_t(row_ptr[r1]) - row_ptr[m], m);
+          std::push_heap(heap.begin(), heap.end());
+        }
+      }
+      wblocks.insert(wblocks.end(), cuts.begin(), cuts.end());
+      std::sort(wblocks.begin(), wblocks.end());
+    }
+  }
   for (int32_t b : wblocks) wblock_k0.push_back(row_ptr[b]);
 
   const int G = adjoint_grid_for(D->ctx, D->nnz);
@@ -173,6 +214,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
       (rc = dev_alloc(&D->wg_c0, static_cast<size_t>(G))) || (rc = dev_alloc(&D->wg_c1, static_cast<size_t>(G))) ||
       (rc = dev_alloc(&D->col_wlo, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
+      (rc = dev_alloc(&D->col_kind, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->pieces, 2 * static_cast<size_t>(G))))
     return rc;
   hipStream_t s = D->ctx->stream;
@@ -185,6 +227,9 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   IMRT_HIP(hipMemcpyAsync(D->wg_c1, wg_c1.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_whi, col_whi.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
+  std::vector<uint8_t> kind(D->nb);
+  for (int c = 0; c < D->nb; ++c) kind[c] = static_cast<uint8_t>(std::min(col_whi[c] - col_wlo[c], 2));
+  IMRT_HIP(hipMemcpyAsync(D->col_kind, kind.data(), D->nb, hipMemcpyHostToDevice, s));
   D->fwd_cap = forward_grid_cap(D->ctx, D);
   D->partials_len = kMaxTrials * (D->fwd_cap + 1) + 16;
   if ((rc = dev_alloc(&D->partials, D->partials_len))) return rc;
@@ -215,6 +260,7 @@ void free_dose(imrt_dose* D) {
   dev_free(D->wg_c1);
   dev_free(D->col_wlo);
   dev_free(D->col_whi);
+  dev_free(D->col_kind);
   dev_free(D->pieces);
   dev_free(D->sid);
   dev_free(D->partials);
@@ -877,10 +923,6 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   if (e == hipSuccess) e = hipMemcpyAsync(P->st, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->st + 1, &P->st_host[0], sizeof(SolverState), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(P->xbuf[0], x_dev, sizeof(float) * D->nb, hipMemcpyDeviceToDevice, s);
-  // the initial evaluation multiplies by x_1 in every trial row
-  for (int q = 0; q < nt && e == hipSuccess; ++q)
-    e = hipMemcpyAsync(P->xstage + static_cast<size_t>(q) * pad4(D->nb), x_dev, sizeof(float) * D->nb,
-                       hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) {
     cleanup();
     return hip_error(e, "solve setup");
@@ -890,8 +932,17 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   FwdArgs fa = base_fwd(D);
   fa.mode = FWD_SOLVE;
   set_plan_penalties(fa, P);
-  fa.x = P->xstage;
-  for (int i = 0; i <= kMaxTrials; ++i) fa.rbuf[i] = P->rbuf[i];
+  fa.g = P->gk;
+  fa.col_kind = D->col_kind;
+  fa.pieces_col = P->pieces_col;
+  fa.pieces = P->pieces;
+  fa.col_wlo = D->col_wlo;
+  fa.col_whi = D->col_whi;
+  fa.g_scale = 2.0;
+  for (int i = 0; i <= kMaxTrials; ++i) {
+    fa.xbuf[i] = P->xbuf[i];
+    fa.rbuf[i] = P->rbuf[i];
+  }
   fa.partials = P->fwd_partials;
   AdjArgs aa = base_adj(D);
   aa.solve = 1;
@@ -902,20 +953,9 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   aa.scale = 2.0;
   aa.fwd_partials = P->fwd_partials;
   aa.fwd_parts = grid;
-  aa.step_partials = P->step_partials;
-  aa.step_parts = step_grid(D->nb);
+  aa.step_partials = P->fwd_partials + static_cast<size_t>(nt) * grid;
+  aa.step_parts = 1;
   aa.trace = cap > 0 ? P->trace : nullptr;
-  StepArgs sa{};
-  sa.col_wlo = D->col_wlo;
-  sa.col_whi = D->col_whi;
-  sa.pieces = P->pieces;
-  sa.pieces_col = P->pieces_col;
-  sa.g = P->gk;
-  sa.scale = 2.0;
-  for (int i = 0; i <= kMaxTrials; ++i) sa.xbuf[i] = P->xbuf[i];
-  sa.xstage = P->xstage;
-  sa.step_partials = P->step_partials;
-  sa.nb = D->nb;
 
   // The two state copies alternate: pass n reads st[n % 2] and writes st[(n + 1) % 2].
   long long pass = 0;
@@ -937,13 +977,9 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     if (r != hipSuccess) return hip_error(r, "hipEventCreate");
     aa.st_in = state_in();
     aa.st_out = state_out();
-    int rr = launch_adjoint(C, D, aa, nt, a0, a1);
+    const int rr = launch_adjoint(C, D, aa, nt, a0, a1);
     ++pass;
-    if (rr) return rr;
-    // gradient completion and trial points for the next forward pass, from
-    // the state the adjoint pass wrote (the forward pass reads it too)
-    sa.st = state_in();
-    return launch_step(C, sa, nt);
+    return rr;
   };
 
   // initial evaluation G(x_1)

@@ -85,11 +85,21 @@ struct FwdArgs {
   int32_t nwblocks;
   int32_t nstruct;
   Penalties pen;
-  const float* x;            // eval/plain input vector; solve: trial vectors [trial][pad4(nb)]
-  float* rbuf[kMaxTrials + 1];  // solve: residual of trial q into rbuf[q] (r(x_k) = rbuf[st->acc])
+  const float* x;            // eval/plain input vector
+  // solve: gradient of x_k (complete for columns of one adjoint workgroup;
+  // shared columns from their pieces), iterate buffers, residual buffers
+  const float* g;
+  const uint8_t* col_kind;   // 0: one adjoint workgroup, 1: two (pieces_col), 2: more (pieces)
+  const double* pieces_col;
+  const double* pieces;
+  const int32_t* col_wlo;
+  const int32_t* col_whi;
+  double g_scale;
+  float* xbuf[kMaxTrials + 1];  // x_k = xbuf[st->xi]; trial q goes to xbuf[(xi + 1 + q) % (NT + 1)]
+  float* rbuf[kMaxTrials + 1];  // residual of trial q into rbuf[q] (r(x_k) = rbuf[st->acc])
   float* d_out;              // eval/plain: dose (nullable in eval)
   float* r_out;              // eval: residual (nullable)
-  double* partials;          // [trial][gridDim.x] objective partials
+  double* partials;          // [trial][gridDim.x] objective partials, then (solve) [trial] step norms
   const SolverState* st_in;  // solve: state before this pass
   SolverState* st_out;       // solve: state after it (copied through by workgroup 0)
 };
@@ -188,6 +198,7 @@ struct imrt_dose {
   int32_t* wg_c1 = nullptr;
   int32_t* col_wlo = nullptr;
   int32_t* col_whi = nullptr;
+  uint8_t* col_kind = nullptr; // per column: 0 one adjoint workgroup, 1 two, 2 more
   double* pieces = nullptr;
   // structure ids from the phantom builder (nullable)
   uint8_t* sid = nullptr;

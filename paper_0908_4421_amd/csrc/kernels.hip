@@ -541,6 +541,118 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
   __syncthreads();
 }
 
+// Trial staging of a solve's forward pass: for every beamlet the gradient
+// entry (columns shared by two adjoint workgroups completed from their two
+// float64 pieces, in order; by more, from the per-workgroup pieces), the
+// iterate x_k (the state names its buffer; every candidate is loaded before
+// the state arrives) and the NT trial points x_t^(q) = max(0, x_k - lambda_q g)
+// (Eq. (4) with the projection of step 2), written to LDS.  The lead
+// workgroup also stores the trials in their iterate buffers and reduces
+// their step norms ||x_t^(q) - x_k||^2.  The initial evaluation stages x_1.
+constexpr int kTrialU = 4;   // beamlets per thread per round of trial staging
+
+template <int NT>
+struct TrialRegs {
+  float xc[NT + 1][kTrialU];
+  float g[kTrialU];
+  double p0[kTrialU], p1[kTrialU];
+  uint32_t kind[kTrialU];
+  double tab;
+};
+
+template <int NT>
+__device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<NT>& R) {
+  const int nb = a.nb;
+#pragma unroll
+  for (int u = 0; u < kTrialU; ++u) {
+    const int i = i0 + u * kThreads;
+    const int ii = i < nb ? i : 0;
+#pragma unroll
+    for (int j = 0; j <= NT; ++j) R.xc[j][u] = a.xbuf[j][ii];
+    R.g[u] = a.g[ii];
+    R.p0[u] = a.pieces_col[2 * ii];
+    R.p1[u] = a.pieces_col[2 * ii + 1];
+    R.kind[u] = a.col_kind[ii];
+  }
+}
+
+// Sum of the pieces of a column shared by three or more adjoint workgroups.
+__device__ __forceinline__ double pieces_sum(const FwdArgs& a, int c) {
+  const int wlo = a.col_wlo[c], whi = a.col_whi[c];
+  double tot = a.pieces[2 * wlo + 1];
+  for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
+  tot += a.pieces[2 * whi];
+  return tot;
+}
+
+struct TrialCtl {
+  bool init, lead;
+  int xi;
+};
+
+template <int NT>
+__device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const TrialRegs<NT>& R, const TrialCtl& T,
+                                            const double (&lam)[NT], float* xs, double (&sq)[NT]) {
+  const int nb = a.nb, nbp = pad4(nb);
+#pragma unroll
+  for (int u = 0; u < kTrialU; ++u) {
+    const int i = i0 + u * kThreads;
+    if (i >= nb) continue;
+    float x = R.xc[0][u];
+#pragma unroll
+    for (int j = 1; j <= NT; ++j) x = (T.xi == j) ? R.xc[j][u] : x;
+    if (T.init) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = x;
+      continue;
+    }
+    float g = R.g[u];
+    if (R.kind[u] == 1) g = static_cast<float>(a.g_scale * (R.p0[u] + R.p1[u]));
+    else if (R.kind[u] > 1) g = static_cast<float>(a.g_scale * pieces_sum(a, i));
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const float t = trial_point(x, g, lam[q]);
+      xs[q * nbp + i] = t;
+      if (T.lead) {
+        select_buf(a.xbuf, (T.xi + 1 + q) % (NT + 1))[i] = t;
+        const double dl = static_cast<double>(t) - static_cast<double>(x);
+        sq[q] += dl * dl;
+      }
+    }
+  }
+}
+
+// After the first round (loaded by the caller): the remaining rounds, the
+// lead workgroup's step norms, the penalty table; ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<NT>& R, const TrialCtl& T,
+                                             const double (&lam)[NT], PenaltyDev* tab, float* xs, double* red) {
+  const int tid = threadIdx.x;
+  double sq[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) sq[q] = 0.0;
+  {
+    double* dst = reinterpret_cast<double*>(tab);
+    if (tid < 4 * a.nstruct) dst[tid] = R.tab;
+    for (int i = tid + kThreads; i < 4 * a.nstruct; i += kThreads)
+      dst[i] = reinterpret_cast<const double*>(a.pen.table)[i];
+  }
+  trial_store<NT>(a, tid, R, T, lam, xs, sq);
+  for (int i0 = tid + kTrialU * kThreads; i0 < a.nb; i0 += kTrialU * kThreads) {
+    TrialRegs<NT> R2;
+    trial_load<NT>(a, i0, R2);
+    trial_store<NT>(a, i0, R2, T, lam, xs, sq);
+  }
+  if (T.lead && !T.init) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const double t = block_sum(sq[q], red);
+      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
+    }
+  }
+  __syncthreads();
+}
+
 template <int NT>
 __device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src, PenaltyDev* tab, float* xs,
                                              bool want_sid) {
@@ -576,6 +688,10 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
   float* rout[NT];
 #pragma unroll
   for (int q = 0; q < NT; ++q) rout[q] = nullptr;
+  TrialCtl T{true, false, 0};
+  double lam[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) lam[q] = 0.0;
   if (solve) {
     const SolverState* st = a.st_in;
     // the state passes through unchanged (word copy by workgroup 0)
@@ -585,6 +701,13 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     const int phase = st->phase;
     if (phase == PH_DONE) return;
     ntr = (phase == PH_INIT) ? 1 : NT;
+    T.init = (phase == PH_INIT);
+    T.lead = (blockIdx.x == 0);
+    T.xi = st->xi;
+    lam[0] = st->lambda;
+    const double alpha = st->alpha;
+#pragma unroll
+    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
 #pragma unroll
     for (int q = 0; q < NT; ++q) rout[q] = a.rbuf[q];
   }
@@ -604,7 +727,14 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     if (b0 + 1 < b1) nxt = block_meta(a, b0 + 1);
   }
 
-  stage_inputs<NT>(a, a.x, tab, xs, want_sid);
+  if (solve) {
+    TrialRegs<NT> TR;
+    trial_load<NT>(a, tid, TR);
+    TR.tab = (tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
+    trial_finish<NT>(a, TR, T, lam, tab, xs, red);
+  } else {
+    stage_inputs<NT>(a, a.x, tab, xs, want_sid);
+  }
 
   double pacc[NT];
 #pragma unroll
@@ -839,6 +969,19 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
 #pragma unroll
   for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
   const rsrc_t dout = make_rsrc(a.d_out, a.d_out ? vbytes : 0u);
+  // a solve's trial inputs are loaded before the state is known
+  TrialRegs<NT> TR;
+  StageRegs<NT> SR;
+  if (solve) {
+    trial_load<NT>(a, tid, TR);
+    TR.tab = (tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
+  } else {
+    stage_start<NT>(a, a.x, want_sid, SR);
+  }
+  TrialCtl T{true, false, 0};
+  double lam[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) lam[q] = 0.0;
   if (solve) {
     const SolverState* st = a.st_in;
     constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
@@ -847,6 +990,13 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     const int phase = st->phase;
     if (phase == PH_DONE) return;
     ntr = (phase == PH_INIT) ? 1 : NT;
+    T.init = (phase == PH_INIT);
+    T.lead = (blockIdx.x == 0);
+    T.xi = st->xi;
+    lam[0] = st->lambda;
+    const double alpha = st->alpha;
+#pragma unroll
+    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
 #pragma unroll
     for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
@@ -878,18 +1028,17 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     return m;
   };
 
-  // Load order: block bounds (above), staging loads, then the first block's
+  // Load order: staging loads (above), block bounds, then the first block's
   // loads, so that waiting for the staging loads does not wait for the
   // block (the wait counter drains in issue order).
-  StageRegs<NT> SR;
-  stage_start<NT>(a, a.x, want_sid, SR);
   WaveStage S;
   WaveBlock cur{0, 0, 0, 0};
   if (b0 < b1) {
     cur = meta(b0);
     if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
   }
-  stage_finish<NT>(a, a.x, want_sid, SR, tab, xs);
+  if (solve) trial_finish<NT>(a, TR, T, lam, tab, xs, red);
+  else stage_finish<NT>(a, a.x, want_sid, SR, tab, xs);
 
   double pacc[NT];
 #pragma unroll
