@@ -277,8 +277,6 @@ void free_plan(imrt_plan* P) {
   for (auto& b : P->rbuf) dev_free(b);
   for (auto& b : P->xbuf) dev_free(b);
   dev_free(P->gk);
-  dev_free(P->xstage);
-  dev_free(P->step_partials);
   dev_free(P->vtmp);
   dev_free(P->fwd_partials);
   dev_free(P->pieces);
@@ -655,8 +653,6 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
   P->fwd_cap = grid;
   if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
       (rc = ensure_buffers(P, 2)) || (rc = dev_alloc(&P->gk, dose->nb)) || (rc = dev_alloc(&P->vtmp, dose->nv)) ||
-      (rc = dev_alloc(&P->xstage, static_cast<size_t>(kMaxTrials) * pad4(dose->nb))) ||
-      (rc = dev_alloc(&P->step_partials, static_cast<size_t>(kMaxTrials) * step_grid(dose->nb))) ||
       (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
       (rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(dose->adj_grid))) ||
       (rc = dev_alloc(&P->pieces_col, 2 * static_cast<size_t>(dose->nb))) || (rc = dev_alloc(&P->misc, 16)) ||

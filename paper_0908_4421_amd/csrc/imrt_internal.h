@@ -137,23 +137,6 @@ struct AdjArgs {
   TraceDev* trace;
 };
 
-// Between an adjoint pass and the next forward pass of a solve: gradient
-// entries of shared columns completed from the adjoint pieces, then the trial
-// points x_t^(q) = max(0, x_k - lambda_q g) and their step norms.
-struct StepArgs {
-  const SolverState* st;     // state after the adjoint pass (read by the next forward pass too)
-  const int32_t* col_wlo;
-  const int32_t* col_whi;
-  const double* pieces;
-  const double* pieces_col;  // 2 * nb: pieces of columns shared by exactly two workgroups
-  float* g;                  // gradient: complete for unshared columns, completed here for shared ones
-  double scale;
-  float* xbuf[kMaxTrials + 1];  // iterate buffers; trial q goes to xbuf[(xi + 1 + q) % (NT + 1)]
-  float* xstage;             // trial vectors for the forward pass, [trial][pad4(nb)]
-  double* step_partials;     // [trial][gridDim.x]
-  int32_t nb;
-};
-
 // ---- host-side objects ------------------------------------------------------------
 struct Tuning {
   int fwd_grid_per_cu = 4;
@@ -223,8 +206,6 @@ struct imrt_plan {
   float* rbuf[imrt::kMaxTrials + 1] = {};
   float* xbuf[imrt::kMaxTrials + 1] = {};
   float* gk = nullptr;
-  float* xstage = nullptr;        // kMaxTrials * pad4(nb) trial vectors of the next forward pass
-  double* step_partials = nullptr;  // kMaxTrials * step grid
   float* vtmp = nullptr;          // nv scratch
   double* fwd_partials = nullptr; // kMaxTrials * (fwd_cap + 1)
   int32_t fwd_cap = 1;
@@ -275,8 +256,6 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
-int step_grid(int nb);
-int launch_step(const imrt_ctx* ctx, const StepArgs& a, int ntrials);
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);

@@ -1,17 +1,16 @@
 // Hot-path kernels of the gradient-projection / Armijo solver for gfx950.
 //
 //  fwd_kernel / fwd_wave_kernel
-//               trial vectors staged in LDS, forward dose z = D x over CSR
-//               (Section 2.1), penalty residual and objective partials
-//               (Eqs. (1)-(2)), in one pass over D.
+//               trial points x_t = max(0, x_k - lambda g) (steps 2 and 4)
+//               staged in LDS, forward dose z = D x over CSR (Section 2.1),
+//               penalty residual and objective partials (Eqs. (1)-(2)), in
+//               one pass over D.
 //  adj_kernel   line-search decision on the preceding forward pass (Armijo
 //               test of Eq. (5), stopping test of step 5), taken identically
 //               by every workgroup, then the beamlet-parallel adjoint
 //               g = 2 D^T r over CSC for an accepted, unfinished iterate.
-//  step_kernel  between the adjoint and the forward pass of a solve:
-//               completes beamlet columns shared by several adjoint
-//               workgroups and writes the trial points and step norms.
-//  adj_final    completes shared columns outside a solve.
+//  adj_final    completes shared columns outside a solve (in a solve the
+//               next forward pass completes them while staging its trials).
 //
 // The solver state is double-buffered: a pass reads one copy and workgroup 0
 // writes the other, so no workgroup ever sees a state written during its own
@@ -1343,62 +1342,6 @@ __global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const So
   a.out[c] = static_cast<float>(a.scale * tot);
 }
 
-// Step kernel of a solve, between the adjoint pass and the next forward pass
-// (steps 2 and 4): for a fresh gradient, the entries of columns shared by
-// several adjoint workgroups are completed (fixed-order sum of the pieces);
-// then every trial point x_t^(q) = max(0, x_k - lambda_q g) is written to its
-// iterate buffer and to the forward pass's staging rows, with per-workgroup
-// partial sums of ||x_t^(q) - x_k||^2.  Idle unless the state asks for a
-// trial pass.
-template <int NT>
-__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
-  __shared__ double red[kWaves];
-  const int c = blockIdx.x * kThreads + threadIdx.x;
-  const bool in = c < a.nb;
-  const int cc = in ? c : 0;
-  // loads that do not wait for the state: every iterate buffer's entry
-  float xc[NT + 1];
-#pragma unroll
-  for (int i = 0; i <= NT; ++i) xc[i] = a.xbuf[i][cc];
-  float g = a.g[cc];
-  const int wlo = a.col_wlo[cc], whi = a.col_whi[cc];
-  const double p0 = a.pieces_col[2 * cc], p1 = a.pieces_col[2 * cc + 1];
-  const SolverState* st = a.st;
-  const int phase = st->phase;
-  if (phase != PH_NEED_GRAD && phase != PH_TRIAL) return;
-  const int xi = st->xi;
-  float x = xc[0];
-#pragma unroll
-  for (int i = 1; i <= NT; ++i) x = (xi == i) ? xc[i] : x;
-  if (phase == PH_NEED_GRAD && in && wlo != whi) {
-    double tot;
-    if (whi - wlo == 1) {
-      tot = p0 + p1;
-    } else {
-      tot = a.pieces[2 * wlo + 1];
-      for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
-      tot += a.pieces[2 * whi];
-    }
-    g = static_cast<float>(a.scale * tot);
-    a.g[c] = g;
-  }
-  const int nbp = pad4(a.nb);
-  double lam = st->lambda;
-  const double alpha = st->alpha;
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    if (q > 0) lam = lam / alpha;
-    const float t = trial_point(x, g, lam);
-    if (in) {
-      select_buf(a.xbuf, (xi + 1 + q) % (NT + 1))[c] = t;
-      a.xstage[q * nbp + c] = t;
-    }
-    const double dl = in ? static_cast<double>(t) - static_cast<double>(x) : 0.0;
-    const double sq = block_sum(dl * dl, red);
-    if (threadIdx.x == 0) a.step_partials[q * gridDim.x + blockIdx.x] = sq;
-  }
-}
-
 // ---- small utility kernels ----------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void sum_kernel(const double* parts, int n, double* out) {
   __shared__ double red[kWaves];
@@ -1550,20 +1493,6 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
   }
   (void)D;
   return rc;
-}
-
-int step_grid(int nb) { return std::max(1, (nb + kThreads - 1) / kThreads); }
-
-int launch_step(const imrt_ctx* ctx, const StepArgs& a, int ntrials) {
-  clear_stale_error();
-  const dim3 gd(step_grid(a.nb)), bd(kThreads);
-  switch (ntrials) {
-    case 1: hipLaunchKernelGGL(step_kernel<1>, gd, bd, 0, ctx->stream, a); break;
-    case 2: hipLaunchKernelGGL(step_kernel<2>, gd, bd, 0, ctx->stream, a); break;
-    case 4: hipLaunchKernelGGL(step_kernel<4>, gd, bd, 0, ctx->stream, a); break;
-    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
-  }
-  return check_launch("step_kernel");
 }
 
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out) {
