@@ -148,12 +148,18 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die
  *                    (shared L2 for residual gathers); 0: dispatch order, so
  *                    every die gets a mix of beams (default)
+ *   "voxel_tiles"    1: imrt_build_dose_matrix stores the rows of D in tiles of
+ *                    4 x 4 x 2 voxels (default), so that the residual gathers
+ *                    of every beam direction touch few cache lines; 0: in
+ *                    grid order.  Voxel-indexed arrays passed to or from the
+ *                    API are in grid order either way.
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
  * "adj_wg_per_cu" and "adj_min_nnz" are read when a dose matrix is created.
  * Results are deterministic for given settings; the settings change only the
- * grouping of the float64 partial sums of G and of shared columns.
+ * grouping of the float32 row sums and of the float64 partial sums of G and
+ * of shared columns.
  * Unknown names or out-of-range values return IMRT_EINVAL. */
 IMRT_API int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value);
 IMRT_API int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t* value);
@@ -162,9 +168,11 @@ IMRT_API int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t*
 
 /* Build the synthetic phantom's structure ids and D on the device (CSR and
  * CSC, float32 values, int32 indices; columns ascending in each row, rows
- * ascending in each column).  voxel_struct_out: nullable host array of
- * nx*ny*nz bytes receiving the structure ids.  Beamlet order: beam-major,
- * then lateral index, then axial index. */
+ * ascending in each column; the rows are held in the internal voxel order
+ * of the "voxel_tiles" option, and imrt_dose_export returns grid order).
+ * voxel_struct_out: nullable host array of nx*ny*nz bytes receiving the
+ * structure ids (grid order j = ix + nx*(iy + ny*iz)).  Beamlet order:
+ * beam-major, then lateral index, then axial index. */
 IMRT_API int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype storage,
                            imrt_dose** out, uint8_t* voxel_struct_out);
 

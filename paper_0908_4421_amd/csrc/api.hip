@@ -261,6 +261,8 @@ void free_dose(imrt_dose* D) {
   dev_free(D->col_wlo);
   dev_free(D->col_whi);
   dev_free(D->col_kind);
+  dev_free(D->vox);
+  dev_free(D->vscratch);
   dev_free(D->pieces);
   dev_free(D->sid);
   dev_free(D->partials);
@@ -409,6 +411,7 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_ADJ_XCD")) c->tune.adj_xcd = (std::atoi(f) != 0) ? 1 : 0;
+  if (const char* f = std::getenv("IMRT_VOXEL_TILES")) c->tune.voxel_tiles = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
   return IMRT_OK;
@@ -447,6 +450,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.adj_xcd;
   }
+  if (n == "voxel_tiles") {
+    *lo = 0;
+    return &ctx->tune.voxel_tiles;
+  }
   return nullptr;
 }
 }  // namespace
@@ -457,7 +464,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd") ? 1 : (int64_t(1) << 30);
+  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1 : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
   return IMRT_OK;
@@ -488,9 +495,15 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
   } catch (const std::bad_alloc&) {
     rc = set_error(IMRT_ENOMEM, "host allocation failed");
   }
+  if (rc == IMRT_OK && D->vox) {
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(&D->vscratch), sizeof(float) * D->nv);
+    if (e != hipSuccess) rc = hip_error(e, "hipMalloc(permutation scratch)");
+  }
   if (rc == IMRT_OK && voxel_struct_out) {
-    const hipError_t e = hipMemcpy(voxel_struct_out, D->sid, D->nv, hipMemcpyDeviceToHost);
+    std::vector<uint8_t> ids(D->nv);
+    const hipError_t e = hipMemcpy(ids.data(), D->sid, D->nv, hipMemcpyDeviceToHost);
     if (e != hipSuccess) rc = hip_error(e, "hipMemcpy(voxel_struct)");
+    for (int32_t p = 0; rc == IMRT_OK && p < D->nv; ++p) voxel_struct_out[D->vox ? D->vox_host[p] : p] = ids[p];
   }
   if (rc) {
     free_dose(D);
@@ -584,33 +597,85 @@ int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, flo
   if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
   int rc = use_device(D->ctx);
   if (rc) return rc;
-  hipStream_t s = D->ctx->stream;
-  const size_t nz = static_cast<size_t>(D->nnz);
   if (voxel_struct && !D->sid) return set_error(IMRT_EINVAL, "this dose matrix has no structure ids");
-  if (row_ptr) IMRT_HIP(hipMemcpyAsync(row_ptr, D->row_ptr, sizeof(int32_t) * (D->nv + 1), hipMemcpyDeviceToHost, s));
-  if (col_idx && nz) IMRT_HIP(hipMemcpyAsync(col_idx, D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
-  if (val && nz) IMRT_HIP(hipMemcpyAsync(val, D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
-  if (col_ptr) IMRT_HIP(hipMemcpyAsync(col_ptr, D->col_ptr, sizeof(int32_t) * (D->nb + 1), hipMemcpyDeviceToHost, s));
-  if (voxel_struct) IMRT_HIP(hipMemcpyAsync(voxel_struct, D->sid, D->nv, hipMemcpyDeviceToHost, s));
-  if ((row_idx || cval) && nz) {
-    // CSC arrays come back in plain column-major order
-    try {
+  hipStream_t s = D->ctx->stream;
+  const int nv = D->nv, nb = D->nb;
+  const size_t nz = static_cast<size_t>(D->nnz);
+  const bool perm = D->vox != nullptr;
+  try {
+    // internal arrays (CSC back in plain column-major order), then the
+    // caller's voxel order: rows of D and row indices of the CSC mapped by vox
+    const bool want_csr = row_ptr || col_idx || val;
+    const bool want_csc = row_idx || cval;
+    std::vector<int32_t> rp(want_csr ? nv + 1 : 0), ci(want_csr ? nz : 0), cp(nb + 1), ri;
+    std::vector<float> va(want_csr ? nz : 0), cv;
+    std::vector<uint8_t> sid(voxel_struct ? nv : 0);
+    if (want_csr) {
+      IMRT_HIP(hipMemcpyAsync(rp.data(), D->row_ptr, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToHost, s));
+      if (nz) IMRT_HIP(hipMemcpyAsync(ci.data(), D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+      if (nz) IMRT_HIP(hipMemcpyAsync(va.data(), D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
+    }
+    IMRT_HIP(hipMemcpyAsync(cp.data(), D->col_ptr, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+    if (want_csc && nz) {
       const size_t nzc = csc_alloc(D->nnz);
-      std::vector<int32_t> ri(row_idx ? nzc : 0);
-      std::vector<float> cv(cval ? nzc : 0);
-      if (row_idx) IMRT_HIP(hipMemcpyAsync(ri.data(), D->row_idx, sizeof(int32_t) * nzc, hipMemcpyDeviceToHost, s));
-      if (cval) IMRT_HIP(hipMemcpyAsync(cv.data(), D->cval, sizeof(float) * nzc, hipMemcpyDeviceToHost, s));
+      std::vector<int32_t> rit(nzc);
+      std::vector<float> cvt(nzc);
+      IMRT_HIP(hipMemcpyAsync(rit.data(), D->row_idx, sizeof(int32_t) * nzc, hipMemcpyDeviceToHost, s));
+      IMRT_HIP(hipMemcpyAsync(cvt.data(), D->cval, sizeof(float) * nzc, hipMemcpyDeviceToHost, s));
       IMRT_HIP(hipStreamSynchronize(s));
+      ri.resize(nz);
+      cv.resize(nz);
       for (size_t k = 0; k < nz; ++k) {
         const int64_t p = csc_slot(static_cast<int64_t>(k));
-        if (row_idx) row_idx[k] = ri[p];
-        if (cval) cval[k] = cv[p];
+        ri[k] = rit[p];
+        cv[k] = cvt[p];
       }
-    } catch (const std::bad_alloc&) {
-      return set_error(IMRT_ENOMEM, "host allocation failed");
     }
+    if (voxel_struct) IMRT_HIP(hipMemcpyAsync(sid.data(), D->sid, nv, hipMemcpyDeviceToHost, s));
+    IMRT_HIP(hipStreamSynchronize(s));
+    if (col_ptr) std::memcpy(col_ptr, cp.data(), sizeof(int32_t) * (nb + 1));
+    if (!perm) {
+      if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int32_t) * (nv + 1));
+      if (col_idx && nz) std::memcpy(col_idx, ci.data(), sizeof(int32_t) * nz);
+      if (val && nz) std::memcpy(val, va.data(), sizeof(float) * nz);
+      if (row_idx && nz) std::memcpy(row_idx, ri.data(), sizeof(int32_t) * nz);
+      if (cval && nz) std::memcpy(cval, cv.data(), sizeof(float) * nz);
+      if (voxel_struct) std::memcpy(voxel_struct, sid.data(), nv);
+      return IMRT_OK;
+    }
+    const std::vector<int32_t>& vox = D->vox_host;
+    std::vector<int32_t> ipos(nv);
+    for (int32_t p = 0; p < nv; ++p) ipos[vox[p]] = p;
+    if (want_csr) {
+      int64_t k = 0;
+      for (int32_t jv = 0; jv < nv; ++jv) {
+        const int32_t p = ipos[jv];
+        if (row_ptr) row_ptr[jv] = static_cast<int32_t>(k);
+        for (int32_t e = rp[p]; e < rp[p + 1]; ++e, ++k) {
+          if (col_idx) col_idx[k] = ci[e];
+          if (val) val[k] = va[e];
+        }
+      }
+      if (row_ptr) row_ptr[nv] = static_cast<int32_t>(k);
+    }
+    if (want_csc) {
+      std::vector<std::pair<int32_t, float>> col;
+      for (int32_t c = 0; c < nb; ++c) {
+        col.clear();
+        for (int32_t e = cp[c]; e < cp[c + 1]; ++e) col.emplace_back(vox[ri[e]], cv[e]);
+        std::sort(col.begin(), col.end(),
+                  [](const std::pair<int32_t, float>& x, const std::pair<int32_t, float>& y) { return x.first < y.first; });
+        for (int32_t e = cp[c]; e < cp[c + 1]; ++e) {
+          if (row_idx) row_idx[e] = col[e - cp[c]].first;
+          if (cval) cval[e] = col[e - cp[c]].second;
+        }
+      }
+    }
+    if (voxel_struct)
+      for (int32_t p = 0; p < nv; ++p) voxel_struct[vox[p]] = sid[p];
+  } catch (const std::bad_alloc&) {
+    return set_error(IMRT_ENOMEM, "host allocation failed");
   }
-  IMRT_HIP(hipStreamSynchronize(s));
   return IMRT_OK;
 }
 
@@ -621,15 +686,20 @@ int imrt_dose_apply(const imrt_dose* D, const float* x_dev, float* d_dev) {
   FwdArgs a = base_fwd(D);
   a.mode = FWD_PLAIN;
   a.x = x_dev;
-  a.d_out = d_dev;
+  a.d_out = D->vox ? D->vscratch : d_dev;
   a.partials = D->partials;
-  return launch_forward(D->ctx, D, a, 1, std::min(forward_grid(D->ctx, D), D->fwd_cap));
+  if ((rc = launch_forward(D->ctx, D, a, 1, std::min(forward_grid(D->ctx, D), D->fwd_cap)))) return rc;
+  return D->vox ? launch_permute(D->ctx, D->vscratch, D->vox, D->nv, d_dev, true) : IMRT_OK;
 }
 
 int imrt_dose_apply_transpose(const imrt_dose* D, const float* r_dev, float* y_dev) {
   if (!D || !r_dev || !y_dev) return set_error(IMRT_EINVAL, "dose, r or y is NULL");
   int rc = use_device(D->ctx);
   if (rc) return rc;
+  if (D->vox) {
+    if ((rc = launch_permute(D->ctx, r_dev, D->vox, D->nv, D->vscratch, false))) return rc;
+    r_dev = D->vscratch;
+  }
   return adjoint_into(D->ctx, D, r_dev, 1.0, y_dev);
 }
 
@@ -683,7 +753,8 @@ int imrt_set_structures(imrt_plan* P, const uint8_t* voxel_struct, int32_t nstru
     return set_error(IMRT_ENOMEM, "host allocation failed");
   }
   if (voxel_struct) {
-    std::memcpy(ids.data(), voxel_struct, D->nv);
+    // caller's voxel order to the internal one
+    for (int32_t p = 0; p < D->nv; ++p) ids[p] = voxel_struct[D->vox ? D->vox_host[p] : p];
   } else {
     if (!D->sid) return set_error(IMRT_EINVAL, "NULL structure ids need a dose matrix from imrt_build_dose_matrix");
     IMRT_HIP(hipMemcpy(ids.data(), D->sid, D->nv, hipMemcpyDeviceToHost));
@@ -744,6 +815,18 @@ int imrt_set_voxel_targets(imrt_plan* P, const float* T_under, const float* T_ov
       return set_error(IMRT_EINVAL, "voxel targets must be finite");
   if (!P->Tu_vox && (rc = dev_alloc(&P->Tu_vox, nv))) return rc;
   if (!P->To_vox && (rc = dev_alloc(&P->To_vox, nv))) return rc;
+  const imrt_dose* D = P->dose;
+  std::vector<float> tu, to;
+  if (D->vox) {
+    tu.resize(nv);
+    to.resize(nv);
+    for (int32_t p = 0; p < nv; ++p) {
+      tu[p] = T_under[D->vox_host[p]];
+      to[p] = T_over[D->vox_host[p]];
+    }
+    T_under = tu.data();
+    T_over = to.data();
+  }
   IMRT_HIP(hipMemcpy(P->Tu_vox, T_under, sizeof(float) * nv, hipMemcpyHostToDevice));
   IMRT_HIP(hipMemcpy(P->To_vox, T_over, sizeof(float) * nv, hipMemcpyHostToDevice));
   return IMRT_OK;
@@ -753,8 +836,11 @@ int imrt_evaluate_objective(imrt_plan* P, const float* x_dev, double* G_out, flo
   int rc = plan_ready(P);
   if (rc) return rc;
   if (!x_dev || !G_out) return set_error(IMRT_EINVAL, "x or G_out is NULL");
-  if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, dose_dev, nullptr, 0)) || (rc = fetch_misc(P, 1)))
-    return rc;
+  const imrt_dose* D = P->dose;
+  float* d_int = (dose_dev && D->vox) ? P->vtmp : dose_dev;
+  if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, d_int, nullptr, 0))) return rc;
+  if (dose_dev && D->vox && (rc = launch_permute(P->ctx, P->vtmp, D->vox, D->nv, dose_dev, true))) return rc;
+  if ((rc = fetch_misc(P, 1))) return rc;
   *G_out = P->misc_host[0];
   return IMRT_OK;
 }

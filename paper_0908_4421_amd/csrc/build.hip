@@ -78,10 +78,15 @@ __device__ __forceinline__ double exponent(const Geo& g, double depth, double u,
   return (g.mu * depth) + (r2 / g.two_sig2);
 }
 
-__global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, uint8_t* sid) {
+// Rows of D follow the internal voxel order: row p is voxel vox[p] (p itself
+// when vox is NULL).
+__device__ __forceinline__ int voxel_of(const int32_t* vox, int p) { return vox ? vox[p] : p; }
+
+__global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, const int32_t* vox, uint8_t* sid) {
   const int nv = g.nx * g.ny * g.nz;
-  const int j = blockIdx.x * kThreads + threadIdx.x;
-  if (j >= nv) return;
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= nv) return;
+  const int j = voxel_of(vox, p);
   double x, y, z;
   voxel_xyz(g, j, x, y, z);
   uint8_t s = 0;
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, uint8_t* sid
   const double dyr = y - cr;
   if (x * x + dyr * dyr <= g.r_rectum * g.r_rectum) s = 2;
   if ((x * x + y * y) + z * z <= g.r_ptv * g.r_ptv) s = 1;
-  sid[j] = s;
+  sid[p] = s;
 }
 
 // One workgroup per beamlet: minimum exponent over all voxels (exact; order-free).
@@ -121,8 +126,8 @@ __global__ __launch_bounds__(kThreads) void emin_kernel(Geo g, const BeamletDev*
 
 // One workgroup per beamlet: ordered compaction of the kept voxels (CSC).
 // With fill == false only the count is produced.
-__global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDev* bl, const double2* dirs,
-                                                          const double* emin, int32_t* counts,
+__global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* vox, const BeamletDev* bl,
+                                                          const double2* dirs, const double* emin, int32_t* counts,
                                                           const int32_t* col_ptr, int32_t* row_idx,
                                                           float* cval, int fill) {
   const int i = blockIdx.x;
@@ -135,13 +140,13 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDe
   if (threadIdx.x == 0) base = fill ? col_ptr[i] : 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < nv; j0 += kThreads) {
-    const int j = j0 + threadIdx.x;
+  for (int p0 = 0; p0 < nv; p0 += kThreads) {
+    const int p = p0 + threadIdx.x;
     bool keep = false;
     double e = 0.0;
-    if (j < nv) {
+    if (p < nv) {
       double x, y, z, depth, u;
-      voxel_xyz(g, j, x, y, z);
+      voxel_xyz(g, voxel_of(vox, p), x, y, z);
       depth_u(g, x, y, d.x, d.y, depth, u);
       e = exponent(g, depth, u, z, b.u_c, b.v_c);
       keep = e <= limit;
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDe
     for (int k = 0; k < w; ++k) before += wave_cnt[k];
     if (keep && fill) {
       const int64_t pos = csc_slot(before + __popcll(mask & ((1ull << lane) - 1ull)));
-      row_idx[pos] = j;
+      row_idx[pos] = p;
       cval[pos] = static_cast<float>(exp(-e));
     }
     __syncthreads();
@@ -168,16 +173,16 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const BeamletDe
 }
 
 // One thread per voxel: kept beamlets in ascending column order (CSR).
-__global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const BeamletDev* bl, const int32_t* beam_first,
-                                                       const double2* dirs, const double* emin,
-                                                       int32_t* counts, const int32_t* row_ptr,
+__global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const int32_t* vox, const BeamletDev* bl,
+                                                       const int32_t* beam_first, const double2* dirs,
+                                                       const double* emin, int32_t* counts, const int32_t* row_ptr,
                                                        int32_t* col_idx, float* val, int fill) {
   const int nv = g.nx * g.ny * g.nz;
-  const int j = blockIdx.x * kThreads + threadIdx.x;
-  if (j >= nv) return;
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= nv) return;
   double x, y, z;
-  voxel_xyz(g, j, x, y, z);
-  int pos = fill ? row_ptr[j] : 0;
+  voxel_xyz(g, voxel_of(vox, p), x, y, z);
+  int pos = fill ? row_ptr[p] : 0;
   for (int beam = 0; beam < g.nbeam; ++beam) {
     const double2 d = dirs[beam];
     double depth, u;
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const BeamletDev* 
       }
     }
   }
-  if (!fill) counts[j] = pos;
+  if (!fill) counts[p] = pos;
 }
 
 struct DevBuf {
@@ -267,19 +272,37 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
                           hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(d_dirs.p, dirs.data(), sizeof(double2) * G->n_beams, hipMemcpyHostToDevice, s));
 
+  // internal voxel order: tiles of 4 x 4 x 2 voxels (x fastest inside a tile,
+  // tiles in x, y, z order), so that the voxels a beamlet crosses sit close
+  // together in memory whatever the beam direction; row p of D is voxel vox[p]
+  if (ctx->tune.voxel_tiles) {
+    constexpr int tx = 4, ty = 4, tz = 2;
+    D->vox_host.resize(static_cast<size_t>(nv));
+    int64_t p = 0;
+    for (int z0 = 0; z0 < G->nz; z0 += tz)
+      for (int y0 = 0; y0 < G->ny; y0 += ty)
+        for (int x0 = 0; x0 < G->nx; x0 += tx)
+          for (int z = z0; z < std::min(z0 + tz, G->nz); ++z)
+            for (int y = y0; y < std::min(y0 + ty, G->ny); ++y)
+              for (int x = x0; x < std::min(x0 + tx, G->nx); ++x)
+                D->vox_host[p++] = x + G->nx * (y + G->ny * z);
+    IMRT_HIP(hipMalloc(&D->vox, sizeof(int32_t) * nv));
+    IMRT_HIP(hipMemcpyAsync(D->vox, D->vox_host.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s));
+  }
+  const int32_t* vox = D->vox;
   IMRT_HIP(hipMalloc(&D->sid, nv));
   const int vgrid = (nv + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(structure_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, D->sid);
+  hipLaunchKernelGGL(structure_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, D->sid);
   IMRT_HIP(hipGetLastError());
   const auto* blp = static_cast<const BeamletDev*>(d_bl.p);
   const auto* dp = static_cast<const double2*>(d_dirs.p);
   auto* em = static_cast<double*>(d_emin.p);
   hipLaunchKernelGGL(emin_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em,
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, vox, blp, dp, em,
                      static_cast<int32_t*>(d_cnt_c.p), nullptr, nullptr, nullptr, 0);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, blp,
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, blp,
                      static_cast<const int32_t*>(d_first.p), dp, em, static_cast<int32_t*>(d_cnt_r.p),
                      nullptr, nullptr, nullptr, 0);
   IMRT_HIP(hipGetLastError());
@@ -311,10 +334,10 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   if (arc) return arc;
   IMRT_HIP(hipMemcpyAsync(D->row_ptr, row_ptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_ptr, col_ptr.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em, nullptr, D->col_ptr,
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, vox, blp, dp, em, nullptr, D->col_ptr,
                      D->row_idx, D->cval, 1);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, blp,
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, blp,
                      static_cast<const int32_t*>(d_first.p), dp, em, nullptr, D->row_ptr, D->col_idx,
                      D->val, 1);
   IMRT_HIP(hipGetLastError());

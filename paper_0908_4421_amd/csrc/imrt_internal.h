@@ -143,6 +143,7 @@ struct Tuning {
   int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
+  int voxel_tiles = 1;         // built phantoms: voxels in 4x4x2 tiles (1) or the grid's own order (0)
   int adj_xcd = 0;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
@@ -183,7 +184,12 @@ struct imrt_dose {
   int32_t* col_whi = nullptr;
   uint8_t* col_kind = nullptr; // per column: 0 one adjoint workgroup, 1 two, 2 more
   double* pieces = nullptr;
-  // structure ids from the phantom builder (nullable)
+  // internal voxel order (nullable: the caller's order): row p of D is voxel
+  // vox[p]; every voxel-indexed array crossing the API is permuted
+  int32_t* vox = nullptr;
+  std::vector<int32_t> vox_host;
+  float* vscratch = nullptr;   // nv floats for permuted products
+  // structure ids from the phantom builder (nullable; internal order)
   uint8_t* sid = nullptr;
   // scratch for plain products
   double* partials = nullptr;
@@ -260,6 +266,8 @@ int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out);
+// out[vox[p]] = in[p] (scatter) or out[p] = in[vox[p]] (gather), p < n
+int launch_permute(const imrt_ctx* ctx, const float* in, const int32_t* vox, int n, float* out, bool scatter);
 
 // phantom builder (build.hip)
 int build_phantom(imrt_ctx* ctx, const imrt_geometry* g, imrt_dose* D);

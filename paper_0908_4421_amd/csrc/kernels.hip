@@ -1386,6 +1386,14 @@ __global__ __launch_bounds__(kThreads) void normalize_kernel(const float* w, int
     v[i] = n > 0.0 ? static_cast<float>(static_cast<double>(w[i]) / n) : 0.0f;
 }
 
+__global__ __launch_bounds__(kThreads) void permute_kernel(const float* in, const int32_t* vox, int n, float* out,
+                                                           int scatter) {
+  const int p = blockIdx.x * kThreads + threadIdx.x;
+  if (p >= n) return;
+  if (scatter) out[vox[p]] = in[p];
+  else out[p] = in[vox[p]];
+}
+
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, what);
@@ -1506,6 +1514,13 @@ int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double l
   clear_stale_error();
   hipLaunchKernelGGL(project_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, x, g, lambda, nb, x_out, s_out);
   return check_launch("project_kernel");
+}
+
+int launch_permute(const imrt_ctx* ctx, const float* in, const int32_t* vox, int n, float* out, bool scatter) {
+  clear_stale_error();
+  hipLaunchKernelGGL(permute_kernel, dim3(grid_for((n + kThreads - 1) / kThreads, 1 << 30)), dim3(kThreads), 0,
+                     ctx->stream, in, vox, n, out, scatter ? 1 : 0);
+  return check_launch("permute_kernel");
 }
 
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out) {

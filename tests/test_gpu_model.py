@@ -11,10 +11,12 @@ from workloads import TINY, penalty_table, power_start_vector, random_csr, rando
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1, 0], ids=["voxel_tiles", "grid_order"])
+def ctx(request):
+    """Built phantoms with rows in voxel tiles (default) or grid order: the
+    structure ids, voxel targets and dose outputs cross the API in grid order."""
     from paper_0908_4421_amd.imrt import Context
-    return Context(0)
+    return Context(0, voxel_tiles=request.param)
 
 
 @pytest.fixture(scope="module")

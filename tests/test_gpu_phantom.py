@@ -17,10 +17,12 @@ ODD = PhantomSpec(name="odd_29x23x17_4mm_7field", nx=29, ny=23, nz=17, h=4.0, r_
 BATCH5 = next(s for s in (draw_batch_instance(k) for k in range(100, 200)) if s.h == 5.0)
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[1, 0], ids=["voxel_tiles", "grid_order"])
+def ctx(request):
+    """Rows of D held in 4x4x2 voxel tiles (default) or in grid order; the
+    exported arrays are in grid order either way."""
     from paper_0908_4421_amd.imrt import Context
-    return Context(0)
+    return Context(0, voxel_tiles=request.param)
 
 
 @pytest.mark.parametrize("spec", [TINY, SMALL, ODD, BATCH5], ids=lambda s: s.name)
@@ -43,6 +45,26 @@ def test_builder_matches_oracle(ctx, spec):
     C = sp.csr_matrix((ex["val"], ex["col_idx"], ex["row_ptr"]), shape=(lib.nv, lib.nb)).tocsc()
     C.sort_indices()
     assert np.array_equal(C.data, ex["cval"])
+
+
+def test_products_in_grid_order(ctx):
+    """D x and D^T r of a built phantom take and return voxel arrays in grid
+    order, whatever the internal row order."""
+    from gpu_util import to_dev, to_host
+    from oracle import model
+    from paper_0908_4421_amd.imrt import Dose
+    want = phantom.build_dose_matrix(SMALL)
+    lib = Dose.from_geometry(ctx, SMALL)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.0, 2.0, want.nb).astype(np.float32)
+    r = rng.standard_normal(want.nv).astype(np.float32)
+    d = to_host(lib.apply(to_dev(x)))
+    y = to_host(lib.apply_transpose(to_dev(r)))
+    d_ref = model.dose(want.csr, x.astype(np.float64))
+    y_ref = model.adjoint(want.csr, r.astype(np.float64))
+    assert np.all(np.abs(d - d_ref) <= 1e-5 * np.abs(d_ref) + 1e-30)
+    scale = abs(want.csr).T.astype(np.float64) @ np.abs(r.astype(np.float64))
+    assert np.all(np.abs(y - y_ref) <= 1e-6 * scale + 1e-30)
 
 
 def test_invalid_geometry_rejected(ctx):
