@@ -227,8 +227,9 @@ def main():
 
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     wave = ctx.get_option("fwd_wave")
-    names = {"forward": f"{'fwd_wave_kernel' if wave else 'fwd_kernel'}<{args.trials_per_pass}>(",
-             "adjoint": f"adj_kernel<{args.trials_per_pass}>("}
+    nt = args.trials_per_pass
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0>(" if wave else f"fwd_kernel<{nt}>(",
+             "adjoint": f"adj_kernel<{nt}>("}
     kern = {}
     for name, nbytes in (("forward", forward_bytes(nv, nb, nnz)), ("adjoint", adjoint_bytes(nv, nb, nnz))):
         ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)
