@@ -145,9 +145,9 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1)
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (>= 1)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
- *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die
- *                    (shared L2 for residual gathers); 0: dispatch order, so
- *                    every die gets a mix of beams (default)
+ *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die,
+ *                    which then share their residual gathers in its L2
+ *                    (default); 0: dispatch order
  *   "voxel_tiles"    1: imrt_build_dose_matrix stores the rows of D in tiles of
  *                    4 x 4 x 2 voxels (default), so that the residual gathers
  *                    of every beam direction touch few cache lines; 0: in

@@ -144,7 +144,7 @@ struct Tuning {
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
   int voxel_tiles = 1;         // built phantoms: voxels in 4x4x2 tiles (1) or the grid's own order (0)
-  int adj_xcd = 0;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
+  int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
 };
 
