@@ -228,7 +228,7 @@ def main():
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0>(" if wave else f"fwd_kernel<{nt}>(",
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}>(" if wave else f"fwd_kernel<{nt}>(",
              "adjoint": f"adj_kernel<{nt}>("}
     kern = {}
     for name, nbytes in (("forward", forward_bytes(nv, nb, nnz)), ("adjoint", adjoint_bytes(nv, nb, nnz))):

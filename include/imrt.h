@@ -142,7 +142,11 @@ IMRT_API int imrt_ctx_destroy(imrt_ctx* ctx);
 IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 
 /* Launch-shape settings of a context, by name:
- *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1)
+ *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1; default
+ *                    1).  A "fwd_wave" workgroup has 16 waves (8 when a pass
+ *                    tries several step sizes) that take row blocks from a
+ *                    shared counter; otherwise the value is scaled by four
+ *                    workgroups of 4 waves.
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (>= 1)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
  *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die,
@@ -156,7 +160,8 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
- * "adj_wg_per_cu" and "adj_min_nnz" are read when a dose matrix is created.
+ * "adj_wg_per_cu", "adj_min_nnz" and "fwd_wg_per_cu" are read when a dose
+ * matrix is created (its work partitions); "fwd_wg_per_cu" also at launch.
  * Results are deterministic for given settings; the settings change only the
  * grouping of the float32 row sums and of the float64 partial sums of G and
  * of shared columns.

@@ -47,12 +47,14 @@ int use_device(const imrt_ctx* ctx) {
 // Largest forward grid of either forward variant at the current settings.
 int forward_grid_cap(imrt_ctx* ctx, const imrt_dose* D) {
   const int saved = ctx->tune.fwd_wave;
-  ctx->tune.fwd_wave = 0;
-  const int g0 = forward_grid(ctx, D);
-  ctx->tune.fwd_wave = 1;
-  const int g1 = forward_grid(ctx, D);
+  int g = 1;
+  for (int wave = 0; wave <= 1; ++wave)
+    for (int nt : {1, 2}) {
+      ctx->tune.fwd_wave = wave;
+      g = std::max(g, forward_grid(ctx, D, nt));
+    }
   ctx->tune.fwd_wave = saved;
-  return std::max(g0, g1);
+  return g;
 }
 
 double pow2_at_least(double q) {
@@ -136,7 +138,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   // nonzeros are halved (by rows) until the count is a multiple of the waves.
   {
     const int nwb = static_cast<int>(wblocks.size()) - 1;
-    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb)) * kWaves;
+    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb)) * forward_waves(1);
     const int64_t target = (nwb + waves - 1) / waves * waves;
     if (nwb > waves && target > nwb) {
       // max-heap of (nonzeros, block start row) over splittable blocks
@@ -1010,7 +1012,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
     return hip_error(e, "solve setup");
   }
 
-  const int grid = std::min(forward_grid(C, D), P->fwd_cap);
+  const int grid = std::min(forward_grid(C, D, nt), P->fwd_cap);
   FwdArgs fa = base_fwd(D);
   fa.mode = FWD_SOLVE;
   set_plan_penalties(fa, P);

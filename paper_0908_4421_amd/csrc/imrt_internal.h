@@ -139,7 +139,7 @@ struct AdjArgs {
 
 // ---- host-side objects ------------------------------------------------------------
 struct Tuning {
-  int fwd_grid_per_cu = 4;
+  int fwd_grid_per_cu = 1;
   int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
@@ -238,8 +238,11 @@ int hip_error(hipError_t e, const char* what);
   } while (0)
 
 // launchers (kernels.hip)
-int forward_grid(const imrt_ctx* ctx, const imrt_dose* D);
-int wave_grid(const imrt_ctx* ctx, int nwblocks);
+// forward grid: wave-granular pass, fwd_grid_per_cu workgroups of 16 waves
+// (8 for several trials) per CU; workgroup-granular pass, 4x as many of 4 waves
+int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials = 1);
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials = 1);
+int forward_waves(int ntrials);
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
 size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }

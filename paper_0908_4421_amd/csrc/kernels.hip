@@ -16,7 +16,10 @@
 // writes the other, so no workgroup ever sees a state written during its own
 // pass.  Every reduction runs in a fixed order, so results are
 // bit-reproducible and independent of workgroup timing; there are no
-// floating-point atomics.  Work is dealt to workgroups in contiguous ranges,
+// floating-point atomics.  (The waves of a wave-granular forward workgroup
+// take row blocks from an integer counter in LDS, but a block's rows and its
+// objective contribution come out the same whichever wave takes it, and the
+// contributions are added in block order.)  Work is dealt to workgroups in contiguous ranges,
 // consecutive ranges on the same accelerator die (workgroups are dispatched
 // round-robin over the 8 dies), so neighbouring beamlet columns share that
 // die's L2 for their residual gathers.
@@ -82,8 +85,9 @@ __device__ __forceinline__ T wave_sum(T v) {
   return group_sum<64>(v);
 }
 
-// Sum of v over the workgroup in a fixed order; the result is valid in thread 0.
-template <typename T>
+// Sum of v over a workgroup of WAVES waves in a fixed order; the result is
+// valid in thread 0.
+template <typename T, int WAVES = kWaves>
 __device__ __forceinline__ T block_sum(T v, T* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -93,7 +97,7 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
   if (threadIdx.x == 0) {
     t = sh[0];
 #pragma unroll
-    for (int i = 1; i < kWaves; ++i) t += sh[i];
+    for (int i = 1; i < WAVES; ++i) t += sh[i];
   }
   __syncthreads();
   return t;
@@ -485,46 +489,46 @@ struct StageRegs {
   double tab;
 };
 
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, bool want_sid, StageRegs<NT>& R) {
   const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
-      const int i = tid + u * kThreads;
+      const int i = tid + u * THREADS;
       R.v[q][u] = src[q * nbp + (i < nb ? i : 0)];
     }
   }
-  // first kThreads doubles of the table (4 per structure); the rest in stage_finish
+  // first THREADS doubles of the table (4 per structure); the rest in stage_finish
   R.tab = (want_sid && tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
 }
 
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src, bool want_sid,
                                              const StageRegs<NT>& R, PenaltyDev* tab, float* xs) {
   const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
   if (want_sid) {
     double* dst = reinterpret_cast<double*>(tab);
     if (tid < 4 * a.nstruct) dst[tid] = R.tab;
-    for (int i = tid + kThreads; i < 4 * a.nstruct; i += kThreads)
+    for (int i = tid + THREADS; i < 4 * a.nstruct; i += THREADS)
       dst[i] = reinterpret_cast<const double*>(a.pen.table)[i];
   }
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
-      const int i = tid + u * kThreads;
+      const int i = tid + u * THREADS;
       if (i < nb) xs[q * nbp + i] = R.v[q][u];
     }
   }
-  for (int i0 = tid + kStageU * kThreads; i0 < nb; i0 += kStageU * kThreads) {
+  for (int i0 = tid + kStageU * THREADS; i0 < nb; i0 += kStageU * THREADS) {
     float v[NT][kStageU];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
 #pragma unroll
       for (int u = 0; u < kStageU; ++u) {
-        const int i = i0 + u * kThreads;
+        const int i = i0 + u * THREADS;
         v[q][u] = src[q * nbp + (i < nb ? i : 0)];
       }
     }
@@ -532,7 +536,7 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
     for (int q = 0; q < NT; ++q) {
 #pragma unroll
       for (int u = 0; u < kStageU; ++u) {
-        const int i = i0 + u * kThreads;
+        const int i = i0 + u * THREADS;
         if (i < nb) xs[q * nbp + i] = v[q][u];
       }
     }
@@ -559,12 +563,12 @@ struct TrialRegs {
   double tab;
 };
 
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<NT>& R) {
   const int nb = a.nb;
 #pragma unroll
   for (int u = 0; u < kTrialU; ++u) {
-    const int i = i0 + u * kThreads;
+    const int i = i0 + u * THREADS;
     const int ii = i < nb ? i : 0;
 #pragma unroll
     for (int j = 0; j <= NT; ++j) R.xc[j][u] = a.xbuf[j][ii];
@@ -589,13 +593,13 @@ struct TrialCtl {
   int xi;
 };
 
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const TrialRegs<NT>& R, const TrialCtl& T,
                                             const double (&lam)[NT], float* xs, double (&sq)[NT]) {
   const int nb = a.nb, nbp = pad4(nb);
 #pragma unroll
   for (int u = 0; u < kTrialU; ++u) {
-    const int i = i0 + u * kThreads;
+    const int i = i0 + u * THREADS;
     if (i >= nb) continue;
     float x = R.xc[0][u];
 #pragma unroll
@@ -623,7 +627,7 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
 
 // After the first round (loaded by the caller): the remaining rounds, the
 // lead workgroup's step norms, the penalty table; ends with a barrier.
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<NT>& R, const TrialCtl& T,
                                              const double (&lam)[NT], PenaltyDev* tab, float* xs, double* red) {
   const int tid = threadIdx.x;
@@ -633,31 +637,31 @@ __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<N
   {
     double* dst = reinterpret_cast<double*>(tab);
     if (tid < 4 * a.nstruct) dst[tid] = R.tab;
-    for (int i = tid + kThreads; i < 4 * a.nstruct; i += kThreads)
+    for (int i = tid + THREADS; i < 4 * a.nstruct; i += THREADS)
       dst[i] = reinterpret_cast<const double*>(a.pen.table)[i];
   }
-  trial_store<NT>(a, tid, R, T, lam, xs, sq);
-  for (int i0 = tid + kTrialU * kThreads; i0 < a.nb; i0 += kTrialU * kThreads) {
+  trial_store<NT, THREADS>(a, tid, R, T, lam, xs, sq);
+  for (int i0 = tid + kTrialU * THREADS; i0 < a.nb; i0 += kTrialU * THREADS) {
     TrialRegs<NT> R2;
-    trial_load<NT>(a, i0, R2);
-    trial_store<NT>(a, i0, R2, T, lam, xs, sq);
+    trial_load<NT, THREADS>(a, i0, R2);
+    trial_store<NT, THREADS>(a, i0, R2, T, lam, xs, sq);
   }
   if (T.lead && !T.init) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      const double t = block_sum(sq[q], red);
+      const double t = block_sum<double, THREADS / 64>(sq[q], red);
       if (tid == 0) a.partials[NT * gridDim.x + q] = t;
     }
   }
   __syncthreads();
 }
 
-template <int NT>
+template <int NT, int THREADS = kThreads>
 __device__ __forceinline__ void stage_inputs(const FwdArgs& a, const float* src, PenaltyDev* tab, float* xs,
                                              bool want_sid) {
   StageRegs<NT> R;
-  stage_start<NT>(a, src, want_sid, R);
-  stage_finish<NT>(a, src, want_sid, R, tab, xs);
+  stage_start<NT, THREADS>(a, src, want_sid, R);
+  stage_finish<NT, THREADS>(a, src, want_sid, R, tab, xs);
 }
 
 // Forward pass.  Each workgroup stages the NT trial vectors
@@ -948,16 +952,30 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
   }
 }
 
-template <int NT, int MODE>
-__global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
+// Waves of a wave-granular forward workgroup: sixteen (one workgroup per
+// compute unit) for one trial, eight for more (LDS).
+template <int NT>
+struct FwdWaves {
+  static constexpr int value = (NT == 1) ? 16 : 8;
+};
+constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
+
+template <int NT, int MODE, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
+  constexpr int THREADS = WAVES * 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = a.nb;
   const int nbp = pad4(nb);
   PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
   float* xs = reinterpret_cast<float*>(tab + a.nstruct);
+  float* prod0 = xs + NT * nbp;
+  int32_t* mrow = reinterpret_cast<int32_t*>(prod0 + WAVES * NT * kWaveNnz + kWaveSlack);
+  int32_t* mk0 = mrow + (kMetaChunk + 1);
+  double* gpart = reinterpret_cast<double*>(mk0 + (kMetaChunk + 1) + 2);   // 8-byte aligned
   const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  float* prod = xs + NT * nbp + wv * (NT * kWaveNnz);
-  __shared__ double red[kWaves];
+  float* prod = prod0 + wv * (NT * kWaveNnz);
+  __shared__ double red[WAVES];
+  __shared__ int next_blk;
 
   const int tid = threadIdx.x;
   constexpr bool solve = (MODE == FWD_SOLVE);
@@ -972,10 +990,10 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
   TrialRegs<NT> TR;
   StageRegs<NT> SR;
   if (solve) {
-    trial_load<NT>(a, tid, TR);
+    trial_load<NT, THREADS>(a, tid, TR);
     TR.tab = (tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
   } else {
-    stage_start<NT>(a, a.x, want_sid, SR);
+    stage_start<NT, THREADS>(a, a.x, want_sid, SR);
   }
   TrialCtl T{true, false, 0};
   double lam[NT];
@@ -1000,129 +1018,162 @@ __global__ __launch_bounds__(kThreads) void fwd_wave_kernel(FwdArgs a) {
     for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
 
-  // this wave's contiguous range of row blocks
+  // This workgroup's contiguous range of row blocks; its waves take blocks
+  // in turn from a counter in LDS (the first WAVES blocks one each), so a
+  // wave that runs faster takes more.  Every block's objective contribution
+  // goes to its own LDS slot and the workgroup adds the slots in block order,
+  // so the total does not depend on which wave took which block.
   const int G = gridDim.x, w = blockIdx.x;
   const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
-  const long long W = static_cast<long long>(G) * kWaves, gw = static_cast<long long>(lw) * kWaves + wv;
-  const int b0 = uniform(static_cast<int>(gw * a.nwblocks / W));
-  const int b1 = uniform(static_cast<int>((gw + 1) * a.nwblocks / W));
-  // lane i holds the bounds of block mb + i (63 blocks per refill)
-  const rsrc_t mrow = make_rsrc(a.wblock_row, 4u * static_cast<uint32_t>(a.nwblocks + 1));
-  const rsrc_t mk0 = make_rsrc(a.wblock_k0, 4u * static_cast<uint32_t>(a.nwblocks + 1));
-  int mb = b0;
-  int lrow = load_i32(mrow, 4 * (mb + lane));
-  int lk0 = load_i32(mk0, 4 * (mb + lane));
-  auto meta = [&](int b) {
-    if (b - mb >= 63) {
-      mb = b;
-      lrow = load_i32(mrow, 4 * (mb + lane));
-      lk0 = load_i32(mk0, 4 * (mb + lane));
-    }
-    const int i = b - mb;
+  const int B0 = uniform(static_cast<int>(static_cast<long long>(lw) * a.nwblocks / G));
+  const int B1 = uniform(static_cast<int>(static_cast<long long>(lw + 1) * a.nwblocks / G));
+  auto global_meta = [&](int b) {
     WaveBlock m;
-    m.r0 = __builtin_amdgcn_readlane(lrow, i);
-    m.r1 = __builtin_amdgcn_readlane(lrow, i + 1);
-    m.k0 = __builtin_amdgcn_readlane(lk0, i);
-    m.k1 = __builtin_amdgcn_readlane(lk0, i + 1);
+    m.r0 = uniform(a.wblock_row[b]);
+    m.r1 = uniform(a.wblock_row[b + 1]);
+    m.k0 = uniform(a.wblock_k0[b]);
+    m.k1 = uniform(a.wblock_k0[b + 1]);
     return m;
   };
-
-  // Load order: staging loads (above), block bounds, then the first block's
-  // loads, so that waiting for the staging loads does not wait for the
-  // block (the wait counter drains in issue order).
+  // the first block's loads follow the staging loads, so waiting for those
+  // does not wait for these (the wait counter drains in issue order)
   WaveStage S;
+  int b = B0 + wv;
   WaveBlock cur{0, 0, 0, 0};
-  if (b0 < b1) {
-    cur = meta(b0);
+  if (b < min(B1, B0 + kMetaChunk)) {
+    cur = global_meta(b);
     if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
   }
-  if (solve) trial_finish<NT>(a, TR, T, lam, tab, xs, red);
-  else stage_finish<NT>(a, a.x, want_sid, SR, tab, xs);
+  if (solve) trial_finish<NT, THREADS>(a, TR, T, lam, tab, xs, red);
+  else stage_finish<NT, THREADS>(a, a.x, want_sid, SR, tab, xs);
 
-  double pacc[NT];
+  double gsum[NT];
 #pragma unroll
-  for (int q = 0; q < NT; ++q) pacc[q] = 0.0;
-
-  for (int b = b0; b < b1; ++b) {
-    const WaveBlock blk = cur;
-    const bool more = (b + 1 < b1);
-    if (more) cur = meta(b + 1);
-    if (blk.k1 - blk.k0 > kWavePartNnz) {
-      // one row longer than a wave block: the wave strides over it
-      float acc[NT];
+  for (int q = 0; q < NT; ++q) gsum[q] = 0.0;
+  for (int c0 = B0; c0 < B1; c0 += kMetaChunk) {
+    const int c1 = min(c0 + kMetaChunk, B1);
+    for (int i = tid; i <= c1 - c0; i += THREADS) {
+      mrow[i] = a.wblock_row[c0 + i];
+      mk0[i] = a.wblock_k0[c0 + i];
+    }
+    if (tid == 0) next_blk = c0 + WAVES;
+    __syncthreads();
+    auto meta = [&](int blk) {
+      const int i = blk - c0;
+      WaveBlock m;
+      m.r0 = uniform(mrow[i]);
+      m.r1 = uniform(mrow[i + 1]);
+      m.k0 = uniform(mk0[i]);
+      m.k1 = uniform(mk0[i + 1]);
+      return m;
+    };
+    if (c0 != B0) {
+      b = c0 + wv;
+      if (b < c1) {
+        cur = meta(b);
+        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+      }
+    }
+    while (b < c1) {
+      // the block after this one (taken now, its loads issued once this
+      // block's products are in LDS)
+      int nxt = 0;
+      if (lane == 0) nxt = atomicAdd(&next_blk, 1);
+      nxt = uniform(nxt);
+      const WaveBlock blk = cur;
+      const bool more = nxt < c1;
+      if (more) cur = meta(nxt);
+      double pb[NT];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) acc[q] = 0.f;
-      for (int base = blk.k0 & ~3; base < blk.k1; base += 512) {
-        const uint32_t bytes = static_cast<uint32_t>((blk.k1 - base) * 4 + 15) & ~15u;
-        const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
-        const rsrc_t rv = make_rsrc(a.val + base, bytes);
+      for (int q = 0; q < NT; ++q) pb[q] = 0.0;
+      if (blk.k1 - blk.k0 > kWavePartNnz) {
+        // one row longer than a wave block: the wave strides over it
+        float acc[NT];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int4 c = load_i4(rc, 16 * lane + 1024 * j);
-          const float4 v = load_f4(rv, 16 * lane + 1024 * j);
-          const int e0 = base + 4 * lane + 256 * j;
-          const int cc[4] = {c.x, c.y, c.z, c.w};
-          const float vv[4] = {v.x, v.y, v.z, v.w};
+        for (int q = 0; q < NT; ++q) acc[q] = 0.f;
+        for (int base = blk.k0 & ~3; base < blk.k1; base += 512) {
+          const uint32_t bytes = static_cast<uint32_t>((blk.k1 - base) * 4 + 15) & ~15u;
+          const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
+          const rsrc_t rv = make_rsrc(a.val + base, bytes);
 #pragma unroll
-          for (int q = 0; q < NT; ++q) {
+          for (int j = 0; j < 2; ++j) {
+            const int4 c = load_i4(rc, 16 * lane + 1024 * j);
+            const float4 v = load_f4(rv, 16 * lane + 1024 * j);
+            const int e0 = base + 4 * lane + 256 * j;
+            const int cc[4] = {c.x, c.y, c.z, c.w};
+            const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float t = vv[i] * xs[q * nbp + cc[i]];
-              acc[q] += (e0 + i >= blk.k0 && e0 + i < blk.k1) ? t : 0.0f;
+            for (int q = 0; q < NT; ++q) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const float t = vv[u] * xs[q * nbp + cc[u]];
+                acc[q] += (e0 + u >= blk.k0 && e0 + u < blk.k1) ? t : 0.0f;
+              }
             }
           }
         }
-      }
-      float d[NT];
+        float d[NT];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) d[q] = wave_sum(acc[q]);
-      if (lane == 63) {
-        const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
-        row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pacc, rout, dout, ntr);
-      }
-      if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
-      continue;
-    }
-    // products of this block into the wave's LDS region (lanes past the
-    // block hold zeros and write slots that no row reads)
+        for (int q = 0; q < NT; ++q) d[q] = wave_sum(acc[q]);
+        if (lane == 63) {
+          const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
+          row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pb, rout, dout, ntr);
+        }
+        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+      } else {
+        // products of this block into the wave's LDS region (lanes past the
+        // block hold zeros and write slots that no row reads)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int off = 4 * lane + 256 * j;
+        for (int j = 0; j < 2; ++j) {
+          const int off = 4 * lane + 256 * j;
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const float* xq = xs + q * nbp;
+            float4 p;
+            p.x = S.v[j].x * xq[S.c[j].x];
+            p.y = S.v[j].y * xq[S.c[j].y];
+            p.z = S.v[j].z * xq[S.c[j].z];
+            p.w = S.v[j].w * xq[S.c[j].w];
+            *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
+          }
+        }
+        // LDS operations of one wave complete in order; the fence only keeps
+        // the compiler from moving the row reads above the product writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const WaveStage R = S;   // this block's row pointers and ids (loads already waited on)
+        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+        switch (log2_lanes(blk.r1 - blk.r0)) {
+          case 0: wave_rows<1, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 1: wave_rows<2, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 2: wave_rows<4, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 3: wave_rows<8, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 4: wave_rows<16, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 5: wave_rows<32, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          default: wave_rows<64, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+        }
+        // the next block's LDS writes must not overtake this block's reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
-        const float* xq = xs + q * nbp;
-        float4 p;
-        p.x = S.v[j].x * xq[S.c[j].x];
-        p.y = S.v[j].y * xq[S.c[j].y];
-        p.z = S.v[j].z * xq[S.c[j].z];
-        p.w = S.v[j].w * xq[S.c[j].w];
-        *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
+        const double t = wave_sum(pb[q]);
+        if (lane == 63) gpart[q * kMetaChunk + (b - c0)] = t;
       }
+      b = nxt;
     }
-    // LDS operations of one wave complete in order; the fence only keeps the
-    // compiler from moving the row reads above the product writes
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const WaveStage R = S;   // this block's row pointers and ids (loads already waited on)
-    if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
-    switch (log2_lanes(blk.r1 - blk.r0)) {
-      case 0: wave_rows<1, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      case 1: wave_rows<2, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      case 2: wave_rows<4, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      case 3: wave_rows<8, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      case 4: wave_rows<16, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      case 5: wave_rows<32, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-      default: wave_rows<64, NT, MODE>(a, prod, lane, blk, R, tab, pacc, rout, dout, ntr); break;
-    }
-    // the next block's LDS writes must not overtake this block's reads
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-
+    __syncthreads();
+    if (tid == 0) {
 #pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const double t = block_sum(pacc[q], red);
-    if (tid == 0) a.partials[q * gridDim.x + blockIdx.x] = t;
+      for (int q = 0; q < NT; ++q)
+        for (int i = 0; i < c1 - c0; ++i) gsum[q] += gpart[q * kMetaChunk + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int q = 0; q < NT; ++q) a.partials[q * gridDim.x + blockIdx.x] = gsum[q];
   }
 }
 
@@ -1417,7 +1468,9 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
                  static_cast<size_t>(ntrials) * nbp * sizeof(float);
   if (wave) {
-    bytes += (static_cast<size_t>(kWaves) * ntrials * kWaveNnz + kWaveSlack) * sizeof(float);
+    const size_t waves = (ntrials == 1) ? 16 : 8;
+    bytes += (waves * ntrials * kWaveNnz + kWaveSlack) * sizeof(float);
+    bytes += (2 * (kMetaChunk + 1) + 2) * sizeof(int32_t) + static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
   } else {
     bytes += static_cast<size_t>(ntrials) * kFwdNnzMax * sizeof(float) +
              static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
@@ -1425,12 +1478,16 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
   return bytes;
 }
 
-int forward_grid(const imrt_ctx* ctx, const imrt_dose* D) {
-  return ctx->tune.fwd_wave ? wave_grid(ctx, D->nwblocks) : grid_for(D->nblocks, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+int forward_waves(int ntrials) { return ntrials == 1 ? 16 : 8; }
+
+int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials) {
+  if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials);
+  return grid_for(D->nblocks, kWaves * ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
-int wave_grid(const imrt_ctx* ctx, int nwblocks) {
-  return grid_for((nwblocks + kWaves - 1) / kWaves, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials) {
+  const int waves = forward_waves(ntrials);
+  return grid_for((nwblocks + waves - 1) / waves, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
@@ -1455,19 +1512,20 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   const dim3 gd(grid), bd(kThreads);
   hipStream_t s = ctx->stream;
   if (wave) {
+    const dim3 bd16(16 * 64), bd8(8 * 64);
     if (a.mode == FWD_SOLVE) {
       switch (ntrials) {
-        case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
-        case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
-        case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE>), gd, bd, lds, s, before, after, 0, a); break;
+        case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16>), gd, bd16, lds, s, before, after, 0, a); break;
+        case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8>), gd, bd8, lds, s, before, after, 0, a); break;
+        case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8>), gd, bd8, lds, s, before, after, 0, a); break;
         default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
       }
     } else if (ntrials != 1) {
       return set_error(IMRT_EINVAL, "evaluation passes take one trial");
     } else if (a.mode == FWD_EVAL) {
-      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL>), gd, bd, lds, s, before, after, 0, a);
+      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 16>), gd, bd16, lds, s, before, after, 0, a);
     } else {
-      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN>), gd, bd, lds, s, before, after, 0, a);
+      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16>), gd, bd16, lds, s, before, after, 0, a);
     }
   } else {
     switch (ntrials) {
