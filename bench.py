@@ -229,7 +229,7 @@ def main():
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
     names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}>(" if wave else f"fwd_kernel<{nt}>(",
-             "adjoint": f"adj_kernel<{nt}>("}
+             "adjoint": f"adj_kernel<{nt}, true>("}
     kern = {}
     for name, nbytes in (("forward", forward_bytes(nv, nb, nnz)), ("adjoint", adjoint_bytes(nv, nb, nnz))):
         ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)

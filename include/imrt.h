@@ -142,12 +142,12 @@ IMRT_API int imrt_ctx_destroy(imrt_ctx* ctx);
 IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 
 /* Launch-shape settings of a context, by name:
- *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (>= 1; default
+ *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (1..64; default
  *                    1).  A "fwd_wave" workgroup has 16 waves (8 when a pass
  *                    tries several step sizes) that take row blocks from a
  *                    shared counter; otherwise the value is scaled by four
  *                    workgroups of 4 waves.
- *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (>= 1)
+ *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (1..64)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
  *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die,
  *                    which then share their residual gathers in its L2

@@ -205,15 +205,22 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
       wg_c1[v] = std::max(wg_c1[v], c + 1);
     }
   }
-  for (int v = 0; v < G; ++v)
-    if (wg_c1[v] == 0) wg_c0[v] = 0;  // no columns
+  std::vector<int32_t> wg_cols(4 * static_cast<size_t>(G), 0);
+  for (int v = 0; v < G; ++v) {
+    if (wg_c1[v] == 0) continue;  // no columns
+    const int c = wg_c0[v];
+    wg_cols[4 * v] = c;
+    wg_cols[4 * v + 1] = wg_c1[v];
+    wg_cols[4 * v + 2] = static_cast<int32_t>(std::max<int64_t>(col_ptr[c], kw(v)));
+    wg_cols[4 * v + 3] = static_cast<int32_t>(std::min<int64_t>(col_ptr[c + 1], kw(v + 1)));
+  }
   D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
   D->nwblocks = static_cast<int32_t>(wblocks.size()) - 1;
   D->adj_grid = G;
   int rc;
   if ((rc = dev_alloc(&D->block_row, blocks.size())) || (rc = dev_alloc(&D->block_k0, block_k0.size())) ||
       (rc = dev_alloc(&D->wblock_row, wblocks.size())) || (rc = dev_alloc(&D->wblock_k0, wblock_k0.size())) ||
-      (rc = dev_alloc(&D->wg_c0, static_cast<size_t>(G))) || (rc = dev_alloc(&D->wg_c1, static_cast<size_t>(G))) ||
+      (rc = dev_alloc(&D->wg_cols, 4 * static_cast<size_t>(G))) ||
       (rc = dev_alloc(&D->col_wlo, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->col_kind, static_cast<size_t>(D->nb))) ||
@@ -225,8 +232,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   IMRT_HIP(hipMemcpyAsync(D->wblock_row, wblocks.data(), sizeof(int32_t) * wblocks.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wblock_k0, wblock_k0.data(), sizeof(int32_t) * wblock_k0.size(),
                           hipMemcpyHostToDevice, s));
-  IMRT_HIP(hipMemcpyAsync(D->wg_c0, wg_c0.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
-  IMRT_HIP(hipMemcpyAsync(D->wg_c1, wg_c1.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wg_cols, wg_cols.data(), sizeof(int32_t) * wg_cols.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_whi, col_whi.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
   std::vector<uint8_t> kind(D->nb);
@@ -258,8 +264,7 @@ void free_dose(imrt_dose* D) {
   dev_free(D->block_k0);
   dev_free(D->wblock_row);
   dev_free(D->wblock_k0);
-  dev_free(D->wg_c0);
-  dev_free(D->wg_c1);
+  dev_free(D->wg_cols);
   dev_free(D->col_wlo);
   dev_free(D->col_whi);
   dev_free(D->col_kind);
@@ -357,8 +362,7 @@ AdjArgs base_adj(const imrt_dose* D) {
   a.row_idx = D->row_idx;
   a.val = D->cval;
   a.col_ptr = D->col_ptr;
-  a.wg_c0 = D->wg_c0;
-  a.wg_c1 = D->wg_c1;
+  a.wg_cols = D->wg_cols;
   a.col_wlo = D->col_wlo;
   a.col_whi = D->col_whi;
   a.nnz = D->nnz;
@@ -407,8 +411,8 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
   if (ncu > 0) c->num_cu = ncu;
   if (lds > 0) c->max_lds = static_cast<size_t>(lds);
-  c->tune.fwd_grid_per_cu = env_int("IMRT_FWD_WG_PER_CU", c->tune.fwd_grid_per_cu);
-  c->tune.adj_grid_per_cu = env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu);
+  c->tune.fwd_grid_per_cu = std::min(64, env_int("IMRT_FWD_WG_PER_CU", c->tune.fwd_grid_per_cu));
+  c->tune.adj_grid_per_cu = std::min(64, env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu));
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
@@ -466,7 +470,9 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1 : (int64_t(1) << 30);
+  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1
+                     : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
+                                                                                 : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
   return IMRT_OK;

@@ -105,7 +105,9 @@ struct FwdArgs {
 };
 
 // Adjoint work partition: workgroup w owns nonzeros [w*nnz/G, (w+1)*nnz/G)
-// of the CSC arrays, i.e. columns [wg_c0[w], wg_c1[w]) in part or whole.
+// of the CSC arrays, i.e. columns [c0, c1) in part or whole, where
+// wg_cols[4w..4w+3] = {c0, c1, lo, hi} and [lo, hi) is the part of column c0
+// inside the range (c0 = c1 = lo = hi = 0 without columns).
 // Column c is shared by workgroups col_wlo[c]..col_whi[c]; a shared column is
 // completed from the per-workgroup pieces (slot 2w: piece of w's first
 // column, slot 2w+1: piece of its last column) in workgroup order.
@@ -113,8 +115,7 @@ struct AdjArgs {
   const int32_t* row_idx;
   const float* val;
   const int32_t* col_ptr;
-  const int32_t* wg_c0;
-  const int32_t* wg_c1;
+  const int32_t* wg_cols;
   const int32_t* col_wlo;
   const int32_t* col_whi;
   int64_t nnz;
@@ -178,8 +179,7 @@ struct imrt_dose {
   int32_t* wblock_row = nullptr;
   int32_t* wblock_k0 = nullptr;
   int32_t adj_grid = 0;        // workgroups of the adjoint partition
-  int32_t* wg_c0 = nullptr;
-  int32_t* wg_c1 = nullptr;
+  int32_t* wg_cols = nullptr;
   int32_t* col_wlo = nullptr;
   int32_t* col_whi = nullptr;
   uint8_t* col_kind = nullptr; // per column: 0 one adjoint workgroup, 1 two, 2 more

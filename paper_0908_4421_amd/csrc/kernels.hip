@@ -24,6 +24,7 @@
 // round-robin over the 8 dies), so neighbouring beamlet columns share that
 // die's L2 for their residual gathers.
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 
 #include <hip/hip_ext.h>
@@ -125,6 +126,9 @@ __device__ __forceinline__ int load_i32(rsrc_t r, uint32_t off) {
 }
 __device__ __forceinline__ float load_f32(rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double load_f64(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 __device__ __forceinline__ uint32_t load_u8(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
@@ -228,30 +232,59 @@ struct Decision {
   double lam, step_sq;
 };
 
-// The first round of partial loads (four per thread and trial) is issued by
-// decide_start, before anything that does not need it, so that waiting for
-// it does not wait for later loads.
+// Everything the decision reads is loaded by decide_start: the first round of
+// partials (four per thread and trial), the state (one 32-bit word per lane
+// of every wave) and the first step-norm part of every trial.
+// The loads are not combined with anything here, so that the compiler waits
+// for them only where decide uses them, after the caller's later loads were
+// issued.
+constexpr int kStateWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
+static_assert(kStateWords <= 64, "the state is loaded one word per lane of a wave");
+
+// floor(i * n / parts) for wave-uniform arguments (64-bit product).
+__device__ __forceinline__ int split_point(int i, int n, int parts) {
+  return uniform(static_cast<int>(static_cast<long long>(i) * n / parts));
+}
+
+// Fields of a state loaded one 32-bit word per lane (lane i holds word i).
+__device__ __forceinline__ int state_int(int32_t sw, size_t byte_off) {
+  return __builtin_amdgcn_readlane(sw, static_cast<int>(byte_off / 4));
+}
+__device__ __forceinline__ double state_f64(int32_t sw, size_t byte_off) {
+  const int lo = __builtin_amdgcn_readlane(sw, static_cast<int>(byte_off / 4));
+  const int hi = __builtin_amdgcn_readlane(sw, static_cast<int>(byte_off / 4) + 1);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<uint32_t>(hi)) << 32) |
+                                        static_cast<uint32_t>(lo));
+}
+
 template <int NT>
 struct DecideLoads {
   double v[NT][4];
+  double step0[NT];
+  int32_t sw;
 };
 
 template <int NT>
-__device__ __forceinline__ void decide_start(const double* partials, int nparts, DecideLoads<NT>& L) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void decide_start(const AdjArgs& a, DecideLoads<NT>& L) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nparts = a.fwd_parts, nsteps = a.step_parts;
+  const rsrc_t rp = make_rsrc(a.fwd_partials, 8u * NT * static_cast<uint32_t>(nparts));
+  const rsrc_t rs = make_rsrc(a.step_partials, 8u * NT * static_cast<uint32_t>(nsteps));
+  const rsrc_t rst = make_rsrc(a.st_in, static_cast<uint32_t>(sizeof(SolverState)));
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = tid + u * kThreads;
-      const double t = partials[q * nparts + (i < nparts ? i : 0)];
-      L.v[q][u] = (i < nparts) ? t : 0.0;
+      L.v[q][u] = load_f64(rp, 8u * static_cast<uint32_t>(q * nparts + (i < nparts ? i : 0)));
     }
+    L.step0[q] = load_f64(rs, 8u * static_cast<uint32_t>(q * nsteps));
   }
+  L.sw = load_i32(rst, 4u * static_cast<uint32_t>(lane < kStateWords ? lane : 0));
 }
 
 template <int NT>
-__device__ void decide(const SolverState* in, const double* partials, int nparts, const double* steps, int nsteps,
+__device__ void decide(const double* partials, int nparts, const double* steps, int nsteps,
                        const DecideLoads<NT>& L, Decision& dec, double* red) {
 #pragma clang fp contract(off)
   __shared__ double Gq[NT];
@@ -262,7 +295,7 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
     // four values per round, summed in index order
     s[q] = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[q] += L.v[q][u];
+    for (int u = 0; u < 4; ++u) s[q] += (tid + u * kThreads < nparts) ? L.v[q][u] : 0.0;
     const double* pq = partials + q * nparts;
     for (int i0 = tid + 4 * kThreads; i0 < nparts; i0 += 4 * kThreads) {
       double v[4];
@@ -276,10 +309,8 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
       for (int u = 0; u < 4; ++u) s[q] += v[u];
     }
   }
-  if (tid == 0) {
-    dec.st = *in;
-    dec.accepted = -1;
-  }
+  if (tid < kStateWords) reinterpret_cast<int32_t*>(&dec.st)[tid] = L.sw;
+  if (tid == 0) dec.accepted = -1;
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const double t = block_sum(s[q], red);
@@ -311,7 +342,8 @@ __device__ void decide(const SolverState* in, const double* partials, int nparts
       double sq[NT];
       for (int q = 0; q < NT; ++q) {
         double t = 0.0;
-        for (int w = 0; w < nsteps; ++w) t += steps[q * nsteps + w];
+        if (nsteps > 0) t += L.step0[q];
+        for (int w = 1; w < nsteps; ++w) t += steps[q * nsteps + w];
         sq[q] = t;
       }
       bool done = false;
@@ -854,7 +886,10 @@ __device__ __forceinline__ int log2_lanes(int nr) {
   return e;
 }
 
-template <int MODE>
+// UNCOND: every row load is issued (rows past the block read zeros out of
+// bounds), so that no load of the block sits in a branch and a later wait
+// for an earlier load can count exactly how many were issued after it.
+template <int MODE, bool UNCOND = false>
 __device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m, int lane, WaveStage& S) {
   const int a0 = m.k0 & ~3;
   const uint32_t bytes = static_cast<uint32_t>((m.k1 - a0) * 4 + 15) & ~15u;
@@ -874,7 +909,12 @@ __device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m,
   for (int p = 0; p < 4; ++p) {
     S.rlo[p] = S.rhi[p] = 0;
     S.sid[p] = 0;
-    if (p < passes) {
+    if (UNCOND) {
+      const int row = (p < passes) ? (p << (6 - e)) + (lane >> e) : nr + 1;
+      S.rlo[p] = load_i32(rp, 4 * row);
+      S.rhi[p] = load_i32(rp, 4 * row + 4);
+      if (MODE != FWD_PLAIN) S.sid[p] = load_u8(rs, row);
+    } else if (p < passes) {
       const int row = (p << (6 - e)) + (lane >> e);
       S.rlo[p] = load_i32(rp, 4 * row);
       S.rhi[p] = load_i32(rp, 4 * row + 4);
@@ -980,43 +1020,6 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   const int tid = threadIdx.x;
   constexpr bool solve = (MODE == FWD_SOLVE);
   constexpr bool want_sid = (MODE != FWD_PLAIN);
-  int ntr = 1;
-  rsrc_t rout[NT];
-  const uint32_t vbytes = 4u * static_cast<uint32_t>(a.nv);
-#pragma unroll
-  for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
-  const rsrc_t dout = make_rsrc(a.d_out, a.d_out ? vbytes : 0u);
-  // a solve's trial inputs are loaded before the state is known
-  TrialRegs<NT> TR;
-  StageRegs<NT> SR;
-  if (solve) {
-    trial_load<NT, THREADS>(a, tid, TR);
-    TR.tab = (tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
-  } else {
-    stage_start<NT, THREADS>(a, a.x, want_sid, SR);
-  }
-  TrialCtl T{true, false, 0};
-  double lam[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q) lam[q] = 0.0;
-  if (solve) {
-    const SolverState* st = a.st_in;
-    constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
-    if (blockIdx.x == 0 && tid < kWords)
-      reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
-    const int phase = st->phase;
-    if (phase == PH_DONE) return;
-    ntr = (phase == PH_INIT) ? 1 : NT;
-    T.init = (phase == PH_INIT);
-    T.lead = (blockIdx.x == 0);
-    T.xi = st->xi;
-    lam[0] = st->lambda;
-    const double alpha = st->alpha;
-#pragma unroll
-    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
-#pragma unroll
-    for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
-  }
 
   // This workgroup's contiguous range of row blocks; its waves take blocks
   // in turn from a counter in LDS (the first WAVES blocks one each), so a
@@ -1025,8 +1028,8 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   // so the total does not depend on which wave took which block.
   const int G = gridDim.x, w = blockIdx.x;
   const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
-  const int B0 = uniform(static_cast<int>(static_cast<long long>(lw) * a.nwblocks / G));
-  const int B1 = uniform(static_cast<int>(static_cast<long long>(lw + 1) * a.nwblocks / G));
+  const int B0 = split_point(lw, a.nwblocks, G);
+  const int B1 = split_point(lw + 1, a.nwblocks, G);
   auto global_meta = [&](int b) {
     WaveBlock m;
     m.r0 = uniform(a.wblock_row[b]);
@@ -1035,14 +1038,63 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
     m.k1 = uniform(a.wblock_k0[b + 1]);
     return m;
   };
-  // the first block's loads follow the staging loads, so waiting for those
-  // does not wait for these (the wait counter drains in issue order)
-  WaveStage S;
+  // Loads in the order their results are needed, none of them in a branch:
+  // the first block's bounds (lanes 0 and 1), the staging inputs (a solve's
+  // trial inputs before the state is known), the state (one word per lane),
+  // then the first block's nonzeros.  So no wait for one of them waits for a
+  // later one, and the block's loads overlap the staging.
   int b = B0 + wv;
+  const bool first = b < min(B1, B0 + kMetaChunk);
+  const uint32_t meta_bytes = 4u * static_cast<uint32_t>(a.nwblocks + 1);
+  const uint32_t moff = 4u * static_cast<uint32_t>(b + (lane & 1));
+  const int mrow0 = load_i32(make_rsrc(a.wblock_row, meta_bytes), moff);
+  const int mk00 = load_i32(make_rsrc(a.wblock_k0, meta_bytes), moff);
+  TrialRegs<NT> TR;
+  StageRegs<NT> SR;
+  int32_t sw = 0;
+  if (solve) {
+    trial_load<NT, THREADS>(a, tid, TR);
+    TR.tab = load_f64(make_rsrc(a.pen.table, 32u * static_cast<uint32_t>(a.nstruct)), 8u * tid);
+    sw = reinterpret_cast<const int32_t*>(a.st_in)[lane < kStateWords ? lane : 0];
+  } else {
+    stage_start<NT, THREADS>(a, a.x, want_sid, SR);
+  }
   WaveBlock cur{0, 0, 0, 0};
-  if (b < min(B1, B0 + kMetaChunk)) {
-    cur = global_meta(b);
-    if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+  if (first) {
+    cur.r0 = __builtin_amdgcn_readlane(mrow0, 0);
+    cur.r1 = __builtin_amdgcn_readlane(mrow0, 1);
+    cur.k0 = __builtin_amdgcn_readlane(mk00, 0);
+    cur.k1 = __builtin_amdgcn_readlane(mk00, 1);
+  }
+  // a row longer than a wave block is streamed in the loop instead
+  const bool short_first = cur.k1 - cur.k0 <= kWavePartNnz;
+  WaveStage S;
+  wave_issue<MODE, true>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+
+  int ntr = 1;
+  rsrc_t rout[NT];
+  const uint32_t vbytes = 4u * static_cast<uint32_t>(a.nv);
+#pragma unroll
+  for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.r_out, a.r_out ? vbytes : 0u);
+  const rsrc_t dout = make_rsrc(a.d_out, a.d_out ? vbytes : 0u);
+  TrialCtl T{true, false, 0};
+  double lam[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) lam[q] = 0.0;
+  if (solve) {
+    if (blockIdx.x == 0 && wv == 0 && lane < kStateWords) reinterpret_cast<int32_t*>(a.st_out)[lane] = sw;
+    const int phase = state_int(sw, offsetof(SolverState, phase));
+    if (phase == PH_DONE) return;
+    ntr = (phase == PH_INIT) ? 1 : NT;
+    T.init = (phase == PH_INIT);
+    T.lead = (blockIdx.x == 0);
+    T.xi = state_int(sw, offsetof(SolverState, xi));
+    lam[0] = state_f64(sw, offsetof(SolverState, lambda));
+    const double alpha = state_f64(sw, offsetof(SolverState, alpha));
+#pragma unroll
+    for (int q = 1; q < NT; ++q) lam[q] = lam[q - 1] / alpha;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
   if (solve) trial_finish<NT, THREADS>(a, TR, T, lam, tab, xs, red);
   else stage_finish<NT, THREADS>(a, a.x, want_sid, SR, tab, xs);
@@ -1164,14 +1216,19 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
       b = nxt;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (wv == 0) {
+      // the chunk's block contributions in a fixed order: lane l adds blocks
+      // l, l + 64, ..., then the lanes are summed
 #pragma unroll
-      for (int q = 0; q < NT; ++q)
-        for (int i = 0; i < c1 - c0; ++i) gsum[q] += gpart[q * kMetaChunk + i];
+      for (int q = 0; q < NT; ++q) {
+        double t = 0.0;
+        for (int i = lane; i < c1 - c0; i += 64) t += gpart[q * kMetaChunk + i];
+        gsum[q] += wave_sum(t);
+      }
     }
     __syncthreads();
   }
-  if (tid == 0) {
+  if (wv == 0 && lane == 63) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) a.partials[q * gridDim.x + blockIdx.x] = gsum[q];
   }
@@ -1258,46 +1315,45 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float 
 // residual gathers before the decision is known, from the residual buffer of
 // the pass's first trial (the one an accepted step of a single-trial pass
 // always lands in); if another trial is accepted they are issued again.
-template <int NT>
+template <int NT, bool SOLVE>
 __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   __shared__ double red[kWaves];
   __shared__ Decision dec;
   const int tid = threadIdx.x;
   const int lw = logical_wg(a.xcd_map != 0);
-  const int k0w = static_cast<int>(static_cast<int64_t>(lw) * a.nnz / a.grid);
-  const int k1w = static_cast<int>(static_cast<int64_t>(lw + 1) * a.nnz / a.grid);
+  const int k0w = split_point(lw, static_cast<int>(a.nnz), a.grid);
+  const int k1w = split_point(lw + 1, static_cast<int>(a.nnz), a.grid);
   const int kb = k0w & ~(kTile - 1);
   const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
   // whole tiles: entries of a partial tile sit anywhere in it
   const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
   const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
   const rsrc_t rv = make_rsrc(a.val + kb, bytes);
-  // the decision's partials first, then the first two rounds' loads: none
-  // depends on anything computed
+  // Every load of the prologue is issued at once and none sits in a branch
+  // (rounds past the range read zeros out of bounds), so each wait below
+  // waits for its own loads only: the decision's inputs, this workgroup's
+  // columns, the first two rounds, then the gathers of the first round.
   DecideLoads<NT> DL;
-  if (a.solve) decide_start<NT>(a.fwd_partials, a.fwd_parts, DL);
+  if (SOLVE) decide_start<NT>(a, DL);
+  const int4 wi = load_i4(make_rsrc(a.wg_cols, 16u * static_cast<uint32_t>(a.grid)), 16u * static_cast<uint32_t>(lw));
   AdjStage A, B;
-  if (nrounds > 0) adj_issue(ri, rv, 0, A);
-  if (nrounds > 1) adj_issue(ri, rv, 1, B);
-  const float* r = a.r;
-  if (a.solve) {
-    const SolverState* st = a.st_in;
-    if (st->phase == PH_DONE) {
-      // finished: the state passes through
-      constexpr int kWords = static_cast<int>(sizeof(SolverState) / sizeof(int32_t));
-      if (blockIdx.x == 0 && tid < kWords)
-        reinterpret_cast<int32_t*>(a.st_out)[tid] = reinterpret_cast<const int32_t*>(st)[tid];
-      return;
-    }
-    r = a.rbuf[0];   // residual of the first trial: the accepted one unless a later trial wins
-  }
-  const int c0 = uniform(a.wg_c0[lw]), c1 = uniform(a.wg_c1[lw]);
+  adj_issue(ri, rv, 0, A);
+  adj_issue(ri, rv, 1, B);
+  const int c0 = uniform(wi.x), c1 = uniform(wi.y);
+  int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
+  auto bounds = [&]() {
+    lo = max(uniform(a.col_ptr[c]), k0w);
+    hi = min(uniform(a.col_ptr[c + 1]), k1w);
+  };
+  // a solve gathers the residual of the first trial: the accepted one
+  // unless a later trial wins
   const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
-  rsrc_t rr = make_rsrc(r, rbytes);
+  rsrc_t rr = make_rsrc(SOLVE ? a.rbuf[0] : a.r, rbytes);
   float g[8];
-  if (nrounds > 0) adj_gather(rr, A, g);
-  if (a.solve) {
-    decide<NT>(a.st_in, a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red);
+  adj_gather(rr, A, g);
+  if (SOLVE) {
+    // (a finished solve passes its state through unchanged and exits here)
+    decide<NT>(a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red);
     if (blockIdx.x == 0 && tid == 0) {
       *a.st_out = dec.st;
       if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
@@ -1313,16 +1369,10 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
     if (dec.st.phase != PH_NEED_GRAD) return;
     if (dec.st.acc != 0) {
       rr = make_rsrc(select_buf(a.rbuf, dec.st.acc), rbytes);
-      if (nrounds > 0) adj_gather(rr, A, g);
+      adj_gather(rr, A, g);
     }
   }
 
-  int c = c0, lo = 0, hi = 0;
-  auto bounds = [&]() {
-    lo = max(uniform(a.col_ptr[c]), k0w);
-    hi = min(uniform(a.col_ptr[c + 1]), k1w);
-  };
-  if (c < c1) bounds();
   double s = 0.0;
   auto close = [&]() {
     const double t = block_sum(s, red);
@@ -1543,16 +1593,19 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
   clear_stale_error();
   const dim3 gd(a.grid), bd(kThreads);
   hipStream_t s = ctx->stream;
-  switch (ntrials) {
-    case 1: hipExtLaunchKernelGGL(adj_kernel<1>, gd, bd, 0, s, before, after, 0, a); break;
-    case 2: hipExtLaunchKernelGGL(adj_kernel<2>, gd, bd, 0, s, before, after, 0, a); break;
-    case 4: hipExtLaunchKernelGGL(adj_kernel<4>, gd, bd, 0, s, before, after, 0, a); break;
+  if (!a.solve && ntrials != 1) return set_error(IMRT_EINVAL, "a plain adjoint pass takes one vector");
+  switch (a.solve ? ntrials : 0) {
+    case 0: hipExtLaunchKernelGGL((adj_kernel<1, false>), gd, bd, 0, s, before, after, 0, a); break;
+    case 1: hipExtLaunchKernelGGL((adj_kernel<1, true>), gd, bd, 0, s, before, after, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((adj_kernel<2, true>), gd, bd, 0, s, before, after, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((adj_kernel<4, true>), gd, bd, 0, s, before, after, 0, a); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
   int rc = check_launch("adj_kernel");
   if (rc) return rc;
   if (!a.solve) {
-    // shared columns completed here (a solve completes them in its step kernel)
+    // shared columns completed here (in a solve the next forward pass
+    // completes them while it stages its trial points)
     const int g2 = (a.nb + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(adj_final_kernel, dim3(g2), dim3(kThreads), 0, s, a, static_cast<const SolverState*>(nullptr));
     rc = check_launch("adj_final_kernel");
