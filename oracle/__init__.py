@@ -10,7 +10,8 @@ Modules:
   phantom   synthetic structures and dose-deposition matrix D (brute force)
   model     dose, one-sided quadratic penalties, objective, gradient, projection
   solver    gradient projection with Armijo's line search, lambda_0, KKT residual
+  quantize  D stored in bfloat16 / binary16 codes with per-beamlet scales
 
 Parity status of each function is recorded with the pins in ``tests/``.
 """
-from . import model, phantom, solver  # noqa: F401
+from . import model, phantom, quantize, solver  # noqa: F401

@@ -93,3 +93,71 @@ def test_mirrored_lateral_axis_is_caught(monkeypatch):
     rows, _ = cols[0]
     want = np.nonzero(dense >= TINY.tau * dense.max())[0]
     assert not np.array_equal(rows, want)
+
+
+def _round_variant(how):
+    """round_to_format with the rounding step replaced (planted mistakes)."""
+    from oracle import quantize
+
+    def f(v, fmt):
+        p, emin = quantize.FORMATS[fmt]
+        v = np.asarray(v, dtype=np.float64)
+        out = np.zeros_like(v)
+        nz = v > 0
+        _, E = np.frexp(v[nz])
+        qe = np.maximum(E.astype(np.int64) - 1, emin) - (p - 1)
+        n = np.ldexp(v[nz], -qe)
+        out[nz] = np.ldexp(how(n), qe)
+        return out
+    return f
+
+
+def test_truncating_quantiser_is_caught(monkeypatch):
+    from oracle import quantize
+    import test_oracle_quantize as T
+    monkeypatch.setattr(quantize, "round_to_format", _round_variant(np.floor))
+    try:
+        T.test_bf16_matches_torch_conversion()
+    except AssertionError:
+        return
+    raise AssertionError("truncation not caught")
+
+
+def test_ties_away_from_zero_is_caught(monkeypatch):
+    from oracle import quantize
+    import test_oracle_quantize as T
+    monkeypatch.setattr(quantize, "round_to_format", _round_variant(lambda n: np.floor(n + 0.5)))
+    try:
+        T.test_ties_go_to_even()
+    except AssertionError:
+        return
+    raise AssertionError("ties away from zero not caught")
+
+
+def test_wrong_exponent_offset_is_caught(monkeypatch):
+    """One significand bit too many (quantum off by a factor two)."""
+    from oracle import quantize
+    import test_oracle_quantize as T
+    monkeypatch.setitem(quantize.FORMATS, "f16", (12, -14))
+    try:
+        T.test_f16_matches_numpy_conversion()
+    except (AssertionError, ValueError):
+        return
+    raise AssertionError("wrong precision not caught")
+
+
+def test_sum_instead_of_max_scale_is_caught(monkeypatch):
+    from oracle import quantize
+    import test_oracle_quantize as T
+
+    def col_sums(D):
+        C = sp.csc_matrix(D)
+        s = np.asarray(C.sum(axis=0)).ravel().astype(np.float32)
+        s[s == 0] = 1.0
+        return s
+    monkeypatch.setattr(quantize, "column_scales", col_sums)
+    try:
+        T.test_stored_form_properties("bf16")
+    except AssertionError:
+        return
+    raise AssertionError("sum scale not caught")
