@@ -63,7 +63,16 @@ typedef enum {
   IMRT_NUMERIC = 4       /* a trial objective was not finite */
 } imrt_solve_status;
 
-/* Storage type of D's values.  Only IMRT_F32 is accepted by this build. */
+/* Storage of D's values.  IMRT_F32: float32 values, int32 indices.
+ * IMRT_BF16 / IMRT_F16: for every beamlet i a float32 scale s_i = max_j D_ij
+ * (1 if no entry of the column is positive) and 16-bit codes
+ * q_ij = RN(D_ij / s_i), the exact quotient rounded once to bfloat16 or
+ * IEEE binary16 (nearest, ties to even); every product then uses
+ * D~_ij = s_i q_ij, and the CSR column indices are 16-bit (nb <= 65536).
+ * Both sparse products still accumulate in float32 (forward) and float64
+ * (adjoint); the objective, the Armijo test and the stopping test stay in
+ * float64.  The 16-bit forms need the "fwd_wave" option at 1.  The paper
+ * stores D in float32; the 16-bit forms halve the bytes of the values. */
 typedef enum { IMRT_F32 = 0, IMRT_BF16 = 1, IMRT_F16 = 2 } imrt_dtype;
 
 /* Penalty parameters of one structure (Eq. (1), generalised to separate
@@ -172,7 +181,7 @@ IMRT_API int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t*
 /* ---- dose-deposition matrix (Section 2.1; stored as CSR, Section 2.3) ---- */
 
 /* Build the synthetic phantom's structure ids and D on the device (CSR and
- * CSC, float32 values, int32 indices; columns ascending in each row, rows
+ * CSC in the given storage, from float32 values; columns ascending in each row, rows
  * ascending in each column; the rows are held in the internal voxel order
  * of the "voxel_tiles" option, and imrt_dose_export returns grid order).
  * voxel_struct_out: nullable host array of nx*ny*nz bytes receiving the
@@ -184,7 +193,8 @@ IMRT_API int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, im
 /* Upload a caller-built D given in CSR form (host arrays, copied).  row_ptr
  * has nv+1 entries starting at 0 and non-decreasing; col_idx entries lie in
  * [0, nb) and increase strictly within each row; values are finite and
- * >= 0.  The CSC copy is derived on the host. */
+ * >= 0.  The CSC copy is derived on the host; 16-bit storage is then
+ * coded on the device from the float32 values. */
 IMRT_API int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz,
                        const int32_t* row_ptr, const int32_t* col_idx, const float* val,
                        imrt_dtype storage, imrt_dose** out);
@@ -193,9 +203,19 @@ IMRT_API int imrt_dose_info(const imrt_dose* dose, int32_t* nv, int32_t* nb, int
 
 /* Copy D back to host arrays (each nullable): CSR row_ptr[nv+1],
  * col_idx[nnz], val[nnz]; CSC col_ptr[nb+1], row_idx[nnz], cval[nnz];
- * voxel_struct[nv] (only for matrices from imrt_build_dose_matrix). */
+ * voxel_struct[nv] (only for matrices from imrt_build_dose_matrix).  With
+ * 16-bit storage val and cval receive the float32 rounding of s_i q_ij. */
 IMRT_API int imrt_dose_export(const imrt_dose* dose, int32_t* row_ptr, int32_t* col_idx, float* val,
                      int32_t* col_ptr, int32_t* row_idx, float* cval, uint8_t* voxel_struct);
+
+/* 16-bit storage only (else IMRT_EINVAL): the codes q_ij as bit patterns in
+ * CSR order (val_code[nnz]) and CSC order (cval_code[nnz]), and the scales
+ * col_scale[nb]; each nullable; same orders as imrt_dose_export. */
+IMRT_API int imrt_dose_export_codes(const imrt_dose* dose, uint16_t* val_code, uint16_t* cval_code,
+                                    float* col_scale);
+
+/* The imrt_dtype D is stored in. */
+IMRT_API int imrt_dose_storage(const imrt_dose* dose, int32_t* storage);
 
 /* d = D x (CSR, voxel-parallel).  x_dev: nb floats; d_dev: nv floats. */
 IMRT_API int imrt_dose_apply(const imrt_dose* dose, const float* x_dev, float* d_dev);

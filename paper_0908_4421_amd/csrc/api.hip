@@ -260,6 +260,10 @@ void free_dose(imrt_dose* D) {
   dev_free(D->col_ptr);
   dev_free(D->row_idx);
   dev_free(D->cval);
+  dev_free(D->col16);
+  dev_free(D->val16);
+  dev_free(D->cval16);
+  dev_free(D->col_scale);
   dev_free(D->block_row);
   dev_free(D->block_k0);
   dev_free(D->wblock_row);
@@ -319,6 +323,10 @@ FwdArgs base_fwd(const imrt_dose* D) {
   a.row_ptr = D->row_ptr;
   a.col_idx = D->col_idx;
   a.val = D->val;
+  a.col16 = D->col16;
+  a.val16 = D->val16;
+  a.col_scale = D->col_scale;
+  a.storage = D->storage;
   a.block_row = D->block_row;
   a.block_k0 = D->block_k0;
   a.nblocks = D->nblocks;
@@ -361,6 +369,9 @@ AdjArgs base_adj(const imrt_dose* D) {
   AdjArgs a{};
   a.row_idx = D->row_idx;
   a.val = D->cval;
+  a.val16 = D->cval16;
+  a.col_scale = D->col_scale;
+  a.storage = D->storage;
   a.col_ptr = D->col_ptr;
   a.wg_cols = D->wg_cols;
   a.col_wlo = D->col_wlo;
@@ -491,7 +502,8 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
                            uint8_t* voxel_struct_out) {
   if (!ctx || !geom || !out) return set_error(IMRT_EINVAL, "ctx, geom or out is NULL");
   *out = nullptr;
-  if (storage != IMRT_F32) return set_error(IMRT_EUNSUPPORTED, "only IMRT_F32 storage is supported");
+  if (storage != IMRT_F32 && storage != IMRT_BF16 && storage != IMRT_F16)
+    return set_error(IMRT_EINVAL, "storage must be IMRT_F32, IMRT_BF16 or IMRT_F16");
   int rc = use_device(ctx);
   if (rc) return rc;
   auto* D = new (std::nothrow) imrt_dose();
@@ -500,6 +512,7 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
   D->device = ctx->device;
   try {
     rc = build_phantom(ctx, geom, D);
+    if (rc == IMRT_OK) rc = store16(D, storage);
   } catch (const std::bad_alloc&) {
     rc = set_error(IMRT_ENOMEM, "host allocation failed");
   }
@@ -525,7 +538,10 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
                        const int32_t* col_idx, const float* val, imrt_dtype storage, imrt_dose** out) {
   if (!ctx || !out || !row_ptr) return set_error(IMRT_EINVAL, "ctx, out or row_ptr is NULL");
   *out = nullptr;
-  if (storage != IMRT_F32) return set_error(IMRT_EUNSUPPORTED, "only IMRT_F32 storage is supported");
+  if (storage != IMRT_F32 && storage != IMRT_BF16 && storage != IMRT_F16)
+    return set_error(IMRT_EINVAL, "storage must be IMRT_F32, IMRT_BF16 or IMRT_F16");
+  if (storage != IMRT_F32 && nb > 65536)
+    return set_error(IMRT_EUNSUPPORTED, "16-bit storage needs nb <= 65536 (16-bit column indices)");
   if (nv <= 0 || nb <= 0) return set_error(IMRT_EINVAL, "nv and nb must be positive");
   if (nnz < 0 || nnz >= (int64_t(1) << 31)) return set_error(IMRT_EINVAL, "nnz must be in [0, 2^31)");
   if (nnz > 0 && (!col_idx || !val)) return set_error(IMRT_EINVAL, "col_idx or val is NULL");
@@ -581,6 +597,7 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
       return hip_error(e, "upload of D");
     }
     rc = finish_dose(D, rp, cp);
+    if (rc == IMRT_OK) rc = store16(D, storage);
   } catch (const std::bad_alloc&) {
     rc = set_error(IMRT_ENOMEM, "host allocation failed");
   }
@@ -600,12 +617,33 @@ int imrt_dose_info(const imrt_dose* dose, int32_t* nv, int32_t* nb, int64_t* nnz
   return IMRT_OK;
 }
 
-int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, float* val, int32_t* col_ptr,
-                     int32_t* row_idx, float* cval, uint8_t* voxel_struct) {
-  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+namespace {
+
+// float64 value of a 16-bit code (bfloat16 or binary16 bit pattern).
+double code_value_host(uint16_t h, int storage) {
+  if (storage == ST_BF16) {
+    const uint32_t b = static_cast<uint32_t>(h) << 16;
+    float f;
+    std::memcpy(&f, &b, sizeof f);
+    return f;
+  }
+  const int e = (h >> 10) & 31, m = h & 1023;
+  const double v = (e == 0) ? std::ldexp(static_cast<double>(m), -24) : std::ldexp(static_cast<double>(m + 1024), e - 25);
+  return (h & 0x8000) ? -v : v;
+}
+
+// Host copies of D in the caller's voxel order: float32 values (for 16-bit
+// storage the float32 rounding of s_i q_ij) and, for 16-bit storage, the
+// codes themselves.
+int export_dose(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, float* val, int32_t* col_ptr,
+                int32_t* row_idx, float* cval, uint8_t* voxel_struct, uint16_t* val_code, uint16_t* cval_code,
+                float* col_scale) {
   int rc = use_device(D->ctx);
   if (rc) return rc;
   if (voxel_struct && !D->sid) return set_error(IMRT_EINVAL, "this dose matrix has no structure ids");
+  const bool s16 = D->storage != ST_F32;
+  if ((val_code || cval_code || col_scale) && !s16)
+    return set_error(IMRT_EINVAL, "this dose matrix stores float32 values, not 16-bit codes");
   hipStream_t s = D->ctx->stream;
   const int nv = D->nv, nb = D->nb;
   const size_t nz = static_cast<size_t>(D->nnz);
@@ -613,41 +651,66 @@ int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, flo
   try {
     // internal arrays (CSC back in plain column-major order), then the
     // caller's voxel order: rows of D and row indices of the CSC mapped by vox
-    const bool want_csr = row_ptr || col_idx || val;
-    const bool want_csc = row_idx || cval;
+    const bool want_csr = row_ptr || col_idx || val || val_code;
+    const bool want_csc = row_idx || cval || cval_code;
     std::vector<int32_t> rp(want_csr ? nv + 1 : 0), ci(want_csr ? nz : 0), cp(nb + 1), ri;
-    std::vector<float> va(want_csr ? nz : 0), cv;
+    std::vector<float> va(want_csr ? nz : 0), cv, sc(s16 ? nb : 0);
+    std::vector<uint16_t> qa(want_csr && s16 ? nz : 0), qc, c16(want_csr && s16 ? nz : 0);
     std::vector<uint8_t> sid(voxel_struct ? nv : 0);
+    if (s16) IMRT_HIP(hipMemcpyAsync(sc.data(), D->col_scale, sizeof(float) * nb, hipMemcpyDeviceToHost, s));
     if (want_csr) {
       IMRT_HIP(hipMemcpyAsync(rp.data(), D->row_ptr, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToHost, s));
-      if (nz) IMRT_HIP(hipMemcpyAsync(ci.data(), D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
-      if (nz) IMRT_HIP(hipMemcpyAsync(va.data(), D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
+      if (nz && !s16) {
+        IMRT_HIP(hipMemcpyAsync(ci.data(), D->col_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+        IMRT_HIP(hipMemcpyAsync(va.data(), D->val, sizeof(float) * nz, hipMemcpyDeviceToHost, s));
+      } else if (nz) {
+        IMRT_HIP(hipMemcpyAsync(c16.data(), D->col16, sizeof(uint16_t) * nz, hipMemcpyDeviceToHost, s));
+        IMRT_HIP(hipMemcpyAsync(qa.data(), D->val16, sizeof(uint16_t) * nz, hipMemcpyDeviceToHost, s));
+      }
     }
     IMRT_HIP(hipMemcpyAsync(cp.data(), D->col_ptr, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+    IMRT_HIP(hipStreamSynchronize(s));
+    if (want_csr && s16)
+      for (size_t k = 0; k < nz; ++k) {
+        ci[k] = c16[k];
+        va[k] = static_cast<float>(static_cast<double>(sc[ci[k]]) * code_value_host(qa[k], D->storage));
+      }
     if (want_csc && nz) {
       const size_t nzc = csc_alloc(D->nnz);
       std::vector<int32_t> rit(nzc);
-      std::vector<float> cvt(nzc);
+      std::vector<float> cvt(s16 ? 0 : nzc);
+      std::vector<uint16_t> qct(s16 ? nzc : 0);
       IMRT_HIP(hipMemcpyAsync(rit.data(), D->row_idx, sizeof(int32_t) * nzc, hipMemcpyDeviceToHost, s));
-      IMRT_HIP(hipMemcpyAsync(cvt.data(), D->cval, sizeof(float) * nzc, hipMemcpyDeviceToHost, s));
+      if (s16) IMRT_HIP(hipMemcpyAsync(qct.data(), D->cval16, sizeof(uint16_t) * nzc, hipMemcpyDeviceToHost, s));
+      else IMRT_HIP(hipMemcpyAsync(cvt.data(), D->cval, sizeof(float) * nzc, hipMemcpyDeviceToHost, s));
       IMRT_HIP(hipStreamSynchronize(s));
       ri.resize(nz);
       cv.resize(nz);
-      for (size_t k = 0; k < nz; ++k) {
-        const int64_t p = csc_slot(static_cast<int64_t>(k));
-        ri[k] = rit[p];
-        cv[k] = cvt[p];
-      }
+      if (s16) qc.resize(nz);
+      for (int32_t c = 0; c < nb; ++c)
+        for (int32_t k = cp[c]; k < cp[c + 1]; ++k) {
+          const int64_t p = csc_slot(k);
+          ri[k] = rit[p];
+          if (s16) {
+            qc[k] = qct[p];
+            cv[k] = static_cast<float>(static_cast<double>(sc[c]) * code_value_host(qct[p], D->storage));
+          } else {
+            cv[k] = cvt[p];
+          }
+        }
     }
     if (voxel_struct) IMRT_HIP(hipMemcpyAsync(sid.data(), D->sid, nv, hipMemcpyDeviceToHost, s));
     IMRT_HIP(hipStreamSynchronize(s));
     if (col_ptr) std::memcpy(col_ptr, cp.data(), sizeof(int32_t) * (nb + 1));
+    if (col_scale && nb) std::memcpy(col_scale, sc.data(), sizeof(float) * nb);
     if (!perm) {
       if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int32_t) * (nv + 1));
       if (col_idx && nz) std::memcpy(col_idx, ci.data(), sizeof(int32_t) * nz);
       if (val && nz) std::memcpy(val, va.data(), sizeof(float) * nz);
+      if (val_code && nz) std::memcpy(val_code, qa.data(), sizeof(uint16_t) * nz);
       if (row_idx && nz) std::memcpy(row_idx, ri.data(), sizeof(int32_t) * nz);
       if (cval && nz) std::memcpy(cval, cv.data(), sizeof(float) * nz);
+      if (cval_code && nz) std::memcpy(cval_code, qc.data(), sizeof(uint16_t) * nz);
       if (voxel_struct) std::memcpy(voxel_struct, sid.data(), nv);
       return IMRT_OK;
     }
@@ -662,20 +725,22 @@ int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, flo
         for (int32_t e = rp[p]; e < rp[p + 1]; ++e, ++k) {
           if (col_idx) col_idx[k] = ci[e];
           if (val) val[k] = va[e];
+          if (val_code) val_code[k] = qa[e];
         }
       }
       if (row_ptr) row_ptr[nv] = static_cast<int32_t>(k);
     }
     if (want_csc) {
-      std::vector<std::pair<int32_t, float>> col;
+      std::vector<int32_t> order;
       for (int32_t c = 0; c < nb; ++c) {
-        col.clear();
-        for (int32_t e = cp[c]; e < cp[c + 1]; ++e) col.emplace_back(vox[ri[e]], cv[e]);
-        std::sort(col.begin(), col.end(),
-                  [](const std::pair<int32_t, float>& x, const std::pair<int32_t, float>& y) { return x.first < y.first; });
+        order.clear();
+        for (int32_t e = cp[c]; e < cp[c + 1]; ++e) order.push_back(e);
+        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return vox[ri[x]] < vox[ri[y]]; });
         for (int32_t e = cp[c]; e < cp[c + 1]; ++e) {
-          if (row_idx) row_idx[e] = col[e - cp[c]].first;
-          if (cval) cval[e] = col[e - cp[c]].second;
+          const int32_t f = order[e - cp[c]];
+          if (row_idx) row_idx[e] = vox[ri[f]];
+          if (cval) cval[e] = cv[f];
+          if (cval_code) cval_code[e] = qc[f];
         }
       }
     }
@@ -684,6 +749,25 @@ int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, flo
   } catch (const std::bad_alloc&) {
     return set_error(IMRT_ENOMEM, "host allocation failed");
   }
+  return IMRT_OK;
+}
+
+}  // namespace
+
+int imrt_dose_export(const imrt_dose* D, int32_t* row_ptr, int32_t* col_idx, float* val, int32_t* col_ptr,
+                     int32_t* row_idx, float* cval, uint8_t* voxel_struct) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  return export_dose(D, row_ptr, col_idx, val, col_ptr, row_idx, cval, voxel_struct, nullptr, nullptr, nullptr);
+}
+
+int imrt_dose_export_codes(const imrt_dose* D, uint16_t* val_code, uint16_t* cval_code, float* col_scale) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  return export_dose(D, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, val_code, cval_code, col_scale);
+}
+
+int imrt_dose_storage(const imrt_dose* D, int32_t* storage) {
+  if (!D || !storage) return set_error(IMRT_EINVAL, "dose or storage is NULL");
+  *storage = D->storage;
   return IMRT_OK;
 }
 

@@ -208,7 +208,109 @@ struct DevBuf {
   }
 };
 
+// ---- 16-bit storage ---------------------------------------------------------------
+// Code of a nonnegative float64 quotient v = D_ij / s_i in bfloat16 (8
+// significand bits, smallest normal exponent -126) or binary16 (11, -14):
+// with 2^e <= v < 2^(e+1), the quantum is 2^(max(e, emin) - p + 1); v divided
+// by it is exact, rint rounds it to nearest with ties to even, and the rounded
+// value is representable in float32 and in the 16-bit format.  The float64
+// quotient of two float32 numbers never lands on (or across) a tie of these
+// formats unless the exact quotient does, so this is the rounding of the
+// exact quotient.
+template <int ST>
+__device__ uint16_t code16(double v) {
+  if (!(v > 0.0)) return 0;
+  constexpr int p = (ST == ST_BF16) ? 8 : 11;
+  constexpr int emin = (ST == ST_BF16) ? -126 : -14;
+  int E = 0;
+  (void)frexp(v, &E);   // v = m 2^E, 1/2 <= m < 1
+  const int qe = max(E - 1, emin) - (p - 1);
+  const float f = static_cast<float>(ldexp(rint(ldexp(v, -qe)), qe));
+  if (ST == ST_BF16) return static_cast<uint16_t>(__float_as_uint(f) >> 16);
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(f));
+}
+
+// One wave per column: s = the largest value (1 when none is positive), then
+// the codes of the column's entries in CSC slot order.
+template <int ST>
+__global__ __launch_bounds__(kThreads) void quantize_columns_kernel(const int32_t* col_ptr, const float* cval,
+                                                                     int nb, float* scale, uint16_t* cval16) {
+  const int c = blockIdx.x * kWaves + static_cast<int>(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= nb) return;
+  const int k0 = col_ptr[c], k1 = col_ptr[c + 1];
+  float m = 0.0f;
+  for (int k = k0 + lane; k < k1; k += 64) m = fmaxf(m, cval[csc_slot(k)]);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  const float sc = (m > 0.0f) ? m : 1.0f;
+  if (lane == 0) scale[c] = sc;
+  for (int k = k0 + lane; k < k1; k += 64) {
+    const int64_t slot = csc_slot(k);
+    cval16[slot] = code16<ST>(static_cast<double>(cval[slot]) / static_cast<double>(sc));
+  }
+}
+
+// CSR codes and 16-bit column indices.
+template <int ST>
+__global__ __launch_bounds__(kThreads) void quantize_rows_kernel(const int32_t* col_idx, const float* val, int64_t nnz,
+                                                                  const float* scale, uint16_t* col16,
+                                                                  uint16_t* val16) {
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; k < nnz;
+       k += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int c = col_idx[k];
+    col16[k] = static_cast<uint16_t>(c);
+    val16[k] = code16<ST>(static_cast<double>(val[k]) / static_cast<double>(scale[c]));
+  }
+}
+
 }  // namespace
+
+int store16(imrt_dose* D, int storage) {
+  if (storage == ST_F32) return IMRT_OK;
+  if (storage != ST_BF16 && storage != ST_F16) return set_error(IMRT_EINVAL, "unknown storage");
+  if (D->nb > 65536) return set_error(IMRT_EUNSUPPORTED, "16-bit storage needs nb <= 65536 (16-bit column indices)");
+  const size_t nz = static_cast<size_t>(D->nnz) + kPad, nzc = csc_alloc(D->nnz);
+  auto alloc = [](void** p, size_t bytes) -> int {
+    const hipError_t e = hipMalloc(p, bytes < 1 ? 1 : bytes);
+    if (e == hipErrorOutOfMemory) return set_error(IMRT_ENOMEM, "hipMalloc: out of device memory");
+    if (e != hipSuccess) return hip_error(e, "hipMalloc(16-bit storage)");
+    return IMRT_OK;
+  };
+  int rc;
+  if ((rc = alloc(reinterpret_cast<void**>(&D->col_scale), sizeof(float) * std::max(D->nb, 1))) ||
+      (rc = alloc(reinterpret_cast<void**>(&D->col16), 2 * nz)) ||
+      (rc = alloc(reinterpret_cast<void**>(&D->val16), 2 * nz)) ||
+      (rc = alloc(reinterpret_cast<void**>(&D->cval16), 2 * nzc)))
+    return rc;
+  hipStream_t s = D->ctx->stream;
+  IMRT_HIP(hipMemsetAsync(D->col16, 0, 2 * nz, s));
+  IMRT_HIP(hipMemsetAsync(D->val16, 0, 2 * nz, s));
+  IMRT_HIP(hipMemsetAsync(D->cval16, 0, 2 * nzc, s));
+  const int gc = std::max(1, (D->nb + kWaves - 1) / kWaves);
+  const int gr = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((D->nnz + kThreads - 1) / kThreads, 8192)));
+  if (storage == ST_BF16) {
+    hipLaunchKernelGGL(quantize_columns_kernel<ST_BF16>, dim3(gc), dim3(kThreads), 0, s, D->col_ptr, D->cval, D->nb,
+                       D->col_scale, D->cval16);
+    hipLaunchKernelGGL(quantize_rows_kernel<ST_BF16>, dim3(gr), dim3(kThreads), 0, s, D->col_idx, D->val, D->nnz,
+                       D->col_scale, D->col16, D->val16);
+  } else {
+    hipLaunchKernelGGL(quantize_columns_kernel<ST_F16>, dim3(gc), dim3(kThreads), 0, s, D->col_ptr, D->cval, D->nb,
+                       D->col_scale, D->cval16);
+    hipLaunchKernelGGL(quantize_rows_kernel<ST_F16>, dim3(gr), dim3(kThreads), 0, s, D->col_idx, D->val, D->nnz,
+                       D->col_scale, D->col16, D->val16);
+  }
+  IMRT_HIP(hipGetLastError());
+  IMRT_HIP(hipStreamSynchronize(s));
+  // the float32 values and indices are not kept
+  IMRT_HIP(hipFree(D->col_idx));
+  IMRT_HIP(hipFree(D->val));
+  IMRT_HIP(hipFree(D->cval));
+  D->col_idx = nullptr;
+  D->val = nullptr;
+  D->cval = nullptr;
+  D->storage = storage;
+  return IMRT_OK;
+}
 
 int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   if (G->nx <= 0 || G->ny <= 0 || G->nz <= 0 || G->n_beams <= 0)

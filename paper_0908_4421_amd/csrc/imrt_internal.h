@@ -73,10 +73,19 @@ struct Penalties {
   const float* To_vox;
 };
 
+// Storage of D's values (the imrt_dtype codes): float32, or 16-bit codes q
+// with a float32 scale per beamlet (D~_ij = col_scale[i] * q_ij), where the
+// CSR column indices are 16-bit too.
+enum Storage : int32_t { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
+
 struct FwdArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
   const float* val;
+  const uint16_t* col16;     // 16-bit storage: column indices
+  const uint16_t* val16;     // 16-bit storage: codes
+  const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
+  int32_t storage;
   const int32_t* block_row;  // nblocks + 1 row boundaries
   const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
@@ -114,6 +123,9 @@ struct FwdArgs {
 struct AdjArgs {
   const int32_t* row_idx;
   const float* val;
+  const uint16_t* val16;     // 16-bit storage: codes (CSC slot order)
+  const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
+  int32_t storage;
   const int32_t* col_ptr;
   const int32_t* wg_cols;
   const int32_t* col_wlo;
@@ -171,6 +183,13 @@ struct imrt_dose {
   int32_t* col_ptr = nullptr;
   int32_t* row_idx = nullptr;
   float* cval = nullptr;
+  // 16-bit storage (then col_idx, val and cval are released): CSR column
+  // indices and codes, CSC codes, per-beamlet scales
+  int32_t storage = 0;
+  uint16_t* col16 = nullptr;
+  uint16_t* val16 = nullptr;
+  uint16_t* cval16 = nullptr;
+  float* col_scale = nullptr;
   // forward row blocks and adjoint chunks
   int32_t nblocks = 0;
   int32_t* block_row = nullptr;
@@ -271,6 +290,8 @@ int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double l
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out);
 // out[vox[p]] = in[p] (scatter) or out[p] = in[vox[p]] (gather), p < n
 int launch_permute(const imrt_ctx* ctx, const float* in, const int32_t* vox, int n, float* out, bool scatter);
+// Replace D's float32 values by 16-bit codes with per-beamlet scales (build.hip).
+int store16(imrt_dose* D, int storage);
 
 // phantom builder (build.hip)
 int build_phantom(imrt_ctx* ctx, const imrt_geometry* g, imrt_dose* D);

@@ -25,6 +25,7 @@
 // die's L2 for their residual gathers.
 #include <algorithm>
 #include <cstddef>
+#include <type_traits>
 #include <cmath>
 
 #include <hip/hip_ext.h>
@@ -129,6 +130,9 @@ __device__ __forceinline__ float load_f32(rsrc_t r, uint32_t off) {
 }
 __device__ __forceinline__ double load_f64(rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ uint2 load_u2(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 __device__ __forceinline__ uint32_t load_u8(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
@@ -412,6 +416,40 @@ __device__ void decide(const double* partials, int nparts, const double* steps, 
   __syncthreads();
 }
 
+// ---- stored values --------------------------------------------------------------
+// A lane holds its entries in groups of four: float32 storage as int4 column
+// indices and float4 values, 16-bit storage as two 32-bit words of packed
+// 16-bit indices or codes (entry u in the low half of word u / 2 when u is
+// even, in the high half when odd).
+template <int ST>
+__device__ __forceinline__ float code_value(uint32_t h) {
+  if constexpr (ST == ST_BF16) {
+    return __uint_as_float(h << 16);
+  } else {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(h)));
+  }
+}
+__device__ __forceinline__ uint32_t half_of(const uint2& w, int u) {
+  const uint32_t x = (u < 2) ? w.x : w.y;
+  return (u & 1) ? (x >> 16) : (x & 0xFFFFu);
+}
+__device__ __forceinline__ int col_of(const int4& c, int u) {
+  return u == 0 ? c.x : u == 1 ? c.y : u == 2 ? c.z : c.w;
+}
+__device__ __forceinline__ int col_of(const uint2& c, int u) { return static_cast<int>(half_of(c, u)); }
+template <int ST>
+__device__ __forceinline__ float val_of(const float4& v, int u) {
+  return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
+}
+template <int ST>
+__device__ __forceinline__ float val_of(const uint2& v, int u) {
+  return code_value<ST>(half_of(v, u));
+}
+template <int ST>
+using ColGroup = std::conditional_t<ST == ST_F32, int4, uint2>;
+template <int ST>
+using ValGroup = std::conditional_t<ST == ST_F32, float4, uint2>;
+
 // ---- forward pass ---------------------------------------------------------------
 struct BlockMeta {
   int r0, r1, k0, k1;
@@ -518,10 +556,11 @@ constexpr int kStageU = 8;   // entries per thread per round and vector
 template <int NT>
 struct StageRegs {
   float v[NT][kStageU];
+  float sc[kStageU];
   double tab;
 };
 
-template <int NT, int THREADS = kThreads>
+template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, bool want_sid, StageRegs<NT>& R) {
   const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
 #pragma unroll
@@ -532,11 +571,20 @@ __device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, 
       R.v[q][u] = src[q * nbp + (i < nb ? i : 0)];
     }
   }
+  if constexpr (ST != ST_F32) {
+#pragma unroll
+    for (int u = 0; u < kStageU; ++u) {
+      const int i = tid + u * THREADS;
+      R.sc[u] = a.col_scale[i < nb ? i : 0];
+    }
+  }
   // first THREADS doubles of the table (4 per structure); the rest in stage_finish
   R.tab = (want_sid && tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
 }
 
-template <int NT, int THREADS = kThreads>
+// With 16-bit storage the staged vector is scaled by the beamlet scales, so
+// that the products use the codes directly: sum_i q_ji (s_i x_i).
+template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src, bool want_sid,
                                              const StageRegs<NT>& R, PenaltyDev* tab, float* xs) {
   const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
@@ -551,7 +599,7 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int i = tid + u * THREADS;
-      if (i < nb) xs[q * nbp + i] = R.v[q][u];
+      if (i < nb) xs[q * nbp + i] = (ST == ST_F32) ? R.v[q][u] : R.v[q][u] * R.sc[u];
     }
   }
   for (int i0 = tid + kStageU * THREADS; i0 < nb; i0 += kStageU * THREADS) {
@@ -562,6 +610,7 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
       for (int u = 0; u < kStageU; ++u) {
         const int i = i0 + u * THREADS;
         v[q][u] = src[q * nbp + (i < nb ? i : 0)];
+        if constexpr (ST != ST_F32) v[q][u] *= a.col_scale[i < nb ? i : 0];
       }
     }
 #pragma unroll
@@ -592,10 +641,11 @@ struct TrialRegs {
   float g[kTrialU];
   double p0[kTrialU], p1[kTrialU];
   uint32_t kind[kTrialU];
+  float sc[kTrialU];
   double tab;
 };
 
-template <int NT, int THREADS = kThreads>
+template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<NT>& R) {
   const int nb = a.nb;
 #pragma unroll
@@ -608,10 +658,12 @@ __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<N
     R.p0[u] = a.pieces_col[2 * ii];
     R.p1[u] = a.pieces_col[2 * ii + 1];
     R.kind[u] = a.col_kind[ii];
+    if constexpr (ST != ST_F32) R.sc[u] = a.col_scale[ii];
   }
 }
 
-// Sum of the pieces of a column shared by three or more adjoint workgroups.
+// Sum of the pieces of a column shared by three or more adjoint workgroups
+// (16-bit storage: of the codes' products, before the beamlet scale).
 __device__ __forceinline__ double pieces_sum(const FwdArgs& a, int c) {
   const int wlo = a.col_wlo[c], whi = a.col_whi[c];
   double tot = a.pieces[2 * wlo + 1];
@@ -625,7 +677,7 @@ struct TrialCtl {
   int xi;
 };
 
-template <int NT, int THREADS = kThreads>
+template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const TrialRegs<NT>& R, const TrialCtl& T,
                                             const double (&lam)[NT], float* xs, double (&sq)[NT]) {
   const int nb = a.nb, nbp = pad4(nb);
@@ -638,16 +690,17 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
     for (int j = 1; j <= NT; ++j) x = (T.xi == j) ? R.xc[j][u] : x;
     if (T.init) {
 #pragma unroll
-      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = x;
+      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = (ST == ST_F32) ? x : x * R.sc[u];
       continue;
     }
+    const double gf = (ST == ST_F32) ? a.g_scale : a.g_scale * static_cast<double>(R.sc[u]);
     float g = R.g[u];
-    if (R.kind[u] == 1) g = static_cast<float>(a.g_scale * (R.p0[u] + R.p1[u]));
-    else if (R.kind[u] > 1) g = static_cast<float>(a.g_scale * pieces_sum(a, i));
+    if (R.kind[u] == 1) g = static_cast<float>(gf * (R.p0[u] + R.p1[u]));
+    else if (R.kind[u] > 1) g = static_cast<float>(gf * pieces_sum(a, i));
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const float t = trial_point(x, g, lam[q]);
-      xs[q * nbp + i] = t;
+      xs[q * nbp + i] = (ST == ST_F32) ? t : t * R.sc[u];
       if (T.lead) {
         select_buf(a.xbuf, (T.xi + 1 + q) % (NT + 1))[i] = t;
         const double dl = static_cast<double>(t) - static_cast<double>(x);
@@ -659,7 +712,7 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
 
 // After the first round (loaded by the caller): the remaining rounds, the
 // lead workgroup's step norms, the penalty table; ends with a barrier.
-template <int NT, int THREADS = kThreads>
+template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<NT>& R, const TrialCtl& T,
                                              const double (&lam)[NT], PenaltyDev* tab, float* xs, double* red) {
   const int tid = threadIdx.x;
@@ -672,11 +725,11 @@ __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<N
     for (int i = tid + THREADS; i < 4 * a.nstruct; i += THREADS)
       dst[i] = reinterpret_cast<const double*>(a.pen.table)[i];
   }
-  trial_store<NT, THREADS>(a, tid, R, T, lam, xs, sq);
+  trial_store<NT, THREADS, ST>(a, tid, R, T, lam, xs, sq);
   for (int i0 = tid + kTrialU * THREADS; i0 < a.nb; i0 += kTrialU * THREADS) {
     TrialRegs<NT> R2;
-    trial_load<NT, THREADS>(a, i0, R2);
-    trial_store<NT, THREADS>(a, i0, R2, T, lam, xs, sq);
+    trial_load<NT, THREADS, ST>(a, i0, R2);
+    trial_store<NT, THREADS, ST>(a, i0, R2, T, lam, xs, sq);
   }
   if (T.lead && !T.init) {
 #pragma unroll
@@ -868,12 +921,40 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 // products of the current one are in LDS.
 constexpr int kWaveSlack = 256;   // LDS floats after the last wave region (over-reads of masked slots)
 
+template <int ST>
 struct WaveStage {
-  int4 c[2];
-  float4 v[2];
+  ColGroup<ST> c[2];
+  ValGroup<ST> v[2];
   int rlo[4], rhi[4];
   uint32_t sid[4];
 };
+
+// Loads of the eight entries base + 4 lane + 256 j + u (j < 2, u < 4) of the
+// CSR index and value arrays; base is a multiple of 4 and the arrays carry a
+// zeroed tail, so whole groups stay in bounds and entries past k1 read zeros.
+template <int ST>
+__device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, int lane, ColGroup<ST> (&c)[2],
+                                          ValGroup<ST> (&v)[2]) {
+  if constexpr (ST == ST_F32) {
+    const uint32_t bytes = static_cast<uint32_t>((k1 - base) * 4 + 15) & ~15u;
+    const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
+    const rsrc_t rv = make_rsrc(a.val + base, bytes);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      c[j] = load_i4(rc, 16 * lane + 1024 * j);
+      v[j] = load_f4(rv, 16 * lane + 1024 * j);
+    }
+  } else {
+    const uint32_t bytes = static_cast<uint32_t>((k1 - base) * 2 + 7) & ~7u;
+    const rsrc_t rc = make_rsrc(a.col16 + base, bytes);
+    const rsrc_t rv = make_rsrc(a.val16 + base, bytes);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      c[j] = load_u2(rc, 8 * lane + 512 * j);
+      v[j] = load_u2(rv, 8 * lane + 512 * j);
+    }
+  }
+}
 
 struct WaveBlock {
   int r0, r1, k0, k1;
@@ -889,17 +970,9 @@ __device__ __forceinline__ int log2_lanes(int nr) {
 // UNCOND: every row load is issued (rows past the block read zeros out of
 // bounds), so that no load of the block sits in a branch and a later wait
 // for an earlier load can count exactly how many were issued after it.
-template <int MODE, bool UNCOND = false>
-__device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m, int lane, WaveStage& S) {
-  const int a0 = m.k0 & ~3;
-  const uint32_t bytes = static_cast<uint32_t>((m.k1 - a0) * 4 + 15) & ~15u;
-  const rsrc_t rc = make_rsrc(a.col_idx + a0, bytes);
-  const rsrc_t rv = make_rsrc(a.val + a0, bytes);
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    S.c[j] = load_i4(rc, 16 * lane + 1024 * j);
-    S.v[j] = load_f4(rv, 16 * lane + 1024 * j);
-  }
+template <int MODE, bool UNCOND = false, int ST = ST_F32>
+__device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m, int lane, WaveStage<ST>& S) {
+  csr_issue<ST>(a, m.k0 & ~3, m.k1, lane, S.c, S.v);
   const int nr = m.r1 - m.r0;
   const int e = log2_lanes(nr);
   const int passes = ((nr << e) + 63) >> 6;
@@ -953,9 +1026,9 @@ __device__ __forceinline__ void row_finish(const FwdArgs& a, int row, uint32_t s
 }
 
 // Row sums of one block with L lanes per row.
-template <int L, int NT, int MODE>
+template <int L, int NT, int MODE, typename WS>
 __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, int lane, const WaveBlock& m,
-                                          const WaveStage& S, const PenaltyDev* tab, double (&pacc)[NT],
+                                          const WS& S, const PenaltyDev* tab, double (&pacc)[NT],
                                           const rsrc_t (&rout)[NT], const rsrc_t& dout, int ntr) {
   constexpr int kRowsPerPass = 64 / L;
   const int a0 = m.k0 & ~3;
@@ -1000,7 +1073,7 @@ struct FwdWaves {
 };
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
-template <int NT, int MODE, int WAVES>
+template <int NT, int MODE, int WAVES, int ST>
 __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   constexpr int THREADS = WAVES * 64;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1053,11 +1126,11 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   StageRegs<NT> SR;
   int32_t sw = 0;
   if (solve) {
-    trial_load<NT, THREADS>(a, tid, TR);
+    trial_load<NT, THREADS, ST>(a, tid, TR);
     TR.tab = load_f64(make_rsrc(a.pen.table, 32u * static_cast<uint32_t>(a.nstruct)), 8u * tid);
     sw = reinterpret_cast<const int32_t*>(a.st_in)[lane < kStateWords ? lane : 0];
   } else {
-    stage_start<NT, THREADS>(a, a.x, want_sid, SR);
+    stage_start<NT, THREADS, ST>(a, a.x, want_sid, SR);
   }
   WaveBlock cur{0, 0, 0, 0};
   if (first) {
@@ -1068,8 +1141,8 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   }
   // a row longer than a wave block is streamed in the loop instead
   const bool short_first = cur.k1 - cur.k0 <= kWavePartNnz;
-  WaveStage S;
-  wave_issue<MODE, true>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+  WaveStage<ST> S;
+  wave_issue<MODE, true, ST>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
 
   int ntr = 1;
   rsrc_t rout[NT];
@@ -1096,8 +1169,8 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
-  if (solve) trial_finish<NT, THREADS>(a, TR, T, lam, tab, xs, red);
-  else stage_finish<NT, THREADS>(a, a.x, want_sid, SR, tab, xs);
+  if (solve) trial_finish<NT, THREADS, ST>(a, TR, T, lam, tab, xs, red);
+  else stage_finish<NT, THREADS, ST>(a, a.x, want_sid, SR, tab, xs);
 
   double gsum[NT];
 #pragma unroll
@@ -1123,7 +1196,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
       b = c0 + wv;
       if (b < c1) {
         cur = meta(b);
-        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
       }
     }
     while (b < c1) {
@@ -1144,21 +1217,17 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = 0.f;
         for (int base = blk.k0 & ~3; base < blk.k1; base += 512) {
-          const uint32_t bytes = static_cast<uint32_t>((blk.k1 - base) * 4 + 15) & ~15u;
-          const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
-          const rsrc_t rv = make_rsrc(a.val + base, bytes);
+          ColGroup<ST> cg[2];
+          ValGroup<ST> vg[2];
+          csr_issue<ST>(a, base, blk.k1, lane, cg, vg);
 #pragma unroll
           for (int j = 0; j < 2; ++j) {
-            const int4 c = load_i4(rc, 16 * lane + 1024 * j);
-            const float4 v = load_f4(rv, 16 * lane + 1024 * j);
             const int e0 = base + 4 * lane + 256 * j;
-            const int cc[4] = {c.x, c.y, c.z, c.w};
-            const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
-                const float t = vv[u] * xs[q * nbp + cc[u]];
+                const float t = val_of<ST>(vg[j], u) * xs[q * nbp + col_of(cg[j], u)];
                 acc[q] += (e0 + u >= blk.k0 && e0 + u < blk.k1) ? t : 0.0f;
               }
             }
@@ -1171,7 +1240,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
           const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
           row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pb, rout, dout, ntr);
         }
-        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
       } else {
         // products of this block into the wave's LDS region (lanes past the
         // block hold zeros and write slots that no row reads)
@@ -1182,10 +1251,10 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
           for (int q = 0; q < NT; ++q) {
             const float* xq = xs + q * nbp;
             float4 p;
-            p.x = S.v[j].x * xq[S.c[j].x];
-            p.y = S.v[j].y * xq[S.c[j].y];
-            p.z = S.v[j].z * xq[S.c[j].z];
-            p.w = S.v[j].w * xq[S.c[j].w];
+            p.x = val_of<ST>(S.v[j], 0) * xq[col_of(S.c[j], 0)];
+            p.y = val_of<ST>(S.v[j], 1) * xq[col_of(S.c[j], 1)];
+            p.z = val_of<ST>(S.v[j], 2) * xq[col_of(S.c[j], 2)];
+            p.w = val_of<ST>(S.v[j], 3) * xq[col_of(S.c[j], 3)];
             *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
           }
         }
@@ -1193,8 +1262,8 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
         // the compiler from moving the row reads above the product writes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const WaveStage R = S;   // this block's row pointers and ids (loads already waited on)
-        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE>(a, cur, lane, S);
+        const WaveStage<ST> R = S;   // this block's row pointers and ids (loads already waited on)
+        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
         switch (log2_lanes(blk.r1 - blk.r0)) {
           case 0: wave_rows<1, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
           case 1: wave_rows<2, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
@@ -1245,9 +1314,10 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 // of two register stages, so one round is always in flight.  A round inside
 // one column adds all its products; a round that meets a column boundary adds
 // each column's share under a mask and closes every column that ends in it.
+template <int ST>
 struct AdjStage {
   int4 c[2];
-  float4 v[2];
+  ValGroup<ST> v[2];
 };
 
 constexpr int kAdjStep = 8 * kThreads;   // nonzeros per round
@@ -1260,17 +1330,23 @@ __device__ __forceinline__ int logical_wg(bool xcd_map) {
   return (xcd_map && G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
 }
 
-__device__ __forceinline__ void adj_issue(rsrc_t ri, rsrc_t rv, int round, AdjStage& S) {
+// rv covers the value array from the same entry as ri: float32 values in
+// the index slots' order, or 16-bit codes in that order at half the width.
+template <int ST>
+__device__ __forceinline__ void adj_issue(rsrc_t ri, rsrc_t rv, int round, AdjStage<ST>& S) {
   const uint32_t t = 16u * threadIdx.x;
   const uint32_t base = static_cast<uint32_t>(round) * (kAdjStep * 4u);
 #pragma unroll
+  for (int j = 0; j < 2; ++j) S.c[j] = load_i4(ri, base + t + 4096u * j);
+#pragma unroll
   for (int j = 0; j < 2; ++j) {
-    S.c[j] = load_i4(ri, base + t + 4096u * j);
-    S.v[j] = load_f4(rv, base + t + 4096u * j);
+    if constexpr (ST == ST_F32) S.v[j] = load_f4(rv, base + t + 4096u * j);
+    else S.v[j] = load_u2(rv, base / 2 + t / 2 + 2048u * j);
   }
 }
 
-__device__ __forceinline__ void adj_gather(rsrc_t rr, const AdjStage& S, float (&g)[8]) {
+template <typename AS>
+__device__ __forceinline__ void adj_gather(rsrc_t rr, const AS& S, float (&g)[8]) {
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     g[4 * j + 0] = load_f32(rr, 4u * S.c[j].x);
@@ -1281,28 +1357,28 @@ __device__ __forceinline__ void adj_gather(rsrc_t rr, const AdjStage& S, float (
 }
 
 // Float64 sum of this thread's eight products, in a fixed order.
-__device__ __forceinline__ double adj_dot(const AdjStage& S, const float (&g)[8]) {
+template <int ST>
+__device__ __forceinline__ double adj_dot(const AdjStage<ST>& S, const float (&g)[8]) {
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s += static_cast<double>(vv[u]) * static_cast<double>(g[4 * j + u]);
+    for (int u = 0; u < 4; ++u) s += static_cast<double>(val_of<ST>(S.v[j], u)) * static_cast<double>(g[4 * j + u]);
   }
   return s;
 }
 
 // The same over the entries with index in [lo, hi) (e0 as above).
-__device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float (&g)[8], int e0, int lo, int hi) {
+template <int ST>
+__device__ __forceinline__ double adj_dot_masked(const AdjStage<ST>& S, const float (&g)[8], int e0, int lo, int hi) {
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const float vv[4] = {S.v[j].x, S.v[j].y, S.v[j].z, S.v[j].w};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int e = e0 + 1024 * j + 64 * u;
       const float r = (e >= lo && e < hi) ? g[4 * j + u] : 0.0f;
-      s += static_cast<double>(vv[u]) * static_cast<double>(r);
+      s += static_cast<double>(val_of<ST>(S.v[j], u)) * static_cast<double>(r);
     }
   }
   return s;
@@ -1315,7 +1391,7 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage& S, const float 
 // residual gathers before the decision is known, from the residual buffer of
 // the pass's first trial (the one an accepted step of a single-trial pass
 // always lands in); if another trial is accepted they are issued again.
-template <int NT, bool SOLVE>
+template <int NT, bool SOLVE, int ST>
 __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   __shared__ double red[kWaves];
   __shared__ Decision dec;
@@ -1328,7 +1404,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   // whole tiles: entries of a partial tile sit anywhere in it
   const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
   const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
-  const rsrc_t rv = make_rsrc(a.val + kb, bytes);
+  const rsrc_t rv = (ST == ST_F32) ? make_rsrc(a.val + kb, bytes) : make_rsrc(a.val16 + kb, bytes / 2);
   // Every load of the prologue is issued at once and none sits in a branch
   // (rounds past the range read zeros out of bounds), so each wait below
   // waits for its own loads only: the decision's inputs, this workgroup's
@@ -1336,14 +1412,18 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   DecideLoads<NT> DL;
   if (SOLVE) decide_start<NT>(a, DL);
   const int4 wi = load_i4(make_rsrc(a.wg_cols, 16u * static_cast<uint32_t>(a.grid)), 16u * static_cast<uint32_t>(lw));
-  AdjStage A, B;
+  AdjStage<ST> A, B;
   adj_issue(ri, rv, 0, A);
   adj_issue(ri, rv, 1, B);
   const int c0 = uniform(wi.x), c1 = uniform(wi.y);
   int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
+  // 16-bit storage: the column's scale, loaded with its bounds
+  float csc = 1.0f;
+  if constexpr (ST != ST_F32) csc = a.col_scale[c < c1 ? c : 0];
   auto bounds = [&]() {
     lo = max(uniform(a.col_ptr[c]), k0w);
     hi = min(uniform(a.col_ptr[c + 1]), k1w);
+    if constexpr (ST != ST_F32) csc = a.col_scale[c];
   };
   // a solve gathers the residual of the first trial: the accepted one
   // unless a later trial wins
@@ -1379,7 +1459,8 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
     if (tid == 0) {
       const int wlo = a.col_wlo[c], whi = a.col_whi[c];
       if (wlo == whi) {
-        a.out[c] = static_cast<float>(a.scale * t);
+        const double f = (ST == ST_F32) ? a.scale : a.scale * static_cast<double>(csc);
+        a.out[c] = static_cast<float>(f * t);
       } else {
         if (c == c0) a.pieces[2 * lw] = t;
         if (c == c1 - 1) a.pieces[2 * lw + 1] = t;
@@ -1392,7 +1473,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
     if (c < c1) bounds();
   };
   // distribute one round's products over the columns it meets
-  auto consume = [&](const AdjStage& cur, const float (&gv)[8], int round) {
+  auto consume = [&](const AdjStage<ST>& cur, const float (&gv)[8], int round) {
     const int base = kb + round * kAdjStep, end = base + kAdjStep;
     while (c < c1 && lo < end) {
       if (lo <= base && hi >= end) {
@@ -1411,7 +1492,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   if (nrounds > 0) {
     consume(A, g, 0);
     round = 1;
-    auto step = [&](const AdjStage& cur, AdjStage& nxt) {
+    auto step = [&](const AdjStage<ST>& cur, AdjStage<ST>& nxt) {
       float gv[8];
       adj_gather(rr, cur, gv);
       if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
@@ -1440,7 +1521,8 @@ __global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const So
   double tot = a.pieces[2 * wlo + 1];
   for (int w = wlo + 1; w < whi; ++w) tot += a.pieces[2 * w];
   tot += a.pieces[2 * whi];
-  a.out[c] = static_cast<float>(a.scale * tot);
+  const double f = (a.col_scale == nullptr) ? a.scale : a.scale * static_cast<double>(a.col_scale[c]);
+  a.out[c] = static_cast<float>(f * tot);
 }
 
 // ---- small utility kernels ----------------------------------------------------------
@@ -1551,6 +1633,27 @@ int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
 // Launches take optional start/stop events, recorded by the dispatch itself
 // around the kernel (hipExtLaunchKernelGGL), so their elapsed time is the
 // kernel's own duration.
+template <int ST>
+int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipStream_t s, hipEvent_t before,
+                        hipEvent_t after) {
+  const dim3 bd16(16 * 64), bd8(8 * 64);
+  if (a.mode == FWD_SOLVE) {
+    switch (ntrials) {
+      case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a); break;
+      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
+      case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
+      default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+    }
+  } else if (ntrials != 1) {
+    return set_error(IMRT_EINVAL, "evaluation passes take one trial");
+  } else if (a.mode == FWD_EVAL) {
+    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+  } else {
+    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+  }
+  return IMRT_OK;
+}
+
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,
                    hipEvent_t before, hipEvent_t after) {
   (void)D;
@@ -1562,22 +1665,17 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   const dim3 gd(grid), bd(kThreads);
   hipStream_t s = ctx->stream;
   if (wave) {
-    const dim3 bd16(16 * 64), bd8(8 * 64);
-    if (a.mode == FWD_SOLVE) {
-      switch (ntrials) {
-        case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16>), gd, bd16, lds, s, before, after, 0, a); break;
-        case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8>), gd, bd8, lds, s, before, after, 0, a); break;
-        case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8>), gd, bd8, lds, s, before, after, 0, a); break;
-        default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
-      }
-    } else if (ntrials != 1) {
-      return set_error(IMRT_EINVAL, "evaluation passes take one trial");
-    } else if (a.mode == FWD_EVAL) {
-      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 16>), gd, bd16, lds, s, before, after, 0, a);
-    } else {
-      hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16>), gd, bd16, lds, s, before, after, 0, a);
+    int rc = IMRT_OK;
+    switch (a.storage) {
+      case ST_F32: rc = launch_wave_forward<ST_F32>(a, ntrials, gd, lds, s, before, after); break;
+      case ST_BF16: rc = launch_wave_forward<ST_BF16>(a, ntrials, gd, lds, s, before, after); break;
+      case ST_F16: rc = launch_wave_forward<ST_F16>(a, ntrials, gd, lds, s, before, after); break;
+      default: return set_error(IMRT_EINVAL, "unknown storage");
     }
+    if (rc) return rc;
   } else {
+    if (a.storage != ST_F32)
+      return set_error(IMRT_EUNSUPPORTED, "16-bit storage needs the wave-granular forward pass (fwd_wave = 1)");
     switch (ntrials) {
       case 1: hipExtLaunchKernelGGL(fwd_kernel<1>, gd, bd, lds, s, before, after, 0, a); break;
       case 2: hipExtLaunchKernelGGL(fwd_kernel<2>, gd, bd, lds, s, before, after, 0, a); break;
@@ -1588,20 +1686,34 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   return check_launch("fwd_kernel");
 }
 
+template <int ST>
+int launch_adjoint_kernel(const AdjArgs& a, int ntrials, dim3 gd, dim3 bd, hipStream_t s, hipEvent_t before,
+                          hipEvent_t after) {
+  switch (a.solve ? ntrials : 0) {
+    case 0: hipExtLaunchKernelGGL((adj_kernel<1, false, ST>), gd, bd, 0, s, before, after, 0, a); break;
+    case 1: hipExtLaunchKernelGGL((adj_kernel<1, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((adj_kernel<2, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((adj_kernel<4, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return IMRT_OK;
+}
+
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials, hipEvent_t before,
                    hipEvent_t after) {
   clear_stale_error();
   const dim3 gd(a.grid), bd(kThreads);
   hipStream_t s = ctx->stream;
   if (!a.solve && ntrials != 1) return set_error(IMRT_EINVAL, "a plain adjoint pass takes one vector");
-  switch (a.solve ? ntrials : 0) {
-    case 0: hipExtLaunchKernelGGL((adj_kernel<1, false>), gd, bd, 0, s, before, after, 0, a); break;
-    case 1: hipExtLaunchKernelGGL((adj_kernel<1, true>), gd, bd, 0, s, before, after, 0, a); break;
-    case 2: hipExtLaunchKernelGGL((adj_kernel<2, true>), gd, bd, 0, s, before, after, 0, a); break;
-    case 4: hipExtLaunchKernelGGL((adj_kernel<4, true>), gd, bd, 0, s, before, after, 0, a); break;
-    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  int rc = IMRT_OK;
+  switch (a.storage) {
+    case ST_F32: rc = launch_adjoint_kernel<ST_F32>(a, ntrials, gd, bd, s, before, after); break;
+    case ST_BF16: rc = launch_adjoint_kernel<ST_BF16>(a, ntrials, gd, bd, s, before, after); break;
+    case ST_F16: rc = launch_adjoint_kernel<ST_F16>(a, ntrials, gd, bd, s, before, after); break;
+    default: return set_error(IMRT_EINVAL, "unknown storage");
   }
-  int rc = check_launch("adj_kernel");
+  if (rc) return rc;
+  rc = check_launch("adj_kernel");
   if (rc) return rc;
   if (!a.solve) {
     // shared columns completed here (in a solve the next forward pass

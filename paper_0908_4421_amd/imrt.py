@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("IMRT_LIBRARY") or os.path.join(_HERE, "libimrt.so")
 IMRT_OK, IMRT_EINVAL, IMRT_ENOMEM, IMRT_EHIP, IMRT_ENOTREADY, IMRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 IMRT_CONVERGED, IMRT_MAX_ITER, IMRT_STALLED, IMRT_LS_FAIL, IMRT_NUMERIC = 0, 1, 2, 3, 4
 IMRT_F32, IMRT_BF16, IMRT_F16 = 0, 1, 2
+STORAGE = {"f32": IMRT_F32, "bf16": IMRT_BF16, "f16": IMRT_F16}
 STATUS_NAMES = {IMRT_CONVERGED: "converged", IMRT_MAX_ITER: "max_iter", IMRT_STALLED: "stalled",
                 IMRT_LS_FAIL: "line_search_failed", IMRT_NUMERIC: "non_finite"}
 
@@ -61,6 +62,7 @@ _i32p = C.POINTER(C.c_int32)
 _f32p = C.POINTER(C.c_float)
 _u8p = C.POINTER(C.c_uint8)
 _dp = C.POINTER(C.c_double)
+_u16p = C.POINTER(C.c_uint16)
 
 # name -> (restype, argtypes); one entry per function of include/imrt.h
 SIGNATURES = {
@@ -74,6 +76,8 @@ SIGNATURES = {
                                      C.POINTER(_vp)]),
     "imrt_dose_info": (C.c_int, [_vp, _i32p, _i32p, C.POINTER(C.c_int64)]),
     "imrt_dose_export": (C.c_int, [_vp, _i32p, _i32p, _f32p, _i32p, _i32p, _f32p, _u8p]),
+    "imrt_dose_export_codes": (C.c_int, [_vp, _u16p, _u16p, _f32p]),
+    "imrt_dose_storage": (C.c_int, [_vp, _i32p]),
     "imrt_dose_apply": (C.c_int, [_vp, _vp, _vp]),
     "imrt_dose_apply_transpose": (C.c_int, [_vp, _vp, _vp]),
     "imrt_dose_destroy": (C.c_int, [_vp]),
@@ -188,6 +192,17 @@ def imrt_dose_export(dose, row_ptr=None, col_idx=None, val=None, col_ptr=None, r
                                           _host(voxel_struct, C.c_uint8)), "imrt_dose_export")
 
 
+def imrt_dose_export_codes(dose, val_code=None, cval_code=None, col_scale=None):
+    return _check(load().imrt_dose_export_codes(dose, _host(val_code, C.c_uint16), _host(cval_code, C.c_uint16),
+                                                _host(col_scale, C.c_float)), "imrt_dose_export_codes")
+
+
+def imrt_dose_storage(dose) -> int:
+    out = C.c_int32()
+    _check(load().imrt_dose_storage(dose, C.byref(out)), "imrt_dose_storage")
+    return out.value
+
+
 def imrt_dose_apply(dose, x_dev: int, d_dev: int):
     return _check(load().imrt_dose_apply(dose, x_dev, d_dev), "imrt_dose_apply")
 
@@ -299,19 +314,30 @@ class Dose:
         self.ctx = ctx
         self.handle = handle
         self.nv, self.nb, self.nnz = imrt_dose_info(handle)
+        self.storage = imrt_dose_storage(handle)
 
     @staticmethod
-    def from_geometry(ctx: Context, spec) -> "Dose":
+    def from_geometry(ctx: Context, spec, storage: str = "f32") -> "Dose":
         g = geometry_of(spec)
-        return Dose(ctx, imrt_build_dose_matrix(ctx.handle, g))
+        return Dose(ctx, imrt_build_dose_matrix(ctx.handle, g, STORAGE[storage]))
 
     @staticmethod
-    def from_csr(ctx: Context, nv, nb, row_ptr, col_idx, val) -> "Dose":
+    def from_csr(ctx: Context, nv, nb, row_ptr, col_idx, val, storage: str = "f32") -> "Dose":
         import numpy as np
         row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
         col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
         val = np.ascontiguousarray(val, dtype=np.float32)
-        return Dose(ctx, imrt_dose_from_csr(ctx.handle, nv, nb, int(row_ptr[-1]), row_ptr, col_idx, val))
+        return Dose(ctx, imrt_dose_from_csr(ctx.handle, nv, nb, int(row_ptr[-1]), row_ptr, col_idx, val,
+                                            STORAGE[storage]))
+
+    def export_codes(self):
+        """16-bit storage: codes in CSR and CSC order and the beamlet scales."""
+        import numpy as np
+        q = np.empty(self.nnz, np.uint16)
+        cq = np.empty(self.nnz, np.uint16)
+        sc = np.empty(self.nb, np.float32)
+        imrt_dose_export_codes(self.handle, q, cq, sc)
+        return dict(val_code=q, cval_code=cq, col_scale=sc)
 
     def export(self, structures: bool = False):
         import numpy as np
