@@ -35,6 +35,112 @@ def adjoint_bytes(nv, nb, nnz):
     return 8 * nnz + 4 * (nb + 1) + 4 * nv + 4 * nb
 
 
+def forward_bytes16(nv, nb, nnz):
+    """The same with 16-bit storage: 16-bit column index and code, plus the
+    beamlet scales."""
+    return 4 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 12 * nb
+
+
+def adjoint_bytes16(nv, nb, nnz):
+    """The same with 16-bit storage: int32 row index and 16-bit code, plus the
+    beamlet scales."""
+    return 6 * nnz + 4 * (nb + 1) + 4 * nv + 8 * nb
+
+
+def timed_plans(ctx, dose, spec, st, args, warmup, steps):
+    """Build a plan on `dose`, run `warmup` untimed and `steps` timed plans
+    (lambda_0 estimate plus solve each); returns (ms per plan, results, x, plan)."""
+    import numpy as np
+    import torch
+
+    from paper_0908_4421_amd.imrt import Plan
+    from workloads import penalty_table, power_start_vector
+    pl = Plan(ctx, dose)
+    pl.set_structures(None, 4)
+    pl.set_penalties(penalty_table(spec))
+    v0 = torch.as_tensor(power_start_vector(dose.nb, spec.seed).astype(np.float32)).cuda()
+    x = torch.empty(dose.nb, dtype=torch.float32, device="cuda")
+
+    def step(profile=0):
+        lam0, _ = pl.lambda0(v0, st.power_iters)
+        x.fill_(st.x0)
+        res, _ = pl.solve(x, eps=st.eps, alpha=st.alpha, lambda0=lam0, delta=st.delta,
+                          max_iter=st.max_iter, max_backtracks=st.max_backtracks,
+                          fixed_iters=st.fixed_iters, trials_per_pass=args.trials_per_pass,
+                          profile=profile)
+        return lam0, res
+
+    for _ in range(warmup):
+        step()
+    # the timed plans carry HIP events around every profile_every-th forward
+    # and adjoint launch (recorded on the solver's stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step(args.profile_every) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, runs, x, pl
+
+
+def kernel_table(runs, res, names, nbytes):
+    """Mean HIP-event duration of each pass over the timed plans, with its
+    algorithmic bytes per launch and the rate against the HBM peak."""
+    kern = {}
+    for name in ("forward", "adjoint"):
+        ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)
+        n = res.forward_passes if name == "forward" else res.adjoint_passes
+        gbs = nbytes[name] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        kern[name] = {"kernel": names[name], "avg_ms": ms, "launches": n, "bytes_per_launch": nbytes[name],
+                      "GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
+    return kern
+
+
+def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
+    """A plan with D stored as 16-bit codes, timed like the float32 plan, and
+    its accuracy against float32 D on the same GPU: the dose of its final x
+    under D~ and under D, and G of that x under D against the float32 plan's
+    final G."""
+    import torch
+
+    from paper_0908_4421_amd.imrt import Dose
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    dose = Dose.from_geometry(ctx, spec, storage=storage)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    ms, runs, x, pl = timed_plans(ctx, dose, spec, st, args, args.warmup, args.steps)
+    lam0, res = runs[-1]
+    print(f"[bench] {spec.name} {storage}: {res.iterations} iterations, {ms:.2f} ms per plan", file=sys.stderr,
+          flush=True)
+    nt = args.trials_per_pass
+    code = {"bf16": 1, "f16": 2}[storage]
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {code}>(",
+             "adjoint": f"adj_kernel<{nt}, true, {code}>("}
+    nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    kern = kernel_table(runs, res, names, {"forward": forward_bytes16(nv, nb, nnz),
+                                           "adjoint": adjoint_bytes16(nv, nb, nnz)})
+    d16 = torch.empty(nv, dtype=torch.float32, device="cuda")
+    d32 = torch.empty(nv, dtype=torch.float32, device="cuda")
+    G16 = pl.objective(x, d16)
+    G32_at = plan32.objective(x, d32)
+    diff = (d16 - d32).abs().max().item()
+    dmax = d32.abs().max().item()
+    return {
+        "storage": storage, "ms_per_plan": ms, "iterations": res.iterations, "status": res.status,
+        "lambda0": lam0, "G_final": res.G_final, "solve_device_ms": res.device_ms, "dose_build_s": build_s,
+        "kernels": kern,
+        "vs_f32": {
+            "time_ratio": ms / ms32,
+            "dose_max_abs": diff, "dose_max_rel": diff / dmax if dmax > 0 else 0.0,
+            "G_under_f32_D_rel": abs(G32_at - res32.G_final) / res32.G_final,
+            "G_stored_vs_f32_rel": abs(G16 - res32.G_final) / res32.G_final,
+            "note": "dose of this plan's x under D~ and under float32 D (max over voxels, relative to the "
+                    "largest dose); G of that x under float32 D and this plan's own G, each against the "
+                    "float32 plan's final G",
+        },
+    }
+
+
 def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
     """The FP64 oracle on the host: lambda_0 estimate plus `sample_iters`
     iterations, scaled to the GPU's iteration count."""
@@ -151,6 +257,8 @@ def main():
     ap.add_argument("--trials-per-pass", type=int, default=1)
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="bf16,f16",
+                    help="16-bit storage forms timed beside the float32 plan (comma list, or 'none')")
     ap.add_argument("--profile-every", type=int, default=32, metavar="N",
                     help="HIP events around every N-th forward and adjoint launch of the timed plans")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -185,8 +293,8 @@ def main():
                           "GB_s_read_plus_write": 8 * n / dt / 1e9}), flush=True)
         return
 
-    from paper_0908_4421_amd.imrt import Context, Dose, Plan
-    from workloads import NAMED, PAPER_SCALE_SETTINGS, TINY_SETTINGS, penalty_table, power_start_vector
+    from paper_0908_4421_amd.imrt import Context, Dose
+    from workloads import NAMED, PAPER_SCALE_SETTINGS, TINY_SETTINGS
 
     spec = NAMED[args.workload]
     st = TINY_SETTINGS if args.workload == "tiny" else PAPER_SCALE_SETTINGS
@@ -196,31 +304,7 @@ def main():
     dose = Dose.from_geometry(ctx, spec)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
-    plan = Plan(ctx, dose)
-    plan.set_structures(None, 4)
-    plan.set_penalties(penalty_table(spec))
-    v0 = torch.as_tensor(power_start_vector(dose.nb, spec.seed).astype(np.float32)).cuda()
-    x = torch.empty(dose.nb, dtype=torch.float32, device="cuda")
-
-    def step(profile=0):
-        lam0, _ = plan.lambda0(v0, st.power_iters)
-        x.fill_(st.x0)
-        res, _ = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=lam0, delta=st.delta,
-                            max_iter=st.max_iter, max_backtracks=st.max_backtracks,
-                            fixed_iters=st.fixed_iters, trials_per_pass=args.trials_per_pass,
-                            profile=profile)
-        return lam0, res
-
-    for _ in range(args.warmup):
-        step()
-    # the timed plans carry HIP events around every profile_every-th forward
-    # and adjoint launch (recorded on the solver's stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    runs = [step(args.profile_every) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step, runs, x, plan = timed_plans(ctx, dose, spec, st, args, args.warmup, args.steps)
     lam0, res = runs[-1]
     print(f"[bench] {spec.name}: {res.iterations} iterations, {ms_per_step:.2f} ms per plan", file=sys.stderr,
           flush=True)
@@ -228,15 +312,10 @@ def main():
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}>(" if wave else f"fwd_kernel<{nt}>(",
-             "adjoint": f"adj_kernel<{nt}, true>("}
-    kern = {}
-    for name, nbytes in (("forward", forward_bytes(nv, nb, nnz)), ("adjoint", adjoint_bytes(nv, nb, nnz))):
-        ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)
-        n = res.forward_passes if name == "forward" else res.adjoint_passes
-        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kern[name] = {"kernel": names[name], "avg_ms": ms, "launches": n, "bytes_per_launch": nbytes,
-                      "GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, 0>(" if wave else f"fwd_kernel<{nt}>(",
+             "adjoint": f"adj_kernel<{nt}, true, 0>("}
+    kern = kernel_table(runs, res, names, {"forward": forward_bytes(nv, nb, nnz),
+                                           "adjoint": adjoint_bytes(nv, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom]),
@@ -273,6 +352,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if forms:
+        out["forms"] = {f: storage_form(ctx, spec, st, args, f, plan, res, ms_per_step) for f in forms}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, st, lam0, res.iterations, args.cpu_sample_iters)
     print(json.dumps(out), flush=True)
