@@ -117,7 +117,9 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
     blocks.push_back(r);
   }
   for (int32_t b : blocks) block_k0.push_back(row_ptr[b]);
-  // the same for one wave (at most kWavePartNnz nonzeros and kWaveRowsMax rows)
+  // the same for one wave (at most wave_part_nnz nonzeros, which depends on
+  // the storage, and kWaveRowsMax rows)
+  const int wave_part = wave_part_nnz(D->storage);
   std::vector<int32_t> wblocks, wblock_k0;
   wblocks.push_back(0);
   r = 0;
@@ -126,10 +128,10 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
     int64_t nz = 0;
     while (r < D->nv && r - start < kWaveRowsMax) {
       const int64_t len = row_ptr[r + 1] - row_ptr[r];
-      if (r > start && nz + len > kWavePartNnz) break;
+      if (r > start && nz + len > wave_part) break;
       nz += len;
       ++r;
-      if (nz > kWavePartNnz) break;
+      if (nz > wave_part) break;
     }
     wblocks.push_back(r);
   }
@@ -510,6 +512,7 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
   if (!D) return set_error(IMRT_ENOMEM, "host allocation failed");
   D->ctx = ctx;
   D->device = ctx->device;
+  D->storage = storage;   // the row-block partition depends on it
   try {
     rc = build_phantom(ctx, geom, D);
     if (rc == IMRT_OK) rc = store16(D, storage);
@@ -564,6 +567,7 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
   D->nv = nv;
   D->nb = nb;
   D->nnz = nnz;
+  D->storage = storage;   // the row-block partition depends on it
   try {
     // CSC by a stable counting sort over columns: rows stay ascending.
     std::vector<int32_t> rp(row_ptr, row_ptr + nv + 1), cp(nb + 1, 0);
@@ -1020,7 +1024,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   const imrt_dose* D = P->dose;
   imrt_ctx* C = P->ctx;
   hipStream_t s = C->stream;
-  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0) > C->max_lds)
+  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0, D->storage) > C->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
 
   // x_1 >= 0 and finite (initialisation of the method)

@@ -17,8 +17,12 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kFwdNnzMax = 2048;       // LDS product slots of one forward row block
 constexpr int kFwdPartNnz = kFwdNnzMax - 4;  // block limit so that 16-byte aligned loads fit
 constexpr int kFwdRowsMax = 512;       // rows of one forward row block
-constexpr int kWaveNnz = 512;          // LDS product slots of one wave's row block
+constexpr int kWaveNnz = 512;          // LDS product slots of one wave's row block (float32 storage)
 constexpr int kWavePartNnz = kWaveNnz - 4;
+// With 16-bit storage a wave's row block holds twice the nonzeros, so that
+// one block's loads are as many bytes as with float32.
+constexpr int wave_nnz(int storage) { return storage == 0 ? kWaveNnz : 2 * kWaveNnz; }
+constexpr int wave_part_nnz(int storage) { return wave_nnz(storage) - 4; }
 constexpr int kWaveRowsMax = 256;      // rows of one wave's row block
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;
@@ -263,7 +267,7 @@ int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials = 1);
 int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials = 1);
 int forward_waves(int ntrials);
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave);
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage = 0);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 
 // CSC nonzero k is stored at slot csc_slot(k): within every aligned tile of

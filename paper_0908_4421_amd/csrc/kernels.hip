@@ -907,7 +907,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 
 // ---- wave-granular forward pass --------------------------------------------------
 // Each of the four waves of a workgroup streams its own contiguous range of
-// small row blocks (at most kWavePartNnz nonzeros and kWaveRowsMax rows),
+// small row blocks (at most wave_part_nnz nonzeros and kWaveRowsMax rows),
 // an even split of the block count (a block's time is mostly latency, so
 // equal counts balance better than equal bytes).
 // Block bounds come from per-lane copies of the block table read with
@@ -921,26 +921,34 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 // products of the current one are in LDS.
 constexpr int kWaveSlack = 256;   // LDS floats after the last wave region (over-reads of masked slots)
 
+// Groups of four entries per lane in one wave's row block: 2 (512 entries)
+// with float32 storage, 4 (1024 entries) with 16-bit storage.
+template <int ST>
+constexpr int wave_groups() { return wave_nnz(ST) / 256; }
+
 template <int ST>
 struct WaveStage {
-  ColGroup<ST> c[2];
-  ValGroup<ST> v[2];
+  ColGroup<ST> c[wave_groups<ST>()];
+  ValGroup<ST> v[wave_groups<ST>()];
   int rlo[4], rhi[4];
   uint32_t sid[4];
 };
 
-// Loads of the eight entries base + 4 lane + 256 j + u (j < 2, u < 4) of the
-// CSR index and value arrays; base is a multiple of 4 and the arrays carry a
-// zeroed tail, so whole groups stay in bounds and entries past k1 read zeros.
+// Loads of the entries base + 4 lane + 256 j + u (u < 4, j < the group count)
+// of the CSR index and value arrays; base is a multiple of 4 and the arrays
+// carry a zeroed tail, so whole groups stay in bounds and entries past k1
+// read zeros.
 template <int ST>
-__device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, int lane, ColGroup<ST> (&c)[2],
-                                          ValGroup<ST> (&v)[2]) {
+__device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, int lane,
+                                          ColGroup<ST> (&c)[wave_groups<ST>()],
+                                          ValGroup<ST> (&v)[wave_groups<ST>()]) {
+  constexpr int G = wave_groups<ST>();
   if constexpr (ST == ST_F32) {
     const uint32_t bytes = static_cast<uint32_t>((k1 - base) * 4 + 15) & ~15u;
     const rsrc_t rc = make_rsrc(a.col_idx + base, bytes);
     const rsrc_t rv = make_rsrc(a.val + base, bytes);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < G; ++j) {
       c[j] = load_i4(rc, 16 * lane + 1024 * j);
       v[j] = load_f4(rv, 16 * lane + 1024 * j);
     }
@@ -949,7 +957,7 @@ __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, in
     const rsrc_t rc = make_rsrc(a.col16 + base, bytes);
     const rsrc_t rv = make_rsrc(a.val16 + base, bytes);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < G; ++j) {
       c[j] = load_u2(rc, 8 * lane + 512 * j);
       v[j] = load_u2(rv, 8 * lane + 512 * j);
     }
@@ -1026,7 +1034,7 @@ __device__ __forceinline__ void row_finish(const FwdArgs& a, int row, uint32_t s
 }
 
 // Row sums of one block with L lanes per row.
-template <int L, int NT, int MODE, typename WS>
+template <int L, int NT, int MODE, int NNZ, typename WS>
 __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, int lane, const WaveBlock& m,
                                           const WS& S, const PenaltyDev* tab, double (&pacc)[NT],
                                           const rsrc_t (&rout)[NT], const rsrc_t& dout, int ntr) {
@@ -1047,7 +1055,7 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
         const int left = s1 - k;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
-          const float* pq = prod + q * kWaveNnz + k;
+          const float* pq = prod + q * NNZ + k;
           float v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -1076,17 +1084,18 @@ constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS a
 template <int NT, int MODE, int WAVES, int ST>
 __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   constexpr int THREADS = WAVES * 64;
+  constexpr int NNZ = wave_nnz(ST), PART = wave_part_nnz(ST), NG = wave_groups<ST>();
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = a.nb;
   const int nbp = pad4(nb);
   PenaltyDev* tab = reinterpret_cast<PenaltyDev*>(smem);
   float* xs = reinterpret_cast<float*>(tab + a.nstruct);
   float* prod0 = xs + NT * nbp;
-  int32_t* mrow = reinterpret_cast<int32_t*>(prod0 + WAVES * NT * kWaveNnz + kWaveSlack);
+  int32_t* mrow = reinterpret_cast<int32_t*>(prod0 + WAVES * NT * NNZ + kWaveSlack);
   int32_t* mk0 = mrow + (kMetaChunk + 1);
   double* gpart = reinterpret_cast<double*>(mk0 + (kMetaChunk + 1) + 2);   // 8-byte aligned
   const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  float* prod = prod0 + wv * (NT * kWaveNnz);
+  float* prod = prod0 + wv * (NT * NNZ);
   __shared__ double red[WAVES];
   __shared__ int next_blk;
 
@@ -1140,7 +1149,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
     cur.k1 = __builtin_amdgcn_readlane(mk00, 1);
   }
   // a row longer than a wave block is streamed in the loop instead
-  const bool short_first = cur.k1 - cur.k0 <= kWavePartNnz;
+  const bool short_first = cur.k1 - cur.k0 <= PART;
   WaveStage<ST> S;
   wave_issue<MODE, true, ST>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
 
@@ -1196,7 +1205,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
       b = c0 + wv;
       if (b < c1) {
         cur = meta(b);
-        if (cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
+        if (cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
       }
     }
     while (b < c1) {
@@ -1211,17 +1220,17 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
       double pb[NT];
 #pragma unroll
       for (int q = 0; q < NT; ++q) pb[q] = 0.0;
-      if (blk.k1 - blk.k0 > kWavePartNnz) {
+      if (blk.k1 - blk.k0 > PART) {
         // one row longer than a wave block: the wave strides over it
         float acc[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = 0.f;
-        for (int base = blk.k0 & ~3; base < blk.k1; base += 512) {
-          ColGroup<ST> cg[2];
-          ValGroup<ST> vg[2];
+        for (int base = blk.k0 & ~3; base < blk.k1; base += NNZ) {
+          ColGroup<ST> cg[NG];
+          ValGroup<ST> vg[NG];
           csr_issue<ST>(a, base, blk.k1, lane, cg, vg);
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < NG; ++j) {
             const int e0 = base + 4 * lane + 256 * j;
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
@@ -1240,12 +1249,12 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
           const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
           row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pb, rout, dout, ntr);
         }
-        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
+        if (more && cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
       } else {
         // products of this block into the wave's LDS region (lanes past the
         // block hold zeros and write slots that no row reads)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NG; ++j) {
           const int off = 4 * lane + 256 * j;
 #pragma unroll
           for (int q = 0; q < NT; ++q) {
@@ -1255,7 +1264,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
             p.y = val_of<ST>(S.v[j], 1) * xq[col_of(S.c[j], 1)];
             p.z = val_of<ST>(S.v[j], 2) * xq[col_of(S.c[j], 2)];
             p.w = val_of<ST>(S.v[j], 3) * xq[col_of(S.c[j], 3)];
-            *reinterpret_cast<float4*>(prod + q * kWaveNnz + off) = p;
+            *reinterpret_cast<float4*>(prod + q * NNZ + off) = p;
           }
         }
         // LDS operations of one wave complete in order; the fence only keeps
@@ -1263,15 +1272,15 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const WaveStage<ST> R = S;   // this block's row pointers and ids (loads already waited on)
-        if (more && cur.k1 - cur.k0 <= kWavePartNnz) wave_issue<MODE, false, ST>(a, cur, lane, S);
+        if (more && cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
         switch (log2_lanes(blk.r1 - blk.r0)) {
-          case 0: wave_rows<1, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          case 1: wave_rows<2, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          case 2: wave_rows<4, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          case 3: wave_rows<8, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          case 4: wave_rows<16, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          case 5: wave_rows<32, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
-          default: wave_rows<64, NT, MODE>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 0: wave_rows<1, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 1: wave_rows<2, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 2: wave_rows<4, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 3: wave_rows<8, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 4: wave_rows<16, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          case 5: wave_rows<32, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
+          default: wave_rows<64, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
         }
         // the next block's LDS writes must not overtake this block's reads
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1595,13 +1604,13 @@ int grid_for(int items, int cap) {
 
 }  // namespace
 
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave) {
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage) {
   const size_t nbp = static_cast<size_t>(pad4(nb));
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
                  static_cast<size_t>(ntrials) * nbp * sizeof(float);
   if (wave) {
     const size_t waves = (ntrials == 1) ? 16 : 8;
-    bytes += (waves * ntrials * kWaveNnz + kWaveSlack) * sizeof(float);
+    bytes += (waves * ntrials * wave_nnz(storage) + kWaveSlack) * sizeof(float);
     bytes += (2 * (kMetaChunk + 1) + 2) * sizeof(int32_t) + static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
   } else {
     bytes += static_cast<size_t>(ntrials) * kFwdNnzMax * sizeof(float) +
@@ -1659,7 +1668,7 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   (void)D;
   clear_stale_error();
   const bool wave = ctx->tune.fwd_wave != 0;
-  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave);
+  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave, a.storage);
   if (lds > ctx->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
   const dim3 gd(grid), bd(kThreads);
