@@ -259,8 +259,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="bf16,f16",
                     help="16-bit storage forms timed beside the float32 plan (comma list, or 'none')")
-    ap.add_argument("--profile-every", type=int, default=32, metavar="N",
-                    help="HIP events around every N-th forward and adjoint launch of the timed plans")
+    ap.add_argument("--profile-every", type=int, default=31, metavar="N",
+                    help="HIP events around every N-th forward and adjoint launch of the timed plans (31: "
+                         "coprime with the 32-iteration batches the solver enqueues, so the samples fall at "
+                         "every position of a batch)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--summarize-pmc", metavar="DIR",
