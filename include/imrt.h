@@ -266,6 +266,25 @@ IMRT_API int imrt_estimate_lambda0(imrt_plan* plan, const float* v0_dev, int32_t
 IMRT_API int imrt_solve(imrt_plan* plan, const imrt_solve_params* params, float* x_dev,
                imrt_solve_result* result);
 
+/* Batched solve of n plans (SURVEY's batched re-plan form; the method of
+ * Section 2.2 run for several independent plans at once).  The plans must be
+ * distinct and share one context; their dose matrices must have one storage
+ * and the params one trials_per_pass; several plans may share a dose matrix.
+ * Each plan is solved exactly as imrt_solve solves it alone -- the same
+ * passes, work partitions and reduction orders, so its result is
+ * bit-identical -- but every forward and every adjoint pass of the batch is
+ * one dispatch over the workgroups of all unfinished plans, batches of
+ * iterations are replayed from a captured HIP graph, and a finished plan
+ * leaves the dispatches at the next poll.  params, x_dev and results are
+ * arrays of n; x_dev[i] (device, nb_i floats) holds x_1 on entry and the
+ * result on return.  results[i].device_ms is the stream time of the whole
+ * batch; forward_kernel_ms and adjoint_kernel_ms are 0.  Needs the
+ * "fwd_wave" option at 1 (IMRT_EUNSUPPORTED otherwise); argument errors as
+ * for imrt_solve, IMRT_EINVAL for a repeated plan, mixed contexts, storage
+ * or trials_per_pass. */
+IMRT_API int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
+                              float* const* x_dev, imrt_solve_result* results);
+
 IMRT_API int imrt_plan_destroy(imrt_plan* plan);
 
 /* Message of the last error on this thread ("" if none). */

@@ -1006,10 +1006,13 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
   return IMRT_OK;
 }
 
-int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_solve_result* res) {
+// Checks of a solve's arguments, x_1 >= 0 (host copy), the plan's buffers and
+// trace, and the initial solver state.
+int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev, int* nt_out, int* cap_out,
+                  SolverState* init_out) {
   int rc = plan_ready(P);
   if (rc) return rc;
-  if (!prm || !x_dev || !res) return set_error(IMRT_EINVAL, "params, x or result is NULL");
+  if (!prm || !x_dev) return set_error(IMRT_EINVAL, "params or x is NULL");
   if (!(prm->eps > 0.0 && prm->eps < 1.0)) return set_error(IMRT_EINVAL, "eps must lie in (0, 1)");
   if (!(prm->alpha > 1.0) || !std::isfinite(prm->alpha)) return set_error(IMRT_EINVAL, "alpha must be > 1");
   if (!(prm->lambda0 > 0.0) || !std::isfinite(prm->lambda0)) return set_error(IMRT_EINVAL, "lambda0 must be > 0");
@@ -1056,6 +1059,54 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   init.alpha = prm->alpha;
   init.lambda0 = prm->lambda0;
   init.delta = prm->delta;
+  *nt_out = nt;
+  *cap_out = cap;
+  *init_out = init;
+  return IMRT_OK;
+}
+
+// The forward and adjoint arguments of a plan's solve passes (without the
+// state pointers, which depend on the pass).
+void solve_args(imrt_plan* P, int nt, int grid, int cap, FwdArgs& fa, AdjArgs& aa) {
+  const imrt_dose* D = P->dose;
+  fa = base_fwd(D);
+  fa.mode = FWD_SOLVE;
+  fa.grid = grid;
+  set_plan_penalties(fa, P);
+  fa.g = P->gk;
+  fa.col_kind = D->col_kind;
+  fa.pieces_col = P->pieces_col;
+  fa.pieces = P->pieces;
+  fa.col_wlo = D->col_wlo;
+  fa.col_whi = D->col_whi;
+  fa.g_scale = 2.0;
+  for (int i = 0; i <= kMaxTrials; ++i) {
+    fa.xbuf[i] = P->xbuf[i];
+    fa.rbuf[i] = P->rbuf[i];
+  }
+  fa.partials = P->fwd_partials;
+  aa = base_adj(D);
+  aa.solve = 1;
+  for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
+  aa.pieces = P->pieces;
+  aa.pieces_col = P->pieces_col;
+  aa.out = P->gk;
+  aa.scale = 2.0;
+  aa.fwd_partials = P->fwd_partials;
+  aa.fwd_parts = grid;
+  aa.step_partials = P->fwd_partials + static_cast<size_t>(nt) * grid;
+  aa.step_parts = 1;
+  aa.trace = cap > 0 ? P->trace : nullptr;
+}
+
+int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_solve_result* res) {
+  if (!res) return set_error(IMRT_EINVAL, "result is NULL");
+  int nt = 1, cap = 0, rc;
+  SolverState init{};
+  if ((rc = solve_prepare(P, prm, x_dev, &nt, &cap, &init))) return rc;
+  const imrt_dose* D = P->dose;
+  imrt_ctx* C = P->ctx;
+  hipStream_t s = C->stream;
   P->st_host[0] = init;
 
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_poll[2] = {nullptr, nullptr};
@@ -1107,33 +1158,9 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
   }
 
   const int grid = std::min(forward_grid(C, D, nt), P->fwd_cap);
-  FwdArgs fa = base_fwd(D);
-  fa.mode = FWD_SOLVE;
-  set_plan_penalties(fa, P);
-  fa.g = P->gk;
-  fa.col_kind = D->col_kind;
-  fa.pieces_col = P->pieces_col;
-  fa.pieces = P->pieces;
-  fa.col_wlo = D->col_wlo;
-  fa.col_whi = D->col_whi;
-  fa.g_scale = 2.0;
-  for (int i = 0; i <= kMaxTrials; ++i) {
-    fa.xbuf[i] = P->xbuf[i];
-    fa.rbuf[i] = P->rbuf[i];
-  }
-  fa.partials = P->fwd_partials;
-  AdjArgs aa = base_adj(D);
-  aa.solve = 1;
-  for (int i = 0; i <= kMaxTrials; ++i) aa.rbuf[i] = P->rbuf[i];
-  aa.pieces = P->pieces;
-  aa.pieces_col = P->pieces_col;
-  aa.out = P->gk;
-  aa.scale = 2.0;
-  aa.fwd_partials = P->fwd_partials;
-  aa.fwd_parts = grid;
-  aa.step_partials = P->fwd_partials + static_cast<size_t>(nt) * grid;
-  aa.step_parts = 1;
-  aa.trace = cap > 0 ? P->trace : nullptr;
+  FwdArgs fa;
+  AdjArgs aa;
+  solve_args(P, nt, grid, cap, fa, aa);
 
   // The two state copies alternate: pass n reads st[n % 2] and writes st[(n + 1) % 2].
   long long pass = 0;
@@ -1299,3 +1326,269 @@ int imrt_plan_destroy(imrt_plan* plan) {
 }
 
 }  // extern "C"
+
+// ---- batched solve -----------------------------------------------------------------
+namespace {
+
+// Slot table of the plans in `active`: each plan's workgroups in order,
+// starting at a multiple of the die count (padding slots idle).
+void batch_slots(const std::vector<int>& active, const std::vector<int>& grids, std::vector<int32_t>& slots) {
+  slots.clear();
+  for (int i : active) {
+    while (slots.size() % kXcds) slots.push_back(-1);
+    for (int w = 0; w < grids[i]; ++w) slots.push_back((i << 16) | w);
+  }
+}
+
+struct BatchBuffers {
+  SolverState* st = nullptr;      // 2 per plan: [2i] read by forward passes, [2i+1] by adjoint passes
+  FwdArgs* fargs = nullptr;
+  AdjArgs* aargs = nullptr;
+  int32_t* fslots = nullptr;
+  int32_t* aslots = nullptr;
+  SolverState* poll = nullptr;    // pinned host, 2 slots of 2n states
+  hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_poll[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchBuffers() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : {ev_start, ev_end, ev_poll[0], ev_poll[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (poll) (void)hipHostFree(poll);
+    for (void* p : {static_cast<void*>(st), static_cast<void*>(fargs), static_cast<void*>(aargs),
+                    static_cast<void*>(fslots), static_cast<void*>(aslots)})
+      if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params, float* const* x_dev,
+                     imrt_solve_result* results) {
+  if (n <= 0 || n > 32767 || !plans || !params || !x_dev || !results)
+    return set_error(IMRT_EINVAL, "n must be in [1, 32767]; plans, params, x and results must not be NULL");
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return set_error(IMRT_EINVAL, "a plan is NULL");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return set_error(IMRT_EINVAL, "a plan appears twice in the batch");
+  }
+  imrt_ctx* C = plans[0]->ctx;
+  for (int i = 0; i < n; ++i) {
+    if (plans[i]->ctx != C) return set_error(IMRT_EINVAL, "all plans of a batch must share one context");
+    if (plans[i]->dose && plans[i]->dose->storage != plans[0]->dose->storage)
+      return set_error(IMRT_EINVAL, "all dose matrices of a batch must have the same storage");
+  }
+  if (C->tune.fwd_wave == 0) return set_error(IMRT_EUNSUPPORTED, "the batched solve needs fwd_wave = 1");
+  std::vector<int> nt(n), cap(n), fgrid(n), agrid(n);
+  std::vector<SolverState> init(n);
+  int rc;
+  for (int i = 0; i < n; ++i) {
+    if ((rc = solve_prepare(plans[i], &params[i], x_dev[i], &nt[i], &cap[i], &init[i]))) return rc;
+    if (nt[i] != nt[0]) return set_error(IMRT_EINVAL, "all plans of a batch must use the same trials_per_pass");
+    if (plans[i]->dose->adj_grid >= 65536) return set_error(IMRT_EUNSUPPORTED, "adjoint grid too large for a batch");
+  }
+  const int storage = plans[0]->dose->storage;
+  BatchBuffers B;
+  // The batch runs on a stream of its own (a graph cannot be captured on the
+  // null stream), ordered after the work already on the context's stream;
+  // the context's stream is restored on return, after the batch finished.
+  struct StreamSwap {
+    imrt_ctx* C = nullptr;
+    hipStream_t user = nullptr, own = nullptr;
+    hipEvent_t ready = nullptr;
+    ~StreamSwap() {
+      if (own) {
+        (void)hipStreamSynchronize(own);
+        (void)hipStreamDestroy(own);
+      }
+      if (ready) (void)hipEventDestroy(ready);
+      if (C) C->stream = user;
+    }
+  } swap;
+  swap.user = C->stream;
+  IMRT_HIP(hipStreamCreateWithFlags(&swap.own, hipStreamNonBlocking));
+  IMRT_HIP(hipEventCreateWithFlags(&swap.ready, hipEventDisableTiming));
+  IMRT_HIP(hipEventRecord(swap.ready, swap.user));
+  IMRT_HIP(hipStreamWaitEvent(swap.own, swap.ready, 0));
+  swap.C = C;
+  C->stream = swap.own;
+  hipStream_t s = C->stream;
+  std::vector<FwdArgs> fa(n);
+  std::vector<AdjArgs> aa(n);
+  size_t lds = 0;
+  for (int i = 0; i < n; ++i) {
+    imrt_plan* P = plans[i];
+    fgrid[i] = std::min(forward_grid(C, P->dose, nt[i]), P->fwd_cap);
+    agrid[i] = P->dose->adj_grid;
+    lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, storage));
+  }
+  if (dev_alloc(&B.st, 2 * static_cast<size_t>(n)) || dev_alloc(&B.fargs, n) || dev_alloc(&B.aargs, n))
+    return IMRT_ENOMEM;
+  for (int i = 0; i < n; ++i) {
+    solve_args(plans[i], nt[i], fgrid[i], cap[i], fa[i], aa[i]);
+    fa[i].st_in = B.st + 2 * i;
+    fa[i].st_out = B.st + 2 * i + 1;
+    aa[i].st_in = B.st + 2 * i + 1;
+    aa[i].st_out = B.st + 2 * i;
+  }
+  std::vector<int> active(n);
+  for (int i = 0; i < n; ++i) active[i] = i;
+  std::vector<int32_t> fs, as;
+  batch_slots(active, fgrid, fs);
+  batch_slots(active, agrid, as);
+  if (dev_alloc(&B.fslots, fs.size()) || dev_alloc(&B.aslots, as.size())) return IMRT_ENOMEM;
+  std::vector<SolverState> st_host(2 * static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) st_host[2 * i] = st_host[2 * i + 1] = init[i];
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&B.poll), sizeof(SolverState) * 4 * n, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreate(&B.ev_start);
+  if (e == hipSuccess) e = hipEventCreate(&B.ev_end);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&B.ev_poll[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&B.ev_poll[1], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(B.ev_start, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.st, st_host.data(), sizeof(SolverState) * 2 * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.fargs, fa.data(), sizeof(FwdArgs) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.aargs, aa.data(), sizeof(AdjArgs) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.fslots, fs.data(), sizeof(int32_t) * fs.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.aslots, as.data(), sizeof(int32_t) * as.size(), hipMemcpyHostToDevice, s);
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(plans[i]->xbuf[0], x_dev[i], sizeof(float) * plans[i]->dose->nb, hipMemcpyDeviceToDevice, s);
+  // the host vectors above must outlive the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(e, "batch setup");
+
+  // initial evaluation G(x_1) of every plan
+  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], storage, lds))) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
+  // Batches of (adjoint, forward) groups over the active plans, captured
+  // once per set of active plans as a graph and replayed; the host polls a
+  // copy of every plan's state one batch behind and drops finished plans
+  // from the slot tables (stream-ordered uploads, then a new capture).
+  const long long K = C->tune.batch_iters;
+  auto capture = [&]() -> int {
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+    hipError_t r = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (r != hipSuccess) return hip_error(r, "hipStreamBeginCapture");
+    int lrc = IMRT_OK;
+    for (long long k = 0; k < K && lrc == IMRT_OK; ++k) {
+      lrc = launch_adjoint_batch(C, B.aargs, B.aslots, static_cast<int>(as.size()), nt[0], storage);
+      if (lrc == IMRT_OK)
+        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], storage, lds);
+    }
+    r = hipStreamEndCapture(s, &B.graph);
+    if (lrc) return lrc;
+    if (r != hipSuccess) return hip_error(r, "hipStreamEndCapture");
+    r = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
+    if (r != hipSuccess) return hip_error(r, "hipGraphInstantiate");
+    return IMRT_OK;
+  };
+  if ((rc = capture())) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
+  long long max_groups = 4;
+  for (int i = 0; i < n; ++i)
+    max_groups = std::max(max_groups, (static_cast<long long>(params[i].max_iter) + 1) *
+                                          (params[i].max_backtracks / nt[i] + 2) + 4);
+  // slot tables whose stream-ordered uploads may still be pending
+  std::vector<std::vector<int32_t>> keep;
+  keep.reserve(4 * static_cast<size_t>(n) + 4);
+  int q[2];
+  int nq = 0, next_slot = 0;
+  long long enq = 0;
+  for (;;) {
+    const bool launch = !active.empty() && nq < 2;
+    if (launch) {
+      e = hipGraphLaunch(B.exec, s);
+      const int slot = next_slot;
+      next_slot ^= 1;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(B.poll + 2 * static_cast<size_t>(n) * slot, B.st, sizeof(SolverState) * 2 * n,
+                           hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(B.ev_poll[slot], s);
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        return hip_error(e, "batch launch");
+      }
+      enq += K;
+      q[nq++] = slot;
+    }
+    if (nq == 2 || (!launch && nq > 0)) {
+      const int slot = q[0];
+      q[0] = q[1];
+      --nq;
+      e = hipEventSynchronize(B.ev_poll[slot]);
+      if (e != hipSuccess) return hip_error(e, "batch poll wait");
+      const SolverState* seen = B.poll + 2 * static_cast<size_t>(n) * slot;
+      std::vector<int> still;
+      for (int i : active)
+        if (seen[2 * i + 1].phase != PH_DONE) still.push_back(i);
+      if (still.size() != active.size()) {
+        active.swap(still);
+        if (!active.empty()) {
+          // (each table stays in `keep` until the end: its upload is asynchronous)
+          keep.emplace_back();
+          batch_slots(active, fgrid, keep.back());
+          const std::vector<int32_t>& nf = keep.back();
+          e = hipMemcpyAsync(B.fslots, nf.data(), sizeof(int32_t) * nf.size(), hipMemcpyHostToDevice, s);
+          fs.assign(nf.begin(), nf.end());
+          keep.emplace_back();
+          batch_slots(active, agrid, keep.back());
+          const std::vector<int32_t>& na = keep.back();
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(B.aslots, na.data(), sizeof(int32_t) * na.size(), hipMemcpyHostToDevice, s);
+          as.assign(na.begin(), na.end());
+          if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);
+            return hip_error(e, "batch slot upload");
+          }
+          if ((rc = capture())) {
+            (void)hipStreamSynchronize(s);
+            return rc;
+          }
+        }
+      }
+    }
+    if (active.empty() && nq == 0) break;
+    if (enq > max_groups) {
+      (void)hipStreamSynchronize(s);
+      return set_error(IMRT_EINVAL, "internal: batched state machines did not terminate");
+    }
+  }
+  e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(st_host.data(), B.st, sizeof(SolverState) * 2 * n, hipMemcpyDeviceToHost);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const int xi = st_host[2 * i + 1].xi;
+    if (xi < 0 || xi > nt[i]) return set_error(IMRT_EINVAL, "internal: iterate buffer index out of range");
+    e = hipMemcpyAsync(x_dev[i], plans[i]->xbuf[xi], sizeof(float) * plans[i]->dose->nb, hipMemcpyDeviceToDevice, s);
+  }
+  if (e == hipSuccess) e = hipEventRecord(B.ev_end, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, B.ev_start, B.ev_end);
+  if (e != hipSuccess) return hip_error(e, "batch finish");
+  for (int i = 0; i < n; ++i) {
+    const SolverState& f = st_host[2 * i + 1];
+    imrt_solve_result& r = results[i];
+    r.iterations = f.k;
+    r.forward_passes = f.n_fwd;
+    r.adjoint_passes = f.n_adj;
+    r.status = f.status;
+    r.G_initial = f.G_init;
+    r.G_final = f.G;
+    r.device_ms = ms;
+    r.forward_kernel_ms = 0.0;
+    r.adjoint_kernel_ms = 0.0;
+    if (params[i].trace && f.k > 0) {
+      const int m = std::min(f.k, cap[i]);
+      e = hipMemcpy(params[i].trace, plans[i]->trace, sizeof(TraceDev) * m, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_error(e, "trace copy");
+    }
+  }
+  return IMRT_OK;
+}

@@ -96,6 +96,7 @@ struct FwdArgs {
   const int32_t* wblock_row; // per-wave row blocks (wave-granular forward)
   const int32_t* wblock_k0;
   int32_t nwblocks;
+  int32_t grid;              // workgroups of this pass (read by the batched pass)
   int32_t nstruct;
   Penalties pen;
   const float* x;            // eval/plain input vector
@@ -288,6 +289,12 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, int ntrials,
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
+// Batched solve passes over a slot table (device arrays of per-plan arguments
+// and of (plan << 16 | workgroup) slots, -1 for an idle slot).
+int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
+                         int storage, size_t lds);
+int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
+                         int storage);
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);

@@ -35,6 +35,15 @@
 namespace imrt {
 namespace {
 
+// A workgroup's place in its pass: index w among the pass's G workgroups.  A
+// single plan's pass has one workgroup per dispatch slot; a batched pass
+// runs several plans' passes in one dispatch, each workgroup looking up its
+// plan and its slot in that plan's pass, so every plan computes exactly what
+// it computes alone.
+struct Slot {
+  int w, G;
+};
+
 // Trial point of steps 2/4: max(0, x - lambda g), evaluated in float64 and
 // rounded once to float32.  NaN propagates (it is not clipped to zero).
 __device__ __forceinline__ float trial_point(float x, float g, double lam) {
@@ -714,7 +723,8 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
 // lead workgroup's step norms, the penalty table; ends with a barrier.
 template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<NT>& R, const TrialCtl& T,
-                                             const double (&lam)[NT], PenaltyDev* tab, float* xs, double* red) {
+                                             const double (&lam)[NT], PenaltyDev* tab, float* xs, double* red,
+                                             int G) {
   const int tid = threadIdx.x;
   double sq[NT];
 #pragma unroll
@@ -735,7 +745,7 @@ __device__ __forceinline__ void trial_finish(const FwdArgs& a, const TrialRegs<N
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const double t = block_sum<double, THREADS / 64>(sq[q], red);
-      if (tid == 0) a.partials[NT * gridDim.x + q] = t;
+      if (tid == 0) a.partials[NT * G + q] = t;
     }
   }
   __syncthreads();
@@ -819,7 +829,7 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
     TrialRegs<NT> TR;
     trial_load<NT>(a, tid, TR);
     TR.tab = (tid < 4 * a.nstruct) ? reinterpret_cast<const double*>(a.pen.table)[tid] : 0.0;
-    trial_finish<NT>(a, TR, T, lam, tab, xs, red);
+    trial_finish<NT>(a, TR, T, lam, tab, xs, red, gridDim.x);
   } else {
     stage_inputs<NT>(a, a.x, tab, xs, want_sid);
   }
@@ -1082,7 +1092,7 @@ struct FwdWaves {
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
 template <int NT, int MODE, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
+__device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   constexpr int THREADS = WAVES * 64;
   constexpr int NNZ = wave_nnz(ST), PART = wave_part_nnz(ST), NG = wave_groups<ST>();
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1108,7 +1118,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   // wave that runs faster takes more.  Every block's objective contribution
   // goes to its own LDS slot and the workgroup adds the slots in block order,
   // so the total does not depend on which wave took which block.
-  const int G = gridDim.x, w = blockIdx.x;
+  const int G = sl.G, w = sl.w;
   const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
   const int B0 = split_point(lw, a.nwblocks, G);
   const int B1 = split_point(lw + 1, a.nwblocks, G);
@@ -1164,12 +1174,12 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 #pragma unroll
   for (int q = 0; q < NT; ++q) lam[q] = 0.0;
   if (solve) {
-    if (blockIdx.x == 0 && wv == 0 && lane < kStateWords) reinterpret_cast<int32_t*>(a.st_out)[lane] = sw;
+    if (sl.w == 0 && wv == 0 && lane < kStateWords) reinterpret_cast<int32_t*>(a.st_out)[lane] = sw;
     const int phase = state_int(sw, offsetof(SolverState, phase));
     if (phase == PH_DONE) return;
     ntr = (phase == PH_INIT) ? 1 : NT;
     T.init = (phase == PH_INIT);
-    T.lead = (blockIdx.x == 0);
+    T.lead = (sl.w == 0);
     T.xi = state_int(sw, offsetof(SolverState, xi));
     lam[0] = state_f64(sw, offsetof(SolverState, lambda));
     const double alpha = state_f64(sw, offsetof(SolverState, alpha));
@@ -1178,7 +1188,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
-  if (solve) trial_finish<NT, THREADS, ST>(a, TR, T, lam, tab, xs, red);
+  if (solve) trial_finish<NT, THREADS, ST>(a, TR, T, lam, tab, xs, red, sl.G);
   else stage_finish<NT, THREADS, ST>(a, a.x, want_sid, SR, tab, xs);
 
   double gsum[NT];
@@ -1308,8 +1318,24 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
   }
   if (wv == 0 && lane == 63) {
 #pragma unroll
-    for (int q = 0; q < NT; ++q) a.partials[q * gridDim.x + blockIdx.x] = gsum[q];
+    for (int q = 0; q < NT; ++q) a.partials[q * sl.G + sl.w] = gsum[q];
   }
+}
+
+template <int NT, int MODE, int WAVES, int ST>
+__global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
+  fwd_wave_pass<NT, MODE, WAVES, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
+}
+
+// Batched solve pass: slots[blockIdx.x] = (plan << 16) | workgroup of that
+// plan's pass, or -1 for an idle slot (plans start at multiples of the die
+// count, so each plan keeps its workgroups' die placement).
+template <int NT, int WAVES, int ST>
+__global__ __launch_bounds__(WAVES * 64) void fwd_wave_batch_kernel(const FwdArgs* args, const int32_t* slots) {
+  const int sv = uniform(slots[blockIdx.x]);
+  if (sv < 0) return;
+  const FwdArgs a = args[sv >> 16];
+  fwd_wave_pass<NT, FWD_SOLVE, WAVES, ST>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
 // ---- adjoint pass ----------------------------------------------------------------
@@ -1334,8 +1360,8 @@ constexpr int kAdjStep = 8 * kThreads;   // nonzeros per round
 // Logical workgroup of this dispatch slot.  With xcd_map and a grid that is a
 // multiple of the die count, workgroup w (on die w % 8) gets logical slot
 // (w % 8) * (grid / 8) + w / 8, so each die owns one contiguous eighth.
-__device__ __forceinline__ int logical_wg(bool xcd_map) {
-  const int G = gridDim.x, w = blockIdx.x;
+__device__ __forceinline__ int logical_wg(const Slot sl, bool xcd_map) {
+  const int G = sl.G, w = sl.w;
   return (xcd_map && G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
 }
 
@@ -1401,11 +1427,11 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage<ST>& S, const fl
 // the pass's first trial (the one an accepted step of a single-trial pass
 // always lands in); if another trial is accepted they are issued again.
 template <int NT, bool SOLVE, int ST>
-__global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
+__device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   __shared__ double red[kWaves];
   __shared__ Decision dec;
   const int tid = threadIdx.x;
-  const int lw = logical_wg(a.xcd_map != 0);
+  const int lw = logical_wg(sl, a.xcd_map != 0);
   const int k0w = split_point(lw, static_cast<int>(a.nnz), a.grid);
   const int k1w = split_point(lw + 1, static_cast<int>(a.nnz), a.grid);
   const int kb = k0w & ~(kTile - 1);
@@ -1443,7 +1469,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   if (SOLVE) {
     // (a finished solve passes its state through unchanged and exits here)
     decide<NT>(a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red);
-    if (blockIdx.x == 0 && tid == 0) {
+    if (sl.w == 0 && tid == 0) {
       *a.st_out = dec.st;
       if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
         TraceDev e;
@@ -1516,6 +1542,20 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
   }
   // empty columns at the end of the range
   while (c < c1) close();
+}
+
+template <int NT, bool SOLVE, int ST>
+__global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
+  adj_pass<NT, SOLVE, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
+}
+
+// Batched solve pass (slots as for fwd_wave_batch_kernel).
+template <int NT, int ST>
+__global__ __launch_bounds__(kThreads) void adj_batch_kernel(const AdjArgs* args, const int32_t* slots) {
+  const int sv = uniform(slots[blockIdx.x]);
+  if (sv < 0) return;
+  const AdjArgs a = args[sv >> 16];
+  adj_pass<NT, true, ST>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
 // Columns shared by several adjoint workgroups (completion not folded): the
@@ -1661,6 +1701,62 @@ int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipS
     hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
   }
   return IMRT_OK;
+}
+
+// Batched solve passes: one dispatch over the slot table of several plans
+// (all with the same storage and trials per pass).
+template <int ST>
+int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslots, int ntrials, size_t lds,
+                            hipStream_t s) {
+  const dim3 gd(nslots);
+  switch (ntrials) {
+    case 1: hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots); break;
+    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return IMRT_OK;
+}
+
+int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
+                         int storage, size_t lds) {
+  if (nslots <= 0) return IMRT_OK;
+  if (lds > ctx->max_lds) return set_error(IMRT_EUNSUPPORTED, "batched forward pass: LDS budget exceeded");
+  int rc;
+  switch (storage) {
+    case ST_F32: rc = launch_forward_batch_st<ST_F32>(args, slots, nslots, ntrials, lds, ctx->stream); break;
+    case ST_BF16: rc = launch_forward_batch_st<ST_BF16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
+    case ST_F16: rc = launch_forward_batch_st<ST_F16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
+    default: return set_error(IMRT_EINVAL, "unknown storage");
+  }
+  if (rc) return rc;
+  return check_launch("fwd_wave_batch_kernel");
+}
+
+template <int ST>
+int launch_adjoint_batch_st(const AdjArgs* args, const int32_t* slots, int nslots, int ntrials, hipStream_t s) {
+  const dim3 gd(nslots), bd(kThreads);
+  switch (ntrials) {
+    case 1: hipLaunchKernelGGL((adj_batch_kernel<1, ST>), gd, bd, 0, s, args, slots); break;
+    case 2: hipLaunchKernelGGL((adj_batch_kernel<2, ST>), gd, bd, 0, s, args, slots); break;
+    case 4: hipLaunchKernelGGL((adj_batch_kernel<4, ST>), gd, bd, 0, s, args, slots); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return IMRT_OK;
+}
+
+int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
+                         int storage) {
+  if (nslots <= 0) return IMRT_OK;
+  int rc;
+  switch (storage) {
+    case ST_F32: rc = launch_adjoint_batch_st<ST_F32>(args, slots, nslots, ntrials, ctx->stream); break;
+    case ST_BF16: rc = launch_adjoint_batch_st<ST_BF16>(args, slots, nslots, ntrials, ctx->stream); break;
+    case ST_F16: rc = launch_adjoint_batch_st<ST_F16>(args, slots, nslots, ntrials, ctx->stream); break;
+    default: return set_error(IMRT_EINVAL, "unknown storage");
+  }
+  if (rc) return rc;
+  return check_launch("adj_batch_kernel");
 }
 
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,

@@ -90,6 +90,8 @@ SIGNATURES = {
     "imrt_project": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _dp]),
     "imrt_estimate_lambda0": (C.c_int, [_vp, _vp, C.c_int32, _dp, _dp]),
     "imrt_solve": (C.c_int, [_vp, C.POINTER(imrt_solve_params), _vp, C.POINTER(imrt_solve_result)]),
+    "imrt_solve_batch": (C.c_int, [C.c_int32, C.POINTER(_vp), C.POINTER(imrt_solve_params), C.POINTER(_vp),
+                                   C.POINTER(imrt_solve_result)]),
     "imrt_plan_destroy": (C.c_int, [_vp]),
     "imrt_last_error": (C.c_char_p, []),
 }
@@ -201,6 +203,12 @@ def imrt_dose_storage(dose) -> int:
     out = C.c_int32()
     _check(load().imrt_dose_storage(dose, C.byref(out)), "imrt_dose_storage")
     return out.value
+
+
+def imrt_solve_batch(n: int, plans, params, x_devs, results):
+    """plans: array of n plan handles; params: array of n imrt_solve_params;
+    x_devs: array of n device pointers; results: array of n imrt_solve_result."""
+    return _check(load().imrt_solve_batch(n, plans, params, x_devs, results), "imrt_solve_batch")
 
 
 def imrt_dose_apply(dose, x_dev: int, d_dev: int):
@@ -417,6 +425,31 @@ class Plan:
 
     def lambda0(self, v0, iters: int = 50):
         return imrt_estimate_lambda0(self.handle, v0.data_ptr(), iters)
+
+    @staticmethod
+    def solve_batch(plans, xs, *, eps, alpha, lambda0s, delta=1e-5, max_iter=20000, max_backtracks=60,
+                    fixed_iters=False, trials_per_pass=1, trace=False):
+        """imrt_solve_batch over `plans` (list of Plan) from the device tensors
+        `xs`; one lambda_0 per plan.  Returns [(result, trace or None)]."""
+        n = len(plans)
+        bufs = [(imrt_trace_entry * max(max_iter, 1))() if trace else None for _ in range(n)]
+        params = (imrt_solve_params * n)(*[
+            imrt_solve_params(eps, alpha, lam, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
+                              trials_per_pass, 0, 0, C.cast(b, C.c_void_p) if trace else None)
+            for lam, b in zip(lambda0s, bufs)])
+        handles = (_vp * n)(*[p.handle for p in plans])
+        xptr = (_vp * n)(*[x.data_ptr() for x in xs])
+        res = (imrt_solve_result * n)()
+        imrt_solve_batch(n, handles, params, xptr, res)
+        out = []
+        for i in range(n):
+            tr = None
+            if trace:
+                b = bufs[i]
+                tr = [(b[j].k, b[j].backtracks, b[j].lambda_, b[j].step_sq, b[j].G)
+                      for j in range(min(res[i].iterations, max_iter))]
+            out.append((res[i], tr))
+        return out
 
     def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
               fixed_iters=False, trials_per_pass=1, trace=False, profile=0):

@@ -1,0 +1,110 @@
+"""Batched solve (imrt_solve_batch) on the GPU: every plan of a batch of
+uneven instances ends bit-identical to its solo solve (trace, final state and
+x), including plans that share one dose matrix, plans that finish at
+different iterations, 16-bit storage, and the argument checks."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, to_dev, to_host
+from workloads import (SMALL, TINY, PAPER_SCALE_SETTINGS, draw_batch_instance, penalty_table,
+                       power_start_vector, random_penalties)
+
+pytestmark = pytest.mark.gpu
+
+ST = PAPER_SCALE_SETTINGS
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0908_4421_amd.imrt import Context
+    return Context(0)
+
+
+def _plan(ctx, dose, table):
+    from paper_0908_4421_amd.imrt import Plan
+    plan = Plan(ctx, dose)
+    plan.set_structures(None, 4)
+    plan.set_penalties(table)
+    return plan
+
+
+def _lambda0(plan, dose, seed):
+    return plan.lambda0(to_dev(power_start_vector(dose.nb, seed).astype(np.float32)), ST.power_iters)[0]
+
+
+def _solo_then_batch(plans, doses, lams, **kw):
+    from paper_0908_4421_amd.imrt import Plan
+    solo = []
+    for plan, dose, lam in zip(plans, doses, lams):
+        x = to_dev(np.full(dose.nb, ST.x0, np.float32))
+        res, tr = plan.solve(x, eps=ST.eps, alpha=ST.alpha, lambda0=lam, trace=True, **kw)
+        solo.append((res, tr, to_host(x)))
+    xs = [to_dev(np.full(d.nb, ST.x0, np.float32)) for d in doses]
+    out = Plan.solve_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=lams, trace=True, **kw)
+    for (rs, ts, xs_solo), (rb, tb), xb in zip(solo, out, xs):
+        assert tb == ts
+        assert (rb.iterations, rb.status, rb.forward_passes, rb.adjoint_passes) == \
+            (rs.iterations, rs.status, rs.forward_passes, rs.adjoint_passes)
+        assert rb.G_final == rs.G_final and rb.G_initial == rs.G_initial
+        assert np.array_equal(to_host(xb), xs_solo)
+    return solo, out
+
+
+def test_uneven_instances_bit_identical_to_solo(ctx):
+    from paper_0908_4421_amd.imrt import Dose
+    specs = [TINY, SMALL] + [draw_batch_instance(s) for s in (100, 101, 102, 105)]
+    banner("batch of " + ", ".join(s.name for s in specs))
+    doses = [Dose.from_geometry(ctx, s) for s in specs]
+    plans = [_plan(ctx, d, penalty_table(s)) for d, s in zip(doses, specs)]
+    lams = [_lambda0(p, d, s.seed) for p, d, s in zip(plans, doses, specs)]
+    solo, _ = _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=3000)
+    iters = [r.iterations for r, _, _ in solo]
+    banner(f"iterations per plan {iters}")
+    assert len(set(iters)) > 1          # the plans finish at different iterations
+
+
+def test_shared_dose_matrix_and_fixed_iterations(ctx):
+    """Two plans on one dose matrix with different penalties (new thresholds
+    for a resident patient), plus a third plan; fixed iteration counts differ
+    per plan through the stopping test being off and max_iter equal."""
+    from paper_0908_4421_amd.imrt import Dose
+    d0 = Dose.from_geometry(ctx, SMALL)
+    d1 = Dose.from_geometry(ctx, TINY)
+    t0 = penalty_table(SMALL)
+    t1 = t0.copy()
+    t1[0, :2] = 66.0      # PTV threshold of a re-plan
+    t1[1:, 1] *= 1.05
+    plans = [_plan(ctx, d0, t0), _plan(ctx, d0, t1), _plan(ctx, d1, penalty_table(TINY))]
+    doses = [d0, d0, d1]
+    lams = [_lambda0(p, d, 3) for p, d in zip(plans, doses)]
+    _solo_then_batch(plans, doses, lams, max_iter=150, fixed_iters=True)
+
+
+def test_random_penalties_and_bf16_storage(ctx):
+    from paper_0908_4421_amd.imrt import Dose
+    specs = [SMALL, draw_batch_instance(103), draw_batch_instance(104)]
+    doses = [Dose.from_geometry(ctx, s, storage="bf16") for s in specs]
+    tables = [np.array([[p.T_under, p.T_over, p.w_under, p.w_over] for p in random_penalties(4, 40 + i, 50.0)])
+              for i in range(3)]
+    plans = [_plan(ctx, d, t) for d, t in zip(doses, tables)]
+    lams = [_lambda0(p, d, 7) for p, d in zip(plans, doses)]
+    _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=2000)
+
+
+def test_batch_argument_checks(ctx):
+    from paper_0908_4421_amd import imrt
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    d = Dose.from_geometry(ctx, TINY)
+    d16 = Dose.from_geometry(ctx, TINY, storage="f16")
+    p = _plan(ctx, d, penalty_table(TINY))
+    p16 = _plan(ctx, d16, penalty_table(TINY))
+    x = to_dev(np.ones(d.nb, np.float32))
+    y = to_dev(np.ones(d.nb, np.float32))
+    for plans in ([p, p], [p, p16]):
+        with pytest.raises(imrt.ImrtError) as e:
+            Plan.solve_batch(plans, [x, y], eps=1e-4, alpha=2.0, lambda0s=[2.0 ** -7] * 2, max_iter=5)
+        assert e.value.code == imrt.IMRT_EINVAL
+    with pytest.raises(imrt.ImrtError) as e:
+        Plan.solve_batch([p], [to_dev(-np.ones(d.nb, np.float32))], eps=1e-4, alpha=2.0, lambda0s=[2.0 ** -7],
+                         max_iter=5)
+    assert e.value.code == imrt.IMRT_EINVAL
