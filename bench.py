@@ -141,6 +141,113 @@ def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
     }
 
 
+def batch_form(ctx, args):
+    """The batched re-plan workload: `args.batch` uneven instances (seeds
+    100, 101, ...), each planned alone in turn and then all together with
+    imrt_solve_batch; aggregate rates of the batched solve."""
+    import numpy as np
+    import torch
+
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    from workloads import PAPER_SCALE_SETTINGS as st
+    from workloads import batch_instances, penalty_table, power_start_vector
+    specs = batch_instances(100, args.batch)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    doses = [Dose.from_geometry(ctx, sp) for sp in specs]
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    plans = []
+    for d, sp in zip(doses, specs):
+        pl = Plan(ctx, d)
+        pl.set_structures(None, 4)
+        pl.set_penalties(penalty_table(sp))
+        plans.append(pl)
+    t = time.perf_counter()
+    lams = [pl.lambda0(torch.as_tensor(power_start_vector(d.nb, sp.seed).astype(np.float32)).cuda(),
+                       st.power_iters)[0] for pl, d, sp in zip(plans, doses, specs)]
+    torch.cuda.synchronize()
+    lam_s = time.perf_counter() - t
+    kw = dict(eps=st.eps, alpha=st.alpha, delta=st.delta, max_iter=st.max_iter, max_backtracks=st.max_backtracks)
+    xs = [torch.full((d.nb,), st.x0, dtype=torch.float32, device="cuda") for d in doses]
+    def solo():
+        out = []
+        for pl, x, lam in zip(plans, xs, lams):
+            x.fill_(st.x0)
+            out.append(pl.solve(x, lambda0=lam, **kw)[0])
+        return out
+
+    # one by one with the default (single-plan) partitions
+    solo()   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    solo()
+    torch.cuda.synchronize()
+    solo_default_s = time.perf_counter() - t
+    for x in xs:
+        x.fill_(st.x0)
+    # launch-shape search (leaves the chosen partition on every matrix; the
+    # one-by-one solves below use it too)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    part = Plan.autotune_batch(plans, xs, eps=st.eps, alpha=st.alpha, lambda0s=lams, delta=st.delta,
+                               tune_iters=args.tune_iters) if args.tune_iters > 0 else doses[0].partition()
+    tune_s = time.perf_counter() - t
+
+    def batched():
+        for x in xs:
+            x.fill_(st.x0)
+        return [r for r, _ in Plan.solve_batch(plans, xs, lambda0s=lams, **kw)]
+
+    solo()   # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    rs = solo()
+    torch.cuda.synchronize()
+    solo_s = time.perf_counter() - t
+    x_solo = [x.clone() for x in xs]
+    batched()   # warm-up
+    times = []
+    for _ in range(max(args.batch_steps, 1)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rb = batched()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    batch_s = sorted(times)[len(times) // 2]
+    same = all(a.iterations == b.iterations and a.G_final == b.G_final and torch.equal(xa, xb)
+               for a, b, xa, xb in zip(rs, rb, x_solo, xs))
+    nbytes = sum(r.forward_passes * forward_bytes(d.nv, d.nb, d.nnz) +
+                 r.adjoint_passes * adjoint_bytes(d.nv, d.nb, d.nnz) for r, d in zip(rb, doses))
+    iters = sum(r.iterations for r in rb)
+    print(f"[bench] batch of {len(specs)}: {iters} iterations, {batch_s * 1e3:.1f} ms batched, "
+          f"{solo_default_s * 1e3:.1f} ms one by one", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{len(specs)} uneven re-plans, seeds 100-{100 + len(specs) - 1}",
+        "instances": len(specs),
+        "nnz_total": sum(d.nnz for d in doses),
+        "nnz_range": [min(d.nnz for d in doses), max(d.nnz for d in doses)],
+        "matrix_MB_total": sum(16 * d.nnz for d in doses) / 1e6,
+        "iterations_total": iters,
+        "iterations_range": [min(r.iterations for r in rb), max(r.iterations for r in rb)],
+        "batch_s": batch_s,
+        "solo_sequential_s": solo_default_s,
+        "solo_sequential_same_partition_s": solo_s,
+        "speedup_vs_sequential": solo_default_s / batch_s,
+        "plans_per_s": len(specs) / batch_s,
+        "iters_per_s": iters / batch_s,
+        "GB_s": nbytes / batch_s / 1e9,
+        "frac_of_peak": nbytes / batch_s / 1e9 / HBM_PEAK_GBS,
+        "bit_identical_to_solo": same,
+        "dose_build_s": build_s,
+        "lambda0_s": lam_s,
+        "partition": {"adj_min_nnz": part[0], "fwd_blocks_per_wave": part[1], "autotune_s": tune_s},
+        "note": "times exclude the dose-matrix builds, the lambda_0 estimates and the launch-shape search "
+                "(reported apart); "
+                "GB/s counts the algorithmic bytes of every pass of every plan",
+    }
+
+
 def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
     """The FP64 oracle on the host: lambda_0 estimate plus `sample_iters`
     iterations, scaled to the GPU's iteration count."""
@@ -257,6 +364,11 @@ def main():
     ap.add_argument("--trials-per-pass", type=int, default=1)
     ap.add_argument("--cpu-sample-iters", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, metavar="N",
+                    help="also time the batched re-plan workload of N uneven instances (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--tune-iters", type=int, default=40,
+                    help="iterations per candidate of the batch's launch-shape search (0: default partition)")
     ap.add_argument("--forms", default="bf16,f16",
                     help="16-bit storage forms timed beside the float32 plan (comma list, or 'none')")
     ap.add_argument("--profile-every", type=int, default=31, metavar="N",
@@ -357,6 +469,8 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if forms:
         out["forms"] = {f: storage_form(ctx, spec, st, args, f, plan, res, ms_per_step) for f in forms}
+    if args.batch > 0:
+        out["batch"] = batch_form(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, st, lam0, res.iterations, args.cpu_sample_iters)
     print(json.dumps(out), flush=True)

@@ -166,11 +166,14 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    of every beam direction touch few cache lines; 0: in
  *                    grid order.  Voxel-indexed arrays passed to or from the
  *                    API are in grid order either way.
+ *   "fwd_blocks_per_wave"  fewest forward row blocks per wave (1..1024,
+ *                    default 1) of dose matrices created afterwards
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
- * "adj_wg_per_cu", "adj_min_nnz" and "fwd_wg_per_cu" are read when a dose
- * matrix is created (its work partitions); "fwd_wg_per_cu" also at launch.
+ * "adj_wg_per_cu", "adj_min_nnz", "fwd_blocks_per_wave" and "fwd_wg_per_cu"
+ * are read when a dose matrix is created (its work partitions);
+ * "fwd_wg_per_cu" and "adj_wg_per_cu" also at launch.
  * Results are deterministic for given settings; the settings change only the
  * grouping of the float32 row sums and of the float64 partial sums of G and
  * of shared columns.
@@ -284,6 +287,28 @@ IMRT_API int imrt_solve(imrt_plan* plan, const imrt_solve_params* params, float*
  * or trials_per_pass. */
 IMRT_API int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
                               float* const* x_dev, imrt_solve_result* results);
+
+/* Work partitions of a dose matrix: the fewest nonzeros per adjoint
+ * workgroup (the CSC is split into ranges of equal nonzero counts) and the
+ * fewest row blocks per forward wave.  A plan alone fills the GPU with fine
+ * partitions (the defaults, from the context's "adj_min_nnz" and
+ * "fwd_blocks_per_wave" options); in a batch coarser ones spend less on each
+ * workgroup's start.  Results depend on the partition only through the
+ * grouping of float64 sums.  Waits for the context's stream; no solve may be
+ * running on the matrix.  adj_min_nnz >= 16, fwd_blocks_per_wave in
+ * [1, 1024], else IMRT_EINVAL. */
+IMRT_API int imrt_dose_repartition(imrt_dose* dose, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave);
+IMRT_API int imrt_dose_partition(const imrt_dose* dose, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave);
+
+/* Launch-shape search for a batch: a few candidate partitions are applied to
+ * every dose matrix of the batch in turn, and a short batched solve of
+ * tune_iters fixed iterations (from copies of x_dev; params as for
+ * imrt_solve_batch, their iteration settings overridden) is timed with
+ * stream events; the fastest partition is left applied and returned
+ * (nullable outputs).  Solving afterwards, alone or batched, uses it. */
+IMRT_API int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
+                                 const float* const* x_dev, int32_t tune_iters, int32_t* adj_min_nnz_out,
+                                 int32_t* fwd_blocks_per_wave_out);
 
 IMRT_API int imrt_plan_destroy(imrt_plan* plan);
 

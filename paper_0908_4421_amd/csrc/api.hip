@@ -140,7 +140,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   // nonzeros are halved (by rows) until the count is a multiple of the waves.
   {
     const int nwb = static_cast<int>(wblocks.size()) - 1;
-    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb)) * forward_waves(1);
+    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb, 1, D->fwd_bpw)) * forward_waves(1);
     const int64_t target = (nwb + waves - 1) / waves * waves;
     if (nwb > waves && target > nwb) {
       // max-heap of (nonzeros, block start row) over splittable blocks
@@ -178,7 +178,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   }
   for (int32_t b : wblocks) wblock_k0.push_back(row_ptr[b]);
 
-  const int G = adjoint_grid_for(D->ctx, D->nnz);
+  const int G = adjoint_grid_for(D->ctx, D->nnz, D->adj_min_nnz);
   const int64_t nnz = D->nnz;
   auto kw = [&](int64_t w) { return w * nnz / G; };
   std::vector<int32_t> wg_c0(G, 0), wg_c1(G, 0), col_wlo(D->nb), col_whi(D->nb);
@@ -219,6 +219,13 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
   D->nwblocks = static_cast<int32_t>(wblocks.size()) - 1;
   D->adj_grid = G;
+  // (a repartition replaces the previous tables)
+  for (int32_t** p : {&D->block_row, &D->block_k0, &D->wblock_row, &D->wblock_k0, &D->wg_cols, &D->col_wlo,
+                      &D->col_whi})
+    dev_free(*p);
+  dev_free(D->col_kind);
+  dev_free(D->pieces);
+  dev_free(D->partials);
   int rc;
   if ((rc = dev_alloc(&D->block_row, blocks.size())) || (rc = dev_alloc(&D->block_k0, block_k0.size())) ||
       (rc = dev_alloc(&D->wblock_row, wblocks.size())) || (rc = dev_alloc(&D->wblock_k0, wblock_k0.size())) ||
@@ -309,6 +316,33 @@ int plan_ready(const imrt_plan* P) {
   if (!P->have_struct) return set_error(IMRT_ENOTREADY, "structures not set (imrt_set_structures)");
   if (!P->have_pen) return set_error(IMRT_ENOTREADY, "penalties not set (imrt_set_penalties)");
   return IMRT_OK;
+}
+
+// A plan's partition-sized buffers follow its dose matrix's partition (which
+// imrt_dose_repartition may change after the plan was created).
+int plan_fit(imrt_plan* P) {
+  const imrt_dose* D = P->dose;
+  int rc = use_device(P->ctx);
+  if (rc) return rc;
+  const int cap = forward_grid_cap(P->ctx, D);
+  if (cap > P->fwd_cap) {
+    dev_free(P->fwd_partials);
+    P->fwd_cap = 0;
+    if ((rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (cap + 1)))) return rc;
+    P->fwd_cap = cap;
+  }
+  if (D->adj_grid > P->pieces_cap) {
+    dev_free(P->pieces);
+    P->pieces_cap = 0;
+    if ((rc = dev_alloc(&P->pieces, 2 * static_cast<size_t>(D->adj_grid)))) return rc;
+    P->pieces_cap = D->adj_grid;
+  }
+  return IMRT_OK;
+}
+
+int plan_use(imrt_plan* P) {
+  const int rc = plan_ready(P);
+  return rc ? rc : plan_fit(P);
 }
 
 Penalties plan_penalties(const imrt_plan* P) {
@@ -428,6 +462,7 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   c->tune.adj_grid_per_cu = std::min(64, env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu));
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
   c->tune.adj_min_nnz = env_int("IMRT_ADJ_MIN_NNZ", c->tune.adj_min_nnz);
+  c->tune.fwd_bpw = std::min(1024, env_int("IMRT_FWD_BLOCKS_PER_WAVE", c->tune.fwd_bpw));
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_ADJ_XCD")) c->tune.adj_xcd = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_VOXEL_TILES")) c->tune.voxel_tiles = (std::atoi(f) != 0) ? 1 : 0;
@@ -465,6 +500,7 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.fwd_wave;
   }
+  if (n == "fwd_blocks_per_wave") return &ctx->tune.fwd_bpw;
   if (n == "adj_xcd") {
     *lo = 0;
     return &ctx->tune.adj_xcd;
@@ -485,6 +521,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   const std::string nm(name);
   const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
+                     : (nm == "fwd_blocks_per_wave")                             ? 1024
                                                                                  : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
@@ -513,6 +550,8 @@ int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype 
   D->ctx = ctx;
   D->device = ctx->device;
   D->storage = storage;   // the row-block partition depends on it
+  D->adj_min_nnz = ctx->tune.adj_min_nnz;
+  D->fwd_bpw = ctx->tune.fwd_bpw;
   try {
     rc = build_phantom(ctx, geom, D);
     if (rc == IMRT_OK) rc = store16(D, storage);
@@ -568,6 +607,8 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
   D->nb = nb;
   D->nnz = nnz;
   D->storage = storage;   // the row-block partition depends on it
+  D->adj_min_nnz = ctx->tune.adj_min_nnz;
+  D->fwd_bpw = ctx->tune.fwd_bpw;
   try {
     // CSC by a stable counting sort over columns: rows stay ascending.
     std::vector<int32_t> rp(row_ptr, row_ptr + nv + 1), cp(nb + 1, 0);
@@ -817,6 +858,7 @@ int imrt_plan_create(imrt_ctx* ctx, const imrt_dose* dose, imrt_plan** out) {
   P->dose = dose;
   const int grid = forward_grid_cap(ctx, dose);
   P->fwd_cap = grid;
+  P->pieces_cap = dose->adj_grid;
   if ((rc = dev_alloc(&P->sid, dose->nv)) || (rc = dev_alloc(&P->table, kMaxStruct)) ||
       (rc = ensure_buffers(P, 2)) || (rc = dev_alloc(&P->gk, dose->nb)) || (rc = dev_alloc(&P->vtmp, dose->nv)) ||
       (rc = dev_alloc(&P->fwd_partials, static_cast<size_t>(kMaxTrials) * (grid + 1))) ||
@@ -929,7 +971,7 @@ int imrt_set_voxel_targets(imrt_plan* P, const float* T_under, const float* T_ov
 }
 
 int imrt_evaluate_objective(imrt_plan* P, const float* x_dev, double* G_out, float* dose_dev) {
-  int rc = plan_ready(P);
+  int rc = plan_use(P);
   if (rc) return rc;
   if (!x_dev || !G_out) return set_error(IMRT_EINVAL, "x or G_out is NULL");
   const imrt_dose* D = P->dose;
@@ -942,7 +984,7 @@ int imrt_evaluate_objective(imrt_plan* P, const float* x_dev, double* G_out, flo
 }
 
 int imrt_gradient(imrt_plan* P, const float* x_dev, float* g_dev, double* G_out) {
-  int rc = plan_ready(P);
+  int rc = plan_use(P);
   if (rc) return rc;
   if (!x_dev || !g_dev) return set_error(IMRT_EINVAL, "x or g is NULL");
   if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, nullptr, P->rbuf[0], 0)) ||
@@ -972,7 +1014,7 @@ int imrt_project(imrt_plan* P, const float* x_dev, const float* g_dev, double la
 
 int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, double* lambda0_out,
                           double* sigma_out) {
-  int rc = plan_ready(P);
+  int rc = plan_use(P);
   if (rc) return rc;
   if (!v0_dev || iters < 0) return set_error(IMRT_EINVAL, "v0 is NULL or iters < 0");
   if ((rc = use_device(P->ctx))) return rc;
@@ -1010,7 +1052,7 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
 // trace, and the initial solver state.
 int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev, int* nt_out, int* cap_out,
                   SolverState* init_out) {
-  int rc = plan_ready(P);
+  int rc = plan_use(P);
   if (rc) return rc;
   if (!prm || !x_dev) return set_error(IMRT_EINVAL, "params or x is NULL");
   if (!(prm->eps > 0.0 && prm->eps < 1.0)) return set_error(IMRT_EINVAL, "eps must lie in (0, 1)");
@@ -1590,5 +1632,110 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
       if (e != hipSuccess) return hip_error(e, "trace copy");
     }
   }
+  return IMRT_OK;
+}
+
+int imrt_dose_repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  if (adj_min_nnz < 16 || fwd_blocks_per_wave < 1 || fwd_blocks_per_wave > 1024)
+    return set_error(IMRT_EINVAL, "adj_min_nnz must be >= 16 and fwd_blocks_per_wave in [1, 1024]");
+  int rc = use_device(D->ctx);
+  if (rc) return rc;
+  hipStream_t s = D->ctx->stream;
+  IMRT_HIP(hipStreamSynchronize(s));
+  if (adj_min_nnz == D->adj_min_nnz && fwd_blocks_per_wave == D->fwd_bpw) return IMRT_OK;
+  try {
+    std::vector<int32_t> rp(static_cast<size_t>(D->nv) + 1), cp(static_cast<size_t>(D->nb) + 1);
+    IMRT_HIP(hipMemcpy(rp.data(), D->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+    IMRT_HIP(hipMemcpy(cp.data(), D->col_ptr, sizeof(int32_t) * cp.size(), hipMemcpyDeviceToHost));
+    D->adj_min_nnz = adj_min_nnz;
+    D->fwd_bpw = fwd_blocks_per_wave;
+    return finish_dose(D, rp, cp);
+  } catch (const std::bad_alloc&) {
+    return set_error(IMRT_ENOMEM, "host allocation failed");
+  }
+}
+
+int imrt_dose_partition(const imrt_dose* D, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  if (adj_min_nnz) *adj_min_nnz = D->adj_min_nnz;
+  if (fwd_blocks_per_wave) *fwd_blocks_per_wave = D->fwd_bpw;
+  return IMRT_OK;
+}
+
+// Launch-shape search for a batch: every candidate (fewest nonzeros per
+// adjoint workgroup, row blocks per forward wave) is applied to all the
+// batch's dose matrices, and a short batched solve (tune_iters fixed
+// iterations from the given x, on copies) is timed by stream events; the
+// fastest candidate is left applied.
+int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
+                        const float* const* x_dev, int32_t tune_iters, int32_t* adj_min_nnz_out,
+                        int32_t* fwd_blocks_per_wave_out) {
+  if (n <= 0 || !plans || !params || !x_dev || tune_iters <= 0)
+    return set_error(IMRT_EINVAL, "n and tune_iters must be positive; plans, params and x must not be NULL");
+  for (int i = 0; i < n; ++i)
+    if (!plans[i] || !plans[i]->dose) return set_error(IMRT_EINVAL, "a plan is NULL or has no dose matrix");
+  std::vector<imrt_dose*> doses;
+  for (int i = 0; i < n; ++i) {
+    imrt_dose* d = const_cast<imrt_dose*>(plans[i]->dose);
+    if (std::find(doses.begin(), doses.end(), d) == doses.end()) doses.push_back(d);
+  }
+  int rc = use_device(plans[0]->ctx);
+  if (rc) return rc;
+  // working copies of the start points and tuning parameters
+  std::vector<float*> xs(n, nullptr);
+  auto release = [&]() {
+    for (float*& p : xs) dev_free(p);
+  };
+  for (int i = 0; i < n; ++i) {
+    if ((rc = dev_alloc(&xs[i], plans[i]->dose->nb))) {
+      release();
+      return rc;
+    }
+  }
+  std::vector<imrt_solve_params> prm(params, params + n);
+  for (auto& p : prm) {
+    p.max_iter = tune_iters;
+    p.fixed_iters = 1;
+    p.trace = nullptr;
+    p.profile = 0;
+  }
+  std::vector<imrt_solve_result> res(n);
+  const int32_t adj_candidates[] = {2048, 8192, 32768};
+  const int32_t bpw_candidates[] = {1, 4};
+  double best = -1.0;
+  int32_t best_adj = doses[0]->adj_min_nnz, best_bpw = doses[0]->fwd_bpw;
+  hipStream_t s = plans[0]->ctx->stream;
+  for (int32_t a : adj_candidates)
+    for (int32_t b : bpw_candidates) {
+      for (imrt_dose* d : doses)
+        if ((rc = imrt_dose_repartition(d, a, b))) {
+          release();
+          return rc;
+        }
+      for (int i = 0; i < n; ++i) {
+        const hipError_t e = hipMemcpyAsync(xs[i], x_dev[i], sizeof(float) * plans[i]->dose->nb,
+                                            hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+          release();
+          return hip_error(e, "autotune copy");
+        }
+      }
+      if ((rc = imrt_solve_batch(n, plans, prm.data(), xs.data(), res.data()))) {
+        release();
+        return rc;
+      }
+      const double ms = res[0].device_ms;
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        best_adj = a;
+        best_bpw = b;
+      }
+    }
+  release();
+  for (imrt_dose* d : doses)
+    if ((rc = imrt_dose_repartition(d, best_adj, best_bpw))) return rc;
+  if (adj_min_nnz_out) *adj_min_nnz_out = best_adj;
+  if (fwd_blocks_per_wave_out) *fwd_blocks_per_wave_out = best_bpw;
   return IMRT_OK;
 }

@@ -164,6 +164,7 @@ struct Tuning {
   int voxel_tiles = 1;         // built phantoms: voxels in 4x4x2 tiles (1) or the grid's own order (0)
   int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
+  int fwd_bpw = 1;             // fewest row blocks per forward wave (new dose matrices)
 };
 
 }  // namespace imrt
@@ -195,6 +196,10 @@ struct imrt_dose {
   uint16_t* val16 = nullptr;
   uint16_t* cval16 = nullptr;
   float* col_scale = nullptr;
+  // work partitions: fewest nonzeros per adjoint workgroup and row blocks
+  // per forward wave (from the context's options when created; changed by
+  // imrt_dose_repartition)
+  int32_t adj_min_nnz = 1024, fwd_bpw = 1;
   // forward row blocks and adjoint chunks
   int32_t nblocks = 0;
   int32_t* block_row = nullptr;
@@ -240,6 +245,7 @@ struct imrt_plan {
   double* fwd_partials = nullptr; // kMaxTrials * (fwd_cap + 1)
   int32_t fwd_cap = 1;
   double* pieces = nullptr;       // 2 * adjoint grid
+  int32_t pieces_cap = 0;         // adjoint grid the pieces were sized for
   double* pieces_col = nullptr;   // 2 * nb
   double* misc = nullptr;         // small reduction scratch
   imrt::SolverState* st = nullptr;  // 2 states, alternately read and written by consecutive passes
@@ -265,9 +271,9 @@ int hip_error(hipError_t e, const char* what);
 // forward grid: wave-granular pass, fwd_grid_per_cu workgroups of 16 waves
 // (8 for several trials) per CU; workgroup-granular pass, 4x as many of 4 waves
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials = 1);
-int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials = 1);
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials = 1, int blocks_per_wave = 1);
 int forward_waves(int ntrials);
-int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz);
+int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz);
 size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage = 0);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 

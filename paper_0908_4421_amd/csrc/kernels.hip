@@ -1662,19 +1662,19 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
 int forward_waves(int ntrials) { return ntrials == 1 ? 16 : 8; }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials) {
-  if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials);
+  if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials, D->fwd_bpw);
   return grid_for(D->nblocks, kWaves * ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
-int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials) {
-  const int waves = forward_waves(ntrials);
-  return grid_for((nwblocks + waves - 1) / waves, ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials, int blocks_per_wave) {
+  const int64_t per = static_cast<int64_t>(forward_waves(ntrials)) * std::max(blocks_per_wave, 1);
+  return grid_for(static_cast<int>((nwblocks + per - 1) / per), ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
-int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz) {
+int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz) {
   const int64_t cap = static_cast<int64_t>(ctx->tune.adj_grid_per_cu) * ctx->num_cu;
-  // at least adj_min_nnz nonzeros per workgroup, at least one workgroup
-  const int64_t per = ctx->tune.adj_min_nnz;
+  // at least min_nnz nonzeros per workgroup, at least one workgroup
+  const int64_t per = std::max(min_nnz, 1);
   const int64_t want = (nnz + per - 1) / per;
   return static_cast<int>(std::max<int64_t>(1, std::min(cap, want)));
 }

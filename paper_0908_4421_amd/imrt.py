@@ -92,6 +92,10 @@ SIGNATURES = {
     "imrt_solve": (C.c_int, [_vp, C.POINTER(imrt_solve_params), _vp, C.POINTER(imrt_solve_result)]),
     "imrt_solve_batch": (C.c_int, [C.c_int32, C.POINTER(_vp), C.POINTER(imrt_solve_params), C.POINTER(_vp),
                                    C.POINTER(imrt_solve_result)]),
+    "imrt_dose_repartition": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "imrt_dose_partition": (C.c_int, [_vp, _i32p, _i32p]),
+    "imrt_batch_autotune": (C.c_int, [C.c_int32, C.POINTER(_vp), C.POINTER(imrt_solve_params), C.POINTER(_vp),
+                                      C.c_int32, _i32p, _i32p]),
     "imrt_plan_destroy": (C.c_int, [_vp]),
     "imrt_last_error": (C.c_char_p, []),
 }
@@ -209,6 +213,24 @@ def imrt_solve_batch(n: int, plans, params, x_devs, results):
     """plans: array of n plan handles; params: array of n imrt_solve_params;
     x_devs: array of n device pointers; results: array of n imrt_solve_result."""
     return _check(load().imrt_solve_batch(n, plans, params, x_devs, results), "imrt_solve_batch")
+
+
+def imrt_dose_repartition(dose, adj_min_nnz: int, fwd_blocks_per_wave: int):
+    return _check(load().imrt_dose_repartition(dose, int(adj_min_nnz), int(fwd_blocks_per_wave)),
+                  "imrt_dose_repartition")
+
+
+def imrt_dose_partition(dose):
+    a, b = C.c_int32(), C.c_int32()
+    _check(load().imrt_dose_partition(dose, C.byref(a), C.byref(b)), "imrt_dose_partition")
+    return a.value, b.value
+
+
+def imrt_batch_autotune(n: int, plans, params, x_devs, tune_iters: int):
+    a, b = C.c_int32(), C.c_int32()
+    _check(load().imrt_batch_autotune(n, plans, params, x_devs, int(tune_iters), C.byref(a), C.byref(b)),
+           "imrt_batch_autotune")
+    return a.value, b.value
 
 
 def imrt_dose_apply(dose, x_dev: int, d_dev: int):
@@ -338,6 +360,12 @@ class Dose:
         return Dose(ctx, imrt_dose_from_csr(ctx.handle, nv, nb, int(row_ptr[-1]), row_ptr, col_idx, val,
                                             STORAGE[storage]))
 
+    def repartition(self, adj_min_nnz: int, fwd_blocks_per_wave: int):
+        imrt_dose_repartition(self.handle, adj_min_nnz, fwd_blocks_per_wave)
+
+    def partition(self):
+        return imrt_dose_partition(self.handle)
+
     def export_codes(self):
         """16-bit storage: codes in CSR and CSC order and the beamlet scales."""
         import numpy as np
@@ -450,6 +478,18 @@ class Plan:
                       for j in range(min(res[i].iterations, max_iter))]
             out.append((res[i], tr))
         return out
+
+    @staticmethod
+    def autotune_batch(plans, xs, *, eps, alpha, lambda0s, delta=1e-5, max_backtracks=60, trials_per_pass=1,
+                       tune_iters=40):
+        """imrt_batch_autotune: returns the (adj_min_nnz, fwd_blocks_per_wave) left applied."""
+        n = len(plans)
+        params = (imrt_solve_params * n)(*[
+            imrt_solve_params(eps, alpha, lam, delta, tune_iters, max_backtracks, 1, trials_per_pass, 0, 0, None)
+            for lam in lambda0s])
+        handles = (_vp * n)(*[p.handle for p in plans])
+        xptr = (_vp * n)(*[x.data_ptr() for x in xs])
+        return imrt_batch_autotune(n, handles, params, xptr, tune_iters)
 
     def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
               fixed_iters=False, trials_per_pass=1, trace=False, profile=0):

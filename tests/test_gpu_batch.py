@@ -108,3 +108,40 @@ def test_batch_argument_checks(ctx):
         Plan.solve_batch([p], [to_dev(-np.ones(d.nb, np.float32))], eps=1e-4, alpha=2.0, lambda0s=[2.0 ** -7],
                          max_iter=5)
     assert e.value.code == imrt.IMRT_EINVAL
+
+
+def test_repartition_and_autotune(ctx):
+    """Coarser work partitions (as a batch prefers) keep every product within
+    the oracle's bounds and the batch bit-identical to solo; the autotuner
+    leaves one of its candidates applied to every dose matrix."""
+    from oracle import model
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    from gpu_util import csr_of
+    from workloads import random_csr
+    A = random_csr(20000, 300, 30.0, 21, empty_frac=0.3)
+    d = Dose.from_csr(ctx, A.nv, A.nb, A.row_ptr, A.col_idx, A.val)
+    D = csr_of(A)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 2, A.nb).astype(np.float32)
+    r = rng.standard_normal(A.nv).astype(np.float32)
+    for adj, bpw in ((1024, 1), (4096, 2), (65536, 8), (16, 1)):
+        d.repartition(adj, bpw)
+        assert d.partition() == (adj, bpw)
+        dd = to_host(d.apply(to_dev(x)))
+        yy = to_host(d.apply_transpose(to_dev(r)))
+        d_ref = model.dose(D, x.astype(np.float64))
+        y_ref = model.adjoint(D, r.astype(np.float64))
+        assert np.all(np.abs(dd - d_ref) <= 1e-5 * np.abs(d_ref) + 1e-30)
+        assert np.all(np.abs(yy - y_ref) <= 1e-6 * (abs(D).T @ np.abs(r.astype(np.float64))) + 1e-30)
+    specs = [SMALL, TINY, draw_batch_instance(106)]
+    doses = [Dose.from_geometry(ctx, s) for s in specs]
+    plans = [_plan(ctx, dz, penalty_table(s)) for dz, s in zip(doses, specs)]
+    lams = [_lambda0(p, dz, s.seed) for p, dz, s in zip(plans, doses, specs)]
+    xs = [to_dev(np.full(dz.nb, ST.x0, np.float32)) for dz in doses]
+    adj, bpw = Plan.autotune_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=lams, tune_iters=20)
+    banner(f"autotune chose adj_min_nnz {adj}, blocks per wave {bpw}")
+    assert adj in (2048, 8192, 32768) and bpw in (1, 4)
+    assert all(dz.partition() == (adj, bpw) for dz in doses)
+    # the start points were not modified by the search
+    assert all(np.all(to_host(x0) == ST.x0) for x0 in xs)
+    _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=2000)
