@@ -312,6 +312,48 @@ IMRT_API int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_
 
 IMRT_API int imrt_plan_destroy(imrt_plan* plan);
 
+/* ---- re-plan server (SURVEY's serving form) ----------------------------
+ * A worker thread keeps every dose matrix, plan and solver state resident on
+ * the device and runs the iterations of all live solves batched (as
+ * imrt_solve_batch does), admitting queued requests between polls when a
+ * slot and HBM are free and retiring finished solves at once: continuous
+ * batching.  Each result equals imrt_solve's for the same plan, lambda_0 and
+ * start point.  Memory: the budget covers resident dose matrices and live
+ * plans; a new patient's matrix is admitted only when the largest matrix
+ * built so far (initially a quarter of a GiB, at most half the budget) still
+ * fits, and unused resident matrices are evicted least recently used first.
+ * All live solves must share one storage and trials_per_pass. */
+typedef struct imrt_server imrt_server;
+
+typedef struct {
+  int64_t patient;                  /* resident dose matrix reused if present */
+  const imrt_geometry* geometry;    /* builds the matrix otherwise (copied) */
+  imrt_dtype storage;
+  const imrt_penalty* penalties;    /* structure table (copied), 1..256 entries */
+  int32_t nstruct;
+  double x0;                        /* every beamlet's start intensity, >= 0 */
+  imrt_solve_params params;         /* lambda0 <= 0: 50 power iterations from the
+                                       all-ones vector; trace and profile ignored */
+} imrt_request;
+
+typedef struct {
+  double queue_ms;                  /* arrival (submit) to admission */
+  double plan_ms;                   /* arrival to result: time to plan */
+  double lambda0;                   /* the lambda_0 the solve used */
+} imrt_serve_times;
+
+IMRT_API int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_live, imrt_server** out);
+/* Queue a request (thread-safe, returns at once with a ticket > 0). */
+IMRT_API int imrt_server_submit(imrt_server* server, const imrt_request* request, int64_t* ticket_out);
+/* Block until the ticket's solve finished; x_out (nullable host array of nb
+ * floats) receives its plan.  A failed request returns its error. */
+IMRT_API int imrt_server_wait(imrt_server* server, int64_t ticket, float* x_out, int32_t nb,
+                              imrt_solve_result* result, imrt_serve_times* times);
+IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t* peak_bytes,
+                               int64_t* resident_matrices, int64_t* served);
+/* Finishes the queued and live requests, then frees everything. */
+IMRT_API int imrt_server_destroy(imrt_server* server);
+
 /* Message of the last error on this thread ("" if none). */
 IMRT_API const char* imrt_last_error(void);
 

@@ -25,6 +25,7 @@ SOURCES = {
     "api.hip": [],
     "kernels.hip": [],
     "build.hip": ["-ffp-contract=off"],
+    "serve.hip": [],
 }
 
 

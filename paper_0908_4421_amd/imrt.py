@@ -57,6 +57,16 @@ class imrt_solve_result(C.Structure):
                 ("adjoint_kernel_ms", C.c_double)]
 
 
+class imrt_request(C.Structure):
+    _fields_ = [("patient", C.c_int64), ("geometry", C.POINTER(imrt_geometry)), ("storage", C.c_int),
+                ("penalties", C.POINTER(imrt_penalty)), ("nstruct", C.c_int32), ("x0", C.c_double),
+                ("params", imrt_solve_params)]
+
+
+class imrt_serve_times(C.Structure):
+    _fields_ = [("queue_ms", C.c_double), ("plan_ms", C.c_double), ("lambda0", C.c_double)]
+
+
 _vp = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
 _f32p = C.POINTER(C.c_float)
@@ -97,6 +107,13 @@ SIGNATURES = {
     "imrt_batch_autotune": (C.c_int, [C.c_int32, C.POINTER(_vp), C.POINTER(imrt_solve_params), C.POINTER(_vp),
                                       C.c_int32, _i32p, _i32p]),
     "imrt_plan_destroy": (C.c_int, [_vp]),
+    "imrt_server_create": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(_vp)]),
+    "imrt_server_submit": (C.c_int, [_vp, C.POINTER(imrt_request), C.POINTER(C.c_int64)]),
+    "imrt_server_wait": (C.c_int, [_vp, C.c_int64, _f32p, C.c_int32, C.POINTER(imrt_solve_result),
+                                   C.POINTER(imrt_serve_times)]),
+    "imrt_server_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]),
+    "imrt_server_destroy": (C.c_int, [_vp]),
     "imrt_last_error": (C.c_char_p, []),
 }
 
@@ -231,6 +248,35 @@ def imrt_batch_autotune(n: int, plans, params, x_devs, tune_iters: int):
     _check(load().imrt_batch_autotune(n, plans, params, x_devs, int(tune_iters), C.byref(a), C.byref(b)),
            "imrt_batch_autotune")
     return a.value, b.value
+
+
+def imrt_server_create(ctx, budget_bytes: int, max_live: int):
+    out = _vp()
+    _check(load().imrt_server_create(ctx, int(budget_bytes), int(max_live), C.byref(out)), "imrt_server_create")
+    return out
+
+
+def imrt_server_submit(server, request: "imrt_request") -> int:
+    t = C.c_int64()
+    _check(load().imrt_server_submit(server, C.byref(request), C.byref(t)), "imrt_server_submit")
+    return t.value
+
+
+def imrt_server_wait(server, ticket: int, x_out=None, nb: int = 0):
+    res, times = imrt_solve_result(), imrt_serve_times()
+    _check(load().imrt_server_wait(server, int(ticket), _host(x_out, C.c_float), int(nb), C.byref(res),
+                                   C.byref(times)), "imrt_server_wait")
+    return res, times
+
+
+def imrt_server_stats(server):
+    v = [C.c_int64() for _ in range(4)]
+    _check(load().imrt_server_stats(server, *[C.byref(x) for x in v]), "imrt_server_stats")
+    return dict(zip(("used_bytes", "peak_bytes", "resident_matrices", "served"), (x.value for x in v)))
+
+
+def imrt_server_destroy(server):
+    return _check(load().imrt_server_destroy(server), "imrt_server_destroy")
 
 
 def imrt_dose_apply(dose, x_dev: int, d_dev: int):
@@ -507,6 +553,49 @@ class Plan:
     def close(self):
         if self.handle:
             imrt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The re-plan server (imrt_server_*): submit requests from any thread,
+    wait for their plans."""
+
+    def __init__(self, ctx: "Context", budget_bytes: int, max_live: int = 64):
+        self.ctx = ctx
+        self.handle = imrt_server_create(ctx.handle, budget_bytes, max_live)
+
+    def submit(self, patient: int, spec, table, *, storage="f32", x0=1.0, eps=1e-4, alpha=2.0, lambda0=0.0,
+               delta=1e-5, max_iter=20000, max_backtracks=60, fixed_iters=False, trials_per_pass=1) -> int:
+        """spec: a PhantomSpec building the patient's matrix when it is not
+        resident (None to require a resident one); table: (nstruct, 4)."""
+        rows = [imrt_penalty(*[float(v) for v in row]) for row in table]
+        pen = (imrt_penalty * len(rows))(*rows)
+        geom = geometry_of(spec) if spec is not None else None
+        req = imrt_request(int(patient), C.pointer(geom) if geom is not None else None, STORAGE[storage], pen,
+                           len(rows), float(x0),
+                           imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks,
+                                             int(bool(fixed_iters)), trials_per_pass, 0, 0, None))
+        return imrt_server_submit(self.handle, req)
+
+    def wait(self, ticket: int, nb: int = 0):
+        """(result, times, x as a numpy array or None when nb == 0)."""
+        import numpy as np
+        x = np.empty(nb, np.float32) if nb else None
+        res, times = imrt_server_wait(self.handle, ticket, x, nb)
+        return res, times, x
+
+    def stats(self):
+        return imrt_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            imrt_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,97 @@
+"""Re-plan server (imrt_server_*) on the GPU: requests submitted together
+(new patients and re-plans of resident patients with new thresholds) each
+end exactly as the same plan solved alone; a small HBM budget serialises
+admissions and evicts unused matrices; a failed request fails alone."""
+import numpy as np
+import pytest
+
+from gpu_util import banner, to_dev, to_host
+from workloads import SMALL, TINY, draw_batch_instance, penalty_table
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0908_4421_amd.imrt import Context
+    return Context(0)
+
+
+def _replan_table(spec, rng):
+    t = penalty_table(spec).copy()
+    t[0, :2] = rng.uniform(66.0, 74.0)
+    t[1:, 1] *= rng.uniform(0.9, 1.1, len(t) - 1)
+    return t
+
+
+def _alone(ctx, dose, table, lam, max_iter=3000):
+    from paper_0908_4421_amd.imrt import Plan
+    p = Plan(ctx, dose)
+    p.set_structures(None, len(table))
+    p.set_penalties(table)
+    x = to_dev(np.ones(dose.nb, np.float32))
+    res, _ = p.solve(x, eps=1e-4, alpha=2.0, lambda0=lam, delta=1e-5, max_iter=max_iter)
+    return res, to_host(x)
+
+
+def test_mix_equals_alone(ctx):
+    from paper_0908_4421_amd.imrt import Dose, Server
+    rng = np.random.default_rng(3)
+    specs = [SMALL, TINY, draw_batch_instance(1000), draw_batch_instance(1001), draw_batch_instance(1002)]
+    doses = [Dose.from_geometry(ctx, sp) for sp in specs]
+    srv = Server(ctx, budget_bytes=8 << 30, max_live=16)
+    reqs = []   # (patient, spec or None, table)
+    for i, sp in enumerate(specs):
+        reqs.append((i, sp, penalty_table(sp)))
+    reqs.append((0, SMALL, _replan_table(SMALL, rng)))      # re-plans of resident patients
+    reqs.append((2, specs[2], _replan_table(specs[2], rng)))
+    reqs.append((1, None, _replan_table(TINY, rng)))        # resident only: no geometry needed
+    banner(f"serve mix of {len(reqs)} requests")
+    tickets = [srv.submit(p, sp, t, max_iter=3000) for p, sp, t in reqs]
+    got = []
+    for (pat, sp, t), tk in zip(reqs, tickets):
+        got.append(srv.wait(tk, doses[pat].nb))
+        banner(f"ticket {tk} done: {got[-1][0].iterations} iterations")
+    st = srv.stats()
+    srv.close()
+    assert st["served"] == len(reqs) and st["resident_matrices"] == len(specs)
+    for (pat, sp, t), (res, times, x) in zip(reqs, got):
+        ref, xr = _alone(ctx, doses[pat], t, times.lambda0)
+        assert (res.iterations, res.status) == (ref.iterations, ref.status)
+        assert res.G_final == ref.G_final and res.G_initial == ref.G_initial
+        assert np.array_equal(x, xr)
+        assert 0.0 <= times.queue_ms <= times.plan_ms
+    banner("plan ms " + ", ".join(f"{times.plan_ms:.1f}" for _, times, _ in got))
+
+
+def test_small_budget_evicts_and_serialises(ctx):
+    from paper_0908_4421_amd.imrt import Server
+    specs = [draw_batch_instance(s) for s in (1000, 1001, 1002, 1005)] + [SMALL, draw_batch_instance(1000)]
+    budget = 40 << 20
+    srv = Server(ctx, budget_bytes=budget, max_live=4)
+    patients = [10, 11, 12, 13, 14, 10]   # the last re-plans the first patient (evicted by then, or not)
+    tickets = [srv.submit(pt, sp, penalty_table(sp), max_iter=2000) for pt, sp in zip(patients, specs)]
+    out = []
+    for tk in tickets:
+        out.append(srv.wait(tk))
+        banner(f"ticket {tk} done")
+    st = srv.stats()
+    srv.close()
+    banner(f"budget {budget >> 20} MiB: peak {st['peak_bytes'] / 2**20:.1f} MiB, resident {st['resident_matrices']}")
+    assert st["served"] == len(specs)
+    assert all(r.status == 0 for r, _, _ in out)
+    assert st["peak_bytes"] <= budget
+
+
+def test_failed_request_fails_alone(ctx):
+    from paper_0908_4421_amd import imrt
+    from paper_0908_4421_amd.imrt import Server
+    srv = Server(ctx, budget_bytes=1 << 30, max_live=4)
+    bad = srv.submit(99, None, penalty_table(TINY))          # not resident, no geometry
+    good = srv.submit(1, TINY, penalty_table(TINY), max_iter=50, fixed_iters=True)
+    with pytest.raises(imrt.ImrtError) as e:
+        srv.wait(bad)
+    assert e.value.code == imrt.IMRT_EINVAL
+    res, times, _ = srv.wait(good)
+    assert res.iterations == 50
+    srv.close()
