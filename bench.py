@@ -248,6 +248,90 @@ def batch_form(ctx, args):
     }
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serve_stream(ctx, reqs, budget, paced, st, storage):
+    """Submit `reqs` to a fresh server (at their arrival times when `paced`,
+    all at once otherwise), wait for every plan; per-request times."""
+    from paper_0908_4421_amd.imrt import Server
+    srv = Server(ctx, budget_bytes=budget, max_live=64)
+    kw = dict(storage=storage, x0=st.x0, eps=st.eps, alpha=st.alpha, delta=st.delta, max_iter=st.max_iter,
+              max_backtracks=st.max_backtracks)
+    t0 = time.perf_counter()
+    tickets = []
+    for r in reqs:
+        if paced:
+            dt = t0 + r.arrival_s - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        tickets.append(srv.submit(r.patient, r.spec, r.table, **kw))
+    got = [srv.wait(tk) for tk in tickets]
+    span = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()
+    res = [g[0] for g in got]
+    times = [g[1] for g in got]
+    plan = [t.plan_ms for t in times]
+    queue = [t.queue_ms for t in times]
+    fb, ab = (forward_bytes, adjoint_bytes) if storage == "f32" else (forward_bytes16, adjoint_bytes16)
+    nbytes = sum(x.forward_passes * fb(t.nv, t.nb, t.nnz) + x.adjoint_passes * ab(t.nv, t.nb, t.nnz)
+                 for x, t in zip(res, times))
+    its = sorted(x.iterations for x in res)
+    status = {}
+    for x in res:
+        status[str(x.status)] = status.get(str(x.status), 0) + 1
+    return {
+        "requests": len(reqs),
+        "replans": sum(r.replan for r in reqs),
+        "span_s": span,
+        "plans_per_s": len(reqs) / span,
+        "time_to_plan_ms": {"p50": _pct(plan, 50), "p99": _pct(plan, 99), "max": max(plan)},
+        "queue_ms": {"p50": _pct(queue, 50), "p99": _pct(queue, 99), "max": max(queue)},
+        "time_to_plan_replans_ms": {"p50": _pct([p for p, r in zip(plan, reqs) if r.replan], 50),
+                                    "p99": _pct([p for p, r in zip(plan, reqs) if r.replan], 99)},
+        "iterations_total": sum(its),
+        "iterations": {"p50": _pct(its, 50), "p99": _pct(its, 99), "max": its[-1]},
+        "status_counts": status,
+        "GB_s": nbytes / span / 1e9,
+        "peak_resident_GB": stats["peak_bytes"] / 1e9,
+        "resident_matrices": stats["resident_matrices"],
+    }
+
+
+def serve_form(ctx, args):
+    """The served re-plan workload: Poisson streams at each rate of
+    `args.serve_rates` (requests / s) over `args.serve_seconds` seconds, 30 %
+    of them re-plans of a resident patient with new thresholds, bfloat16
+    dose matrices, admission against an HBM budget; then a burst of
+    `args.serve_burst` requests submitted at once (the server's capacity)."""
+    import torch
+
+    from workloads import PAPER_SCALE_SETTINGS as st
+    from workloads import served_requests
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(288e9, 0.8 * free))
+    out = {"storage": args.serve_storage, "budget_GB": budget / 1e9, "rates": {}}
+    for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+        n = max(int(round(rate * args.serve_seconds)), 4)
+        r = serve_stream(ctx, served_requests(rate, n, seed=int(rate * 10)), budget, True, st, args.serve_storage)
+        out["rates"][f"{rate:g}"] = r
+        print(f"[bench] serve {rate:g} req/s: {n} requests, p50 {r['time_to_plan_ms']['p50']:.1f} ms, "
+              f"p99 {r['time_to_plan_ms']['p99']:.1f} ms to plan", file=sys.stderr, flush=True)
+    if args.serve_burst > 0:
+        r = serve_stream(ctx, served_requests(1.0, args.serve_burst, seed=99), budget, False, st,
+                         args.serve_storage)
+        out["burst"] = r
+        print(f"[bench] serve burst of {args.serve_burst}: {r['plans_per_s']:.1f} plans/s", file=sys.stderr,
+              flush=True)
+    out["note"] = ("times from arrival (submission) to the plan on the host, including the dose-matrix build "
+                   "of a new patient and the lambda_0 estimate; requests i use geometry seed 1000 + i; "
+                   f"{args.serve_seconds:g} s of arrivals per rate")
+    return out
+
+
 def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
     """The FP64 oracle on the host: lambda_0 estimate plus `sample_iters`
     iterations, scaled to the GPU's iteration count."""
@@ -369,6 +453,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--tune-iters", type=int, default=40,
                     help="iterations per candidate of the batch's launch-shape search (0: default partition)")
+    ap.add_argument("--serve-rates", default="2,5,10,20",
+                    help="Poisson arrival rates (requests / s) of the served re-plan workload ('' : skip)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0, help="seconds of arrivals per rate")
+    ap.add_argument("--serve-burst", type=int, default=64, help="requests submitted at once after the streams")
+    ap.add_argument("--serve-storage", default="bf16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--forms", default="bf16,f16",
                     help="16-bit storage forms timed beside the float32 plan (comma list, or 'none')")
     ap.add_argument("--profile-every", type=int, default=31, metavar="N",
@@ -471,6 +560,8 @@ def main():
         out["forms"] = {f: storage_form(ctx, spec, st, args, f, plan, res, ms_per_step) for f in forms}
     if args.batch > 0:
         out["batch"] = batch_form(ctx, args)
+    if args.serve_rates or args.serve_burst > 0:
+        out["serve"] = serve_form(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, st, lam0, res.iterations, args.cpu_sample_iters)
     print(json.dumps(out), flush=True)

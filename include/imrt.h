@@ -168,6 +168,9 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    API are in grid order either way.
  *   "fwd_blocks_per_wave"  fewest forward row blocks per wave (1..1024,
  *                    default 1) of dose matrices created afterwards
+ *   "serve_adj_min_nnz", "serve_fwd_blocks_per_wave"  the same two for the
+ *                    matrices of servers created afterwards (defaults 32768
+ *                    and 4)
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
@@ -312,7 +315,7 @@ IMRT_API int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_
 
 IMRT_API int imrt_plan_destroy(imrt_plan* plan);
 
-/* ---- re-plan server (SURVEY's serving form) ----------------------------
+/* ---- re-plan server -------------------------------------------------------
  * A worker thread keeps every dose matrix, plan and solver state resident on
  * the device and runs the iterations of all live solves batched (as
  * imrt_solve_batch does), admitting queued requests between polls when a
@@ -322,7 +325,11 @@ IMRT_API int imrt_plan_destroy(imrt_plan* plan);
  * plans; a new patient's matrix is admitted only when the largest matrix
  * built so far (initially a quarter of a GiB, at most half the budget) still
  * fits, and unused resident matrices are evicted least recently used first.
- * All live solves must share one storage and trials_per_pass. */
+ * All live solves must share one storage and trials_per_pass.  Matrices the
+ * server builds take the context's "serve_adj_min_nnz" and
+ * "serve_fwd_blocks_per_wave" partition (read at server creation), coarser
+ * than a lone plan's since every dispatch holds several plans; a result
+ * equals imrt_solve's on a matrix with that partition. */
 typedef struct imrt_server imrt_server;
 
 typedef struct {
@@ -340,6 +347,8 @@ typedef struct {
   double queue_ms;                  /* arrival (submit) to admission */
   double plan_ms;                   /* arrival to result: time to plan */
   double lambda0;                   /* the lambda_0 the solve used */
+  int64_t nnz;                      /* the dose matrix's nonzeros, voxels, beamlets */
+  int32_t nv, nb;
 } imrt_serve_times;
 
 IMRT_API int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_live, imrt_server** out);

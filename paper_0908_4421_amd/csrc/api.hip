@@ -501,6 +501,11 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     return &ctx->tune.fwd_wave;
   }
   if (n == "fwd_blocks_per_wave") return &ctx->tune.fwd_bpw;
+  if (n == "serve_adj_min_nnz") {
+    *lo = 16;
+    return &ctx->tune.serve_adj_min_nnz;
+  }
+  if (n == "serve_fwd_blocks_per_wave") return &ctx->tune.serve_fwd_bpw;
   if (n == "adj_xcd") {
     *lo = 0;
     return &ctx->tune.adj_xcd;
@@ -521,7 +526,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   const std::string nm(name);
   const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
-                     : (nm == "fwd_blocks_per_wave")                             ? 1024
+                     : (nm == "fwd_blocks_per_wave" || nm == "serve_fwd_blocks_per_wave") ? 1024
                                                                                  : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);

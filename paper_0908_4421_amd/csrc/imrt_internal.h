@@ -165,6 +165,8 @@ struct Tuning {
   int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
   int fwd_bpw = 1;             // fewest row blocks per forward wave (new dose matrices)
+  int serve_adj_min_nnz = 32768;   // the same two for matrices a server builds, which
+  int serve_fwd_bpw = 4;           // share every dispatch with other live plans
 };
 
 }  // namespace imrt

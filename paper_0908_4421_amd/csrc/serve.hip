@@ -402,6 +402,9 @@ void worker_main(imrt_server* S) {
       out.times.queue_ms = ms_between(L.arrival, L.admitted);
       out.times.plan_ms = ms_between(L.arrival, now);
       out.times.lambda0 = L.lambda0;
+      out.times.nnz = D->nnz;
+      out.times.nv = D->nv;
+      out.times.nb = D->nb;
       const int64_t ticket = L.ticket;   // (release clears the slot's record)
       release(S, i);
       std::lock_guard<std::mutex> g(S->mu);
@@ -425,6 +428,9 @@ int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_live
   S->user = ctx;
   S->ctx = *ctx;
   S->ctx.stream = nullptr;
+  // matrices the server builds take the partition meant for shared dispatches
+  S->ctx.tune.adj_min_nnz = ctx->tune.serve_adj_min_nnz;
+  S->ctx.tune.fwd_bpw = ctx->tune.serve_fwd_bpw;
   S->budget = hbm_budget_bytes;
   S->reserve = std::min<int64_t>(hbm_budget_bytes / 2, int64_t(1) << 28);
   S->max_live = max_live;

@@ -64,7 +64,8 @@ class imrt_request(C.Structure):
 
 
 class imrt_serve_times(C.Structure):
-    _fields_ = [("queue_ms", C.c_double), ("plan_ms", C.c_double), ("lambda0", C.c_double)]
+    _fields_ = [("queue_ms", C.c_double), ("plan_ms", C.c_double), ("lambda0", C.c_double),
+                ("nnz", C.c_int64), ("nv", C.c_int32), ("nb", C.c_int32)]
 
 
 _vp = C.c_void_p

@@ -39,6 +39,9 @@ def test_mix_equals_alone(ctx):
     rng = np.random.default_rng(3)
     specs = [SMALL, TINY, draw_batch_instance(1000), draw_batch_instance(1001), draw_batch_instance(1002)]
     doses = [Dose.from_geometry(ctx, sp) for sp in specs]
+    part = (ctx.get_option("serve_adj_min_nnz"), ctx.get_option("serve_fwd_blocks_per_wave"))
+    for d in doses:             # the server's matrices carry this partition
+        d.repartition(*part)
     srv = Server(ctx, budget_bytes=8 << 30, max_live=16)
     reqs = []   # (patient, spec or None, table)
     for i, sp in enumerate(specs):
@@ -61,6 +64,7 @@ def test_mix_equals_alone(ctx):
         assert res.G_final == ref.G_final and res.G_initial == ref.G_initial
         assert np.array_equal(x, xr)
         assert 0.0 <= times.queue_ms <= times.plan_ms
+        assert (times.nv, times.nb, times.nnz) == (doses[pat].nv, doses[pat].nb, doses[pat].nnz)
     banner("plan ms " + ", ".join(f"{times.plan_ms:.1f}" for _, times, _ in got))
 
 

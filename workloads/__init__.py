@@ -164,6 +164,52 @@ def batch_instances(first_seed: int = 100, count: int = 32) -> List[PhantomSpec]
     return [draw_batch_instance(first_seed + i) for i in range(count)]
 
 
+def replan_penalty_table(spec: PhantomSpec, rng: np.random.Generator) -> np.ndarray:
+    """New thresholds for a re-plan of a resident patient: the PTV's under- and
+    overdose thresholds both drawn uniform in [66, 74) Gy, each other
+    structure's overdose threshold scaled by a factor uniform in [0.9, 1.1)."""
+    t = penalty_table(spec).copy()
+    t[0, 0] = t[0, 1] = rng.uniform(66.0, 74.0)
+    t[1:, 1] *= rng.uniform(0.9, 1.1, len(t) - 1)
+    return t
+
+
+@dataclass
+class ServedRequest:
+    """One request of the served re-plan workload."""
+    arrival_s: float           # seconds after the start of the stream
+    patient: int
+    spec: PhantomSpec          # the patient's geometry (seed 1000 + first request index)
+    table: np.ndarray          # (nstruct, 4) penalties
+    replan: bool               # True: a resident patient with new thresholds
+
+
+def served_requests(rate: float, count: int, seed: int = 0, reuse: float = 0.3) -> List[ServedRequest]:
+    """Poisson stream of ``count`` requests at ``rate`` per second.
+
+    Request i is, with probability ``reuse`` (once a patient exists), a re-plan
+    of an earlier request's patient chosen uniformly with thresholds from
+    ``replan_penalty_table``; otherwise a new patient whose geometry is
+    ``draw_batch_instance(1000 + i)`` with the standard penalties.  One
+    generator ``default_rng(seed)`` draws, per request in order: the
+    exponential gap, the reuse coin, then the patient choice and thresholds.
+    """
+    rng = np.random.default_rng(seed)
+    out: List[ServedRequest] = []
+    patients: List[Tuple[int, PhantomSpec]] = []
+    t = 0.0
+    for i in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        if patients and rng.random() < reuse:
+            pid, spec = patients[int(rng.integers(len(patients)))]
+            out.append(ServedRequest(t, pid, spec, replan_penalty_table(spec, rng), True))
+        else:
+            spec = draw_batch_instance(1000 + i)
+            patients.append((i, spec))
+            out.append(ServedRequest(t, i, spec, penalty_table(spec), False))
+    return out
+
+
 def power_start_vector(nb: int, seed: int) -> np.ndarray:
     """Seeded positive start vector (float64) for the step-size power iteration."""
     rng = np.random.default_rng(seed)
