@@ -210,6 +210,18 @@ def served_requests(rate: float, count: int, seed: int = 0, reuse: float = 0.3) 
     return out
 
 
+def day_geometry(spec: PhantomSpec, ptv_scale: float = 0.95, rectum_scale: float = 0.9,
+                 bladder_scale: float = 1.2) -> PhantomSpec:
+    """The patient's anatomy on a treatment day, for re-optimisation towards
+    the original plan's dose: the target shrinks and the bladder fills (its
+    radius grows), the rectum empties; the organs stay in contact with the
+    target, so they move with it.  Same grid, beams and beamlet model; the
+    beamlets are those covering the new target."""
+    return dataclasses.replace(spec, name=f"{spec.name}_day", r_ptv=spec.r_ptv * ptv_scale,
+                               r_rectum=spec.r_rectum * rectum_scale,
+                               r_bladder=spec.r_bladder * bladder_scale)
+
+
 def power_start_vector(nb: int, seed: int) -> np.ndarray:
     """Seeded positive start vector (float64) for the step-size power iteration."""
     rng = np.random.default_rng(seed)
