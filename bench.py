@@ -29,6 +29,20 @@ def forward_bytes(nv, nb, nnz):
     return 8 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 8 * nb
 
 
+def forward_bytes_c16(nv, nb, nnz):
+    """The same when the forward reads 16-bit column indices beside the
+    float32 values (float32 matrices with nb <= 65536, the default)."""
+    return 6 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 8 * nb
+
+
+def f32_forward(ctx, nb):
+    """(forward layout code of the kernel name, forward bytes model) of a
+    float32 matrix with nb beamlets built under the context's options."""
+    if ctx.get_option("fwd_wave") and ctx.get_option("fwd_col16") and nb <= 65536:
+        return 3, forward_bytes_c16
+    return 0, forward_bytes
+
+
 def adjoint_bytes(nv, nb, nnz):
     """Algorithmic bytes of one adjoint pass: CSC (int32 row, float32 value,
     int32 column pointer), every residual once, gradient out."""
@@ -217,7 +231,7 @@ def batch_form(ctx, args):
     batch_s = sorted(times)[len(times) // 2]
     same = all(a.iterations == b.iterations and a.G_final == b.G_final and torch.equal(xa, xb)
                for a, b, xa, xb in zip(rs, rb, x_solo, xs))
-    nbytes = sum(r.forward_passes * forward_bytes(d.nv, d.nb, d.nnz) +
+    nbytes = sum(r.forward_passes * f32_forward(ctx, d.nb)[1](d.nv, d.nb, d.nnz) +
                  r.adjoint_passes * adjoint_bytes(d.nv, d.nb, d.nnz) for r, d in zip(rb, doses))
     iters = sum(r.iterations for r in rb)
     print(f"[bench] batch of {len(specs)}: {iters} iterations, {batch_s * 1e3:.1f} ms batched, "
@@ -290,7 +304,7 @@ def replan_form(ctx, plan, x, spec, st, args):
     sid = dose.export(structures=True)["struct_id"]
     ptv = sid == PTV
     rel = np.abs(d[ptv] - T[ptv]) / np.maximum(T[ptv], 1e-30)
-    nbytes = res.forward_passes * forward_bytes(dose.nv, dose.nb, dose.nnz) + \
+    nbytes = res.forward_passes * f32_forward(ctx, dose.nb)[1](dose.nv, dose.nb, dose.nnz) + \
         res.adjoint_passes * adjoint_bytes(dose.nv, dose.nb, dose.nnz)
     print(f"[bench] re-plan on {day.name}: {res.iterations} iterations, {ms:.2f} ms", file=sys.stderr, flush=True)
     return {
@@ -337,7 +351,9 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
     times = [g[1] for g in got]
     plan = [t.plan_ms for t in times]
     queue = [t.queue_ms for t in times]
-    fb, ab = (forward_bytes, adjoint_bytes) if storage == "f32" else (forward_bytes16, adjoint_bytes16)
+    def fb(nv, nb, nnz):
+        return f32_forward(ctx, nb)[1](nv, nb, nnz) if storage == "f32" else forward_bytes16(nv, nb, nnz)
+    ab = adjoint_bytes if storage == "f32" else adjoint_bytes16
     nbytes = sum(x.forward_passes * fb(t.nv, t.nb, t.nnz) + x.adjoint_passes * ab(t.nv, t.nb, t.nnz)
                  for x, t in zip(res, times))
     its = sorted(x.iterations for x in res)
@@ -578,9 +594,10 @@ def main():
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, 0>(" if wave else f"fwd_kernel<{nt}>(",
+    lay, fwd_model = f32_forward(ctx, nb)
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {lay}>(" if wave else f"fwd_kernel<{nt}>(",
              "adjoint": f"adj_kernel<{nt}, true, 0>("}
-    kern = kernel_table(runs, res, names, {"forward": forward_bytes(nv, nb, nnz),
+    kern = kernel_table(runs, res, names, {"forward": fwd_model(nv, nb, nnz),
                                            "adjoint": adjoint_bytes(nv, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -101,6 +101,8 @@ int alloc_nonzeros(imrt_dose* D) {
 // kFwdRowsMax rows each, or one longer row alone), and the adjoint partition:
 // workgroup w of G owns nonzeros [w*nnz/G, (w+1)*nnz/G) of the CSC arrays.
 int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::vector<int32_t>& col_ptr) {
+  if (D->fwd_st < 0)   // the forward layout, fixed with the first partition
+    D->fwd_st = (D->storage == ST_F32 && D->nb <= 65536 && D->ctx->tune.fwd_col16) ? ST_F32C16 : D->storage;
   std::vector<int32_t> blocks, block_k0;
   blocks.push_back(0);
   int r = 0;
@@ -119,7 +121,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   for (int32_t b : blocks) block_k0.push_back(row_ptr[b]);
   // the same for one wave (at most wave_part_nnz nonzeros, which depends on
   // the storage, and kWaveRowsMax rows)
-  const int wave_part = wave_part_nnz(D->storage);
+  const int wave_part = wave_part_nnz(D->fwd_st);
   std::vector<int32_t> wblocks, wblock_k0;
   wblocks.push_back(0);
   r = 0;
@@ -362,7 +364,7 @@ FwdArgs base_fwd(const imrt_dose* D) {
   a.col16 = D->col16;
   a.val16 = D->val16;
   a.col_scale = D->col_scale;
-  a.storage = D->storage;
+  a.storage = D->fwd_st;
   a.block_row = D->block_row;
   a.block_k0 = D->block_k0;
   a.nblocks = D->nblocks;
@@ -466,6 +468,7 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   if (const char* f = std::getenv("IMRT_FWD_WAVE")) c->tune.fwd_wave = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_ADJ_XCD")) c->tune.adj_xcd = (std::atoi(f) != 0) ? 1 : 0;
   if (const char* f = std::getenv("IMRT_VOXEL_TILES")) c->tune.voxel_tiles = (std::atoi(f) != 0) ? 1 : 0;
+  if (const char* f = std::getenv("IMRT_FWD_COL16")) c->tune.fwd_col16 = (std::atoi(f) != 0) ? 1 : 0;
   c->stream = static_cast<hipStream_t>(hip_stream);  // NULL: the device's null stream
   *out = c;
   return IMRT_OK;
@@ -501,6 +504,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     return &ctx->tune.fwd_wave;
   }
   if (n == "fwd_blocks_per_wave") return &ctx->tune.fwd_bpw;
+  if (n == "fwd_col16") {
+    *lo = 0;
+    return &ctx->tune.fwd_col16;
+  }
   if (n == "serve_adj_min_nnz") {
     *lo = 16;
     return &ctx->tune.serve_adj_min_nnz;
@@ -524,7 +531,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles") ? 1
+  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles" || nm == "fwd_col16") ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
                      : (nm == "fwd_blocks_per_wave" || nm == "serve_fwd_blocks_per_wave") ? 1024
                                                                                  : (int64_t(1) << 30);
@@ -1074,7 +1081,7 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   const imrt_dose* D = P->dose;
   imrt_ctx* C = P->ctx;
   hipStream_t s = C->stream;
-  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0, D->storage) > C->max_lds)
+  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0, D->fwd_st) > C->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
 
   // x_1 >= 0 and finite (initialisation of the method)
@@ -1423,8 +1430,9 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   imrt_ctx* C = plans[0]->ctx;
   for (int i = 0; i < n; ++i) {
     if (plans[i]->ctx != C) return set_error(IMRT_EINVAL, "all plans of a batch must share one context");
-    if (plans[i]->dose && plans[i]->dose->storage != plans[0]->dose->storage)
-      return set_error(IMRT_EINVAL, "all dose matrices of a batch must have the same storage");
+    if (plans[i]->dose && (plans[i]->dose->storage != plans[0]->dose->storage ||
+                           plans[i]->dose->fwd_st != plans[0]->dose->fwd_st))
+      return set_error(IMRT_EINVAL, "all dose matrices of a batch must have the same storage and layout");
   }
   if (C->tune.fwd_wave == 0) return set_error(IMRT_EUNSUPPORTED, "the batched solve needs fwd_wave = 1");
   std::vector<int> nt(n), cap(n), fgrid(n), agrid(n);
@@ -1435,7 +1443,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     if (nt[i] != nt[0]) return set_error(IMRT_EINVAL, "all plans of a batch must use the same trials_per_pass");
     if (plans[i]->dose->adj_grid >= 65536) return set_error(IMRT_EUNSUPPORTED, "adjoint grid too large for a batch");
   }
-  const int storage = plans[0]->dose->storage;
+  const int storage = plans[0]->dose->storage, fst = plans[0]->dose->fwd_st;
   BatchBuffers B;
   // The batch runs on a stream of its own (a graph cannot be captured on the
   // null stream), ordered after the work already on the context's stream;
@@ -1468,7 +1476,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     imrt_plan* P = plans[i];
     fgrid[i] = std::min(forward_grid(C, P->dose, nt[i]), P->fwd_cap);
     agrid[i] = P->dose->adj_grid;
-    lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, storage));
+    lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, fst));
   }
   if (dev_alloc(&B.st, 2 * static_cast<size_t>(n)) || dev_alloc(&B.fargs, n) || dev_alloc(&B.aargs, n))
     return IMRT_ENOMEM;
@@ -1505,7 +1513,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   if (e != hipSuccess) return hip_error(e, "batch setup");
 
   // initial evaluation G(x_1) of every plan
-  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], storage, lds))) {
+  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, lds))) {
     (void)hipStreamSynchronize(s);
     return rc;
   }
@@ -1525,7 +1533,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     for (long long k = 0; k < K && lrc == IMRT_OK; ++k) {
       lrc = launch_adjoint_batch(C, B.aargs, B.aslots, static_cast<int>(as.size()), nt[0], storage);
       if (lrc == IMRT_OK)
-        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], storage, lds);
+        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, lds);
     }
     r = hipStreamEndCapture(s, &B.graph);
     if (lrc) return lrc;

@@ -263,10 +263,34 @@ __global__ __launch_bounds__(kThreads) void quantize_rows_kernel(const int32_t* 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void narrow_columns_kernel(const int32_t* col_idx, int64_t nnz,
+                                                                   uint16_t* col16) {
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; k < nnz;
+       k += static_cast<int64_t>(gridDim.x) * kThreads)
+    col16[k] = static_cast<uint16_t>(col_idx[k]);
+}
+
+// float32 storage read by the forward pass through 16-bit column indices
+// (nb <= 65536): a 16-bit copy of the CSR column indices beside the 32-bit
+// ones, which the other passes and the export keep using.
+int narrow_columns(imrt_dose* D) {
+  const size_t nz = static_cast<size_t>(D->nnz) + kPad;
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(&D->col16), 2 * nz);
+  if (e == hipErrorOutOfMemory) return set_error(IMRT_ENOMEM, "hipMalloc: out of device memory");
+  if (e != hipSuccess) return hip_error(e, "hipMalloc(16-bit column indices)");
+  hipStream_t s = D->ctx->stream;
+  IMRT_HIP(hipMemsetAsync(D->col16, 0, 2 * nz, s));
+  const int gr = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((D->nnz + kThreads - 1) / kThreads, 8192)));
+  hipLaunchKernelGGL(narrow_columns_kernel, dim3(gr), dim3(kThreads), 0, s, D->col_idx, D->nnz, D->col16);
+  IMRT_HIP(hipGetLastError());
+  IMRT_HIP(hipStreamSynchronize(s));
+  return IMRT_OK;
+}
+
 }  // namespace
 
 int store16(imrt_dose* D, int storage) {
-  if (storage == ST_F32) return IMRT_OK;
+  if (storage == ST_F32) return D->fwd_st == ST_F32C16 ? narrow_columns(D) : IMRT_OK;
   if (storage != ST_BF16 && storage != ST_F16) return set_error(IMRT_EINVAL, "unknown storage");
   if (D->nb > 65536) return set_error(IMRT_EUNSUPPORTED, "16-bit storage needs nb <= 65536 (16-bit column indices)");
   const size_t nz = static_cast<size_t>(D->nnz) + kPad, nzc = csc_alloc(D->nnz);

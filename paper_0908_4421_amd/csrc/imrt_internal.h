@@ -20,8 +20,9 @@ constexpr int kFwdRowsMax = 512;       // rows of one forward row block
 constexpr int kWaveNnz = 512;          // LDS product slots of one wave's row block (float32 storage)
 constexpr int kWavePartNnz = kWaveNnz - 4;
 // With 16-bit storage a wave's row block holds twice the nonzeros, so that
-// one block's loads are as many bytes as with float32.
-constexpr int wave_nnz(int storage) { return storage == 0 ? kWaveNnz : 2 * kWaveNnz; }
+// one block's loads are as many bytes as with float32; with float32 values
+// and 16-bit column indices it holds 1.5 times as many (6 bytes each).
+constexpr int wave_nnz(int storage) { return storage == 0 ? kWaveNnz : storage == 3 ? 3 * kWaveNnz / 2 : 2 * kWaveNnz; }
 constexpr int wave_part_nnz(int storage) { return wave_nnz(storage) - 4; }
 constexpr int kWaveRowsMax = 256;      // rows of one wave's row block
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
@@ -81,12 +82,17 @@ struct Penalties {
 // with a float32 scale per beamlet (D~_ij = col_scale[i] * q_ij), where the
 // CSR column indices are 16-bit too.
 enum Storage : int32_t { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2 };
+// Layout the forward pass reads: the storage's own, or for float32 values
+// with nb <= 65536 the CSR column indices as 16 bits (ST_F32C16).  The
+// arithmetic is that of float32 storage.
+constexpr int32_t ST_F32C16 = 3;
+constexpr bool coded(int st) { return st == ST_BF16 || st == ST_F16; }
 
 struct FwdArgs {
   const int32_t* row_ptr;
   const int32_t* col_idx;
   const float* val;
-  const uint16_t* col16;     // 16-bit storage: column indices
+  const uint16_t* col16;     // 16-bit storage or ST_F32C16: column indices
   const uint16_t* val16;     // 16-bit storage: codes
   const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
   int32_t storage;
@@ -165,6 +171,7 @@ struct Tuning {
   int adj_xcd = 1;             // adjoint ranges contiguous per accelerator die (1) or in dispatch order (0)
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
   int fwd_bpw = 1;             // fewest row blocks per forward wave (new dose matrices)
+  int fwd_col16 = 1;           // float32 matrices with nb <= 65536: 16-bit CSR columns for the forward
   int serve_adj_min_nnz = 32768;   // the same two for matrices a server builds, which
   int serve_fwd_bpw = 4;           // share every dispatch with other live plans
 };
@@ -194,7 +201,8 @@ struct imrt_dose {
   // 16-bit storage (then col_idx, val and cval are released): CSR column
   // indices and codes, CSC codes, per-beamlet scales
   int32_t storage = 0;
-  uint16_t* col16 = nullptr;
+  int32_t fwd_st = -1;         // the forward layout (Storage or ST_F32C16), set with the partition
+  uint16_t* col16 = nullptr;   // (also kept beside col_idx for ST_F32C16)
   uint16_t* val16 = nullptr;
   uint16_t* cval16 = nullptr;
   float* col_scale = nullptr;

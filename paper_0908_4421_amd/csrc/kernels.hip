@@ -429,7 +429,8 @@ __device__ void decide(const double* partials, int nparts, const double* steps, 
 // A lane holds its entries in groups of four: float32 storage as int4 column
 // indices and float4 values, 16-bit storage as two 32-bit words of packed
 // 16-bit indices or codes (entry u in the low half of word u / 2 when u is
-// even, in the high half when odd).
+// even, in the high half when odd); the ST_F32C16 layout pairs packed 16-bit
+// indices with float4 values.
 template <int ST>
 __device__ __forceinline__ float code_value(uint32_t h) {
   if constexpr (ST == ST_BF16) {
@@ -457,7 +458,7 @@ __device__ __forceinline__ float val_of(const uint2& v, int u) {
 template <int ST>
 using ColGroup = std::conditional_t<ST == ST_F32, int4, uint2>;
 template <int ST>
-using ValGroup = std::conditional_t<ST == ST_F32, float4, uint2>;
+using ValGroup = std::conditional_t<coded(ST), uint2, float4>;
 
 // ---- forward pass ---------------------------------------------------------------
 struct BlockMeta {
@@ -580,7 +581,7 @@ __device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, 
       R.v[q][u] = src[q * nbp + (i < nb ? i : 0)];
     }
   }
-  if constexpr (ST != ST_F32) {
+  if constexpr (coded(ST)) {
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int i = tid + u * THREADS;
@@ -608,7 +609,7 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int i = tid + u * THREADS;
-      if (i < nb) xs[q * nbp + i] = (ST == ST_F32) ? R.v[q][u] : R.v[q][u] * R.sc[u];
+      if (i < nb) xs[q * nbp + i] = !coded(ST) ? R.v[q][u] : R.v[q][u] * R.sc[u];
     }
   }
   for (int i0 = tid + kStageU * THREADS; i0 < nb; i0 += kStageU * THREADS) {
@@ -619,7 +620,7 @@ __device__ __forceinline__ void stage_finish(const FwdArgs& a, const float* src,
       for (int u = 0; u < kStageU; ++u) {
         const int i = i0 + u * THREADS;
         v[q][u] = src[q * nbp + (i < nb ? i : 0)];
-        if constexpr (ST != ST_F32) v[q][u] *= a.col_scale[i < nb ? i : 0];
+        if constexpr (coded(ST)) v[q][u] *= a.col_scale[i < nb ? i : 0];
       }
     }
 #pragma unroll
@@ -667,7 +668,7 @@ __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<N
     R.p0[u] = a.pieces_col[2 * ii];
     R.p1[u] = a.pieces_col[2 * ii + 1];
     R.kind[u] = a.col_kind[ii];
-    if constexpr (ST != ST_F32) R.sc[u] = a.col_scale[ii];
+    if constexpr (coded(ST)) R.sc[u] = a.col_scale[ii];
   }
 }
 
@@ -699,17 +700,17 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
     for (int j = 1; j <= NT; ++j) x = (T.xi == j) ? R.xc[j][u] : x;
     if (T.init) {
 #pragma unroll
-      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = (ST == ST_F32) ? x : x * R.sc[u];
+      for (int q = 0; q < NT; ++q) xs[q * nbp + i] = !coded(ST) ? x : x * R.sc[u];
       continue;
     }
-    const double gf = (ST == ST_F32) ? a.g_scale : a.g_scale * static_cast<double>(R.sc[u]);
+    const double gf = !coded(ST) ? a.g_scale : a.g_scale * static_cast<double>(R.sc[u]);
     float g = R.g[u];
     if (R.kind[u] == 1) g = static_cast<float>(gf * (R.p0[u] + R.p1[u]));
     else if (R.kind[u] > 1) g = static_cast<float>(gf * pieces_sum(a, i));
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
       const float t = trial_point(x, g, lam[q]);
-      xs[q * nbp + i] = (ST == ST_F32) ? t : t * R.sc[u];
+      xs[q * nbp + i] = !coded(ST) ? t : t * R.sc[u];
       if (T.lead) {
         select_buf(a.xbuf, (T.xi + 1 + q) % (NT + 1))[i] = t;
         const double dl = static_cast<double>(t) - static_cast<double>(x);
@@ -932,7 +933,8 @@ __global__ __launch_bounds__(kThreads) void fwd_kernel(FwdArgs a) {
 constexpr int kWaveSlack = 256;   // LDS floats after the last wave region (over-reads of masked slots)
 
 // Groups of four entries per lane in one wave's row block: 2 (512 entries)
-// with float32 storage, 4 (1024 entries) with 16-bit storage.
+// with float32 storage, 3 (768) with float32 values and 16-bit indices, 4
+// (1024 entries) with 16-bit storage.
 template <int ST>
 constexpr int wave_groups() { return wave_nnz(ST) / 256; }
 
@@ -960,6 +962,15 @@ __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, in
 #pragma unroll
     for (int j = 0; j < G; ++j) {
       c[j] = load_i4(rc, 16 * lane + 1024 * j);
+      v[j] = load_f4(rv, 16 * lane + 1024 * j);
+    }
+  } else if constexpr (ST == ST_F32C16) {
+    const uint32_t n = static_cast<uint32_t>(k1 - base);
+    const rsrc_t rc = make_rsrc(a.col16 + base, (n * 2 + 7) & ~7u);
+    const rsrc_t rv = make_rsrc(a.val + base, (n * 4 + 15) & ~15u);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      c[j] = load_u2(rc, 8 * lane + 512 * j);
       v[j] = load_f4(rv, 16 * lane + 1024 * j);
     }
   } else {
@@ -1454,11 +1465,11 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
   // 16-bit storage: the column's scale, loaded with its bounds
   float csc = 1.0f;
-  if constexpr (ST != ST_F32) csc = a.col_scale[c < c1 ? c : 0];
+  if constexpr (coded(ST)) csc = a.col_scale[c < c1 ? c : 0];
   auto bounds = [&]() {
     lo = max(uniform(a.col_ptr[c]), k0w);
     hi = min(uniform(a.col_ptr[c + 1]), k1w);
-    if constexpr (ST != ST_F32) csc = a.col_scale[c];
+    if constexpr (coded(ST)) csc = a.col_scale[c];
   };
   // a solve gathers the residual of the first trial: the accepted one
   // unless a later trial wins
@@ -1727,6 +1738,7 @@ int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t
     case ST_F32: rc = launch_forward_batch_st<ST_F32>(args, slots, nslots, ntrials, lds, ctx->stream); break;
     case ST_BF16: rc = launch_forward_batch_st<ST_BF16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
     case ST_F16: rc = launch_forward_batch_st<ST_F16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
+    case ST_F32C16: rc = launch_forward_batch_st<ST_F32C16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
     default: return set_error(IMRT_EINVAL, "unknown storage");
   }
   if (rc) return rc;
@@ -1775,11 +1787,12 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
       case ST_F32: rc = launch_wave_forward<ST_F32>(a, ntrials, gd, lds, s, before, after); break;
       case ST_BF16: rc = launch_wave_forward<ST_BF16>(a, ntrials, gd, lds, s, before, after); break;
       case ST_F16: rc = launch_wave_forward<ST_F16>(a, ntrials, gd, lds, s, before, after); break;
+      case ST_F32C16: rc = launch_wave_forward<ST_F32C16>(a, ntrials, gd, lds, s, before, after); break;
       default: return set_error(IMRT_EINVAL, "unknown storage");
     }
     if (rc) return rc;
   } else {
-    if (a.storage != ST_F32)
+    if (coded(a.storage))   // (ST_F32C16 matrices keep their 32-bit column indices for this pass)
       return set_error(IMRT_EUNSUPPORTED, "16-bit storage needs the wave-granular forward pass (fwd_wave = 1)");
     switch (ntrials) {
       case 1: hipExtLaunchKernelGGL(fwd_kernel<1>, gd, bd, lds, s, before, after, 0, a); break;

@@ -76,7 +76,7 @@ struct Finished {
 // plan's buffers, as allocated by this library.
 int64_t dose_bytes(const imrt_dose* D) {
   const int64_t nnz = D->nnz, nv = D->nv, nb = D->nb;
-  const int64_t per_nz = (D->storage == ST_F32) ? 16 : 10;
+  const int64_t per_nz = (D->storage == ST_F32) ? (D->col16 ? 18 : 16) : 10;
   return per_nz * nnz + 4 * (nv + 1) + 4 * (nb + 1) + 2 * nv /* ids, order */ + 4 * nv /* permutation scratch */ +
          4 * static_cast<int64_t>(D->nwblocks + D->nblocks) * 2 + 16 * D->adj_grid + 9 * nb;
 }
@@ -336,7 +336,7 @@ void worker_main(imrt_server* S) {
     // slot tables of the live plans (each at a multiple of the die count)
     fs.clear();
     as.clear();
-    int storage = -1, nt = 1;
+    int storage = -1, fst = -1, nt = 1;
     size_t lds = 0;
     bool mixed = false;
     for (int i : active) {
@@ -344,17 +344,18 @@ void worker_main(imrt_server* S) {
       const imrt_dose* D = L.plan->dose;
       if (storage < 0) {
         storage = D->storage;
+        fst = D->fwd_st;
         nt = L.nt;
       }
-      mixed = mixed || D->storage != storage || L.nt != nt;
+      mixed = mixed || D->storage != storage || D->fwd_st != fst || L.nt != nt;
       while (fs.size() % kXcds) fs.push_back(-1);
       for (int w = 0; w < L.grid; ++w) fs.push_back((i << 16) | w);
       while (as.size() % kXcds) as.push_back(-1);
       for (int w = 0; w < D->adj_grid; ++w) as.push_back((i << 16) | w);
-      lds = std::max(lds, forward_lds_bytes(D->nb, L.nt, L.plan->nstruct, true, D->storage));
+      lds = std::max(lds, forward_lds_bytes(D->nb, L.nt, L.plan->nstruct, true, D->fwd_st));
     }
     int rc = IMRT_OK;
-    if (mixed) rc = set_error(IMRT_EINVAL, "live solves of one server must share storage and trials_per_pass");
+    if (mixed) rc = set_error(IMRT_EINVAL, "live solves of one server must share storage, layout and trials_per_pass");
     if (!rc) rc = grow_slots(S, &S->fslots, &S->fslot_cap, fs.size());
     if (!rc) rc = grow_slots(S, &S->aslots, &S->aslot_cap, as.size());
     hipError_t e = hipSuccess;
@@ -364,7 +365,7 @@ void worker_main(imrt_server* S) {
     if (!rc && e != hipSuccess) rc = hip_error(e, "server slot upload");
     for (int k = 0; k < K && !rc; ++k) {
       rc = launch_adjoint_batch(C, S->aargs, S->aslots, static_cast<int>(as.size()), nt, storage);
-      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, storage, lds);
+      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, lds);
     }
     if (!rc) {
       e = hipMemcpyAsync(seen.data(), S->st, sizeof(SolverState) * 2 * S->max_live, hipMemcpyDeviceToHost, s);

@@ -13,15 +13,16 @@ from workloads import TINY, TINY_SETTINGS, penalty_table, power_start_vector
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=[(1024, 1), (16, 0), (16, 1)],
-                ids=["default", "shared_cols_block_fwd", "shared_cols_wave_fwd"])
+@pytest.fixture(scope="module", params=[(1024, 1, 1), (16, 0, 1), (16, 1, 1), (1024, 1, 0)],
+                ids=["default", "shared_cols_block_fwd", "shared_cols_wave_fwd", "col32_wave_fwd"])
 def ctx(request):
     """Default launch settings, or many short adjoint workgroup ranges (most
     beamlet columns shared by several workgroups) with workgroup-wide or
-    wave-wide forward row blocks."""
+    wave-wide forward row blocks, or the wave forward over 32-bit column
+    indices (512-entry blocks) instead of 16-bit ones (768-entry blocks)."""
     from paper_0908_4421_amd.imrt import Context
-    min_nnz, wave = request.param
-    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave)
+    min_nnz, wave, col16 = request.param
+    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave, fwd_col16=col16)
 
 
 @pytest.fixture(scope="module")

@@ -22,13 +22,15 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=[(1024, 1), (16, 0)], ids=["default", "shared_cols_block_fwd"])
+@pytest.fixture(scope="module", params=[(1024, 1, 1), (16, 0, 1), (1024, 1, 0)],
+                ids=["default", "shared_cols_block_fwd", "col32_wave_fwd"])
 def ctx(request):
     """Default launch settings, or many short adjoint workgroup ranges (most
-    columns shared by several workgroups) with workgroup-wide forward blocks."""
+    columns shared by several workgroups) with workgroup-wide forward blocks,
+    or the wave forward over 32-bit column indices."""
     from paper_0908_4421_amd.imrt import Context
-    min_nnz, wave = request.param
-    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave)
+    min_nnz, wave, col16 = request.param
+    return Context(0, adj_min_nnz=min_nnz, fwd_wave=wave, fwd_col16=col16)
 
 
 def _dose(ctx, A):
@@ -109,3 +111,21 @@ def test_context_options(ctx):
         with pytest.raises(imrt.ImrtError) as e:
             ctx.set_option(*bad)
         assert e.value.code == imrt.IMRT_EINVAL
+
+
+def test_beamlets_beyond_the_staging_limit(ctx):
+    """x is staged in LDS: a matrix with more beamlets than fit is built and
+    exported, but its forward product reports IMRT_EUNSUPPORTED; its adjoint
+    product needs no staging and still matches the oracle."""
+    from paper_0908_4421_amd import imrt
+    A = random_csr(3000, 70000, 10.0, 8, empty_frac=0.3)
+    lib = _dose(ctx, A)
+    assert np.array_equal(lib.export()["col_idx"], A.col_idx)
+    with pytest.raises(imrt.ImrtError) as e:
+        lib.apply(to_dev(np.ones(A.nb, np.float32)))
+    assert e.value.code == imrt.IMRT_EUNSUPPORTED
+    r = np.random.default_rng(3).standard_normal(A.nv).astype(np.float32)
+    y = to_host(lib.apply_transpose(to_dev(r)))
+    D = csr_of(A)
+    y_ref = model.adjoint(D, r.astype(np.float64))
+    assert np.all(np.abs(y - y_ref) <= 1e-6 * (abs(D).T @ np.abs(r.astype(np.float64))) + 1e-30)
