@@ -130,7 +130,21 @@ SMALL = PhantomSpec(name="small_33x27x11_4mm_7field", nx=33, ny=27, nz=11, h=4.0
                     r_ptv=15.0, r_rectum=6.0, r_bladder=11.25, n_beams=7,
                     beamlet=5.0, sigma=3.0, tau=0.005, seed=2)
 
-NAMED = {"tiny": TINY, "paper": PAPER_SCALE, "small": SMALL}
+# The shape of the paper's largest scenario (Table 1, scenario 3: 9 fields,
+# 5 mm beamlets, 6,453 beamlets, 143,329 voxels, 43.3 M nonzeros, about 300
+# per voxel) on a uniform 4 mm grid with wide beamlet kernels: 6,444
+# beamlets, 142,560 voxels, about 41 M nonzeros.  Its CSR and CSC (about
+# 0.6 GB) exceed the 256 MB last-level cache, so its passes stream from HBM.
+SCENARIO3_SHAPE = PhantomSpec(name="scenario3_shape_66x54x40_4mm_9field", nx=66, ny=54, nz=40, h=4.0,
+                              r_ptv=67.0, r_rectum=26.8, r_bladder=50.25, n_beams=9, beamlet=5.0,
+                              sigma=7.5, tau=0.005, seed=4)
+
+# A small phantom with the same wide kernels (rows of up to 656 nonzeros,
+# most columns reaching a sixth of the voxels) for parity tests.
+WIDE = PhantomSpec(name="wide_30x26x16_4mm_9field", nx=30, ny=26, nz=16, h=4.0, r_ptv=40.0,
+                   r_rectum=16.0, r_bladder=30.0, n_beams=9, beamlet=5.0, sigma=7.5, tau=0.005, seed=5)
+
+NAMED = {"tiny": TINY, "paper": PAPER_SCALE, "small": SMALL, "scenario3": SCENARIO3_SHAPE}
 
 # Fixed box of the batched / served instances (mm) and the grids it gives.
 _BOX_GRIDS = {2.5: (160, 104, 80), 4.0: (100, 65, 50), 5.0: (80, 52, 40)}
