@@ -364,6 +364,27 @@ def shape_form(ctx, args):
     }
 
 
+def read_probe(gib=4, reps=5):
+    """Achievable HBM read rate: a float32 sum over `gib` GiB (16 times the
+    256 MB last-level cache), timed with events; the best of `reps`."""
+    import torch
+    n = gib * (1 << 30) // 4
+    buf = torch.ones(n, dtype=torch.float32, device="cuda")
+    buf.sum()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        buf.sum()
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del buf
+    torch.cuda.empty_cache()
+    return 4 * n / (best * 1e-3) / 1e9
+
+
 def _pct(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
@@ -643,9 +664,11 @@ def main():
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nv, nb, nnz),
                                            "adjoint": adjoint_bytes(nv, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    probe = read_probe()
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom]),
-                "kernel": kern[dom]["kernel"]}
+                "kernel": kern[dom]["kernel"], "read_probe_GB_s": probe,
+                "frac_of_read_probe": kern[dom]["GB_s"] / probe}
 
     out = {
         "metric": "time-to-plan (s) + SpMV HBM GB/s vs peak, 9-field 2.5mm; p99 served re-plan",
