@@ -364,25 +364,18 @@ def shape_form(ctx, args):
     }
 
 
-def read_probe(gib=4, reps=5):
-    """Achievable HBM read rate: a float32 sum over `gib` GiB (16 times the
-    256 MB last-level cache), timed with events; the best of `reps`."""
+def read_probe(ctx, gib=4, reps=5):
+    """Achievable HBM read rate: the library's streaming-read probe over
+    `gib` GiB (16 times the 256 MB last-level cache); the best of `reps`."""
     import torch
-    n = gib * (1 << 30) // 4
-    buf = torch.ones(n, dtype=torch.float32, device="cuda")
-    buf.sum()
-    best = None
-    for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        buf.sum()
-        b.record()
-        b.synchronize()
-        ms = a.elapsed_time(b)
-        best = ms if best is None else min(best, ms)
+
+    from paper_0908_4421_amd.imrt import imrt_read_probe
+    buf = torch.ones(gib * (1 << 30) // 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    gbs = imrt_read_probe(ctx.handle, buf.data_ptr(), buf.numel() * 4, reps)
     del buf
     torch.cuda.empty_cache()
-    return 4 * n / (best * 1e-3) / 1e9
+    return gbs
 
 
 def _pct(v, q):
@@ -664,7 +657,7 @@ def main():
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nv, nb, nnz),
                                            "adjoint": adjoint_bytes(nv, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    probe = read_probe()
+    probe = read_probe(ctx)
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom]),
                 "kernel": kern[dom]["kernel"], "read_probe_GB_s": probe,

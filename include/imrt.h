@@ -363,6 +363,14 @@ IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t
 /* Finishes the queued and live requests, then frees everything. */
 IMRT_API int imrt_server_destroy(imrt_server* server);
 
+/* Measurement aid, outside the method: the best of `reps` timed streaming
+ * reads (after one untimed) of `bytes` of the device buffer `buf` (16-byte
+ * aligned, nonnegative float32 values, not modified) on the context's
+ * stream, in GB/s (1e9 bytes/s); the read rate the products' streams can be
+ * compared with.  Synchronous.  IMRT_EINVAL for NULL pointers, misalignment,
+ * bytes < 16 or reps < 1. */
+IMRT_API int imrt_read_probe(imrt_ctx* ctx, const void* buf, int64_t bytes, int32_t reps, double* gbs_out);
+
 /* Message of the last error on this thread ("" if none). */
 IMRT_API const char* imrt_last_error(void);
 

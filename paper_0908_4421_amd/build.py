@@ -26,6 +26,7 @@ SOURCES = {
     "kernels.hip": [],
     "build.hip": ["-ffp-contract=off"],
     "serve.hip": [],
+    "probe.hip": [],
 }
 
 

@@ -86,6 +86,7 @@ SIGNATURES = {
     "imrt_dose_from_csr": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int64, _i32p, _i32p, _f32p, C.c_int,
                                      C.POINTER(_vp)]),
     "imrt_dose_info": (C.c_int, [_vp, _i32p, _i32p, C.POINTER(C.c_int64)]),
+    "imrt_read_probe": (C.c_int, [_vp, _vp, C.c_int64, C.c_int32, C.POINTER(C.c_double)]),
     "imrt_dose_export": (C.c_int, [_vp, _i32p, _i32p, _f32p, _i32p, _i32p, _f32p, _u8p]),
     "imrt_dose_export_codes": (C.c_int, [_vp, _u16p, _u16p, _f32p]),
     "imrt_dose_storage": (C.c_int, [_vp, _i32p]),
@@ -200,6 +201,13 @@ def imrt_dose_from_csr(ctx, nv, nb, nnz, row_ptr, col_idx, val, storage: int = I
     _check(load().imrt_dose_from_csr(ctx, nv, nb, nnz, _host(row_ptr, C.c_int32), _host(col_idx, C.c_int32),
                                      _host(val, C.c_float), storage, C.byref(out)), "imrt_dose_from_csr")
     return out
+
+
+def imrt_read_probe(ctx, buf_ptr: int, nbytes: int, reps: int = 5) -> float:
+    """GB/s of the best of `reps` streaming reads of a device buffer."""
+    out = C.c_double()
+    _check(load().imrt_read_probe(ctx, C.c_void_p(buf_ptr), nbytes, reps, C.byref(out)), "imrt_read_probe")
+    return out.value
 
 
 def imrt_dose_info(dose):
