@@ -20,7 +20,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KERNEL_SOURCES = ("paper_0908_4421_amd/csrc/kernels.hip", "paper_0908_4421_amd/csrc/imrt_internal.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_fwd_adj_prostate_160x104x80.txt")
+# counter summaries per workload (by phantom name)
+TRAFFIC_PROFILES = {
+    "prostate_160x104x80_2.5mm_9field": os.path.join(ROOT, "profiles", "hbm_traffic_fwd_adj_prostate_160x104x80.txt"),
+    "scenario3_shape_66x54x40_4mm_9field": os.path.join(ROOT, "profiles",
+                                                        "hbm_traffic_fwd_adj_scenario3_shape_66x54x40.txt"),
+}
 
 
 def forward_bytes(nv, nb, nnz):
@@ -358,6 +363,7 @@ def shape_form(ctx, args):
         "iters_per_s": res.iterations / (ms / 1e3),
         "lambda0": lam0,
         "kernels": kern,
+        "traffic": {k: traffic_from_profile(names[k], spec.name) for k in names},
         "dose_build_s": build_s,
         "note": "the paper's Table 1 scenario 3 has 6,453 beamlets, 143,329 voxels and 43.3 M nonzeros "
                 "(its own time is context only: other hardware, data and iteration count)",
@@ -532,15 +538,16 @@ def summarize_pmc(folder):
               f"median {statistics.median(work):.1f} | mean {statistics.fmean(work):.1f}")
 
 
-def traffic_from_profile(kernel_key):
-    """HBM bytes per launch of the named kernel from the committed counter
-    summary: FETCH_SIZE and WRITE_SIZE medians (KiB per dispatch), each scaled
-    by the factor a plain device copy of known size gave for the same counter.
-    None when the summary is missing or the kernel sources changed since."""
+def traffic_from_profile(kernel_key, workload="prostate_160x104x80_2.5mm_9field"):
+    """HBM bytes per launch of the named kernel on the named workload from the
+    committed counter summary: FETCH_SIZE and WRITE_SIZE medians (KiB per
+    dispatch), each scaled by the factor a plain device copy of known size
+    gave for the same counter.  None when there is no summary for the
+    workload or the kernel sources changed since."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(TRAFFIC_PROFILES[workload]) as f:
             lines = f.read().splitlines()
-    except OSError:
+    except (KeyError, OSError):
         return None
     kv = {}
     ctr = {}
@@ -659,7 +666,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     probe = read_probe(ctx)
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom]),
+                "frac": kern[dom]["GB_s"] / HBM_PEAK_GBS, "traffic": traffic_from_profile(names[dom], spec.name),
                 "kernel": kern[dom]["kernel"], "read_probe_GB_s": probe,
                 "frac_of_read_probe": kern[dom]["GB_s"] / probe}
 
