@@ -1342,10 +1342,11 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 // plan's pass, or -1 for an idle slot (plans start at multiples of the die
 // count, so each plan keeps its workgroups' die placement).
 template <int NT, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64) void fwd_wave_batch_kernel(const FwdArgs* args, const int32_t* slots) {
+__global__ __launch_bounds__(WAVES * 64) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
+                                                                    const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
-  const FwdArgs a = args[sv >> 16];
+  const FwdArgs& a = args[sv >> 16];
   fwd_wave_pass<NT, FWD_SOLVE, WAVES, ST>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
@@ -1562,10 +1563,12 @@ __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
 
 // Batched solve pass (slots as for fwd_wave_batch_kernel).
 template <int NT, int ST>
-__global__ __launch_bounds__(kThreads) void adj_batch_kernel(const AdjArgs* args, const int32_t* slots) {
+__global__ __launch_bounds__(kThreads) void adj_batch_kernel(const AdjArgs* __restrict__ args,
+                                                             const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
-  const AdjArgs a = args[sv >> 16];
+  // read in place (uniform, read-only): a local copy would live in scratch
+  const AdjArgs& a = args[sv >> 16];
   adj_pass<NT, true, ST>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
