@@ -325,7 +325,9 @@ IMRT_API int imrt_plan_destroy(imrt_plan* plan);
  * plans; a new patient's matrix is admitted only when the largest matrix
  * built so far (initially a quarter of a GiB, at most half the budget) still
  * fits, and unused resident matrices are evicted least recently used first.
- * All live solves must share one storage and trials_per_pass.  Matrices the
+ * One dispatch holds one storage, forward layout and trials_per_pass: a
+ * request that differs from the live solves in these waits until they have
+ * finished (requests keep their arrival order).  Matrices the
  * server builds take the context's "serve_adj_min_nnz" and
  * "serve_fwd_blocks_per_wave" partition (read at server creation), coarser
  * than a lone plan's since every dispatch holds several plans; a result

@@ -189,6 +189,13 @@ bool admit(imrt_server* S, Pending& p, int slot) {
     rit = S->residents.emplace(p.patient, r).first;
   }
   const int nt = p.params.trials_per_pass == 0 ? 1 : p.params.trials_per_pass;
+  // One dispatch serves one storage, forward layout and trial count: a
+  // request that differs from the live solves waits until they are done.
+  for (int i = 0; i < S->max_live; ++i) {
+    if (!S->occupied[i]) continue;
+    const imrt_dose* LD = S->live[i].plan->dose;
+    if (LD->storage != D->storage || LD->fwd_st != D->fwd_st || S->live[i].nt != nt) return false;
+  }
   const int64_t pb = plan_bytes(D, nt);
   if (S->used + pb > S->budget) {
     rit->second.users += 1;   // keep it while making room for the plan

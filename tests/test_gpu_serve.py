@@ -24,13 +24,13 @@ def _replan_table(spec, rng):
     return t
 
 
-def _alone(ctx, dose, table, lam, max_iter=3000):
+def _alone(ctx, dose, table, lam, max_iter=3000, fixed=False):
     from paper_0908_4421_amd.imrt import Plan
     p = Plan(ctx, dose)
     p.set_structures(None, len(table))
     p.set_penalties(table)
     x = to_dev(np.ones(dose.nb, np.float32))
-    res, _ = p.solve(x, eps=1e-4, alpha=2.0, lambda0=lam, delta=1e-5, max_iter=max_iter)
+    res, _ = p.solve(x, eps=1e-4, alpha=2.0, lambda0=lam, delta=1e-5, max_iter=max_iter, fixed_iters=fixed)
     return res, to_host(x)
 
 
@@ -99,3 +99,29 @@ def test_failed_request_fails_alone(ctx):
     res, times, _ = srv.wait(good)
     assert res.iterations == 50
     srv.close()
+
+
+def test_storage_change_waits_for_the_live_mix(ctx):
+    """Requests in float32, bfloat16, float32 submitted together: each waits
+    until the solves of the other storage ahead of it are done (arrival order
+    is kept), and every plan equals the same plan solved alone."""
+    from paper_0908_4421_amd.imrt import Dose, Server
+    part = (ctx.get_option("serve_adj_min_nnz"), ctx.get_option("serve_fwd_blocks_per_wave"))
+    reqs = [(20, TINY, "f32"), (21, SMALL, "bf16"), (22, draw_batch_instance(1003), "f32")]
+    srv = Server(ctx, budget_bytes=4 << 30, max_live=8)
+    tickets = [srv.submit(pt, sp, penalty_table(sp), storage=st, max_iter=400, fixed_iters=True)
+               for pt, sp, st in reqs]
+    got = []
+    for tk in tickets:
+        got.append(srv.wait(tk, 0))
+        banner(f"ticket {tk} done")
+    srv.close()
+    for (pt, sp, st), (res, times, _) in zip(reqs, got):
+        d = Dose.from_geometry(ctx, sp, storage=st)
+        d.repartition(*part)
+        ref, _ = _alone(ctx, d, penalty_table(sp), times.lambda0, max_iter=400, fixed=True)
+        assert res.iterations == ref.iterations == 400
+        assert res.G_final == ref.G_final
+    # admitted one after the other (arrivals lie within a millisecond)
+    assert got[1][1].queue_ms >= got[0][1].plan_ms - 1.0
+    assert got[2][1].queue_ms >= got[1][1].plan_ms - 1.0
