@@ -357,7 +357,9 @@ IMRT_API int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t
 /* Queue a request (thread-safe, returns at once with a ticket > 0). */
 IMRT_API int imrt_server_submit(imrt_server* server, const imrt_request* request, int64_t* ticket_out);
 /* Block until the ticket's solve finished; x_out (nullable host array of nb
- * floats) receives its plan.  A failed request returns its error. */
+ * floats) receives its plan.  A failed request returns its error.  Each
+ * ticket can be waited on once (IMRT_EINVAL for an unknown ticket or a
+ * second wait). */
 IMRT_API int imrt_server_wait(imrt_server* server, int64_t ticket, float* x_out, int32_t nb,
                               imrt_solve_result* result, imrt_serve_times* times);
 IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t* peak_bytes,

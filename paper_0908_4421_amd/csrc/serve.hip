@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -97,6 +98,7 @@ struct imrt_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Pending> queue;
   std::map<int64_t, Finished> finished;
+  std::set<int64_t> delivered;  // tickets already handed to a waiter
   std::map<int64_t, Resident> residents;
   uint64_t use_clock = 0;
   int64_t next_ticket = 1;
@@ -500,6 +502,8 @@ int imrt_server_wait(imrt_server* S, int64_t ticket, float* x_out, int32_t nb, i
   {
     std::unique_lock<std::mutex> lk(S->mu);
     if (ticket <= 0 || ticket >= S->next_ticket) return set_error(IMRT_EINVAL, "unknown ticket");
+    if (S->delivered.count(ticket)) return set_error(IMRT_EINVAL, "ticket already waited on");
+    S->delivered.insert(ticket);   // (a second waiter on the same ticket is turned away)
     S->cv_done.wait(lk, [&] { return S->finished.count(ticket) != 0; });
     f = std::move(S->finished[ticket]);
     S->finished.erase(ticket);

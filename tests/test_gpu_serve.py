@@ -98,6 +98,10 @@ def test_failed_request_fails_alone(ctx):
     assert e.value.code == imrt.IMRT_EINVAL
     res, times, _ = srv.wait(good)
     assert res.iterations == 50
+    for tk in (good, 0, 999):     # waited on already, never issued
+        with pytest.raises(imrt.ImrtError) as e:
+            srv.wait(tk)
+        assert e.value.code == imrt.IMRT_EINVAL
     srv.close()
 
 
