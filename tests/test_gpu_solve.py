@@ -184,3 +184,32 @@ def test_invalid_solve_arguments(tiny):
         with pytest.raises(imrt.ImrtError) as e:
             plan.solve(ok, max_iter=5, **kw)
         assert e.value.code == imrt.IMRT_EINVAL
+
+
+def test_empty_matrix(ctx):
+    """D with no nonzeros (every voxel out of every beam): both products are
+    zero, the objective is the structures' under-dose penalty at zero dose,
+    the gradient vanishes, so the first trial equals x_1 and the solve stops
+    as stalled (as the oracle does); the lambda_0 estimate reports the zero
+    vector it reaches."""
+    from paper_0908_4421_amd import imrt
+    nv, nb = 300, 17
+    Dz = sp.csr_matrix((nv, nb), dtype=np.float32)
+    sid = (np.arange(nv) % 3).astype(np.uint8)
+    table = [(5.0, 6.0, 1.0, 0.5), (0.0, 2.0, 0.0, 0.3), (0.0, 1.0, 0.0, 0.1)]
+    lib, plan = _plan_from_csr(ctx, Dz, sid, table)
+    assert (lib.nv, lib.nb, lib.nnz) == (nv, nb, 0)
+    assert np.all(to_host(lib.apply(to_dev(np.ones(nb, np.float32)))) == 0.0)
+    assert np.all(to_host(lib.apply_transpose(to_dev(np.ones(nv, np.float32)))) == 0.0)
+    pen = model.VoxelPenalties.from_structures(sid, np.array(table))
+    x1 = np.full(nb, 2.0)
+    ref = solver.solve(Dz, pen, x1, eps=1e-4, alpha=2.0, lambda0=1.0, max_iter=10)
+    assert ref.status == solver.STALLED and ref.iterations == 0
+    x = to_dev(x1.astype(np.float32))
+    res, _ = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=1.0, max_iter=10)
+    assert res.status == ref.status and res.iterations == 0
+    assert res.G_initial == ref.G_initial == 100 * 25.0
+    assert np.all(to_host(x) == 2.0)
+    with pytest.raises(imrt.ImrtError) as e:
+        plan.lambda0(to_dev(np.ones(nb, np.float32)), 50)
+    assert e.value.code == imrt.IMRT_EINVAL
