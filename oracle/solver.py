@@ -16,7 +16,10 @@ The iteration follows the paper's initialisation and five steps:
 Readings taken where the paper is silent or garbled:
   * Eq. (5) multiplies a row vector by its transpose: the squared Euclidean
     norm of the step.  C_k is recomputed for every trial lambda.
-  * lambda restarts from lambda_0 in every iteration (step 2).
+  * lambda restarts from lambda_0 in every iteration (step 2).  A variant
+    (``warm_start``, not the paper's step 2) starts iteration k + 1 at alpha
+    times the step accepted in iteration k; the first iteration starts at
+    lambda_0.
   * Step 5 is applied after acceptance to the newest pair,
     |G_{k+1} - G_k| / G_{k+1} < delta; G_{k+1} == 0 also stops.
   * A trial with ||x_{k+1} - x_k|| == 0 can never pass the strict test of
@@ -95,7 +98,7 @@ def power_of_two_at_least(q: float) -> float:
 def solve(D, pen: model.VoxelPenalties, x1: np.ndarray, *, eps: float, alpha: float,
           lambda0: float, delta: float = 1e-5, max_iter: int = 20000,
           max_backtracks: int = 60, fixed_iters: bool = False,
-          keep_trace: bool = True) -> SolveResult:
+          keep_trace: bool = True, warm_start: bool = False) -> SolveResult:
     """Run the Armijo gradient-projection method from ``x1`` (float64)."""
     if not (0.0 < eps < 1.0) or not (alpha > 1.0) or not (lambda0 > 0.0):
         raise ValueError("need 0 < eps < 1, alpha > 1, lambda0 > 0")
@@ -107,6 +110,7 @@ def solve(D, pen: model.VoxelPenalties, x1: np.ndarray, *, eps: float, alpha: fl
     G = model.objective_from_dose(z, pen)
     G_init = G
     n_fwd, n_adj, k = 1, 0, 0
+    lam_start = lambda0
     trace: List[TraceEntry] = []
     status = None
     if max_iter <= 0:
@@ -114,7 +118,7 @@ def solve(D, pen: model.VoxelPenalties, x1: np.ndarray, *, eps: float, alpha: fl
     while status is None:
         g = 2.0 * (Df.T @ model.residual(z, pen))        # step 1
         n_adj += 1
-        lam, m = lambda0, 0                               # step 2
+        lam, m = lam_start, 0                             # step 2
         while True:
             xt = model.project(x - lam * g)
             step = xt - x
@@ -141,6 +145,8 @@ def solve(D, pen: model.VoxelPenalties, x1: np.ndarray, *, eps: float, alpha: fl
         G_prev = G
         x, z, G = xt, zt, Gt
         k += 1
+        if warm_start:
+            lam_start = alpha * lam
         if keep_trace:
             trace.append(TraceEntry(k, lam, m, s, G))
         if fixed_iters:                                   # step 5

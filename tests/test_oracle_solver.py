@@ -183,3 +183,40 @@ def test_stopping_rule_relative_change():
     Gs = [res.G_initial] + [e.G for e in res.trace]
     rel = [abs(b - a) / b for a, b in zip(Gs, Gs[1:])]
     assert rel[-1] < 1e-3 and all(r >= 1e-3 for r in rel[:-1])
+
+
+def _one_voxel():
+    """One voxel, one beamlet, D = [1], two-sided threshold 4 with unit
+    weights: G(x) = (x - 4)^2 and grad G = 2 (x - 4); every value below is a
+    dyadic rational, exact in float64."""
+    D = sp.csr_matrix(np.array([[1.0]], dtype=np.float32))
+    pen = model.VoxelPenalties(np.array([4.0]), np.array([4.0]), np.array([1.0]), np.array([1.0]))
+    return D, pen
+
+
+def test_warm_start_closed_form():
+    """Warm start: lambda of iteration k + 1 starts at 2 lambda_k.  From x = 0
+    with lambda_0 = 1/8 the steps are 1/8, 1/4, 1/2: x = 1, 2.5, 4, G = 9,
+    2.25, 0 (stop at G = 0).  Restarting at lambda_0 instead shrinks the
+    error by 3/4 per iteration: G = 16 (9/16)^k."""
+    D, pen = _one_voxel()
+    w = solver.solve(D, pen, np.zeros(1), eps=1e-4, alpha=2.0, lambda0=0.125, warm_start=True)
+    assert w.status == solver.CONVERGED and w.iterations == 3
+    assert [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in w.trace] == \
+        [(1, 0.125, 0, 1.0, 9.0), (2, 0.25, 0, 2.25, 2.25), (3, 0.5, 0, 2.25, 0.0)]
+    assert w.x[0] == 4.0
+    c = solver.solve(D, pen, np.zeros(1), eps=1e-4, alpha=2.0, lambda0=0.125, max_iter=3, fixed_iters=True)
+    assert [e.lam for e in c.trace] == [0.125] * 3
+    assert [e.G for e in c.trace] == [16.0 * (9.0 / 16.0) ** k for k in (1, 2, 3)]
+
+
+def test_warm_start_with_backtracking_closed_form():
+    """lambda_0 = 3/4 overshoots to x = 6 (G = 4); from then on the doubled
+    step 3/2 always overshoots (rejected) and 3/4 is accepted after one
+    reduction: x = 3, 4.5 with G = 1, 1/4."""
+    D, pen = _one_voxel()
+    w = solver.solve(D, pen, np.zeros(1), eps=1e-4, alpha=2.0, lambda0=0.75, max_iter=3, fixed_iters=True,
+                     warm_start=True)
+    assert [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in w.trace] == \
+        [(1, 0.75, 0, 36.0, 4.0), (2, 0.75, 1, 9.0, 1.0), (3, 0.75, 1, 2.25, 0.25)]
+    assert w.forward_products == 1 + 1 + 2 + 2 and w.x[0] == 4.5
