@@ -111,7 +111,9 @@ typedef struct {
   int32_t trials_per_pass;/* trial step sizes evaluated per pass over D: 1, 2 or 4 (0 = 1) */
   int32_t profile;        /* >= 0; n > 0: time every n-th forward and every n-th adjoint launch
                            * with HIP events on the context stream (1 = every launch) */
-  int32_t reserved;       /* must be 0 */
+  int32_t warm_start;     /* 0: every line search starts at lambda0 (Section 2.2,
+                             step 2); 1: iteration k+1 starts at alpha times the
+                             step accepted in iteration k (the first at lambda0) */
   void* trace;            /* nullable host buffer of max_iter imrt_trace_entry, filled on return */
 } imrt_solve_params;
 

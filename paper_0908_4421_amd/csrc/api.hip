@@ -1073,7 +1073,7 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   if (!(prm->delta >= 0.0)) return set_error(IMRT_EINVAL, "delta must be >= 0");
   if (prm->max_iter < 0 || prm->max_backtracks < 0)
     return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
-  if (prm->reserved != 0) return set_error(IMRT_EINVAL, "reserved must be 0");
+  if (prm->warm_start != 0 && prm->warm_start != 1) return set_error(IMRT_EINVAL, "warm_start must be 0 or 1");
   if (prm->profile < 0) return set_error(IMRT_EINVAL, "profile must be >= 0");
   const int nt = prm->trials_per_pass == 0 ? 1 : prm->trials_per_pass;
   if (nt != 1 && nt != 2 && nt != 4) return set_error(IMRT_EINVAL, "trials_per_pass must be 0, 1, 2 or 4");
@@ -1108,6 +1108,7 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   init.max_bt = prm->max_backtracks;
   init.fixed = prm->fixed_iters ? 1 : 0;
   init.trace_cap = cap;
+  init.warm = prm->warm_start;
   init.lambda = prm->lambda0;
   init.eps = prm->eps;
   init.alpha = prm->alpha;

@@ -45,7 +45,7 @@ struct SolverState {
   int32_t phase, status, k, m;        // phase, imrt_solve_status, accepted iterations, backtracks
   int32_t acc, xi, n_fwd, n_adj;      // trial whose residual buffer holds r(x_k), iterate buffer of x_k, pass counters
   int32_t ntrials, max_iter, max_bt, fixed;
-  int32_t trace_cap, pad;
+  int32_t trace_cap, warm;            // trace capacity; warm start of the line search (0/1)
   double lambda;                      // first trial step of the next forward pass
   double G, G_prev, G_init;
   double eps, alpha, lambda0, delta;

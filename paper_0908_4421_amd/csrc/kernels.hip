@@ -398,7 +398,7 @@ __device__ void decide(const double* partials, int nparts, const double* steps, 
         st.acc = accepted;
         st.xi = (st.xi + 1 + accepted) % (NT + 1);
         st.m = 0;
-        st.lambda = st.lambda0;
+        st.lambda = st.warm ? st.alpha * l : st.lambda0;   // step 2 of the next iteration
         if (st.fixed) {
           if (st.k >= st.max_iter) {
             st.status = IMRT_MAX_ITER;

@@ -42,7 +42,7 @@ class imrt_solve_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("lambda0", C.c_double),
                 ("delta", C.c_double), ("max_iter", C.c_int32), ("max_backtracks", C.c_int32),
                 ("fixed_iters", C.c_int32), ("trials_per_pass", C.c_int32), ("profile", C.c_int32),
-                ("reserved", C.c_int32), ("trace", C.c_void_p)]
+                ("warm_start", C.c_int32), ("trace", C.c_void_p)]
 
 
 class imrt_trace_entry(C.Structure):
@@ -511,14 +511,14 @@ class Plan:
 
     @staticmethod
     def solve_batch(plans, xs, *, eps, alpha, lambda0s, delta=1e-5, max_iter=20000, max_backtracks=60,
-                    fixed_iters=False, trials_per_pass=1, trace=False):
+                    fixed_iters=False, trials_per_pass=1, trace=False, warm_start=False):
         """imrt_solve_batch over `plans` (list of Plan) from the device tensors
         `xs`; one lambda_0 per plan.  Returns [(result, trace or None)]."""
         n = len(plans)
         bufs = [(imrt_trace_entry * max(max_iter, 1))() if trace else None for _ in range(n)]
         params = (imrt_solve_params * n)(*[
             imrt_solve_params(eps, alpha, lam, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
-                              trials_per_pass, 0, 0, C.cast(b, C.c_void_p) if trace else None)
+                              trials_per_pass, 0, int(bool(warm_start)), C.cast(b, C.c_void_p) if trace else None)
             for lam, b in zip(lambda0s, bufs)])
         handles = (_vp * n)(*[p.handle for p in plans])
         xptr = (_vp * n)(*[x.data_ptr() for x in xs])
@@ -547,10 +547,10 @@ class Plan:
         return imrt_batch_autotune(n, handles, params, xptr, tune_iters)
 
     def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
-              fixed_iters=False, trials_per_pass=1, trace=False, profile=0):
+              fixed_iters=False, trials_per_pass=1, trace=False, profile=0, warm_start=False):
         buf = (imrt_trace_entry * max(max_iter, 1))() if trace else None
         p = imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
-                              trials_per_pass, int(profile), 0,
+                              trials_per_pass, int(profile), int(bool(warm_start)),
                               C.cast(buf, C.c_void_p) if trace else None)
         res = imrt_solve(self.handle, p, x.data_ptr())
         tr = None
@@ -580,7 +580,8 @@ class Server:
         self.handle = imrt_server_create(ctx.handle, budget_bytes, max_live)
 
     def submit(self, patient: int, spec, table, *, storage="f32", x0=1.0, eps=1e-4, alpha=2.0, lambda0=0.0,
-               delta=1e-5, max_iter=20000, max_backtracks=60, fixed_iters=False, trials_per_pass=1) -> int:
+               delta=1e-5, max_iter=20000, max_backtracks=60, fixed_iters=False, trials_per_pass=1,
+               warm_start=False) -> int:
         """spec: a PhantomSpec building the patient's matrix when it is not
         resident (None to require a resident one); table: (nstruct, 4)."""
         rows = [imrt_penalty(*[float(v) for v in row]) for row in table]
@@ -589,7 +590,8 @@ class Server:
         req = imrt_request(int(patient), C.pointer(geom) if geom is not None else None, STORAGE[storage], pen,
                            len(rows), float(x0),
                            imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks,
-                                             int(bool(fixed_iters)), trials_per_pass, 0, 0, None))
+                                             int(bool(fixed_iters)), trials_per_pass, 0, int(bool(warm_start)),
+                                             None))
         return imrt_server_submit(self.handle, req)
 
     def wait(self, ticket: int, nb: int = 0):

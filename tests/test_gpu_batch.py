@@ -145,3 +145,13 @@ def test_repartition_and_autotune(ctx):
     # the start points were not modified by the search
     assert all(np.all(to_host(x0) == ST.x0) for x0 in xs)
     _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=2000)
+
+
+def test_warm_start_batch_bit_identical_to_solo(ctx):
+    from paper_0908_4421_amd.imrt import Dose
+    specs = [SMALL, TINY, draw_batch_instance(107)]
+    doses = [Dose.from_geometry(ctx, s) for s in specs]
+    plans = [_plan(ctx, d, penalty_table(s)) for d, s in zip(doses, specs)]
+    lams = [_lambda0(p, d, s.seed) for p, d, s in zip(plans, doses, specs)]
+    solo, _ = _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=1500, warm_start=True)
+    banner(f"warm start: iterations {[r.iterations for r, _, _ in solo]}")

@@ -213,3 +213,47 @@ def test_empty_matrix(ctx):
     with pytest.raises(imrt.ImrtError) as e:
         plan.lambda0(to_dev(np.ones(nb, np.float32)), 50)
     assert e.value.code == imrt.IMRT_EINVAL
+
+
+@pytest.mark.parametrize("nt", [1, 2, 4])
+def test_warm_start_one_voxel_exact(ctx, nt):
+    """The warm-start variant (iteration k+1 starts at alpha times the
+    accepted step) on D = [1], threshold 4: the oracle's closed-form
+    trajectories, bit for bit (all values dyadic)."""
+    D = np.array([[1.0]], dtype=np.float32)
+    lib, plan = _plan_from_csr(ctx, D, np.zeros(1, np.uint8), [(4.0, 4.0, 1.0, 1.0)])
+    x = to_dev(np.zeros(1, np.float32))
+    res, tr = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=0.125, max_iter=50, trials_per_pass=nt, trace=True,
+                         warm_start=True)
+    assert res.status == 0 and res.iterations == 3
+    assert tr == [(1, 0, 0.125, 1.0, 9.0), (2, 0, 0.25, 2.25, 2.25), (3, 0, 0.5, 2.25, 0.0)]
+    assert to_host(x)[0] == 4.0
+    x = to_dev(np.zeros(1, np.float32))
+    res, tr = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=0.75, max_iter=3, fixed_iters=True, trials_per_pass=nt,
+                         trace=True, warm_start=True)
+    assert tr == [(1, 0, 0.75, 36.0, 4.0), (2, 1, 0.75, 9.0, 1.0), (3, 1, 0.75, 2.25, 0.25)]
+    assert to_host(x)[0] == 4.5
+    # one pass per trial group: 1 initial + 1 + 2 + 2 with one trial per pass
+    assert res.forward_passes == 1 + sum(-(-(m + 1) // nt) for m in (0, 1, 1))
+
+
+@pytest.mark.parametrize("nt", [1, 2])
+def test_warm_start_tiny_phantom(tiny, nt):
+    D, lib, plan, pen, lam0 = tiny
+    x1 = np.ones(D.nb)
+    ref = solver.solve(D.csr, pen, x1, eps=1e-4, alpha=2.0, lambda0=lam0, max_iter=120, fixed_iters=True,
+                       warm_start=True)
+    assert sum(e.backtracks for e in ref.trace) > 0      # the doubled steps do get rejected
+    x = to_dev(x1.astype(np.float32))
+    res, tr = plan.solve(x, eps=1e-4, alpha=2.0, lambda0=lam0, max_iter=120, fixed_iters=True,
+                         trials_per_pass=nt, trace=True, warm_start=True)
+    # the same steps, backtracks and objective; the step norms are squared
+    # differences of float32 iterates, and the overshooting trials of the
+    # warm start make them follow the iterates' float32 rounding more
+    # closely than the cold start's (1e-3 instead of 1e-4)
+    assert len(tr) == len(ref.trace)
+    for (k, m, lam, s, G), e in zip(tr, ref.trace):
+        assert k == e.k and m == e.backtracks and lam == e.lam, (k, m, e.backtracks)
+        assert abs(G - e.G) <= 1e-6 * abs(e.G), (k, G, e.G)
+        assert abs(s - e.step_sq) <= 1e-3 * e.step_sq + 1e-30, (k, s, e.step_sq)
+    assert abs(res.G_final - ref.G) <= 1e-6 * ref.G
