@@ -1091,6 +1091,9 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   for (float v : xh)
     if (!(v >= 0.0f) || !std::isfinite(v)) return set_error(IMRT_EINVAL, "x_1 must be finite and >= 0");
   if ((rc = ensure_buffers(P, nt + 1))) return rc;
+  // the iterate buffers other than x_1's start zeroed (the forward pass
+  // blends all candidates with 0/1 weights, so none may be non-finite)
+  for (int j = 1; j <= nt; ++j) IMRT_HIP(hipMemsetAsync(P->xbuf[j], 0, sizeof(float) * D->nb, s));
   const int cap = prm->trace ? prm->max_iter : 0;
   if (cap > P->trace_cap) {
     dev_free(P->trace);

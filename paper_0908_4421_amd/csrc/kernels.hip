@@ -697,7 +697,15 @@ __device__ __forceinline__ void trial_store(const FwdArgs& a, int i0, const Tria
     if (i >= nb) continue;
     float x = R.xc[0][u];
 #pragma unroll
-    for (int j = 1; j <= NT; ++j) x = (T.xi == j) ? R.xc[j][u] : x;
+    // x_k is the candidate the state names.  Blended with exact 0/1 weights
+    // rather than selected: a select among elements of the candidate array
+    // becomes an indexed load from a stack copy of it (scratch memory).  The
+    // candidates are finite: each solve starts with the other iterate
+    // buffers zeroed, and a non-finite trial ends the solve.
+    for (int j = 1; j <= NT; ++j) {
+      const float c = (T.xi == j) ? 1.0f : 0.0f;
+      x = x * (1.0f - c) + R.xc[j][u] * c;
+    }
     if (T.init) {
 #pragma unroll
       for (int q = 0; q < NT; ++q) xs[q * nbp + i] = !coded(ST) ? x : x * R.sc[u];
