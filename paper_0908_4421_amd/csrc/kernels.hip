@@ -1103,10 +1103,10 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
 }
 
 // Waves of a wave-granular forward workgroup: sixteen (one workgroup per
-// compute unit) for one trial, eight for more (LDS).
+// compute unit) for one or two trials, eight for four (registers).
 template <int NT>
 struct FwdWaves {
-  static constexpr int value = (NT == 1) ? 16 : 8;
+  static constexpr int value = (NT <= 2) ? 16 : 8;
 };
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
@@ -1671,7 +1671,7 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
                  static_cast<size_t>(ntrials) * nbp * sizeof(float);
   if (wave) {
-    const size_t waves = (ntrials == 1) ? 16 : 8;
+    const size_t waves = static_cast<size_t>(forward_waves(ntrials));
     bytes += (waves * ntrials * wave_nnz(storage) + kWaveSlack) * sizeof(float);
     bytes += (2 * (kMetaChunk + 1) + 2) * sizeof(int32_t) + static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
   } else {
@@ -1681,7 +1681,7 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
   return bytes;
 }
 
-int forward_waves(int ntrials) { return ntrials == 1 ? 16 : 8; }
+int forward_waves(int ntrials) { return ntrials <= 2 ? 16 : 8; }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials) {
   if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials, D->fwd_bpw);
@@ -1711,7 +1711,7 @@ int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipS
   if (a.mode == FWD_SOLVE) {
     switch (ntrials) {
       case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a); break;
-      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
+      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a); break;
       case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
       default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
     }
@@ -1733,7 +1733,7 @@ int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslot
   const dim3 gd(nslots);
   switch (ntrials) {
     case 1: hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots); break;
-    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots); break;
     case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
