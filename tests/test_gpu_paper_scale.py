@@ -140,4 +140,5 @@ def _check_full_solve(built, fx):
         z = float(v.astype(np.float64) @ xg[c])
         zmax = max(zmax, abs(z))
         err = max(err, abs(d[j] - z) / max(abs(z), 1e-30))
+    banner(f"paper-scale: worst G error {worst:.2e} over {n} iterations, dose error {err:.2e} (200 voxels)")
     assert err <= 1e-5
