@@ -102,12 +102,19 @@ def test_full_solve_trajectory_block_forward(built, fx):
     _check_full_solve((ctx, dose, plan, built[3]), fx)
 
 
-def _check_full_solve(built, fx):
+def test_full_solve_trajectory_two_trials(built, fx):
+    """The same with two trial steps per forward pass (16-wave workgroups):
+    the trajectory does not depend on how the trials are grouped."""
+    banner("paper-scale solve, two trials per pass")
+    _check_full_solve(built, fx, nt=2)
+
+
+def _check_full_solve(built, fx, nt=1):
     ctx, dose, plan, ex = built
     st = PAPER_SCALE_SETTINGS
     x = to_dev(start_point(dose.nb, st).astype(np.float32))
     res, tr = plan.solve(x, eps=st.eps, alpha=st.alpha, lambda0=fx["lambda0"], delta=st.delta,
-                         max_iter=st.max_iter, max_backtracks=st.max_backtracks, trace=True)
+                         max_iter=st.max_iter, max_backtracks=st.max_backtracks, trace=True, trials_per_pass=nt)
     banner(f"paper-scale solve: {res.iterations} iterations, {res.device_ms:.1f} ms")
     assert res.status == 0
     assert abs(res.G_initial - fx["G_initial"]) <= 1e-6 * fx["G_initial"]
