@@ -155,3 +155,21 @@ def test_warm_start_batch_bit_identical_to_solo(ctx):
     lams = [_lambda0(p, d, s.seed) for p, d, s in zip(plans, doses, specs)]
     solo, _ = _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=1500, warm_start=True)
     banner(f"warm start: iterations {[r.iterations for r, _, _ in solo]}")
+
+
+def test_full_batch_workload_bit_identical_to_solo(ctx):
+    """The benchmark's batched re-plan workload at full size (32 instances,
+    seeds 100-131, 40 M nonzeros) with the partition the launch-shape search
+    picks: every plan bit-identical to its solo solve on that partition."""
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    from workloads import batch_instances
+    specs = batch_instances(100, 32)
+    doses = [Dose.from_geometry(ctx, s) for s in specs]
+    banner(f"full batch: {sum(d.nnz for d in doses)} nonzeros")
+    plans = [_plan(ctx, d, penalty_table(s)) for d, s in zip(doses, specs)]
+    lams = [_lambda0(p, d, s.seed) for p, d, s in zip(plans, doses, specs)]
+    xs = [to_dev(np.full(d.nb, ST.x0, np.float32)) for d in doses]
+    part = Plan.autotune_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=lams, delta=ST.delta, tune_iters=20)
+    banner(f"full batch partition {part}")
+    solo, _ = _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=ST.max_iter)
+    assert all(r.status == 0 for r, _, _ in solo)
