@@ -129,3 +129,29 @@ def test_storage_change_waits_for_the_live_mix(ctx):
     # admitted one after the other (arrivals lie within a millisecond)
     assert got[1][1].queue_ms >= got[0][1].plan_ms - 1.0
     assert got[2][1].queue_ms >= got[1][1].plan_ms - 1.0
+
+
+def test_served_workload_mix_equals_alone(ctx):
+    """24 requests of the served re-plan workload (bfloat16 matrices, 30 %
+    re-plans of resident patients with new thresholds) submitted at once:
+    every plan equals the same plan solved alone."""
+    from paper_0908_4421_amd.imrt import Dose, Server
+    from workloads import served_requests
+    reqs = served_requests(20.0, 24, seed=200)
+    part = (ctx.get_option("serve_adj_min_nnz"), ctx.get_option("serve_fwd_blocks_per_wave"))
+    srv = Server(ctx, budget_bytes=16 << 30, max_live=64)
+    tickets = [srv.submit(r.patient, r.spec, r.table, storage="bf16", max_iter=20000) for r in reqs]
+    got = [srv.wait(tk, 0) for tk in tickets]
+    st = srv.stats()
+    srv.close()
+    banner(f"served mix: {sum(r.replan for r in reqs)} re-plans, {st['resident_matrices']} matrices, "
+           f"iterations {[g[0].iterations for g in got]}")
+    doses = {}
+    for r, (res, times, _) in zip(reqs, got):
+        if r.patient not in doses:
+            d = Dose.from_geometry(ctx, r.spec, storage="bf16")
+            d.repartition(*part)
+            doses[r.patient] = d
+        ref, _ = _alone(ctx, doses[r.patient], r.table, times.lambda0, max_iter=20000)
+        assert (res.iterations, res.status) == (ref.iterations, ref.status)
+        assert res.G_final == ref.G_final
