@@ -126,9 +126,11 @@ def test_storage_change_waits_for_the_live_mix(ctx):
         ref, _ = _alone(ctx, d, penalty_table(sp), times.lambda0, max_iter=400, fixed=True)
         assert res.iterations == ref.iterations == 400
         assert res.G_final == ref.G_final
-    # admitted one after the other (arrivals lie within a millisecond)
-    assert got[1][1].queue_ms >= got[0][1].plan_ms - 1.0
-    assert got[2][1].queue_ms >= got[1][1].plan_ms - 1.0
+    # admitted one after the other (the three arrivals lie within a few
+    # milliseconds: submission only queues the request)
+    gap = 20.0
+    assert got[1][1].queue_ms >= got[0][1].plan_ms - gap
+    assert got[2][1].queue_ms >= got[1][1].plan_ms - gap
 
 
 def test_served_workload_mix_equals_alone(ctx):
