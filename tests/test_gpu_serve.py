@@ -128,7 +128,7 @@ def test_storage_change_waits_for_the_live_mix(ctx):
         assert res.G_final == ref.G_final
     # admitted one after the other (the three arrivals lie within a few
     # milliseconds: submission only queues the request)
-    gap = 20.0
+    gap = 5.0
     assert got[1][1].queue_ms >= got[0][1].plan_ms - gap
     assert got[2][1].queue_ms >= got[1][1].plan_ms - gap
 
