@@ -155,7 +155,7 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 /* Launch-shape settings of a context, by name:
  *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (1..64; default
  *                    1).  A "fwd_wave" workgroup has 16 waves (8 when a pass
- *                    tries several step sizes) that take row blocks from a
+ *                    tries four step sizes) that take row blocks from a
  *                    shared counter; otherwise the value is scaled by four
  *                    workgroups of 4 waves.
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (1..64)
@@ -175,9 +175,14 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    and 4)
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
+ *   "fwd_col16"      1 (default): float32 matrices with nb <= 65536 created
+ *                    afterwards keep a 16-bit copy of the CSR column indices,
+ *                    which the wave forward pass reads (6 instead of 8 bytes
+ *                    per nonzero, 768-entry row blocks); 0: 32-bit indices
  *   "batch_iters"    solver iterations enqueued between host polls (>= 1)
- * "adj_wg_per_cu", "adj_min_nnz", "fwd_blocks_per_wave" and "fwd_wg_per_cu"
- * are read when a dose matrix is created (its work partitions);
+ * "adj_wg_per_cu", "adj_min_nnz", "fwd_blocks_per_wave", "fwd_col16" and
+ * "fwd_wg_per_cu" are read when a dose matrix is created (its work
+ * partitions and layout);
  * "fwd_wg_per_cu" and "adj_wg_per_cu" also at launch.
  * Results are deterministic for given settings; the settings change only the
  * grouping of the float32 row sums and of the float64 partial sums of G and
