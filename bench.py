@@ -710,8 +710,8 @@ def main():
         "config": {"workload": spec.name, "nv": nv, "nb": nb, "nnz": nnz, "delta": st.delta,
                    "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
                    "trials_per_pass": args.trials_per_pass,
-                   "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz", "fwd_col16",
-                                                             "batch_iters", "fwd_wave", "adj_xcd")}},
+                   "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz",
+                                                             "fwd_col16", "batch_iters", "fwd_wave", "adj_xcd")}},
         "iterations": res.iterations,
         "iters_per_s": res.iterations / (ms_per_step / 1e3),
         "forward_passes": res.forward_passes,
