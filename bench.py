@@ -408,6 +408,73 @@ def read_probe(ctx, gib=4, reps=5):
     return gbs
 
 
+def tile_order(nx, ny, nz, tx=4, ty=4, tz=2):
+    """Grid voxel indices in tiles of tx x ty x tz voxels (x fastest inside a
+    tile, tiles in x, y, z order): the row order of a built phantom."""
+    import numpy as np
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    key = (((z // tz) * ((ny + ty - 1) // ty) + y // ty) * ((nx + tx - 1) // tx) + x // tx)
+    inner = ((z % tz) * ty + y % ty) * tx + x % tx
+    j = (x + nx * (y + ny * z)).ravel()
+    return j[np.lexsort((inner.ravel(), key.ravel()))]
+
+
+def shard_form(ctx, dose, spec, iters=100):
+    """One GPU's share of a plan sharded by voxel rows over G GPUs (G = 2, 4,
+    8): contiguous row ranges of the tile order holding equal numbers of
+    nonzeros; the share with the most nonzeros, with its voxels' structures
+    and penalties, solved as its own plan for a fixed number of iterations;
+    the mean duration of its forward and adjoint passes (HIP events around
+    every 7th launch), against the whole matrix solved the same way.  The
+    all-reduces of G and g a sharded solve adds are not part of it."""
+    import numpy as np
+    import torch
+
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    from workloads import penalty_table
+    ex = dose.export(structures=True)
+    nv, nb = dose.nv, dose.nb
+    rp = ex["row_ptr"].astype(np.int64)
+    lens = np.diff(rp)
+    order = tile_order(spec.nx, spec.ny, spec.nz)
+    table = penalty_table(spec)
+
+    def measure(d, sid):
+        p = Plan(ctx, d)
+        p.set_structures(sid, len(table))
+        p.set_penalties(table)
+        x = torch.ones(d.nb, dtype=torch.float32, device="cuda")
+        kw = dict(eps=1e-4, alpha=2.0, lambda0=2.0 ** -11, max_iter=iters, fixed_iters=True, profile=7)
+        p.solve(x, **kw)
+        x.fill_(1.0)
+        res, _ = p.solve(x, **kw)
+        tf, ta = 1e3 * res.forward_kernel_ms, 1e3 * res.adjoint_kernel_ms
+        bf = f32_forward(ctx, nb)[1](d.nv, nb, d.nnz)
+        ba = adjoint_bytes(d.nv, nb, d.nnz)
+        return {"rows": d.nv, "nnz": d.nnz, "forward_us": tf, "adjoint_us": ta,
+                "forward_GB_s": bf / (tf * 1e-6) / 1e9, "adjoint_GB_s": ba / (ta * 1e-6) / 1e9}
+
+    out = {"whole": measure(dose, None)}
+    for G in (2, 4, 8):
+        cum = np.concatenate([[0], np.cumsum(lens[order])])
+        bounds = [0] + [int(np.searchsorted(cum, g * cum[-1] / G)) for g in range(1, G)] + [nv]
+        nnz_g = [int(cum[bounds[g + 1]] - cum[bounds[g]]) for g in range(G)]
+        g = int(np.argmax(nnz_g))
+        rows = order[bounds[g]:bounds[g + 1]]
+        sl = lens[rows]
+        srp = np.zeros(len(rows) + 1, np.int64)
+        np.cumsum(sl, out=srp[1:])
+        idx = np.repeat(rp[rows] - srp[:-1], sl) + np.arange(srp[-1])
+        d = Dose.from_csr(ctx, len(rows), nb, srp.astype(np.int32), ex["col_idx"][idx], ex["val"][idx])
+        m = measure(d, ex["struct_id"][rows])
+        m["share_of_nnz"] = m["nnz"] / dose.nnz
+        out[f"{G}_gpus"] = m
+        d.close()
+        print(f"[bench] row share of {G} GPUs: {m['rows']} rows, {m['nnz']} nonzeros, forward "
+              f"{m['forward_us']:.1f} us, adjoint {m['adjoint_us']:.1f} us", file=sys.stderr, flush=True)
+    return out
+
+
 def _pct(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
@@ -616,6 +683,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--tune-iters", type=int, default=40,
                     help="iterations per candidate of the batch's launch-shape search (0: default partition)")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the timing of one GPU's row share of the plan")
     ap.add_argument("--no-shape", action="store_true",
                     help="skip the plan on the shape of the paper's largest scenario")
     ap.add_argument("--no-replan", action="store_true",
@@ -727,6 +796,8 @@ def main():
     }
     if not args.no_replan:
         out["replan"] = replan_form(ctx, plan, x, spec, st, args)
+    if not args.no_shard:
+        out["row_shards"] = shard_form(ctx, dose, spec)
     if not args.no_shape and args.workload == "paper":
         out["scenario3_shape"] = shape_form(ctx, args)
     forms = [f for f in args.forms.split(",") if f and f != "none"]
