@@ -710,8 +710,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs the solver on exactly one GPU; multi-GPU runs are not part of this build "
-              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs the solver on exactly one GPU and has no multi-GPU path; the row_shards object "
+              "of its output times one GPU's share of a plan sharded by voxel rows.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

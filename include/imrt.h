@@ -51,7 +51,7 @@ typedef enum {
   IMRT_ENOMEM = -2,      /* device or host allocation failed */
   IMRT_EHIP = -3,        /* a HIP runtime call failed; the message carries hipGetErrorString */
   IMRT_ENOTREADY = -4,   /* structures or penalties not set on the plan */
-  IMRT_EUNSUPPORTED = -5 /* valid request outside what this build supports (message says which limit) */
+  IMRT_EUNSUPPORTED = -5 /* valid request outside what the library supports (message says which limit) */
 } imrt_error;
 
 /* Final state of a solve (imrt_solve_result.status). */
@@ -279,10 +279,10 @@ IMRT_API int imrt_estimate_lambda0(imrt_plan* plan, const float* v0_dev, int32_t
 IMRT_API int imrt_solve(imrt_plan* plan, const imrt_solve_params* params, float* x_dev,
                imrt_solve_result* result);
 
-/* Batched solve of n plans (SURVEY's batched re-plan form; the method of
- * Section 2.2 run for several independent plans at once).  The plans must be
+/* Batched solve of n plans (the method of Section 2.2 run for several
+ * independent plans at once, e.g. re-plans of several patients).  The plans must be
  * distinct and share one context; their dose matrices must have one storage
- * and the params one trials_per_pass; several plans may share a dose matrix.
+ * and forward layout and the params one trials_per_pass; several plans may share a dose matrix.
  * Each plan is solved exactly as imrt_solve solves it alone -- the same
  * passes, work partitions and reduction orders, so its result is
  * bit-identical -- but every forward and every adjoint pass of the batch is
