@@ -173,6 +173,10 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *   "serve_adj_min_nnz", "serve_fwd_blocks_per_wave"  the same two for the
  *                    matrices of servers created afterwards (defaults 32768
  *                    and 4)
+ *   "serve_groups_per_poll"  (adjoint, forward) dispatch groups a server
+ *                    created afterwards runs between polls (1..4096,
+ *                    default 16): more groups poll less often, fewer admit
+ *                    and retire sooner
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "fwd_col16"      1 (default): float32 matrices with nb <= 65536 created

@@ -513,6 +513,7 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     return &ctx->tune.serve_adj_min_nnz;
   }
   if (n == "serve_fwd_blocks_per_wave") return &ctx->tune.serve_fwd_bpw;
+  if (n == "serve_groups_per_poll") return &ctx->tune.serve_groups;
   if (n == "adj_xcd") {
     *lo = 0;
     return &ctx->tune.adj_xcd;
@@ -534,6 +535,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles" || nm == "fwd_col16") ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
                      : (nm == "fwd_blocks_per_wave" || nm == "serve_fwd_blocks_per_wave") ? 1024
+                     : (nm == "serve_groups_per_poll")                                      ? 4096
                                                                                  : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);

@@ -174,6 +174,7 @@ struct Tuning {
   int fwd_col16 = 1;           // float32 matrices with nb <= 65536: 16-bit CSR columns for the forward
   int serve_adj_min_nnz = 32768;   // the same two for matrices a server builds, which
   int serve_fwd_bpw = 4;           // share every dispatch with other live plans
+  int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
 };
 
 }  // namespace imrt

@@ -286,7 +286,7 @@ void worker_main(imrt_server* S) {
   (void)hipSetDevice(S->ctx.device);
   imrt_ctx* C = &S->ctx;
   hipStream_t s = C->stream;
-  const int K = 8;   // groups between polls: bounds the wait of a new request
+  const int K = std::max(1, S->ctx.tune.serve_groups);   // groups between polls: bounds a new request's wait
   std::vector<SolverState> seen(2 * static_cast<size_t>(S->max_live));
   std::vector<int32_t> fs, as;
   for (;;) {
