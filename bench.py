@@ -561,37 +561,72 @@ def serve_form(ctx, args):
     return out
 
 
-def cpu_baseline(spec, st, lam0, gpu_iterations, sample_iters):
-    """The FP64 oracle on the host: lambda_0 estimate plus `sample_iters`
-    iterations, scaled to the GPU's iteration count."""
+def cpu_baseline_child(workload, repeats):
+    """The FP64 oracle on the host: lambda_0 estimate plus a full solve of the
+    workload to the stopping rule, on one core.
+
+    Runs in a fresh interpreter that never touches the GPU (bench.py starts it
+    before its own first GPU call), so the oracle's dose-matrix build may use
+    a process pool; the timed part then runs pinned to one core with one
+    BLAS/OpenMP thread.  Prints one JSON object."""
+    import statistics
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import model, phantom, solver
-    from workloads import penalty_table, power_start_vector, start_point
-
-    D = phantom.build_dose_matrix(spec, workers=min(spec.n_beams, os.cpu_count() or 1))
+    from workloads import NAMED, PAPER_SCALE_SETTINGS, TINY_SETTINGS, penalty_table, power_start_vector, \
+        start_point
+    spec = NAMED[workload]
+    st = TINY_SETTINGS if workload == "tiny" else PAPER_SCALE_SETTINGS
+    t = time.perf_counter()
+    D = phantom.build_dose_matrix(spec, workers=min(spec.n_beams, 16, os.cpu_count() or 1))
+    build_s = time.perf_counter() - t
     pen = model.VoxelPenalties.from_structures(D.struct_id, penalty_table(spec))
+    core = min(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {core})
+    runs = []
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        lam_ref, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, spec.seed),
-                                                         st.power_iters)
-        t1 = time.perf_counter()
-        ref = solver.solve(D.csr, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam_ref,
-                           max_iter=sample_iters, max_backtracks=st.max_backtracks, fixed_iters=True,
-                           keep_trace=False)
-        t2 = time.perf_counter()
-    per_iter = (t2 - t1) / max(ref.iterations, 1)
-    est = (t1 - t0) + per_iter * gpu_iterations
-    return {
-        "value": est, "unit": "s", "cores": 1, "kind": "oracle",
-        "sample": (f"lambda_0 estimate ({st.power_iters} power iterations, {t1 - t0:.2f} s) plus "
-                   f"{ref.iterations} of the plan's iterations ({t2 - t1:.2f} s), scaled to the GPU's "
-                   f"{gpu_iterations} iterations; scipy.sparse float64, one thread"),
-        "lambda0_matches": lam_ref == lam0,
+        for _ in range(max(1, repeats)):
+            t0 = time.perf_counter()
+            lam_ref, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, spec.seed),
+                                                             st.power_iters)
+            t1 = time.perf_counter()
+            ref = solver.solve(D.csr, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam_ref,
+                               delta=st.delta, max_iter=st.max_iter, max_backtracks=st.max_backtracks,
+                               fixed_iters=st.fixed_iters, keep_trace=False)
+            t2 = time.perf_counter()
+            runs.append((t2 - t0, t1 - t0, ref.iterations, ref.G))
+    total = statistics.median(r[0] for r in runs)
+    print(json.dumps({
+        "value": total, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"{len(runs)} full plan(s) of {spec.name} (median): lambda_0 estimate ({st.power_iters} power "
+                   f"iterations, {runs[-1][1]:.2f} s) plus the solve to the stopping rule, {runs[-1][2]} "
+                   f"iterations; scipy.sparse float64, one thread pinned to one core; the oracle's matrix "
+                   f"build ({build_s:.1f} s, process pool) not timed"),
+        "oracle_iterations": runs[-1][2],
+        "oracle_G_final": runs[-1][3],
+        "lambda0": lam_ref,
+        "runs_s": [r[0] for r in runs],
         "host_cpu": _cpu_model(),
         "host_nproc": os.cpu_count(),
-    }
+    }), flush=True)
+
+
+def cpu_baseline(workload, repeats):
+    """Run cpu_baseline_child in a child interpreter and return its JSON."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload,
+           "--cpu-repeats", str(repeats)]
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    print(f"[bench] cpu baseline: the oracle on one host core ({workload})", file=sys.stderr, flush=True)
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed ({out.returncode}):\n{out.stderr[-2000:]}")
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    print(f"[bench] cpu baseline: {res['value']:.2f} s per plan, {res['oracle_iterations']} iterations",
+          file=sys.stderr, flush=True)
+    return res
 
 
 def kernel_source_hash():
@@ -676,8 +711,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "small", "scenario3"])
     ap.add_argument("--trials-per-pass", type=int, default=1)
-    ap.add_argument("--cpu-sample-iters", type=int, default=100)
+    ap.add_argument("--cpu-repeats", type=int, default=1,
+                    help="full oracle plans timed for the CPU baseline (median); one takes about 20 s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=32, metavar="N",
                     help="also time the batched re-plan workload of N uneven instances (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -708,11 +745,18 @@ def main():
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc)
         return
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args.workload, args.cpu_repeats)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs the solver on exactly one GPU and has no multi-GPU path; the row_shards object "
               "of its output times one GPU's share of a plan sharded by voxel rows.", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle runs first, in a child interpreter, before this process
+    # touches the GPU
+    cpu = None if (args.no_cpu_baseline or args.copy_calibration) else cpu_baseline(args.workload, args.cpu_repeats)
 
     import numpy as np
     import torch
@@ -807,8 +851,9 @@ def main():
         out["batch"] = batch_form(ctx, args)
     if args.serve_rates or args.serve_burst > 0:
         out["serve"] = serve_form(ctx, args)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, st, lam0, res.iterations, args.cpu_sample_iters)
+    if cpu is not None:
+        cpu["lambda0_matches"] = cpu["lambda0"] == lam0
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

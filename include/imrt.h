@@ -51,7 +51,8 @@ typedef enum {
   IMRT_ENOMEM = -2,      /* device or host allocation failed */
   IMRT_EHIP = -3,        /* a HIP runtime call failed; the message carries hipGetErrorString */
   IMRT_ENOTREADY = -4,   /* structures or penalties not set on the plan */
-  IMRT_EUNSUPPORTED = -5 /* valid request outside what the library supports (message says which limit) */
+  IMRT_EUNSUPPORTED = -5,/* valid request outside what the library supports (message says which limit) */
+  IMRT_ETIMEDOUT = -6    /* a bounded wait ended before its result was ready */
 } imrt_error;
 
 /* Final state of a solve (imrt_solve_result.status). */
@@ -367,12 +368,15 @@ typedef struct {
 IMRT_API int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_live, imrt_server** out);
 /* Queue a request (thread-safe, returns at once with a ticket > 0). */
 IMRT_API int imrt_server_submit(imrt_server* server, const imrt_request* request, int64_t* ticket_out);
-/* Block until the ticket's solve finished; x_out (nullable host array of nb
- * floats) receives its plan.  A failed request returns its error.  Each
- * ticket can be waited on once (IMRT_EINVAL for an unknown ticket or a
- * second wait). */
+/* Wait at most timeout_ms milliseconds (> 0) for the ticket's solve; x_out
+ * (nullable host array of nb floats) receives its plan.  A failed request
+ * returns its error.  When the time runs out first the call returns
+ * IMRT_ETIMEDOUT and the ticket stays pending (it may be waited on again);
+ * the device work of the live solves is not affected.  A ticket's result is
+ * handed out once (IMRT_EINVAL for an unknown ticket, for a ticket already
+ * handed out, or while another thread waits on it). */
 IMRT_API int imrt_server_wait(imrt_server* server, int64_t ticket, float* x_out, int32_t nb,
-                              imrt_solve_result* result, imrt_serve_times* times);
+                              imrt_solve_result* result, imrt_serve_times* times, int64_t timeout_ms);
 IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t* peak_bytes,
                                int64_t* resident_matrices, int64_t* served);
 /* Finishes the queued and live requests, then frees everything. */

@@ -186,11 +186,14 @@ def build_dose_matrix(spec: PhantomSpec, workers: int = 1) -> DoseMatrix:
     """Brute-force D for the whole phantom, in CSC then CSR (indices sorted).
 
     ``workers`` > 1 evaluates the beams in separate processes; each column is
-    computed by the same code either way.
+    computed by the same code either way.  The workers are fresh interpreters
+    (the "spawn" start method), never forks: a fork of a process that holds a
+    GPU runtime can inherit a lock held by one of its threads and never
+    finish, so the pool must not copy the caller's state.
     """
     if workers > 1 and spec.n_beams > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, spec.n_beams)) as pool:
+        with mp.get_context("spawn").Pool(min(workers, spec.n_beams)) as pool:
             per_beam = pool.map(_columns_of_beam, [(spec, b) for b in range(spec.n_beams)])
         bls = beamlets(spec)
         cols = [c for group in per_beam for c in group]

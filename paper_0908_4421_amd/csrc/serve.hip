@@ -496,15 +496,22 @@ int imrt_server_submit(imrt_server* S, const imrt_request* r, int64_t* ticket_ou
 }
 
 int imrt_server_wait(imrt_server* S, int64_t ticket, float* x_out, int32_t nb, imrt_solve_result* result,
-                     imrt_serve_times* times) {
+                     imrt_serve_times* times, int64_t timeout_ms) {
   if (!S) return set_error(IMRT_EINVAL, "server is NULL");
+  if (timeout_ms <= 0) return set_error(IMRT_EINVAL, "timeout_ms must be positive");
   Finished f;
   {
     std::unique_lock<std::mutex> lk(S->mu);
     if (ticket <= 0 || ticket >= S->next_ticket) return set_error(IMRT_EINVAL, "unknown ticket");
-    if (S->delivered.count(ticket)) return set_error(IMRT_EINVAL, "ticket already waited on");
+    if (S->delivered.count(ticket)) return set_error(IMRT_EINVAL, "ticket already handed out or being waited on");
     S->delivered.insert(ticket);   // (a second waiter on the same ticket is turned away)
-    S->cv_done.wait(lk, [&] { return S->finished.count(ticket) != 0; });
+    const bool ready = S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                                           [&] { return S->finished.count(ticket) != 0; });
+    if (!ready) {
+      S->delivered.erase(ticket);  // still pending: a later wait may collect it
+      return set_error(IMRT_ETIMEDOUT, "ticket " + std::to_string(ticket) + " not finished after " +
+                                           std::to_string(timeout_ms) + " ms");
+    }
     f = std::move(S->finished[ticket]);
     S->finished.erase(ticket);
   }

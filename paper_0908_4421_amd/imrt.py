@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("IMRT_LIBRARY") or os.path.join(_HERE, "libimrt.so")
 
 # ---- error / status codes (imrt.h) ------------------------------------------
-IMRT_OK, IMRT_EINVAL, IMRT_ENOMEM, IMRT_EHIP, IMRT_ENOTREADY, IMRT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+IMRT_OK, IMRT_EINVAL, IMRT_ENOMEM, IMRT_EHIP, IMRT_ENOTREADY, IMRT_EUNSUPPORTED, IMRT_ETIMEDOUT = (
+    0, -1, -2, -3, -4, -5, -6)
 IMRT_CONVERGED, IMRT_MAX_ITER, IMRT_STALLED, IMRT_LS_FAIL, IMRT_NUMERIC = 0, 1, 2, 3, 4
 IMRT_F32, IMRT_BF16, IMRT_F16 = 0, 1, 2
 STORAGE = {"f32": IMRT_F32, "bf16": IMRT_BF16, "f16": IMRT_F16}
@@ -112,7 +113,7 @@ SIGNATURES = {
     "imrt_server_create": (C.c_int, [_vp, C.c_int64, C.c_int32, C.POINTER(_vp)]),
     "imrt_server_submit": (C.c_int, [_vp, C.POINTER(imrt_request), C.POINTER(C.c_int64)]),
     "imrt_server_wait": (C.c_int, [_vp, C.c_int64, _f32p, C.c_int32, C.POINTER(imrt_solve_result),
-                                   C.POINTER(imrt_serve_times)]),
+                                   C.POINTER(imrt_serve_times), C.c_int64]),
     "imrt_server_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),
     "imrt_server_destroy": (C.c_int, [_vp]),
@@ -271,10 +272,10 @@ def imrt_server_submit(server, request: "imrt_request") -> int:
     return t.value
 
 
-def imrt_server_wait(server, ticket: int, x_out=None, nb: int = 0):
+def imrt_server_wait(server, ticket: int, x_out=None, nb: int = 0, timeout_ms: int = 120000):
     res, times = imrt_solve_result(), imrt_serve_times()
     _check(load().imrt_server_wait(server, int(ticket), _host(x_out, C.c_float), int(nb), C.byref(res),
-                                   C.byref(times)), "imrt_server_wait")
+                                   C.byref(times), int(timeout_ms)), "imrt_server_wait")
     return res, times
 
 
@@ -594,11 +595,13 @@ class Server:
                                              None))
         return imrt_server_submit(self.handle, req)
 
-    def wait(self, ticket: int, nb: int = 0):
-        """(result, times, x as a numpy array or None when nb == 0)."""
+    def wait(self, ticket: int, nb: int = 0, timeout_s: float = 120.0):
+        """(result, times, x as a numpy array or None when nb == 0).  Raises
+        ImrtError with code IMRT_ETIMEDOUT when the plan is not ready within
+        timeout_s seconds (the ticket stays pending)."""
         import numpy as np
         x = np.empty(nb, np.float32) if nb else None
-        res, times = imrt_server_wait(self.handle, ticket, x, nb)
+        res, times = imrt_server_wait(self.handle, ticket, x, nb, max(1, int(timeout_s * 1e3)))
         return res, times, x
 
     def stats(self):

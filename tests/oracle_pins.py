@@ -92,3 +92,31 @@ def armijo_trace_errors(D, pen, x1, res, eps, alpha, lambda0):
             bad.append((e.k, -1, "G not decreasing"))
         x, G = xt, Gt
     return bad
+
+
+def kkt_closed_form_errors():
+    """The projected-gradient residual |x - max(0, x - grad G(x))| of one-voxel,
+    one-beamlet problems against its value worked by hand.
+
+    With D = [d], G(x) = w_u min(dx - T_u, 0)^2 + w_o max(dx - T_o, 0)^2 and
+    grad G = 2 d r.  Cases (d, T_u, T_o, w_u, w_o, x, residual):
+      under-dosed at 0: r = -2, g = -4, max(0, 4) = 4          -> 4
+      over-dosed at 3:  r = 1,  g = 2,  max(0, 1) = 1          -> 2
+      over-only at 0.5: g = 2 * 0.5 = 1, max(0, -0.5) = 0      -> 0.5
+      inside [T_u, T_o] at 2.5 (d = 2: dose 5 in [4, 6]): g = 0 -> 0
+      d = 0.5, two-sided T = 1, w = 2, x = 1: dose 0.5, r = -1,
+      g = -1, max(0, 2) = 2                                    -> 1
+    Returns the cases whose residual differs by more than 1e-15."""
+    cases = [(1.0, 2.0, 2.0, 1.0, 1.0, 0.0, 4.0),
+             (1.0, 2.0, 2.0, 1.0, 1.0, 3.0, 2.0),
+             (1.0, 0.0, 0.0, 0.0, 1.0, 0.5, 0.5),
+             (2.0, 4.0, 6.0, 1.0, 1.0, 2.5, 0.0),
+             (0.5, 1.0, 1.0, 2.0, 2.0, 1.0, 1.0)]
+    bad = []
+    for d, Tu, To, wu, wo, x, want in cases:
+        D = sp.csr_matrix(np.array([[d]], np.float32))
+        pen = model.VoxelPenalties(np.array([Tu]), np.array([To]), np.array([wu]), np.array([wo]))
+        got = solver.kkt_residual(D, pen, np.array([x]))
+        if abs(got - want) > 1e-15:
+            bad.append((d, Tu, To, wu, wo, x, got, want))
+    return bad

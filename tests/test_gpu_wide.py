@@ -22,7 +22,7 @@ def ctx(request):
 
 @pytest.fixture(scope="module")
 def wide():
-    D = phantom.build_dose_matrix(WIDE, workers=4)
+    D = phantom.build_dose_matrix(WIDE)
     pen = model.VoxelPenalties.from_structures(D.struct_id, penalty_table(WIDE))
     lam0, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, WIDE.seed))
     ref = solver.solve(D.csr, pen, np.ones(D.nb), eps=1e-4, alpha=2.0, lambda0=lam0, max_iter=60,

@@ -187,3 +187,58 @@ def test_tiny_shape_statistics():
     assert abs((lens > 0).mean() - 0.682) < 0.001
     cl = np.diff(D.csc.indptr)
     assert int(cl.min()) == 640 and int(cl.max()) == 806
+
+
+# An odd-sized grid with an odd number of beams (three: 0, 120, 240 degrees),
+# so that no beam is axis-aligned but the first.
+ODD = PhantomSpec(name="odd_17x13x9_5mm_3field", nx=17, ny=13, nz=9, h=5.0, r_ptv=12.5,
+                  r_rectum=5.0, r_bladder=7.5, n_beams=3, beamlet=5.0, sigma=3.0, tau=0.01)
+
+
+@pytest.mark.parametrize("spec", [TINY, SMALL, ODD], ids=lambda s: s.name)
+def test_dose_rows_equal_the_matrix_rows(spec):
+    """dose_rows (rows of D evaluated voxel by voxel, given every beamlet's
+    e_min) gives exactly the rows of the column-built matrix, for every row:
+    the same kept beamlets and bit-identical float32 values."""
+    D = phantom.build_dose_matrix(spec)
+    emin = phantom.column_minima(spec)
+    rows = phantom.dose_rows(spec, np.arange(spec.nv), emin)
+    csr = D.csr
+    for j, (cols, vals) in enumerate(rows):
+        lo, hi = csr.indptr[j], csr.indptr[j + 1]
+        assert np.array_equal(cols, csr.indices[lo:hi]), j
+        assert vals.dtype == np.float32 and np.array_equal(vals, csr.data[lo:hi]), j
+
+
+@pytest.mark.parametrize("spec", [TINY, SMALL, ODD], ids=lambda s: s.name)
+def test_column_minima_give_the_column_maxima(spec):
+    """exp(-e_min) rounded to float32 is each column's largest entry (every
+    column keeps its own minimum-exponent voxel), and e_min is the smallest
+    exponent of the column: no voxel of the grid has a smaller one."""
+    D = phantom.build_dose_matrix(spec)
+    emin = phantom.column_minima(spec)
+    assert emin.shape == (D.nb,) and np.all(np.isfinite(emin)) and np.all(emin >= 0)
+    colmax = np.array([D.csc.data[D.csc.indptr[i]:D.csc.indptr[i + 1]].max() for i in range(D.nb)])
+    assert np.array_equal(np.exp(-emin).astype(np.float32), colmax)
+    # brute force over the grid for a few beamlets, one formula at a time
+    x, y, z = phantom.voxel_centres(spec)
+    bls = phantom.beamlets(spec)
+    for i in range(0, D.nb, max(1, D.nb // 7)):
+        b = bls[i]
+        th = (2.0 * math.pi * b.beam) / spec.n_beams
+        c, s = math.cos(th), math.sin(th)
+        depth, u = phantom.beam_depth_and_u(spec, x, y, c, s)
+        e = (spec.mu * depth) + (((u - b.u_c) ** 2 + (z - b.v_c) ** 2) / ((2.0 * spec.sigma) * spec.sigma))
+        assert abs(e.min() - emin[i]) <= 1e-12 * max(1.0, emin[i])
+
+
+def test_process_pool_build_equals_serial():
+    """The process-pool build gives the serial build's arrays, element for
+    element (the paper-scale fixtures are written with a pool)."""
+    a = phantom.build_dose_matrix(SMALL)
+    b = phantom.build_dose_matrix(SMALL, workers=3)
+    for p, q in ((a.csr, b.csr), (a.csc, b.csc)):
+        assert np.array_equal(p.indptr, q.indptr) and np.array_equal(p.indices, q.indices)
+        assert p.data.dtype == q.data.dtype and np.array_equal(p.data, q.data)
+    assert np.array_equal(a.struct_id, b.struct_id)
+    assert [(t.beam, t.m, t.n) for t in a.beamlets] == [(t.beam, t.m, t.n) for t in b.beamlets]

@@ -7,7 +7,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from oracle import model, phantom, solver
-from oracle_pins import fd_gradient_error, floats, worked_example
+from oracle_pins import fd_gradient_error, floats, kkt_closed_form_errors, worked_example
 from workloads import TINY, random_csr, random_penalties
 
 
@@ -23,6 +23,22 @@ def _problem():
 def test_pins_hold_without_mistakes():
     D, pen, x = _problem()
     assert fd_gradient_error(D, pen, x, range(25))[0] <= 1e-6
+    assert kkt_closed_form_errors() == []
+
+
+def test_constant_kkt_residual_is_caught(monkeypatch):
+    """A residual that always reads 0 (it would pass every check made at an
+    optimum) fails the hand-worked one-voxel cases."""
+    monkeypatch.setattr(solver, "kkt_residual", lambda D_, p, x_: 0.0)
+    assert len(kkt_closed_form_errors()) == 4
+
+
+def test_kkt_residual_without_projection_is_caught(monkeypatch):
+    """Dropping the projection (|grad G| instead of |x - max(0, x - grad G)|)
+    fails the cases where the bound x >= 0 is active."""
+    monkeypatch.setattr(solver, "kkt_residual",
+                        lambda D_, p, x_: float(np.max(np.abs(model.gradient(D_, x_, p)))))
+    assert kkt_closed_form_errors() != []
 
 
 def test_dropped_underdose_term_is_caught(monkeypatch):
