@@ -116,6 +116,22 @@ typedef struct {
                              step 2); 1: iteration k+1 starts at alpha times the
                              step accepted in iteration k (the first at lambda0) */
   void* trace;            /* nullable host buffer of max_iter imrt_trace_entry, filled on return */
+  /* Resuming an interrupted solve (checkpoint and restart of Section 2.2's
+   * iteration).  resume = 0: a fresh start at x_1, the other three fields
+   * unused.  resume = 1: x holds the iterate x_K of an earlier solve after
+   * K = k0 >= 1 accepted iterations, G_prev is G(x_{K-1}) (G(x_1) when
+   * K = 1) and lambda_prev > 0 the step accepted in iteration K.  The solve
+   * then applies step 5's stopping test to the pair (G(x_K), G_prev) before
+   * its first iteration (and stops with 0 iterations, IMRT_CONVERGED, when
+   * it holds; not with fixed_iters), a warm-started line search begins at
+   * alpha * lambda_prev, and trace entries are numbered from k0 + 1;
+   * max_iter caps this call's iterations.  A solve continued this way from
+   * the x, G and lambda of iteration K reproduces the uninterrupted
+   * trajectory bit for bit. */
+  int32_t resume;
+  int32_t k0;
+  double G_prev;
+  double lambda_prev;
 } imrt_solve_params;
 
 /* One accepted iteration. */
@@ -354,7 +370,10 @@ typedef struct {
   int32_t nstruct;
   double x0;                        /* every beamlet's start intensity, >= 0 */
   imrt_solve_params params;         /* lambda0 <= 0: 50 power iterations from the
-                                       all-ones vector; trace and profile ignored */
+                                       all-ones vector; profile ignored; a trace
+                                       buffer (max_iter entries) is filled by the
+                                       ticket's imrt_server_wait and must stay
+                                       valid until that wait returns */
 } imrt_request;
 
 typedef struct {

@@ -1062,6 +1062,14 @@ int imrt_estimate_lambda0(imrt_plan* P, const float* v0_dev, int32_t iters, doub
   return IMRT_OK;
 }
 
+// Trace entries of a resumed solve continue the numbering of the solve it
+// resumes.
+void number_trace(const imrt_solve_params* prm, int n) {
+  if (!prm->resume) return;
+  auto* t = static_cast<imrt_trace_entry*>(prm->trace);
+  for (int i = 0; i < n; ++i) t[i].k += prm->k0;
+}
+
 // Checks of a solve's arguments, x_1 >= 0 (host copy), the plan's buffers and
 // trace, and the initial solver state.
 int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev, int* nt_out, int* cap_out,
@@ -1077,6 +1085,14 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
     return set_error(IMRT_EINVAL, "max_iter and max_backtracks must be >= 0");
   if (prm->warm_start != 0 && prm->warm_start != 1) return set_error(IMRT_EINVAL, "warm_start must be 0 or 1");
   if (prm->profile < 0) return set_error(IMRT_EINVAL, "profile must be >= 0");
+  if (prm->resume != 0 && prm->resume != 1) return set_error(IMRT_EINVAL, "resume must be 0 or 1");
+  if (prm->resume) {
+    if (prm->k0 < 1) return set_error(IMRT_EINVAL, "a resumed solve needs k0 >= 1");
+    if (!(prm->G_prev >= 0.0) || !std::isfinite(prm->G_prev))
+      return set_error(IMRT_EINVAL, "a resumed solve needs a finite G_prev >= 0");
+    if (!(prm->lambda_prev > 0.0) || !std::isfinite(prm->lambda_prev))
+      return set_error(IMRT_EINVAL, "a resumed solve needs a finite lambda_prev > 0");
+  }
   const int nt = prm->trials_per_pass == 0 ? 1 : prm->trials_per_pass;
   if (nt != 1 && nt != 2 && nt != 4) return set_error(IMRT_EINVAL, "trials_per_pass must be 0, 1, 2 or 4");
   if ((rc = use_device(P->ctx))) return rc;
@@ -1114,7 +1130,12 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   init.fixed = prm->fixed_iters ? 1 : 0;
   init.trace_cap = cap;
   init.warm = prm->warm_start;
-  init.lambda = prm->lambda0;
+  init.resume = prm->resume;
+  init.G_prev = prm->resume ? prm->G_prev : 0.0;
+  // first trial step: step 2's lambda0, or after a resumed warm-started
+  // iteration alpha times the step accepted last (the product the decision
+  // forms on the device)
+  init.lambda = (prm->resume && prm->warm_start) ? prm->alpha * prm->lambda_prev : prm->lambda0;
   init.eps = prm->eps;
   init.alpha = prm->alpha;
   init.lambda0 = prm->lambda0;
@@ -1375,6 +1396,7 @@ int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_so
       cleanup();
       return hip_error(e, "trace copy");
     }
+    number_trace(prm, n);
   }
   cleanup();
   return IMRT_OK;
@@ -1649,6 +1671,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
       const int m = std::min(f.k, cap[i]);
       e = hipMemcpy(params[i].trace, plans[i]->trace, sizeof(TraceDev) * m, hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_error(e, "trace copy");
+      number_trace(&params[i], m);
     }
   }
   return IMRT_OK;

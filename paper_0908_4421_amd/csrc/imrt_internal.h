@@ -46,6 +46,7 @@ struct SolverState {
   int32_t acc, xi, n_fwd, n_adj;      // trial whose residual buffer holds r(x_k), iterate buffer of x_k, pass counters
   int32_t ntrials, max_iter, max_bt, fixed;
   int32_t trace_cap, warm;            // trace capacity; warm start of the line search (0/1)
+  int32_t resume, pad_;               // resumed solve: G_prev holds G(x_{K-1}) on entry
   double lambda;                      // first trial step of the next forward pass
   double G, G_prev, G_init;
   double eps, alpha, lambda0, delta;

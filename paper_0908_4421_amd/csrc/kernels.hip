@@ -335,15 +335,19 @@ __device__ void decide(const double* partials, int nparts, const double* steps, 
     SolverState st = dec.st;
     st.n_fwd += 1;
     if (init) {
+      // (st.lambda already holds the first trial step: lambda0, or for a
+      // warm-started resumed solve alpha times the step accepted last)
       const double G0 = Gq[0];
       st.G = G0;
       st.G_init = G0;
-      st.G_prev = G0;
+      if (!st.resume) st.G_prev = G0;
       st.acc = 0;
       st.m = 0;
-      st.lambda = st.lambda0;
       if (!isfinite(G0)) {
         st.status = IMRT_NUMERIC;
+        st.phase = PH_DONE;
+      } else if (st.resume && !st.fixed && (G0 == 0.0 || fabs(G0 - st.G_prev) / G0 < st.delta)) {
+        st.status = IMRT_CONVERGED;   // step 5 on the pair the interrupted solve ended with
         st.phase = PH_DONE;
       } else if (st.max_iter <= 0) {
         st.status = IMRT_MAX_ITER;

@@ -63,6 +63,9 @@ struct Live {
   int nt = 1, grid = 1;
   Clock::time_point arrival, admitted;
   double lambda0 = 0.0;
+  void* trace_dst = nullptr;   // the request's trace buffer (filled by its wait)
+  int trace_cap = 0;
+  int32_t resume = 0, k0 = 0;
 };
 
 struct Finished {
@@ -71,6 +74,8 @@ struct Finished {
   std::vector<float> x;
   int rc = IMRT_OK;
   std::string error;
+  std::vector<imrt_trace_entry> trace;   // accepted iterations, numbered as in imrt_solve
+  void* trace_dst = nullptr;
 };
 
 // Device bytes of a dose matrix (values, indices, partition tables) and of a
@@ -198,7 +203,8 @@ bool admit(imrt_server* S, Pending& p, int slot) {
     const imrt_dose* LD = S->live[i].plan->dose;
     if (LD->storage != D->storage || LD->fwd_st != D->fwd_st || S->live[i].nt != nt) return false;
   }
-  const int64_t pb = plan_bytes(D, nt);
+  const int64_t pb = plan_bytes(D, nt) + (p.params.trace ? static_cast<int64_t>(sizeof(imrt_trace_entry)) *
+                                                              std::max(0, p.params.max_iter) : 0);
   if (S->used + pb > S->budget) {
     rit->second.users += 1;   // keep it while making room for the plan
     const bool ok = make_room(S, pb);
@@ -236,14 +242,17 @@ bool admit(imrt_server* S, Pending& p, int slot) {
   if (e != hipSuccess) return fail(hip_error(e, "upload"));
   int cap = 0;
   SolverState init{};
-  p.params.trace = nullptr;
   p.params.profile = 0;
   if ((rc = solve_prepare(L.plan, &p.params, L.x, &L.nt, &cap, &init))) return fail(rc);
   if (S->ctx.tune.fwd_wave == 0) return fail(set_error(IMRT_EUNSUPPORTED, "serving needs fwd_wave = 1"));
   L.grid = std::min(forward_grid(C, D, L.nt), L.plan->fwd_cap);
   FwdArgs fa;
   AdjArgs aa;
-  solve_args(L.plan, L.nt, L.grid, 0, fa, aa);
+  solve_args(L.plan, L.nt, L.grid, cap, fa, aa);
+  L.trace_dst = p.params.trace;
+  L.trace_cap = cap;
+  L.resume = p.params.resume;
+  L.k0 = p.params.k0;
   fa.st_in = S->st + 2 * slot;
   fa.st_out = S->st + 2 * slot + 1;
   aa.st_in = S->st + 2 * slot + 1;
@@ -415,6 +424,18 @@ void worker_main(imrt_server* S) {
       out.times.nnz = D->nnz;
       out.times.nv = D->nv;
       out.times.nb = D->nb;
+      if (L.trace_dst && f.k > 0 && out.rc == IMRT_OK) {
+        out.trace.resize(std::min(f.k, L.trace_cap));
+        e = hipMemcpy(out.trace.data(), L.plan->trace, sizeof(imrt_trace_entry) * out.trace.size(),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+          out.rc = hip_error(e, "trace copy");
+          out.error = imrt_last_error();
+        }
+        if (L.resume)
+          for (auto& t : out.trace) t.k += L.k0;
+        out.trace_dst = L.trace_dst;
+      }
       const int64_t ticket = L.ticket;   // (release clears the slot's record)
       release(S, i);
       std::lock_guard<std::mutex> g(S->mu);
@@ -522,6 +543,8 @@ int imrt_server_wait(imrt_server* S, int64_t ticket, float* x_out, int32_t nb, i
   }
   if (result) *result = f.result;
   if (times) *times = f.times;
+  if (f.trace_dst && !f.trace.empty())
+    std::memcpy(f.trace_dst, f.trace.data(), sizeof(imrt_trace_entry) * f.trace.size());
   return IMRT_OK;
 }
 

@@ -43,7 +43,8 @@ class imrt_solve_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("alpha", C.c_double), ("lambda0", C.c_double),
                 ("delta", C.c_double), ("max_iter", C.c_int32), ("max_backtracks", C.c_int32),
                 ("fixed_iters", C.c_int32), ("trials_per_pass", C.c_int32), ("profile", C.c_int32),
-                ("warm_start", C.c_int32), ("trace", C.c_void_p)]
+                ("warm_start", C.c_int32), ("trace", C.c_void_p), ("resume", C.c_int32), ("k0", C.c_int32),
+                ("G_prev", C.c_double), ("lambda_prev", C.c_double)]
 
 
 class imrt_trace_entry(C.Structure):
@@ -548,11 +549,18 @@ class Plan:
         return imrt_batch_autotune(n, handles, params, xptr, tune_iters)
 
     def solve(self, x, *, eps, alpha, lambda0, delta=1e-5, max_iter=20000, max_backtracks=60,
-              fixed_iters=False, trials_per_pass=1, trace=False, profile=0, warm_start=False):
+              fixed_iters=False, trials_per_pass=1, trace=False, profile=0, warm_start=False, resume=None):
+        """imrt_solve from the device tensor x (updated in place).  resume:
+        None for a fresh start, else (k0, G_prev, lambda_prev) of the solve x
+        comes from.  Returns (result, trace as (k, backtracks, lambda,
+        step_sq, G) tuples or None)."""
         buf = (imrt_trace_entry * max(max_iter, 1))() if trace else None
         p = imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks, int(bool(fixed_iters)),
                               trials_per_pass, int(profile), int(bool(warm_start)),
                               C.cast(buf, C.c_void_p) if trace else None)
+        if resume is not None:
+            p.resume = 1
+            p.k0, p.G_prev, p.lambda_prev = int(resume[0]), float(resume[1]), float(resume[2])
         res = imrt_solve(self.handle, p, x.data_ptr())
         tr = None
         if trace:
@@ -579,21 +587,34 @@ class Server:
     def __init__(self, ctx: "Context", budget_bytes: int, max_live: int = 64):
         self.ctx = ctx
         self.handle = imrt_server_create(ctx.handle, budget_bytes, max_live)
+        self._traces = {}   # ticket -> trace buffer, kept alive until its wait
 
     def submit(self, patient: int, spec, table, *, storage="f32", x0=1.0, eps=1e-4, alpha=2.0, lambda0=0.0,
                delta=1e-5, max_iter=20000, max_backtracks=60, fixed_iters=False, trials_per_pass=1,
-               warm_start=False) -> int:
+               warm_start=False, trace=False) -> int:
         """spec: a PhantomSpec building the patient's matrix when it is not
-        resident (None to require a resident one); table: (nstruct, 4)."""
+        resident (None to require a resident one); table: (nstruct, 4).
+        trace: the plan's accepted iterations come back from wait()."""
         rows = [imrt_penalty(*[float(v) for v in row]) for row in table]
         pen = (imrt_penalty * len(rows))(*rows)
         geom = geometry_of(spec) if spec is not None else None
+        buf = (imrt_trace_entry * max(max_iter, 1))() if trace else None
         req = imrt_request(int(patient), C.pointer(geom) if geom is not None else None, STORAGE[storage], pen,
                            len(rows), float(x0),
                            imrt_solve_params(eps, alpha, lambda0, delta, max_iter, max_backtracks,
                                              int(bool(fixed_iters)), trials_per_pass, 0, int(bool(warm_start)),
-                                             None))
-        return imrt_server_submit(self.handle, req)
+                                             C.cast(buf, C.c_void_p) if trace else None))
+        ticket = imrt_server_submit(self.handle, req)
+        if trace:
+            self._traces[ticket] = (buf, max_iter)
+        return ticket
+
+    def trace_of(self, ticket: int, iterations: int):
+        """The trace of a waited-on ticket submitted with trace=True, as
+        (k, backtracks, lambda, step_sq, G) tuples."""
+        buf, cap = self._traces.pop(ticket)
+        return [(buf[i].k, buf[i].backtracks, buf[i].lambda_, buf[i].step_sq, buf[i].G)
+                for i in range(min(iterations, cap))]
 
     def wait(self, ticket: int, nb: int = 0, timeout_s: float = 120.0):
         """(result, times, x as a numpy array or None when nb == 0).  Raises

@@ -20,6 +20,9 @@ from oracle import model, phantom, solver  # noqa: E402
 from workloads import PAPER_SCALE, PAPER_SCALE_SETTINGS, penalty_table, power_start_vector, start_point  # noqa: E402
 
 
+EXTRA = 40   # iterations stored beyond the oracle's stop
+
+
 def sha(a, dtype):
     return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
 
@@ -35,6 +38,12 @@ def main():
     res = solver.solve(D.csr, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam0,
                        delta=st.delta, max_iter=st.max_iter, max_backtracks=st.max_backtracks,
                        fixed_iters=st.fixed_iters)
+    # the same trajectory continued past the stop, so that a run which stops
+    # a little later can be compared at its own stop index
+    ext = solver.solve(D.csr, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam0,
+                       max_iter=res.iterations + EXTRA, max_backtracks=st.max_backtracks, fixed_iters=True)
+    assert [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace[:res.iterations]] == \
+        [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in res.trace]
     out = {
         "workload": spec.name,
         "nv": D.nv, "nb": D.nb, "nnz": D.nnz,
@@ -47,7 +56,8 @@ def main():
         "emin": emin.tolist(),
         "lambda0": lam0, "sigma": sigma,
         "G_initial": res.G_initial, "status": res.status, "iterations": res.iterations,
-        "trace": [[e.k, e.lam, e.backtracks, e.step_sq, e.G] for e in res.trace],
+        "trace": [[e.k, e.lam, e.backtracks, e.step_sq, e.G] for e in ext.trace],
+        "trace_note": f"the stopped trajectory's {res.iterations} iterations, then {EXTRA} more (stopping test off)",
         "seconds": time.time() - t0,
     }
     with open(os.path.join(HERE, "paper_scale_oracle.json"), "w") as f:

@@ -21,6 +21,9 @@ from oracle import model, phantom, quantize, solver  # noqa: E402
 from workloads import PAPER_SCALE, PAPER_SCALE_SETTINGS, penalty_table, power_start_vector, start_point  # noqa: E402
 
 
+EXTRA = 40   # iterations stored beyond the oracle's stop
+
+
 def sha(a, dtype):
     return hashlib.sha256(np.ascontiguousarray(a, dtype=dtype).tobytes()).hexdigest()
 
@@ -38,13 +41,17 @@ def main():
         res = solver.solve(S.Dq, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam0,
                            delta=st.delta, max_iter=st.max_iter, max_backtracks=st.max_backtracks,
                            fixed_iters=st.fixed_iters)
+        # continued past the stop (stopping test off), for runs that stop later
+        ext = solver.solve(S.Dq, pen, start_point(D.nb, st), eps=st.eps, alpha=st.alpha, lambda0=lam0,
+                           max_iter=res.iterations + EXTRA, max_backtracks=st.max_backtracks, fixed_iters=True)
+        assert [e.G for e in ext.trace[:res.iterations]] == [e.G for e in res.trace]
         out["forms"][fmt] = {
             "sha256_scale": sha(S.scale, "<f4"),
             "sha256_q_csr": sha(S.q_csr, "<u2"),
             "sha256_q_csc": sha(S.q_csc, "<u2"),
             "lambda0": lam0, "sigma": sigma,
             "G_initial": res.G_initial, "status": res.status, "iterations": res.iterations,
-            "trace": [[e.k, e.lam, e.backtracks, e.step_sq, e.G] for e in res.trace],
+            "trace": [[e.k, e.lam, e.backtracks, e.step_sq, e.G] for e in ext.trace],
         }
         print(fmt, res.iterations, res.G, time.time() - t0, flush=True)
     out["seconds"] = time.time() - t0

@@ -39,3 +39,53 @@ def rel_normwise(got, want) -> float:
 
 def banner(msg: str):
     print(f"[gpu] {msg}", flush=True)
+
+
+def check_trajectory(tr, res, ref, ref_G0, ref_stop, delta=None, tol=1e-6, slack=None):
+    """Compare a GPU solve with the oracle's trajectory of the same problem.
+
+    tr: the GPU trace [(k, backtracks, lambda, step_sq, G)] and res its
+    result; ref: the oracle's trace [(k, lambda, backtracks, step_sq, G)],
+    run at least as far as the GPU's stop index, and ref_G0 its G(x_1);
+    ref_stop: the iteration at
+    which the oracle stopped (its own stopping rule), None when both ran a
+    fixed count; delta: the stopping tolerance when the stopping rule was on.
+
+    Every index: same numbering, backtracks and step; G within tol relative
+    (plus `slack(k, G)` absolute when given).  The GPU's final G is compared
+    with the oracle's G at the GPU's stop index.  The stop indices agree, or
+    the GPU's own trace shows it applied step 5 correctly and the oracle's
+    relative change at the first index where the two decisions differ lies
+    within what the worst measured G error can move it (a decision that
+    close to delta can go either way in float32 arithmetic).
+    Returns (worst relative G error, GPU stop index, oracle stop index)."""
+    K = len(tr)
+    assert K == res.iterations and K <= len(ref), (K, res.iterations, len(ref))
+    assert abs(res.G_initial - ref_G0) <= tol * abs(ref_G0), (res.G_initial, ref_G0)
+    worst = 0.0
+    for (k, m, lam, s, G), (rk, rlam, rm, rs, rG) in zip(tr, ref[:K]):
+        assert k == rk and m == rm and lam == rlam, (k, m, rm, lam, rlam)
+        bound = tol * abs(rG) + (slack(k, rG) if slack else 0.0)
+        assert abs(G - rG) <= bound, (k, G, rG)
+        worst = max(worst, abs(G - rG) / abs(rG) if rG else 0.0)
+    if K:
+        rG = ref[K - 1][4]
+        assert abs(res.G_final - rG) <= tol * abs(rG) + (slack(K, rG) if slack else 0.0), (res.G_final, rG)
+    if ref_stop is None:
+        return worst, K, None
+    Gs = [res.G_initial] + [e[4] for e in tr]
+    rGs = [ref_G0] + [e[4] for e in ref]
+
+    def stops(g, k):
+        return g[k] == 0.0 or abs(g[k] - g[k - 1]) / g[k] < delta
+
+    # the GPU's own stopping decisions
+    for k in range(1, K):
+        assert not stops(Gs, k), ("GPU continued past its stopping test", k)
+    if res.status == 0:
+        assert K >= 1 and stops(Gs, K), ("GPU stopped without its test holding", K)
+    if K != ref_stop:
+        k = min(K, ref_stop)
+        rho = abs(rGs[k] - rGs[k - 1]) / rGs[k]
+        assert abs(rho - delta) <= 2.0 * worst * (1.0 + rho) + 1e-15, (K, ref_stop, rho, worst)
+    return worst, K, ref_stop

@@ -40,13 +40,36 @@ def test_binding_covers_the_header_with_the_same_names():
         assert callable(getattr(imrt, name)), name
 
 
-def test_struct_layouts():
-    # sizes follow the C declarations on x86-64 (natural alignment)
-    assert ctypes.sizeof(imrt.imrt_penalty) == 32
-    assert ctypes.sizeof(imrt.imrt_trace_entry) == 32
-    assert ctypes.sizeof(imrt.imrt_solve_result) == 56
-    assert ctypes.sizeof(imrt.imrt_solve_params) == 64
-    assert ctypes.sizeof(imrt.imrt_geometry) == 96
+STRUCTS = ("imrt_penalty", "imrt_geometry", "imrt_solve_params", "imrt_trace_entry", "imrt_solve_result",
+           "imrt_request", "imrt_serve_times")
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Size and every field offset of each ctypes structure equal what the C
+    compiler gives for the declaration in include/imrt.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "imrt.h"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(imrt, name)
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            cfield = "lambda" if field == "lambda_" else field
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {cfield}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, stdout=subprocess.PIPE, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, value = line.split()
+        cls = getattr(imrt, name)
+        got = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(value), line
 
 
 def test_host_side_argument_errors_without_device_work():

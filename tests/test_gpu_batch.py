@@ -173,3 +173,54 @@ def test_full_batch_workload_bit_identical_to_solo(ctx):
     banner(f"full batch partition {part}")
     solo, _ = _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=ST.max_iter)
     assert all(r.status == 0 for r, _, _ in solo)
+
+
+def _oracle_runs(problems, delta, max_iter):
+    """For each (D, penalties, lambda0): the oracle's stop index under the
+    stopping rule and its trajectory continued 40 iterations past it."""
+    from oracle import solver
+    out = []
+    for D, pen, lam in problems:
+        x1 = np.full(D.shape[1], ST.x0)
+        stop = solver.solve(D, pen, x1, eps=ST.eps, alpha=ST.alpha, lambda0=lam, delta=delta,
+                            max_iter=max_iter, keep_trace=False)
+        ext = solver.solve(D, pen, x1, eps=ST.eps, alpha=ST.alpha, lambda0=lam,
+                           max_iter=stop.iterations + 40, fixed_iters=True)
+        out.append((stop.iterations, ext.G_initial, [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace]))
+    return out
+
+
+def test_batch_against_oracle(ctx):
+    """A batch of the tiny and small phantoms, a re-plan of the small one on
+    the same dose matrix, and two drawn re-plan geometries, solved together to
+    the stopping rule: each plan's trajectory against the FP64 oracle's (same
+    steps and backtracks, G within 1e-6 at every index, final G at the GPU's
+    stop index)."""
+    from oracle import model, phantom, solver
+    from paper_0908_4421_amd.imrt import Dose, Plan
+    from gpu_util import check_trajectory
+    specs = [TINY, SMALL, SMALL, draw_batch_instance(105), draw_batch_instance(113)]
+    tables = [penalty_table(s) for s in specs]
+    tables[2] = tables[2].copy()
+    tables[2][1, :2] = 68.0     # the re-plan: new target thresholds, new organ limits
+    tables[2][2:, 1] *= 0.95
+    Ds = {}
+    problems, doses, plans = [], [], []
+    for i, (sp, t) in enumerate(zip(specs, tables)):
+        if sp.name not in Ds:
+            Ds[sp.name] = (phantom.build_dose_matrix(sp), Dose.from_geometry(ctx, sp))
+        D, lib = Ds[sp.name]
+        pen = model.VoxelPenalties.from_structures(D.struct_id, t)
+        lam, _ = solver.lambda0_from_power_iteration(D.csr, pen, power_start_vector(D.nb, sp.seed + i))
+        problems.append((D.csr, pen, lam))
+        doses.append(lib)
+        plans.append(_plan(ctx, lib, t))
+    assert doses[1] is doses[2]
+    banner("batch against the oracle: " + ", ".join(s.name for s in specs))
+    refs = _oracle_runs(problems, ST.delta, 3000)
+    xs = [to_dev(np.full(d.nb, ST.x0, np.float32)) for d in doses]
+    out = Plan.solve_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=[p[2] for p in problems],
+                           delta=ST.delta, max_iter=3000, trace=True)
+    for sp, (res, tr), (stop, G0, ref) in zip(specs, out, refs):
+        worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=ST.delta)
+        banner(f"{sp.name}: {K} iterations (oracle {Ko}), worst G error {worst:.2e}")

@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_util import banner, f32_ulp_diff, to_dev, to_host
+from gpu_util import banner, check_trajectory, f32_ulp_diff, to_dev, to_host
 from oracle import phantom
 from workloads import PAPER_SCALE, PAPER_SCALE_SETTINGS, penalty_table, power_start_vector, start_point
 
@@ -110,6 +110,8 @@ def test_full_solve_trajectory_two_trials(built, fx):
 
 
 def _check_full_solve(built, fx, nt=1):
+    import scipy.sparse as sp
+    import torch
     ctx, dose, plan, ex = built
     st = PAPER_SCALE_SETTINGS
     x = to_dev(start_point(dose.nb, st).astype(np.float32))
@@ -117,35 +119,31 @@ def _check_full_solve(built, fx, nt=1):
                          max_iter=st.max_iter, max_backtracks=st.max_backtracks, trace=True, trials_per_pass=nt)
     banner(f"paper-scale solve: {res.iterations} iterations, {res.device_ms:.1f} ms")
     assert res.status == 0
-    assert abs(res.G_initial - fx["G_initial"]) <= 1e-6 * fx["G_initial"]
-    ref = fx["trace"]
-    n = min(len(tr), len(ref))
-    assert abs(len(tr) - len(ref)) <= max(5, len(ref) // 50)
-    worst = 0.0
-    for (k, m, lam, s, G), (rk, rlam, rm, rs, rG) in zip(tr[:n], ref[:n]):
-        assert k == rk
-        worst = max(worst, abs(G - rG) / rG)
-    assert worst <= 1e-6, worst
-    # final objective against the oracle's at the same iteration index
-    K = len(tr)
-    if K <= len(ref):
-        assert abs(res.G_final - ref[K - 1][4]) <= 1e-6 * ref[K - 1][4]
-    import torch
+    # every iteration, and the final objective at the GPU's own stop index,
+    # within 1e-6 of the oracle's trajectory (stored 40 iterations past its stop)
+    worst, K, Ko = check_trajectory(tr, res, fx["trace"], fx["G_initial"], fx["iterations"], delta=st.delta)
     d = torch.empty(dose.nv, dtype=torch.float32, device="cuda")
     G_at = plan.objective(x, d)
     assert G_at == res.G_final
-    d = to_host(d)
+    d = to_host(d).astype(np.float64)
     xg = to_host(x).astype(np.float64)
     assert np.all(xg >= 0)
+    # dose of the final plan over every voxel: ||d - D x||_inf / ||D x||_inf
+    # with D x in float64 from the exported matrix (whose index arrays hash to
+    # the oracle's and whose values are within one float32 ulp of them)
+    Dx = sp.csr_matrix((ex["val"].astype(np.float64), ex["col_idx"], ex["row_ptr"]),
+                       shape=(dose.nv, dose.nb)) @ xg
+    err_all = float(np.max(np.abs(d - Dx)) / np.max(np.abs(Dx)))
+    # and per voxel, with oracle rows computed here at sampled voxels
     lens = np.diff(ex["row_ptr"])
     rng = np.random.default_rng(7)
     rows = rng.choice(np.nonzero(lens > 0)[0], 200, replace=False)
     orow = phantom.dose_rows(PAPER_SCALE, rows, np.array(fx["emin"]))
-    zmax = 0.0
     err = 0.0
     for j, (c, v) in zip(rows, orow):
         z = float(v.astype(np.float64) @ xg[c])
-        zmax = max(zmax, abs(z))
         err = max(err, abs(d[j] - z) / max(abs(z), 1e-30))
-    banner(f"paper-scale: worst G error {worst:.2e} over {n} iterations, dose error {err:.2e} (200 voxels)")
+    banner(f"paper-scale: stop {K} (oracle {Ko}), worst G error {worst:.2e}, dose error {err_all:.2e} "
+           f"over all voxels, {err:.2e} per voxel (200 sampled)")
+    assert err_all <= 1e-5
     assert err <= 1e-5

@@ -157,3 +157,47 @@ def test_served_workload_mix_equals_alone(ctx):
         ref, _ = _alone(ctx, doses[r.patient], r.table, times.lambda0, max_iter=20000)
         assert (res.iterations, res.status) == (ref.iterations, ref.status)
         assert res.G_final == ref.G_final
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_served_against_oracle(ctx, storage):
+    """Requests served together (new patients and a re-plan of a resident
+    one, continuous batching) against the FP64 oracle: every served plan's
+    trajectory (traced by the server) has the oracle's steps and backtracks,
+    G within 1e-6 at every index and the final G at the served stop index;
+    with bfloat16 storage the oracle runs on the stored matrix D~."""
+    from oracle import model, phantom, quantize, solver
+    from paper_0908_4421_amd.imrt import Server
+    from gpu_util import check_trajectory
+    rng = np.random.default_rng(11)
+    specs = [TINY, SMALL, draw_batch_instance(105)]
+    reqs = [(0, TINY, penalty_table(TINY)), (1, SMALL, penalty_table(SMALL)),
+            (2, specs[2], penalty_table(specs[2])), (1, None, _replan_table(SMALL, rng))]
+    mats = {}
+    for pat, sp in enumerate(specs):
+        D = phantom.build_dose_matrix(sp)
+        Dv = D.csr if storage == "f32" else quantize.store(D.csr, storage).Dq
+        mats[pat] = (D, Dv)
+    refs, lams = [], []
+    for pat, sp, t in reqs:
+        D, Dv = mats[pat]
+        pen = model.VoxelPenalties.from_structures(D.struct_id, t)
+        lam, _ = solver.lambda0_from_power_iteration(Dv, pen, np.ones(D.nb))
+        x1 = np.ones(D.nb)
+        stop = solver.solve(Dv, pen, x1, eps=1e-4, alpha=2.0, lambda0=lam, delta=1e-5, max_iter=3000,
+                            keep_trace=False)
+        ext = solver.solve(Dv, pen, x1, eps=1e-4, alpha=2.0, lambda0=lam, max_iter=stop.iterations + 40,
+                           fixed_iters=True)
+        refs.append((stop.iterations, ext.G_initial,
+                     [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace]))
+        lams.append(lam)
+    srv = Server(ctx, budget_bytes=8 << 30, max_live=16)
+    banner(f"served against the oracle ({storage}): {len(reqs)} requests")
+    tickets = [srv.submit(p, sp, t, storage=storage, lambda0=lam, max_iter=3000, trace=True)
+               for (p, sp, t), lam in zip(reqs, lams)]
+    for (pat, sp, t), tk, (stop, G0, ref) in zip(reqs, tickets, refs):
+        res, times, _ = srv.wait(tk)
+        tr = srv.trace_of(tk, res.iterations)
+        worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=1e-5)
+        banner(f"ticket {tk}: {K} iterations (oracle {Ko}), worst G error {worst:.2e}")
+    srv.close()
