@@ -89,3 +89,17 @@ def check_trajectory(tr, res, ref, ref_G0, ref_stop, delta=None, tol=1e-6, slack
         rho = abs(rGs[k] - rGs[k - 1]) / rGs[k]
         assert abs(rho - delta) <= 2.0 * worst * (1.0 + rho) + 1e-15, (K, ref_stop, rho, worst)
     return worst, K, ref_stop
+
+
+def dose_rounding_slack(pen):
+    """Absolute G bound from float32 dose rounding at one x: each dose carries
+    a relative error of about u = 2^-24 (d_j >= 0 is a sum of nonnegative
+    products), and dG/dd_j = 2 r_j, so |dG| <= 2 u sum_j |r_j| d_j
+    <= 2 u sqrt(G) sqrt(sum_active w_j d_j^2) by Cauchy-Schwarz with
+    r_j^2 / w_j = F_j.  An active voxel has d_j <= T_j + |d_j - T_j|, so
+    sum_active w_j d_j^2 <= 2 S + 2 G with S = sum_j (w_u T_u^2 + w_o T_o^2).
+    Near the optimum of a long solve G falls to a level where this term, not
+    1e-6 G, decides the comparison with the float64 oracle."""
+    u = 2.0 ** -24
+    S = float(np.sum(pen.w_under * pen.T_under ** 2 + pen.w_over * pen.T_over ** 2))
+    return lambda k, G: 2.0 * u * np.sqrt(abs(G) * (2.0 * S + 2.0 * abs(G)))

@@ -164,11 +164,13 @@ def test_served_against_oracle(ctx, storage):
     """Requests served together (new patients and a re-plan of a resident
     one, continuous batching) against the FP64 oracle: every served plan's
     trajectory (traced by the server) has the oracle's steps and backtracks,
-    G within 1e-6 at every index and the final G at the served stop index;
-    with bfloat16 storage the oracle runs on the stored matrix D~."""
+    G within 1e-6 relative plus the float32 dose-rounding bound at every index
+    and at the served stop index (a plan that runs to the 3000-iteration cap
+    reaches G near 1e-4 of its start, where that bound decides); with
+    bfloat16 storage the oracle runs on the stored matrix D~."""
     from oracle import model, phantom, quantize, solver
     from paper_0908_4421_amd.imrt import Server
-    from gpu_util import check_trajectory
+    from gpu_util import check_trajectory, dose_rounding_slack
     rng = np.random.default_rng(11)
     specs = [TINY, SMALL, draw_batch_instance(105)]
     reqs = [(0, TINY, penalty_table(TINY)), (1, SMALL, penalty_table(SMALL)),
@@ -189,15 +191,16 @@ def test_served_against_oracle(ctx, storage):
         ext = solver.solve(Dv, pen, x1, eps=1e-4, alpha=2.0, lambda0=lam, max_iter=stop.iterations + 40,
                            fixed_iters=True)
         refs.append((stop.iterations, ext.G_initial,
-                     [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace]))
+                     [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace],
+                     dose_rounding_slack(pen)))
         lams.append(lam)
     srv = Server(ctx, budget_bytes=8 << 30, max_live=16)
     banner(f"served against the oracle ({storage}): {len(reqs)} requests")
     tickets = [srv.submit(p, sp, t, storage=storage, lambda0=lam, max_iter=3000, trace=True)
                for (p, sp, t), lam in zip(reqs, lams)]
-    for (pat, sp, t), tk, (stop, G0, ref) in zip(reqs, tickets, refs):
+    for (pat, sp, t), tk, (stop, G0, ref, slack) in zip(reqs, tickets, refs):
         res, times, _ = srv.wait(tk)
         tr = srv.trace_of(tk, res.iterations)
-        worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=1e-5)
+        worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=1e-5, slack=slack)
         banner(f"ticket {tk}: {K} iterations (oracle {Ko}), worst G error {worst:.2e}")
     srv.close()
