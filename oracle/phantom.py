@@ -27,6 +27,16 @@ sparsity pattern bit for bit:
 Voxel j = ix + nx*(iy + ny*iz).  Beamlets are beam-major, then m ascending,
 then n ascending; a beamlet exists if the point of its square closest to the
 beam axis lies within r_ptv + margin.
+
+With coarse unspecified tissue (Section 3.1: twice the voxel size in each
+dimension outside the target and organs), every aligned, complete block of
+2x2x2 grid voxels that are all normal tissue is one voxel centred at
+  c_a = (2*b_a + 1)*h - (n_a*h)/2                      (a = x, y, z)
+of structure "normal"; the voxel order is then the remaining grid voxels
+(j ascending) followed by the coarse voxels (b = bx + cx*(by + cy*bz)
+ascending, cx = nx//2, cy = ny//2).  e_min stays the minimum over the full
+grid (the beamlet's maximum dose at full resolution), so the voxels at the
+grid spacing keep exactly the rows they have in the uniform phantom.
 """
 from __future__ import annotations
 
@@ -40,8 +50,8 @@ import scipy.sparse as sp
 from workloads import BLADDER, NORMAL, PTV, RECTUM, PhantomSpec
 
 
-def voxel_centres(spec: PhantomSpec):
-    """Voxel centre coordinates (x, y, z) in mm, float64, voxel order j."""
+def grid_centres(spec: PhantomSpec):
+    """Centre coordinates (x, y, z) in mm, float64, of every grid voxel j."""
     def axis(n):
         i = np.arange(n, dtype=np.float64)
         return (i + 0.5) * spec.h - (n * spec.h) / 2.0
@@ -50,14 +60,89 @@ def voxel_centres(spec: PhantomSpec):
     return x.ravel(), y.ravel(), z.ravel()
 
 
-def structure_ids(spec: PhantomSpec) -> np.ndarray:
-    """Structure id of every voxel (uint8), priority PTV > rectum > bladder > normal.
+def grid_structure_ids(spec: PhantomSpec) -> np.ndarray:
+    """Structure id of every grid voxel (uint8), priority PTV > rectum > bladder > normal.
 
     A voxel belongs to a structure when its centre lies inside or on it:
     PTV sphere at the origin, rectum cylinder along z centred at
     (0, -(r_ptv + r_rectum)), bladder sphere centred at (0, r_ptv + r_bladder, 0).
     """
-    x, y, z = voxel_centres(spec)
+    return _structure_at(spec, *grid_centres(spec))
+
+
+def coarse_blocks(spec: PhantomSpec) -> np.ndarray:
+    """Indices b = bx + cx*(by + cy*bz) of the coarse voxels: the aligned,
+    complete 2x2x2 blocks of grid voxels that are all normal tissue (none
+    for a uniform grid)."""
+    if not spec.coarse_normal:
+        return np.zeros(0, dtype=np.int64)
+    cx, cy, cz = spec.nx // 2, spec.ny // 2, spec.nz // 2
+    sid = grid_structure_ids(spec).reshape(spec.nz, spec.ny, spec.nx)
+    sub = sid[:2 * cz, :2 * cy, :2 * cx].reshape(cz, 2, cy, 2, cx, 2)
+    normal = np.all(sub == NORMAL, axis=(1, 3, 5))
+    return np.nonzero(normal.ravel())[0].astype(np.int64)
+
+
+def block_axes(spec: PhantomSpec, blocks: np.ndarray):
+    """(bx, by, bz) of coarse block indices."""
+    cx, cy = spec.nx // 2, spec.ny // 2
+    return blocks % cx, (blocks // cx) % cy, blocks // (cx * cy)
+
+
+def voxel_layout(spec: PhantomSpec):
+    """(fine, blocks): grid indices of the voxels kept at the grid spacing
+    (ascending) and the coarse voxels' block indices (ascending).  The
+    voxel order of D is fine first, then blocks."""
+    n = spec.grid_voxels
+    blocks = coarse_blocks(spec)
+    if len(blocks) == 0:
+        return np.arange(n, dtype=np.int64), blocks
+    bx, by, bz = block_axes(spec, blocks)
+    covered = np.zeros(n, dtype=bool)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                covered[(2 * bx + dx) + spec.nx * ((2 * by + dy) + spec.ny * (2 * bz + dz))] = True
+    return np.nonzero(~covered)[0].astype(np.int64), blocks
+
+
+def coarse_centres(spec: PhantomSpec, blocks: np.ndarray):
+    """Centres (x, y, z) of coarse voxels: c_a = (2 b_a + 1) h - (n_a h)/2."""
+    bx, by, bz = block_axes(spec, blocks)
+
+    def axis(b, n):
+        return (2.0 * b.astype(np.float64) + 1.0) * spec.h - (n * spec.h) / 2.0
+    return axis(bx, spec.nx), axis(by, spec.ny), axis(bz, spec.nz)
+
+
+def voxel_count(spec: PhantomSpec) -> int:
+    """Rows of D: grid voxels, or fine plus coarse voxels of a coarse layout."""
+    fine, blocks = voxel_layout(spec)
+    return len(fine) + len(blocks)
+
+
+def voxel_centres(spec: PhantomSpec):
+    """Centre coordinates (x, y, z) in mm, float64, of every voxel in D's row
+    order (the grid's voxels for a uniform grid)."""
+    x, y, z = grid_centres(spec)
+    fine, blocks = voxel_layout(spec)
+    if len(blocks) == 0:
+        return x, y, z
+    cx, cy, cz = coarse_centres(spec, blocks)
+    return (np.concatenate([x[fine], cx]), np.concatenate([y[fine], cy]), np.concatenate([z[fine], cz]))
+
+
+def structure_ids(spec: PhantomSpec) -> np.ndarray:
+    """Structure id of every voxel of D's row order (uint8): the grid voxel's
+    own for voxels at the grid spacing, normal tissue for coarse voxels."""
+    fine, blocks = voxel_layout(spec)
+    sid = grid_structure_ids(spec)
+    if len(blocks) == 0:
+        return sid
+    return np.concatenate([sid[fine], np.full(len(blocks), NORMAL, dtype=np.uint8)])
+
+
+def _structure_at(spec: PhantomSpec, x, y, z) -> np.ndarray:
     sid = np.full(x.shape, NORMAL, dtype=np.uint8)
     cb = spec.r_ptv + spec.r_bladder
     dyb = y - cb
@@ -145,10 +230,10 @@ class DoseMatrix:
         return int(self.csr.nnz)
 
 
-def dose_column(spec: PhantomSpec, depth, u, z, bl: Beamlet):
-    """Kept voxel indices (ascending) and float32 values of one beamlet."""
-    e = beamlet_exponent(spec, depth, u, z, bl)
-    keep_limit = e.min() + math.log(1.0 / spec.tau)
+def kept_entries(spec: PhantomSpec, e: np.ndarray, emin: float):
+    """Kept voxel indices (ascending) and float32 values of one beamlet, from
+    its exponents e at the voxels and its minimum emin over the grid."""
+    keep_limit = emin + math.log(1.0 / spec.tau)
     rows = np.nonzero(e <= keep_limit)[0].astype(np.int32)
     vals = np.exp(-e[rows]).astype(np.float32)
     return rows, vals
@@ -158,10 +243,16 @@ def build_columns(spec: PhantomSpec, which=None):
     """Columns of D for the beamlet indices ``which`` (all when None).
 
     Returns (list of beamlets, list of (rows, vals)) in the requested order.
+    The exponents are evaluated on the whole grid (for e_min); a coarse
+    layout keeps its fine voxels' values and adds the coarse voxels'.
     """
     bls = beamlets(spec)
     dirs = beam_directions(spec)
-    x, y, z = voxel_centres(spec)
+    x, y, z = grid_centres(spec)
+    fine, blocks = voxel_layout(spec)
+    coarse = len(blocks) > 0
+    if coarse:
+        xc, yc, zc = coarse_centres(spec, blocks)
     idx = range(len(bls)) if which is None else which
     cache = {}
     cols = []
@@ -169,9 +260,14 @@ def build_columns(spec: PhantomSpec, which=None):
         bl = bls[i]
         if bl.beam not in cache:
             cache.clear()
-            cache[bl.beam] = beam_depth_and_u(spec, x, y, *dirs[bl.beam])
-        depth, u = cache[bl.beam]
-        cols.append(dose_column(spec, depth, u, z, bl))
+            cache[bl.beam] = (beam_depth_and_u(spec, x, y, *dirs[bl.beam]),
+                              beam_depth_and_u(spec, xc, yc, *dirs[bl.beam]) if coarse else None)
+        (depth, u), cdu = cache[bl.beam]
+        e = beamlet_exponent(spec, depth, u, z, bl)
+        emin = e.min()
+        if coarse:
+            e = np.concatenate([e[fine], beamlet_exponent(spec, cdu[0], cdu[1], zc, bl)])
+        cols.append(kept_entries(spec, e, emin))
     return bls, cols
 
 
@@ -199,7 +295,7 @@ def build_dose_matrix(spec: PhantomSpec, workers: int = 1) -> DoseMatrix:
         cols = [c for group in per_beam for c in group]
     else:
         bls, cols = build_columns(spec)
-    nv, nb = spec.nv, len(bls)
+    nv, nb = voxel_count(spec), len(bls)
     lens = np.array([len(r) for r, _ in cols], dtype=np.int64)
     col_ptr = np.zeros(nb + 1, dtype=np.int64)
     np.cumsum(lens, out=col_ptr[1:])
@@ -213,10 +309,10 @@ def build_dose_matrix(spec: PhantomSpec, workers: int = 1) -> DoseMatrix:
 
 
 def column_minima(spec: PhantomSpec, workers: int = 1) -> np.ndarray:
-    """e_min of every beamlet (float64), by brute force over all voxels."""
+    """e_min of every beamlet (float64), by brute force over all grid voxels."""
     bls = beamlets(spec)
     dirs = beam_directions(spec)
-    x, y, z = voxel_centres(spec)
+    x, y, z = grid_centres(spec)
     out = np.empty(len(bls))
     cache = {}
     for i, bl in enumerate(bls):
@@ -230,7 +326,8 @@ def column_minima(spec: PhantomSpec, workers: int = 1) -> np.ndarray:
 
 def dose_rows(spec: PhantomSpec, rows, emin: np.ndarray):
     """Rows of D (kept beamlet indices ascending, float32 values) for the voxel
-    indices ``rows``, given every beamlet's e_min; same formulas as the columns."""
+    indices ``rows`` (D's row order), given every beamlet's e_min over the
+    grid; same formulas as the columns."""
     bls = beamlets(spec)
     dirs = beam_directions(spec)
     x, y, z = voxel_centres(spec)

@@ -18,10 +18,8 @@ def ctx():
 
 
 def _replan_table(spec, rng):
-    t = penalty_table(spec).copy()
-    t[0, :2] = rng.uniform(66.0, 74.0)
-    t[1:, 1] *= rng.uniform(0.9, 1.1, len(t) - 1)
-    return t
+    from workloads import replan_penalty_table
+    return replan_penalty_table(spec, rng)
 
 
 def _alone(ctx, dose, table, lam, max_iter=3000, fixed=False):

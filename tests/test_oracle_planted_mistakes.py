@@ -177,3 +177,54 @@ def test_sum_instead_of_max_scale_is_caught(monkeypatch):
     except AssertionError:
         return
     raise AssertionError("sum scale not caught")
+
+
+def _coarse_pins_fail():
+    """Run the coarse-layout pins; return True if any of them fails."""
+    import pytest as _pytest
+    import test_oracle_coarse as C
+    from workloads import TINY_COARSE
+    try:
+        C.test_layout_block_by_block(C.EVEN)
+        C.test_coarse_centres_are_exact_block_means(TINY_COARSE)
+        C.test_rows_against_the_uniform_and_the_doubled_grid(C.EVEN)
+    except (AssertionError, _pytest.fail.Exception):
+        return True
+    return False
+
+
+def test_coarse_pins_hold_without_mistakes():
+    assert not _coarse_pins_fail()
+
+
+def test_coarse_centre_off_by_half_a_voxel_is_caught(monkeypatch):
+    """Coarse centres at 2 b h - n h / 2 (the block's corner voxel instead of
+    the block's middle) fail the block-mean and doubled-grid pins."""
+    real = phantom.coarse_centres
+
+    def shifted(spec, blocks):
+        x, y, z = real(spec, blocks)
+        return x - spec.h / 2, y - spec.h / 2, z - spec.h / 2
+    monkeypatch.setattr(phantom, "coarse_centres", shifted)
+    assert _coarse_pins_fail()
+
+
+def test_coarse_minima_over_the_layout_are_caught(monkeypatch):
+    """Truncating against the minimum over the layout's voxels (instead of
+    the full grid) changes kept entries, which the uniform-phantom rows
+    catch."""
+    real = phantom.kept_entries
+    monkeypatch.setattr(phantom, "kept_entries", lambda spec, e, emin: real(spec, e, e.min()))
+    assert _coarse_pins_fail()
+
+
+def test_coarse_blocks_with_an_organ_voxel_are_caught(monkeypatch):
+    """Merging blocks with up to one non-normal voxel fails the block scan."""
+    def loose(spec):
+        cx, cy, cz = spec.nx // 2, spec.ny // 2, spec.nz // 2
+        sid = phantom.grid_structure_ids(spec).reshape(spec.nz, spec.ny, spec.nx)
+        sub = sid[:2 * cz, :2 * cy, :2 * cx].reshape(cz, 2, cy, 2, cx, 2)
+        ok = np.sum(sub != 0, axis=(1, 3, 5)) <= 1
+        return np.nonzero(ok.ravel())[0].astype(np.int64)
+    monkeypatch.setattr(phantom, "coarse_blocks", loose)
+    assert _coarse_pins_fail()

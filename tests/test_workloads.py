@@ -3,8 +3,8 @@ the served request stream, re-plan thresholds, the day's anatomy and the
 tile order used to cut row shares."""
 import numpy as np
 
-from workloads import (PAPER_SCALE, SMALL, day_geometry, penalty_table, replan_penalty_table,
-                       served_requests)
+from workloads import (BLADDER, NORMAL, PAPER_SCALE, PTV, RECTUM, SMALL, day_geometry, penalty_table,
+                       replan_penalty_table, served_requests)
 
 
 def test_served_requests_deterministic_and_shaped():
@@ -31,8 +31,11 @@ def test_replan_thresholds_within_their_ranges():
     base = penalty_table(SMALL)
     for _ in range(200):
         t = replan_penalty_table(SMALL, rng)
-        assert 66.0 <= t[0, 0] < 74.0 and t[0, 0] == t[0, 1]
-        ratio = t[1:, 1] / base[1:, 1]
+        # rows are structure ids: the target's two thresholds are redrawn
+        assert 66.0 <= t[PTV, 0] < 74.0 and t[PTV, 0] == t[PTV, 1]
+        others = [NORMAL, RECTUM, BLADDER]
+        assert np.array_equal(t[others, 0], base[others, 0])
+        ratio = t[others, 1] / base[others, 1]
         assert np.all((ratio >= 0.9) & (ratio < 1.1))
         assert np.array_equal(t[:, 2:], base[:, 2:])          # weights unchanged
 

@@ -62,6 +62,13 @@ class PhantomSpec:
     at angles 2*pi*b/n_beams; square beamlets of side ``beamlet`` mm cover the
     PTV projection plus ``margin`` mm.  Dose kernel exp(-(mu*depth + r^2 /
     (2 sigma^2))), truncated below ``tau`` times the beamlet maximum.
+
+    ``coarse_normal``: unspecified tissue at twice the voxel size in each
+    dimension (Section 3.1).  Every aligned, complete 2x2x2 block of grid
+    voxels that are all normal tissue becomes one voxel of side 2h at the
+    block's centre; the other voxels keep the grid spacing.  The voxel count
+    then depends on the structures, which each phantom builder evaluates
+    itself, so ``nv`` is defined for uniform grids only.
     """
     name: str
     nx: int
@@ -79,10 +86,18 @@ class PhantomSpec:
     margin: float = 5.0
     penalties: Tuple[Penalty, ...] = PROSTATE_PENALTIES
     seed: int = 0
+    coarse_normal: bool = False
+
+    @property
+    def grid_voxels(self) -> int:
+        return self.nx * self.ny * self.nz
 
     @property
     def nv(self) -> int:
-        return self.nx * self.ny * self.nz
+        if self.coarse_normal:
+            raise ValueError(f"{self.name}: the voxel count of a layout with coarse unspecified tissue "
+                             "comes from its phantom builder")
+        return self.grid_voxels
 
     def as_dict(self) -> dict:
         d = dataclasses.asdict(self)
@@ -144,7 +159,16 @@ SCENARIO3_SHAPE = PhantomSpec(name="scenario3_shape_66x54x40_4mm_9field", nx=66,
 WIDE = PhantomSpec(name="wide_30x26x16_4mm_9field", nx=30, ny=26, nz=16, h=4.0, r_ptv=40.0,
                    r_rectum=16.0, r_bladder=30.0, n_beams=9, beamlet=5.0, sigma=7.5, tau=0.005, seed=5)
 
-NAMED = {"tiny": TINY, "paper": PAPER_SCALE, "small": SMALL, "scenario3": SCENARIO3_SHAPE}
+# The same phantoms with unspecified tissue at twice the voxel size (the
+# paper's reduction of the problem size, Section 3.1).  SMALL's odd grid
+# leaves incomplete blocks at its upper faces, which keep the grid spacing.
+TINY_COARSE = dataclasses.replace(TINY, name="tiny_40x40x20_5mm_5field_coarse", coarse_normal=True)
+SMALL_COARSE = dataclasses.replace(SMALL, name="small_33x27x11_4mm_7field_coarse", coarse_normal=True)
+PAPER_SCALE_COARSE = dataclasses.replace(PAPER_SCALE, name="prostate_160x104x80_2.5mm_9field_coarse",
+                                         coarse_normal=True)
+
+NAMED = {"tiny": TINY, "paper": PAPER_SCALE, "small": SMALL, "scenario3": SCENARIO3_SHAPE,
+         "paper_coarse": PAPER_SCALE_COARSE}
 
 # Fixed box of the batched / served instances (mm) and the grids it gives.
 _BOX_GRIDS = {2.5: (160, 104, 80), 4.0: (100, 65, 50), 5.0: (80, 52, 40)}
@@ -183,8 +207,9 @@ def replan_penalty_table(spec: PhantomSpec, rng: np.random.Generator) -> np.ndar
     overdose thresholds both drawn uniform in [66, 74) Gy, each other
     structure's overdose threshold scaled by a factor uniform in [0.9, 1.1)."""
     t = penalty_table(spec).copy()
-    t[0, 0] = t[0, 1] = rng.uniform(66.0, 74.0)
-    t[1:, 1] *= rng.uniform(0.9, 1.1, len(t) - 1)
+    t[PTV, 0] = t[PTV, 1] = rng.uniform(66.0, 74.0)
+    others = [s for s in range(len(t)) if s != PTV]     # rows are structure ids
+    t[others, 1] *= rng.uniform(0.9, 1.1, len(others))
     return t
 
 
