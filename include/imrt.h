@@ -280,8 +280,31 @@ IMRT_API int imrt_set_voxel_targets(imrt_plan* plan, const float* T_under, const
  * (nullable, nv floats) receives D x. */
 IMRT_API int imrt_evaluate_objective(imrt_plan* plan, const float* x_dev, double* G_out, float* dose_dev);
 
-/* g = grad G(x) = 2 D^T r(D x) (nb floats).  G_out (nullable host) receives G(x). */
+/* Gradient of step 1 (Section 2.2; the derivative of Eqs. (1)-(2)):
+ * g = grad G(x) = 2 D^T r(D x), r_j = w_u,j min(z_j - T_u,j, 0) +
+ * w_o,j max(z_j - T_o,j, 0).  x_dev, g_dev: nb floats.  G_out (nullable
+ * host) receives G(x); when it is given the call synchronises the stream.
+ * Uses the plan's own buffers (a plan whose dose matrix was repartitioned
+ * may grow them on first use). */
 IMRT_API int imrt_gradient(imrt_plan* plan, const float* x_dev, float* g_dev, double* G_out);
+
+/* Size of the per-device scratch of imrt_gradient_noalloc (bytes): the
+ * residual (4 nv bytes) plus a few kilobytes of partial sums, so plans of up
+ * to about 4 million voxels. */
+#define IMRT_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* imrt_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): the same kernels and partition,
+ * so the same g and G bit for bit, but every intermediate lives in a static
+ * device array of IMRT_NOALLOC_SCRATCH_BYTES per device, held until the
+ * process ends; the call allocates nothing (no hipMalloc, no plan buffer).
+ * Arguments as imrt_gradient.  IMRT_EINVAL if the plan needs more scratch
+ * than that (the message gives both sizes).  Every call on one device shares
+ * its scratch: calls that overlap on a device (two streams, two threads)
+ * race and must be serialised by the caller.  Nothing in the scratch needs
+ * to start at zero.  With G_out NULL it only enqueues kernels (no memset,
+ * no copy) on the context's stream. */
+IMRT_API int imrt_gradient_noalloc(imrt_plan* plan, const float* x_dev, float* g_dev, double* G_out);
 
 /* Trial point of step 2/4: x_out = max(0, x - lambda g) (computed in
  * float64, stored as float32) and *step_sq_out = ||x_out - x||^2 (float64,
@@ -296,7 +319,10 @@ IMRT_API int imrt_project(imrt_plan* plan, const float* x_dev, const float* g_de
 IMRT_API int imrt_estimate_lambda0(imrt_plan* plan, const float* v0_dev, int32_t iters,
                           double* lambda0_out, double* sigma_out);
 
-/* Solve from x_dev (in: x_1 >= 0, finite; out: the final iterate). */
+/* The method of Section 2.2 (Eq. (5), steps 1-5): gradient projection with
+ * Armijo's line search on G, from x_dev (in: x_1 >= 0, finite, nb floats;
+ * out: the final iterate).  The Armijo decision and the stopping test run on
+ * the device; the call synchronises the stream and fills *result. */
 IMRT_API int imrt_solve(imrt_plan* plan, const imrt_solve_params* params, float* x_dev,
                imrt_solve_result* result);
 

@@ -5,11 +5,18 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "imrt_internal.h"
+
+// Device memory of imrt_gradient_noalloc (residual, forward partials, adjoint
+// pieces, objective total): one copy per device, held until the process
+// ends.  Host code never passes this name to a kernel; it uses the address
+// that hipGetSymbolAddress returned for the device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[IMRT_NOALLOC_SCRATCH_BYTES];
 
 namespace imrt {
 
@@ -78,6 +85,30 @@ int hip_error(hipError_t e, const char* what) {
 // Device arrays of D: row and column pointers, and the four nonzero arrays,
 // each followed by kPad zeroed entries so that 16-byte vector loads that
 // straddle the end stay in bounds.
+// Device address of `scratch` per device, looked up once per device with
+// that device current (at context creation).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return set_error(IMRT_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return IMRT_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+  if (!p) return set_error(IMRT_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+  g_scratch_ptr[device] = p;
+  return IMRT_OK;
+}
+
+unsigned char* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return static_cast<unsigned char*>(g_scratch_ptr[device]);
+}
+
 int alloc_nonzeros(imrt_dose* D) {
   const size_t nz = static_cast<size_t>(D->nnz) + kPad;
   const size_t nzc = csc_alloc(D->nnz);
@@ -452,6 +483,8 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   IMRT_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return set_error(IMRT_EINVAL, "device index out of range");
   IMRT_HIP(hipSetDevice(device));
+  int rc0 = noalloc_scratch_init(device);
+  if (rc0) return rc0;
   auto* c = new (std::nothrow) imrt_ctx();
   if (!c) return set_error(IMRT_ENOMEM, "host allocation failed");
   c->device = device;
@@ -1006,6 +1039,58 @@ int imrt_gradient(imrt_plan* P, const float* x_dev, float* g_dev, double* G_out)
     return rc;
   if (G_out) {
     if ((rc = fetch_misc(P, 1))) return rc;
+    *G_out = P->misc_host[0];
+  }
+  return IMRT_OK;
+}
+
+int imrt_gradient_noalloc(imrt_plan* P, const float* x_dev, float* g_dev, double* G_out) {
+  int rc = plan_ready(P);
+  if (rc) return rc;
+  if (!x_dev || !g_dev) return set_error(IMRT_EINVAL, "x or g is NULL");
+  if ((rc = use_device(P->ctx))) return rc;
+  unsigned char* base = noalloc_scratch(P->ctx->device);
+  if (!base) return set_error(IMRT_EINVAL, "no scratch for this device (create the context first)");
+  const imrt_dose* D = P->dose;
+  const int grid = forward_grid(P->ctx, D, 1);
+  // scratch layout, every part 256-byte aligned: residual (nv floats),
+  // forward objective partials (grid doubles), adjoint pieces (2 per
+  // adjoint workgroup), objective total (one double)
+  auto up = [](size_t n) { return (n + 255) & ~static_cast<size_t>(255); };
+  const size_t off_r = 0;
+  const size_t off_part = off_r + up(sizeof(float) * static_cast<size_t>(D->nv));
+  const size_t off_pieces = off_part + up(sizeof(double) * (static_cast<size_t>(grid) + 1));
+  const size_t off_total = off_pieces + up(sizeof(double) * 2 * static_cast<size_t>(D->adj_grid));
+  const size_t need = off_total + up(sizeof(double));
+  if (need > IMRT_NOALLOC_SCRATCH_BYTES)
+    return set_error(IMRT_EINVAL, "imrt_gradient_noalloc: the plan needs " + std::to_string(need) +
+                                      " bytes of scratch, more than the " +
+                                      std::to_string(static_cast<long long>(IMRT_NOALLOC_SCRATCH_BYTES)) +
+                                      " available (about 4 million voxels)");
+  float* r = reinterpret_cast<float*>(base + off_r);
+  double* parts = reinterpret_cast<double*>(base + off_part);
+  double* pieces = reinterpret_cast<double*>(base + off_pieces);
+  double* total = reinterpret_cast<double*>(base + off_total);
+  // forward pass: residual and objective partials (every workgroup writes its
+  // own partial and every row its residual, so nothing starts at zero)
+  FwdArgs fa = base_fwd(D);
+  fa.mode = FWD_EVAL;
+  set_plan_penalties(fa, P);
+  fa.x = x_dev;
+  fa.r_out = r;
+  fa.partials = parts;
+  if ((rc = launch_forward(P->ctx, D, fa, 1, grid)) || (rc = launch_sum(P->ctx, parts, grid, total))) return rc;
+  // adjoint pass: g = 2 D^T r (pieces written by the workgroups that share a column)
+  AdjArgs aa = base_adj(D);
+  aa.solve = 0;
+  aa.r = r;
+  aa.pieces = pieces;
+  aa.out = g_dev;
+  aa.scale = 2.0;
+  if ((rc = launch_adjoint(P->ctx, D, aa, 1))) return rc;
+  if (G_out) {
+    IMRT_HIP(hipMemcpyAsync(P->misc_host, total, sizeof(double), hipMemcpyDeviceToHost, P->ctx->stream));
+    IMRT_HIP(hipStreamSynchronize(P->ctx->stream));
     *G_out = P->misc_host[0];
   }
   return IMRT_OK;

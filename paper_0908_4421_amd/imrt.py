@@ -101,6 +101,7 @@ SIGNATURES = {
     "imrt_set_voxel_targets": (C.c_int, [_vp, _f32p, _f32p]),
     "imrt_evaluate_objective": (C.c_int, [_vp, _vp, _dp, _vp]),
     "imrt_gradient": (C.c_int, [_vp, _vp, _vp, _dp]),
+    "imrt_gradient_noalloc": (C.c_int, [_vp, _vp, _vp, _dp]),
     "imrt_project": (C.c_int, [_vp, _vp, _vp, C.c_double, _vp, _dp]),
     "imrt_estimate_lambda0": (C.c_int, [_vp, _vp, C.c_int32, _dp, _dp]),
     "imrt_solve": (C.c_int, [_vp, C.POINTER(imrt_solve_params), _vp, C.POINTER(imrt_solve_result)]),
@@ -334,6 +335,15 @@ def imrt_gradient(plan, x_dev: int, g_dev: int) -> float:
     return G.value
 
 
+def imrt_gradient_noalloc(plan, x_dev: int, g_dev: int, want_G: bool = True) -> Optional[float]:
+    """imrt_gradient through the library's per-device static scratch (no
+    device allocation); with want_G False nothing is copied back."""
+    G = C.c_double()
+    _check(load().imrt_gradient_noalloc(plan, x_dev, g_dev, C.byref(G) if want_G else None),
+           "imrt_gradient_noalloc")
+    return G.value if want_G else None
+
+
 def imrt_project(plan, x_dev: int, g_dev: int, lam: float, x_out_dev: int) -> float:
     s = C.c_double()
     _check(load().imrt_project(plan, x_dev, g_dev, lam, x_out_dev, C.byref(s)), "imrt_project")
@@ -501,6 +511,10 @@ class Plan:
         g = torch.empty(self.dose.nb, dtype=torch.float32, device=x.device) if g is None else g
         G = imrt_gradient(self.handle, x.data_ptr(), g.data_ptr())
         return g, G
+
+    def gradient_noalloc(self, x, g, want_G: bool = True):
+        """Gradient into the caller's g through the allocation-free entry point."""
+        return imrt_gradient_noalloc(self.handle, x.data_ptr(), g.data_ptr(), want_G)
 
     def project(self, x, g, lam: float, out=None):
         import torch
