@@ -189,11 +189,15 @@ def batch_form(ctx, args):
     lam_s = time.perf_counter() - t
     kw = dict(eps=st.eps, alpha=st.alpha, delta=st.delta, max_iter=st.max_iter, max_backtracks=st.max_backtracks)
     xs = [torch.full((d.nb,), st.x0, dtype=torch.float32, device="cuda") for d in doses]
+    solo_ms = [0.0] * len(plans)
+
     def solo():
         out = []
-        for pl, x, lam in zip(plans, xs, lams):
+        for i, (pl, x, lam) in enumerate(zip(plans, xs, lams)):
             x.fill_(st.x0)
+            t0 = time.perf_counter()
             out.append(pl.solve(x, lambda0=lam, **kw)[0])
+            solo_ms[i] = (time.perf_counter() - t0) * 1e3
         return out
 
     # one by one with the default (single-plan) partitions
@@ -203,6 +207,7 @@ def batch_form(ctx, args):
     solo()
     torch.cuda.synchronize()
     solo_default_s = time.perf_counter() - t
+    solo_default_ms = list(solo_ms)
     for x in xs:
         x.fill_(st.x0)
     # launch-shape search (leaves the chosen partition on every matrix; the
@@ -261,6 +266,8 @@ def batch_form(ctx, args):
         "dose_build_s": build_s,
         "lambda0_s": lam_s,
         "partition": {"adj_min_nnz": part[0], "fwd_blocks_per_wave": part[1], "autotune_s": tune_s},
+        "per_plan": [{"nnz": d.nnz, "iterations": r.iterations, "solo_ms": a, "solo_same_partition_ms": b}
+                     for d, r, a, b in zip(doses, rb, solo_default_ms, solo_ms)],
         "note": "times exclude the dose-matrix builds, the lambda_0 estimates and the launch-shape search "
                 "(reported apart); "
                 "GB/s counts the algorithmic bytes of every pass of every plan",
@@ -352,15 +359,24 @@ def replan_form(ctx, plan, x, spec, st, args):
     }
 
 
-def shape_form(ctx, args):
-    """A plan on the shape of the paper's largest scenario (about 300 nonzeros
-    per voxel, 0.6 GB of CSR and CSC: beyond the last-level cache), float32,
-    timed like the headline plan; per-pass rates from HIP events."""
+SCENARIO3_NOTE = ("the paper's Table 1 scenario 3 has 6,453 beamlets, 143,329 voxels and 43.3 M nonzeros "
+                  "(its own time is context only: other hardware, data and iteration count)")
+COARSE_NOTE = ("the paper-scale phantom with unspecified tissue at twice the voxel size in each dimension "
+               "(Section 3.1's reduction of the problem size): every 2x2x2 block of normal-tissue voxels is "
+               "one voxel")
+
+
+def shape_form(ctx, args, spec=None, note=SCENARIO3_NOTE):
+    """A further float32 plan timed like the headline plan (by default the
+    shape of the paper's largest scenario: about 300 nonzeros per voxel,
+    0.6 GB of CSR and CSC, beyond the last-level cache); per-pass rates from
+    HIP events."""
     import torch
 
     from paper_0908_4421_amd.imrt import Dose
     from workloads import PAPER_SCALE_SETTINGS as st
-    from workloads import SCENARIO3_SHAPE as spec
+    from workloads import SCENARIO3_SHAPE
+    spec = SCENARIO3_SHAPE if spec is None else spec
     torch.cuda.synchronize()
     t = time.perf_counter()
     dose = Dose.from_geometry(ctx, spec)
@@ -389,8 +405,7 @@ def shape_form(ctx, args):
         "kernels": kern,
         "traffic": {k: traffic_from_profile(names[k], spec.name) for k in names},
         "dose_build_s": build_s,
-        "note": "the paper's Table 1 scenario 3 has 6,453 beamlets, 143,329 voxels and 43.3 M nonzeros "
-                "(its own time is context only: other hardware, data and iteration count)",
+        "note": note,
     }
 
 
@@ -480,6 +495,26 @@ def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
+def shared_live_time(live, patients):
+    """Time during which live plans share a resident matrix.  live[i] =
+    (start, end) of request i, patients[i] its patient.  Returns (sum over
+    requests of the time another live plan of the same patient overlaps it,
+    sum of live times, number of requests with such a partner)."""
+    shared, total, partners = 0.0, 0.0, 0
+    for i, (a, b) in enumerate(live):
+        cuts = sorted((max(a, c), min(b, d)) for j, (c, d) in enumerate(live)
+                      if j != i and patients[j] == patients[i] and c < b and d > a)
+        covered, end = 0.0, a
+        for c, d in cuts:
+            if d > end:
+                covered += d - max(c, end)
+                end = d
+        shared += covered
+        total += b - a
+        partners += bool(cuts)
+    return shared, total, partners
+
+
 def serve_stream(ctx, reqs, budget, paced, st, storage):
     """Submit `reqs` to a fresh server (at their arrival times when `paced`,
     all at once otherwise), wait for every plan; per-request times."""
@@ -488,12 +523,13 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
     kw = dict(storage=storage, x0=st.x0, eps=st.eps, alpha=st.alpha, delta=st.delta, max_iter=st.max_iter,
               max_backtracks=st.max_backtracks)
     t0 = time.perf_counter()
-    tickets = []
+    tickets, sub = [], []
     for r in reqs:
         if paced:
             dt = t0 + r.arrival_s - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
+        sub.append((time.perf_counter() - t0) * 1e3)
         tickets.append(srv.submit(r.patient, r.spec, r.table, **kw))
     got = [srv.wait(tk) for tk in tickets]
     span = time.perf_counter() - t0
@@ -503,6 +539,14 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
     times = [g[1] for g in got]
     plan = [t.plan_ms for t in times]
     queue = [t.queue_ms for t in times]
+    # how often live plans share a resident matrix: each request is live
+    # from its admission to its result; a plan shares its matrix while
+    # another live plan of the same patient overlaps it
+    live = [(s0 + t.queue_ms, s0 + t.plan_ms) for s0, t in zip(sub, times)]
+    shared_ms, live_ms, with_partner = shared_live_time(live, [r.patient for r in reqs])
+
+    def pct(v):
+        return {"n": len(v), "p50": _pct(v, 50), "p99": _pct(v, 99), "max": max(v) if v else None}
     def fb(nv, nb, nnz):
         return f32_forward(ctx, nb)[1](nv, nb, nnz) if storage == "f32" else forward_bytes16(nv, nb, nnz)
     ab = adjoint_bytes if storage == "f32" else adjoint_bytes16
@@ -517,10 +561,13 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
         "replans": sum(r.replan for r in reqs),
         "span_s": span,
         "plans_per_s": len(reqs) / span,
-        "time_to_plan_ms": {"p50": _pct(plan, 50), "p99": _pct(plan, 99), "max": max(plan)},
-        "queue_ms": {"p50": _pct(queue, 50), "p99": _pct(queue, 99), "max": max(queue)},
-        "time_to_plan_replans_ms": {"p50": _pct([p for p, r in zip(plan, reqs) if r.replan], 50),
-                                    "p99": _pct([p for p, r in zip(plan, reqs) if r.replan], 99)},
+        "time_to_plan_ms": pct(plan),
+        "time_to_plan_converged_ms": pct([p for p, x in zip(plan, res) if x.status == 0]),
+        "time_to_plan_capped_ms": pct([p for p, x in zip(plan, res) if x.status == 1]),
+        "queue_ms": pct(queue),
+        "time_to_plan_replans_ms": pct([p for p, r in zip(plan, reqs) if r.replan]),
+        "shared_matrix": {"live_time_fraction": shared_ms / live_ms if live_ms > 0 else 0.0,
+                          "requests_with_a_live_partner": with_partner},
         "iterations_total": sum(its),
         "iterations": {"p50": _pct(its, 50), "p99": _pct(its, 99), "max": its[-1]},
         "status_counts": status,
@@ -548,7 +595,10 @@ def serve_form(ctx, args):
         r = serve_stream(ctx, served_requests(rate, n, seed=int(rate * 10)), budget, True, st, args.serve_storage)
         out["rates"][f"{rate:g}"] = r
         print(f"[bench] serve {rate:g} req/s: {n} requests, p50 {r['time_to_plan_ms']['p50']:.1f} ms, "
-              f"p99 {r['time_to_plan_ms']['p99']:.1f} ms to plan", file=sys.stderr, flush=True)
+              f"p99 {r['time_to_plan_ms']['p99']:.1f} ms to plan; converged p99 "
+              f"{r['time_to_plan_converged_ms']['p99']} ms (n {r['time_to_plan_converged_ms']['n']}); "
+              f"shared-matrix live fraction {r['shared_matrix']['live_time_fraction']:.3f}",
+              file=sys.stderr, flush=True)
     if args.serve_burst > 0:
         r = serve_stream(ctx, served_requests(1.0, args.serve_burst, seed=99), budget, False, st,
                          args.serve_storage)
@@ -722,13 +772,15 @@ def main():
                     help="iterations per candidate of the batch's launch-shape search (0: default partition)")
     ap.add_argument("--no-shard", action="store_true",
                     help="skip the timing of one GPU's row share of the plan")
+    ap.add_argument("--no-coarse", action="store_true",
+                    help="skip the paper-scale plan with coarse unspecified tissue")
     ap.add_argument("--no-shape", action="store_true",
                     help="skip the plan on the shape of the paper's largest scenario")
     ap.add_argument("--no-replan", action="store_true",
                     help="skip the re-plan towards the original plan's dose on the day's anatomy")
     ap.add_argument("--serve-rates", default="2,5,10,20",
                     help="Poisson arrival rates (requests / s) of the served re-plan workload ('' : skip)")
-    ap.add_argument("--serve-seconds", type=float, default=6.0, help="seconds of arrivals per rate")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of arrivals per rate")
     ap.add_argument("--serve-burst", type=int, default=64, help="requests submitted at once after the streams")
     ap.add_argument("--serve-storage", default="bf16", choices=["f32", "bf16", "f16"])
     ap.add_argument("--forms", default="bf16,f16",
@@ -844,6 +896,9 @@ def main():
         out["row_shards"] = shard_form(ctx, dose, spec)
     if not args.no_shape and args.workload == "paper":
         out["scenario3_shape"] = shape_form(ctx, args)
+    if not args.no_coarse and args.workload == "paper":
+        from workloads import PAPER_SCALE_COARSE
+        out["coarse_normal"] = shape_form(ctx, args, PAPER_SCALE_COARSE, COARSE_NOTE)
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if forms:
         out["forms"] = {f: storage_form(ctx, spec, st, args, f, plan, res, ms_per_step) for f in forms}

@@ -91,13 +91,21 @@ typedef struct {
  * angles 2*pi*b/n_beams; square beamlets of side `beamlet` whose closest
  * point to the beam axis lies within r_ptv + margin; D_ij =
  * float32(exp(-(mu*depth + r^2/(2 sigma^2)))) kept where it is >= tau times
- * the beamlet's maximum. */
+ * the beamlet's maximum over the grid.
+ * coarse_normal (0 or 1): unspecified tissue at twice the voxel size in each
+ * dimension (Section 3.1).  Every aligned, complete 2x2x2 block of grid
+ * voxels that are all normal tissue is then one voxel (structure 0) centred
+ * at c_a = (2*b_a + 1)*h - (n_a*h)/2; the voxels of D are the remaining grid
+ * voxels (grid index ascending) followed by the coarse voxels (block index
+ * bx + (nx/2)*(by + (ny/2)*bz) ascending), and imrt_dose_info reports
+ * their count. */
 typedef struct {
   int32_t nx, ny, nz;
   double h;
   double r_ptv, r_rectum, r_bladder;
   int32_t n_beams;
   double beamlet, sigma, tau, mu, margin;
+  int32_t coarse_normal;
 } imrt_geometry;
 
 /* Solver settings (Section 2.2). */
@@ -218,8 +226,9 @@ IMRT_API int imrt_ctx_get_option(const imrt_ctx* ctx, const char* name, int64_t*
  * CSC in the given storage, from float32 values; columns ascending in each row, rows
  * ascending in each column; the rows are held in the internal voxel order
  * of the "voxel_tiles" option, and imrt_dose_export returns grid order).
- * voxel_struct_out: nullable host array of nx*ny*nz bytes receiving the
- * structure ids (grid order j = ix + nx*(iy + ny*iz)).  Beamlet order:
+ * voxel_struct_out: nullable host array receiving the nv structure ids
+ * (grid order j = ix + nx*(iy + ny*iz); with coarse_normal the layout's
+ * voxel order, nv <= nx*ny*nz, so nx*ny*nz bytes always suffice).  Beamlet order:
  * beam-major, then lateral index, then axial index. */
 IMRT_API int imrt_build_dose_matrix(imrt_ctx* ctx, const imrt_geometry* geom, imrt_dtype storage,
                            imrt_dose** out, uint8_t* voxel_struct_out);

@@ -11,9 +11,17 @@
 //                  min((lo_a - p_a)/dir_a, (hi_a - p_a)/dir_a)
 //   lateral        u = (-sin)*x + cos*y,  v = z
 //   exponent       e = (mu*depth) + (((u-u_c)^2 + (v-v_c)^2) / ((2*sigma)*sigma))
-//   kept           e <= e_min(beamlet) + log(1/tau)
+//   kept           e <= e_min(beamlet) + log(1/tau), e_min over every grid voxel
 //   value          float32(exp(-e))
 // Beam angles' cosines/sines and log(1/tau) are computed once on the host.
+//
+// Unspecified tissue at twice the voxel size (Section 3.1): with
+// coarse_normal, every aligned, complete 2x2x2 block of grid voxels that are
+// all normal tissue becomes one voxel centred at
+//   c_a = (2*b_a + 1)*h - (n_a*h)/2
+// of structure "normal".  The voxels crossing the API are then the remaining
+// grid voxels (grid index ascending) followed by the coarse voxels (block
+// index bx + (nx/2)*(by + (ny/2)*bz) ascending).
 #pragma clang fp contract(off)
 
 #include <algorithm>
@@ -27,6 +35,8 @@ namespace {
 
 struct Geo {
   int nx, ny, nz;
+  int ngrid, nv;               // grid voxels; rows of D (the layout's voxels)
+  int cx, cy;                  // coarse blocks per x row and per y column (nx/2, ny/2)
   double h, hx, hy;            // half extents (n*h)/2 in x and y
   double r_ptv, r_rectum, r_bladder;
   double mu, two_sig2;         // (2*sigma)*sigma
@@ -54,6 +64,25 @@ __device__ __forceinline__ void voxel_xyz(const Geo& g, int j, double& x, double
   z = centre(iz, g.nz, g.h);
 }
 
+__device__ __forceinline__ double coarse_centre(int b, int n, double h) {
+  return (2.0 * static_cast<double>(b) + 1.0) * h - (static_cast<double>(n) * h) / 2.0;
+}
+
+// Centre of the voxel with point code c: a grid index (c >= 0) or the coarse
+// block -1 - c.
+__device__ __forceinline__ void voxel_point(const Geo& g, int c, double& x, double& y, double& z) {
+  if (c >= 0) {
+    voxel_xyz(g, c, x, y, z);
+    return;
+  }
+  const int b = -1 - c;
+  const int bx = b % g.cx;
+  const int t = b / g.cx;
+  x = coarse_centre(bx, g.nx, g.h);
+  y = coarse_centre(t % g.cy, g.ny, g.h);
+  z = coarse_centre(t / g.cy, g.nz, g.h);
+}
+
 __device__ __forceinline__ void depth_u(const Geo& g, double x, double y, double c, double s,
                                         double& depth, double& u) {
   double t = 0.0;
@@ -78,17 +107,21 @@ __device__ __forceinline__ double exponent(const Geo& g, double depth, double u,
   return (g.mu * depth) + (r2 / g.two_sig2);
 }
 
-// Rows of D follow the internal voxel order: row p is voxel vox[p] (p itself
-// when vox is NULL).
-__device__ __forceinline__ int voxel_of(const int32_t* vox, int p) { return vox ? vox[p] : p; }
+// Rows of D follow the internal voxel order: row p is the voxel with point
+// code code[p] (grid voxel p itself when code is NULL).
+__device__ __forceinline__ int code_of(const int32_t* code, int p) { return code ? code[p] : p; }
 
-__global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, const int32_t* vox, uint8_t* sid) {
-  const int nv = g.nx * g.ny * g.nz;
+// Structure id of rows [0, n): coarse voxels are normal tissue.
+__global__ __launch_bounds__(kThreads) void structure_kernel(Geo g, int n, const int32_t* code, uint8_t* sid) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
-  if (p >= nv) return;
-  const int j = voxel_of(vox, p);
+  if (p >= n) return;
+  const int c = code_of(code, p);
+  if (c < 0) {
+    sid[p] = 0;
+    return;
+  }
   double x, y, z;
-  voxel_xyz(g, j, x, y, z);
+  voxel_xyz(g, c, x, y, z);
   uint8_t s = 0;
   const double cb = g.r_ptv + g.r_bladder;
   const double dyb = y - cb;
@@ -106,9 +139,8 @@ __global__ __launch_bounds__(kThreads) void emin_kernel(Geo g, const BeamletDev*
   const int i = blockIdx.x;
   const BeamletDev b = bl[i];
   const double2 d = dirs[b.beam];
-  const int nv = g.nx * g.ny * g.nz;
   double m = INFINITY;
-  for (int j = threadIdx.x; j < nv; j += kThreads) {
+  for (int j = threadIdx.x; j < g.ngrid; j += kThreads) {
     double x, y, z, depth, u;
     voxel_xyz(g, j, x, y, z);
     depth_u(g, x, y, d.x, d.y, depth, u);
@@ -126,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void emin_kernel(Geo g, const BeamletDev*
 
 // One workgroup per beamlet: ordered compaction of the kept voxels (CSC).
 // With fill == false only the count is produced.
-__global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* vox, const BeamletDev* bl,
+__global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* code, const BeamletDev* bl,
                                                           const double2* dirs, const double* emin, int32_t* counts,
                                                           const int32_t* col_ptr, int32_t* row_idx,
                                                           float* cval, int fill) {
@@ -134,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* 
   const BeamletDev b = bl[i];
   const double2 d = dirs[b.beam];
   const double limit = emin[i] + g.keep_log;
-  const int nv = g.nx * g.ny * g.nz;
+  const int nv = g.nv;
   __shared__ int wave_cnt[kWaves];
   __shared__ int base;
   if (threadIdx.x == 0) base = fill ? col_ptr[i] : 0;
@@ -146,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* 
     double e = 0.0;
     if (p < nv) {
       double x, y, z, depth, u;
-      voxel_xyz(g, voxel_of(vox, p), x, y, z);
+      voxel_point(g, code_of(code, p), x, y, z);
       depth_u(g, x, y, d.x, d.y, depth, u);
       e = exponent(g, depth, u, z, b.u_c, b.v_c);
       keep = e <= limit;
@@ -173,15 +205,14 @@ __global__ __launch_bounds__(kThreads) void column_kernel(Geo g, const int32_t* 
 }
 
 // One thread per voxel: kept beamlets in ascending column order (CSR).
-__global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const int32_t* vox, const BeamletDev* bl,
+__global__ __launch_bounds__(kThreads) void row_kernel(Geo g, const int32_t* code, const BeamletDev* bl,
                                                        const int32_t* beam_first, const double2* dirs,
                                                        const double* emin, int32_t* counts, const int32_t* row_ptr,
                                                        int32_t* col_idx, float* val, int fill) {
-  const int nv = g.nx * g.ny * g.nz;
   const int p = blockIdx.x * kThreads + threadIdx.x;
-  if (p >= nv) return;
+  if (p >= g.nv) return;
   double x, y, z;
-  voxel_xyz(g, voxel_of(vox, p), x, y, z);
+  voxel_point(g, code_of(code, p), x, y, z);
   int pos = fill ? row_ptr[p] : 0;
   for (int beam = 0; beam < g.nbeam; ++beam) {
     const double2 d = dirs[beam];
@@ -344,7 +375,8 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   if (!(G->h > 0) || !(G->beamlet > 0) || !(G->sigma > 0) || !(G->tau > 0 && G->tau <= 1) ||
       !(G->mu >= 0) || !(G->r_ptv > 0) || !(G->r_rectum >= 0) || !(G->r_bladder >= 0) || !(G->margin >= 0))
     return set_error(IMRT_EINVAL, "geometry: lengths, sigma, tau or mu out of range");
-  const int nv = static_cast<int>(nv64);
+  if (G->coarse_normal != 0 && G->coarse_normal != 1) return set_error(IMRT_EINVAL, "geometry: coarse_normal must be 0 or 1");
+  const int ngrid = static_cast<int>(nv64);
 
   // Beam directions and beamlets on the host (libm cos/sin, exact integer scans).
   std::vector<double2> dirs(G->n_beams);
@@ -375,6 +407,10 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
 
   Geo g;
   g.nx = G->nx; g.ny = G->ny; g.nz = G->nz;
+  g.ngrid = ngrid;
+  g.nv = ngrid;
+  g.cx = G->nx / 2;
+  g.cy = G->ny / 2;
   g.h = G->h;
   g.hx = (static_cast<double>(G->nx) * G->h) / 2.0;
   g.hy = (static_cast<double>(G->ny) * G->h) / 2.0;
@@ -386,49 +422,128 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
 
   hipStream_t s = ctx->stream;
   (void)hipGetLastError();  // drop an error left by an unrelated earlier call
-  DevBuf d_bl, d_first, d_dirs, d_emin, d_cnt_c, d_cnt_r;
+  DevBuf d_bl, d_first, d_dirs, d_emin, d_cnt_c, d_cnt_r, d_code;
   IMRT_HIP(hipMalloc(&d_bl.p, sizeof(BeamletDev) * nb));
   IMRT_HIP(hipMalloc(&d_first.p, sizeof(int32_t) * (G->n_beams + 1)));
   IMRT_HIP(hipMalloc(&d_dirs.p, sizeof(double2) * G->n_beams));
   IMRT_HIP(hipMalloc(&d_emin.p, sizeof(double) * nb));
   IMRT_HIP(hipMalloc(&d_cnt_c.p, sizeof(int32_t) * nb));
-  IMRT_HIP(hipMalloc(&d_cnt_r.p, sizeof(int32_t) * nv));
   IMRT_HIP(hipMemcpyAsync(d_bl.p, bls.data(), sizeof(BeamletDev) * nb, hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(d_first.p, beam_first.data(), sizeof(int32_t) * (G->n_beams + 1),
                           hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(d_dirs.p, dirs.data(), sizeof(double2) * G->n_beams, hipMemcpyHostToDevice, s));
 
-  // internal voxel order: tiles of 4 x 4 x 2 voxels (x fastest inside a tile,
-  // tiles in x, y, z order), so that the voxels a beamlet crosses sit close
-  // together in memory whatever the beam direction; row p of D is voxel vox[p]
+  // Voxel layout.  api_code[a] is the point code of the voxel with API index
+  // a (empty for a uniform grid, where the API index is the grid index);
+  // fine_api and block_api give the API index of a grid voxel and of a
+  // coarse block (-1: merged into a block, or not coarse).
+  std::vector<int32_t> api_code, fine_api, block_api;
+  int nv = ngrid;
+  if (G->coarse_normal) {
+    DevBuf d_gsid;
+    IMRT_HIP(hipMalloc(&d_gsid.p, static_cast<size_t>(ngrid)));
+    hipLaunchKernelGGL(structure_kernel, dim3((ngrid + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g, ngrid,
+                       static_cast<const int32_t*>(nullptr), static_cast<uint8_t*>(d_gsid.p));
+    IMRT_HIP(hipGetLastError());
+    std::vector<uint8_t> gsid(static_cast<size_t>(ngrid));
+    IMRT_HIP(hipMemcpyAsync(gsid.data(), d_gsid.p, static_cast<size_t>(ngrid), hipMemcpyDeviceToHost, s));
+    IMRT_HIP(hipStreamSynchronize(s));
+    const int cx = g.cx, cy = g.cy, cz = G->nz / 2;
+    std::vector<uint8_t> merged(static_cast<size_t>(ngrid), 0);
+    std::vector<int32_t> blocks;
+    block_api.assign(static_cast<size_t>(cx) * cy * cz, -1);
+    for (int bz = 0; bz < cz; ++bz)
+      for (int by = 0; by < cy; ++by)
+        for (int bx = 0; bx < cx; ++bx) {
+          bool normal = true;
+          for (int d = 0; d < 8 && normal; ++d) {
+            const int j = (2 * bx + (d & 1)) + G->nx * ((2 * by + ((d >> 1) & 1)) + G->ny * (2 * bz + (d >> 2)));
+            normal = gsid[j] == 0;
+          }
+          if (!normal) continue;
+          blocks.push_back(bx + cx * (by + cy * bz));
+          for (int d = 0; d < 8; ++d)
+            merged[(2 * bx + (d & 1)) + G->nx * ((2 * by + ((d >> 1) & 1)) + G->ny * (2 * bz + (d >> 2)))] = 1;
+        }
+    fine_api.assign(static_cast<size_t>(ngrid), -1);
+    api_code.reserve(static_cast<size_t>(ngrid));
+    for (int j = 0; j < ngrid; ++j)
+      if (!merged[j]) {
+        fine_api[j] = static_cast<int32_t>(api_code.size());
+        api_code.push_back(j);
+      }
+    for (int32_t b : blocks) {
+      block_api[b] = static_cast<int32_t>(api_code.size());
+      api_code.push_back(-1 - b);
+    }
+    nv = static_cast<int>(api_code.size());
+  }
+  g.nv = nv;
+
+  // Internal voxel order: tiles of 4 x 4 x 2 grid voxels (x fastest inside a
+  // tile, tiles in x, y, z order; a tile's coarse voxels after its grid
+  // voxels), so that the voxels a beamlet crosses sit close together in
+  // memory whatever the beam direction.  Row p of D is the voxel with API
+  // index vox[p] and point code codes[p].
+  std::vector<int32_t> codes;
   if (ctx->tune.voxel_tiles) {
     constexpr int tx = 4, ty = 4, tz = 2;
     D->vox_host.resize(static_cast<size_t>(nv));
+    codes.resize(static_cast<size_t>(nv));
     int64_t p = 0;
     for (int z0 = 0; z0 < G->nz; z0 += tz)
       for (int y0 = 0; y0 < G->ny; y0 += ty)
-        for (int x0 = 0; x0 < G->nx; x0 += tx)
+        for (int x0 = 0; x0 < G->nx; x0 += tx) {
           for (int z = z0; z < std::min(z0 + tz, G->nz); ++z)
             for (int y = y0; y < std::min(y0 + ty, G->ny); ++y)
-              for (int x = x0; x < std::min(x0 + tx, G->nx); ++x)
-                D->vox_host[p++] = x + G->nx * (y + G->ny * z);
+              for (int x = x0; x < std::min(x0 + tx, G->nx); ++x) {
+                const int j = x + G->nx * (y + G->ny * z);
+                const int a = api_code.empty() ? j : fine_api[j];
+                if (a < 0) continue;
+                if (p >= nv) return set_error(IMRT_EINVAL, "internal: voxel tiles overrun the layout");
+                D->vox_host[p] = a;
+                codes[p] = j;
+                ++p;
+              }
+          if (api_code.empty()) continue;
+          const int bz = z0 / 2;
+          if (bz >= G->nz / 2) continue;
+          for (int by = y0 / 2; by < std::min(y0 / 2 + ty / 2, g.cy); ++by)
+            for (int bx = x0 / 2; bx < std::min(x0 / 2 + tx / 2, g.cx); ++bx) {
+              const int b = bx + g.cx * (by + g.cy * bz);
+              const int a = block_api[b];
+              if (a < 0) continue;
+              if (p >= nv) return set_error(IMRT_EINVAL, "internal: voxel tiles overrun the layout");
+              D->vox_host[p] = a;
+              codes[p] = -1 - b;
+              ++p;
+            }
+        }
+    if (p != nv) return set_error(IMRT_EINVAL, "internal: voxel tiles do not cover the layout");
     IMRT_HIP(hipMalloc(&D->vox, sizeof(int32_t) * nv));
     IMRT_HIP(hipMemcpyAsync(D->vox, D->vox_host.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s));
+  } else if (!api_code.empty()) {
+    codes = api_code;   // rows in API order
   }
-  const int32_t* vox = D->vox;
+  if (!codes.empty()) {
+    IMRT_HIP(hipMalloc(&d_code.p, sizeof(int32_t) * nv));
+    IMRT_HIP(hipMemcpyAsync(d_code.p, codes.data(), sizeof(int32_t) * nv, hipMemcpyHostToDevice, s));
+  }
+  const int32_t* code = static_cast<const int32_t*>(d_code.p);
+  IMRT_HIP(hipMalloc(&d_cnt_r.p, sizeof(int32_t) * nv));
   IMRT_HIP(hipMalloc(&D->sid, nv));
   const int vgrid = (nv + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(structure_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, D->sid);
+  hipLaunchKernelGGL(structure_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, nv, code, D->sid);
   IMRT_HIP(hipGetLastError());
   const auto* blp = static_cast<const BeamletDev*>(d_bl.p);
   const auto* dp = static_cast<const double2*>(d_dirs.p);
   auto* em = static_cast<double*>(d_emin.p);
   hipLaunchKernelGGL(emin_kernel, dim3(nb), dim3(kThreads), 0, s, g, blp, dp, em);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, vox, blp, dp, em,
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, code, blp, dp, em,
                      static_cast<int32_t*>(d_cnt_c.p), nullptr, nullptr, nullptr, 0);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, blp,
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, code, blp,
                      static_cast<const int32_t*>(d_first.p), dp, em, static_cast<int32_t*>(d_cnt_r.p),
                      nullptr, nullptr, nullptr, 0);
   IMRT_HIP(hipGetLastError());
@@ -460,10 +575,10 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
   if (arc) return arc;
   IMRT_HIP(hipMemcpyAsync(D->row_ptr, row_ptr.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_ptr, col_ptr.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, vox, blp, dp, em, nullptr, D->col_ptr,
+  hipLaunchKernelGGL(column_kernel, dim3(nb), dim3(kThreads), 0, s, g, code, blp, dp, em, nullptr, D->col_ptr,
                      D->row_idx, D->cval, 1);
   IMRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, vox, blp,
+  hipLaunchKernelGGL(row_kernel, dim3(vgrid), dim3(kThreads), 0, s, g, code, blp,
                      static_cast<const int32_t*>(d_first.p), dp, em, nullptr, D->row_ptr, D->col_idx,
                      D->val, 1);
   IMRT_HIP(hipGetLastError());

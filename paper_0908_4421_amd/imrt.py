@@ -36,7 +36,8 @@ class imrt_geometry(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("h", C.c_double),
                 ("r_ptv", C.c_double), ("r_rectum", C.c_double), ("r_bladder", C.c_double),
                 ("n_beams", C.c_int32), ("beamlet", C.c_double), ("sigma", C.c_double),
-                ("tau", C.c_double), ("mu", C.c_double), ("margin", C.c_double)]
+                ("tau", C.c_double), ("mu", C.c_double), ("margin", C.c_double),
+                ("coarse_normal", C.c_int32)]
 
 
 class imrt_solve_params(C.Structure):
@@ -657,4 +658,5 @@ class Server:
 def geometry_of(spec) -> imrt_geometry:
     """imrt_geometry from a workload PhantomSpec (duck-typed)."""
     return imrt_geometry(spec.nx, spec.ny, spec.nz, spec.h, spec.r_ptv, spec.r_rectum, spec.r_bladder,
-                         spec.n_beams, spec.beamlet, spec.sigma, spec.tau, spec.mu, spec.margin)
+                         spec.n_beams, spec.beamlet, spec.sigma, spec.tau, spec.mu, spec.margin,
+                         1 if getattr(spec, "coarse_normal", False) else 0)

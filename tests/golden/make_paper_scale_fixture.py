@@ -1,8 +1,10 @@
 """Write the oracle's fingerprint of the paper-scale phantom and its full
-Armijo trajectory (tests/golden/paper_scale_oracle.json).
+Armijo trajectory (tests/golden/paper_scale_oracle.json; with --coarse, of
+the same phantom with unspecified tissue at twice the voxel size, to
+tests/golden/paper_scale_coarse_oracle.json).
 
 Calls only the FP64 oracle and the workload specification.  Run from the
-repository root:  python tests/golden/make_paper_scale_fixture.py
+repository root:  python tests/golden/make_paper_scale_fixture.py [--coarse]
 (about two minutes on one core plus the parallel matrix build).
 """
 import hashlib
@@ -17,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import model, phantom, solver  # noqa: E402
-from workloads import PAPER_SCALE, PAPER_SCALE_SETTINGS, penalty_table, power_start_vector, start_point  # noqa: E402
+from workloads import (PAPER_SCALE, PAPER_SCALE_COARSE, PAPER_SCALE_SETTINGS, penalty_table,  # noqa: E402
+                       power_start_vector, start_point)
 
 
 EXTRA = 40   # iterations stored beyond the oracle's stop
@@ -28,7 +31,9 @@ def sha(a, dtype):
 
 
 def main():
-    spec, st = PAPER_SCALE, PAPER_SCALE_SETTINGS
+    coarse = "--coarse" in sys.argv[1:]
+    spec, st = (PAPER_SCALE_COARSE if coarse else PAPER_SCALE), PAPER_SCALE_SETTINGS
+    name = "paper_scale_coarse_oracle.json" if coarse else "paper_scale_oracle.json"
     t0 = time.time()
     D = phantom.build_dose_matrix(spec, workers=9)
     emin = phantom.column_minima(spec)
@@ -60,9 +65,9 @@ def main():
         "trace_note": f"the stopped trajectory's {res.iterations} iterations, then {EXTRA} more (stopping test off)",
         "seconds": time.time() - t0,
     }
-    with open(os.path.join(HERE, "paper_scale_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f)
-    print("wrote paper_scale_oracle.json", res.iterations, res.G, time.time() - t0)
+    print("wrote", name, res.iterations, res.G, time.time() - t0)
 
 
 if __name__ == "__main__":

@@ -61,3 +61,16 @@ def test_tile_order_matches_nested_tiles():
                             for x in range(x0, min(x0 + 4, nx)):
                                 want.append(x + nx * (y + ny * z))
         assert bench.tile_order(nx, ny, nz).tolist() == want
+
+
+def test_shared_live_time_by_hand():
+    import bench
+    # patient 0: [0, 10) and [5, 20) overlap for 5 ms each way; patient 1 alone;
+    # a third plan of patient 0 inside [12, 14) overlaps the second only
+    live = [(0.0, 10.0), (5.0, 20.0), (0.0, 30.0), (12.0, 14.0)]
+    patients = [0, 0, 1, 0]
+    shared, total, partners = bench.shared_live_time(live, patients)
+    assert total == 10 + 15 + 30 + 2
+    assert shared == 5 + (5 + 2) + 0 + 2      # overlaps of [5,20) with [0,10) and [12,14) are disjoint
+    assert partners == 3
+    assert bench.shared_live_time([(0.0, 1.0)], [7]) == (0.0, 1.0, 0)
