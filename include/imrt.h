@@ -202,6 +202,11 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    created afterwards runs between polls (1..4096,
  *                    default 16): more groups poll less often, fewer admit
  *                    and retire sooner
+ *   "serve_shared_adjoint"  1 (default): live solves of a server created
+ *                    afterwards that share a resident dose matrix (re-plans
+ *                    of one patient) take their gradients from one pass over
+ *                    its CSC, up to four solves per pass, each solve's
+ *                    arithmetic unchanged; 0: one pass per solve
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "fwd_col16"      1 (default): float32 matrices with nb <= 65536 created
@@ -433,6 +438,10 @@ IMRT_API int imrt_server_wait(imrt_server* server, int64_t ticket, float* x_out,
                               imrt_solve_result* result, imrt_serve_times* times, int64_t timeout_ms);
 IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t* peak_bytes,
                                int64_t* resident_matrices, int64_t* served);
+/* Adjoint dispatch groups the server has run: *shared counts those that
+ * served two or more solves on one resident matrix in one pass over its
+ * CSC (the shared-matrix adjoint), *total all of them.  Either may be NULL. */
+IMRT_API int imrt_server_adjoint_groups(imrt_server* server, int64_t* shared, int64_t* total);
 /* Finishes the queued and live requests, then frees everything. */
 IMRT_API int imrt_server_destroy(imrt_server* server);
 

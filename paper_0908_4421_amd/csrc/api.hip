@@ -547,6 +547,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
   }
   if (n == "serve_fwd_blocks_per_wave") return &ctx->tune.serve_fwd_bpw;
   if (n == "serve_groups_per_poll") return &ctx->tune.serve_groups;
+  if (n == "serve_shared_adjoint") {
+    *lo = 0;
+    return &ctx->tune.serve_shared_adj;
+  }
   if (n == "adj_xcd") {
     *lo = 0;
     return &ctx->tune.adj_xcd;
@@ -565,7 +569,9 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
   int* slot = option_slot(ctx, name, &lo);
   if (!slot) return set_error(IMRT_EINVAL, std::string("unknown option: ") + (name ? name : "(null)"));
   const std::string nm(name);
-  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles" || nm == "fwd_col16") ? 1
+  const int64_t hi = (nm == "fwd_wave" || nm == "adj_xcd" || nm == "voxel_tiles" || nm == "fwd_col16" ||
+                      nm == "serve_shared_adjoint")
+                         ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
                      : (nm == "fwd_blocks_per_wave" || nm == "serve_fwd_blocks_per_wave") ? 1024
                      : (nm == "serve_groups_per_poll")                                      ? 4096
@@ -1517,9 +1523,16 @@ struct BatchBuffers {
   hipEvent_t ev_start = nullptr, ev_end = nullptr, ev_poll[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // graphs replaced while a launch of theirs may still be queued; destroyed
+  // with the buffers, after the batch's stream has drained (the stream guard
+  // of imrt_solve_batch is destroyed first and synchronises it)
+  std::vector<hipGraphExec_t> old_exec;
+  std::vector<hipGraph_t> old_graph;
   ~BatchBuffers() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    for (hipGraphExec_t x : old_exec) (void)hipGraphExecDestroy(x);
+    for (hipGraph_t g : old_graph) (void)hipGraphDestroy(g);
     for (hipEvent_t e : {ev_start, ev_end, ev_poll[0], ev_poll[1]})
       if (e) (void)hipEventDestroy(e);
     if (poll) (void)hipHostFree(poll);
@@ -1636,8 +1649,9 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   // from the slot tables (stream-ordered uploads, then a new capture).
   const long long K = C->tune.batch_iters;
   auto capture = [&]() -> int {
-    if (B.exec) (void)hipGraphExecDestroy(B.exec);
-    if (B.graph) (void)hipGraphDestroy(B.graph);
+    // the previous graph may still have a launch queued: keep it until the end
+    if (B.exec) B.old_exec.push_back(B.exec);
+    if (B.graph) B.old_graph.push_back(B.graph);
     B.exec = nullptr;
     B.graph = nullptr;
     hipError_t r = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);

@@ -176,6 +176,7 @@ struct Tuning {
   int serve_adj_min_nnz = 32768;   // the same two for matrices a server builds, which
   int serve_fwd_bpw = 4;           // share every dispatch with other live plans
   int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
+  int serve_shared_adj = 1;        // live solves on one resident matrix share its adjoint pass
 };
 
 }  // namespace imrt
@@ -313,6 +314,11 @@ int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t
                          int storage, size_t lds);
 int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
                          int storage);
+// Adjoint passes of groups of solves sharing a dose matrix: groups[(K + 1) g]
+// = n <= K, then n plan indices into args; slots = (group << 16) | workgroup.
+// group_k (K) is 2 or 4.
+int launch_adjoint_multi_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* groups, int group_k,
+                               const int32_t* slots, int nslots, int ntrials, int storage);
 int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);

@@ -1584,6 +1584,163 @@ __global__ __launch_bounds__(kThreads) void adj_batch_kernel(const AdjArgs* __re
   adj_pass<NT, true, ST>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
+// Adjoint pass of n <= K solves that share one dose matrix (the same CSC
+// arrays and work partition; re-plans of one resident patient): the
+// matrix stream of the workgroup's range is read once, and every solve gets
+// exactly the arithmetic adj_pass gives it alone -- its own decision, its
+// residual gathers, its float64 column sums in the same order and the same
+// workgroup-level reductions, its outputs.  plans[q] indexes args.
+template <int NT, int ST, int K>
+__device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args, const int32_t* plans, int n,
+                                               const Slot sl) {
+  __shared__ double red[kWaves];
+  __shared__ Decision dec[K];
+  const AdjArgs& a = args[uniform(plans[0])];   // the shared matrix and partition
+  const int tid = threadIdx.x;
+  const int lw = logical_wg(sl, a.xcd_map != 0);
+  const int k0w = split_point(lw, static_cast<int>(a.nnz), a.grid);
+  const int k1w = split_point(lw + 1, static_cast<int>(a.nnz), a.grid);
+  const int kb = k0w & ~(kTile - 1);
+  const int nrounds = (k1w > kb) ? (k1w - kb + kAdjStep - 1) / kAdjStep : 0;
+  const uint32_t bytes = static_cast<uint32_t>((((k1w + kTile - 1) & ~(kTile - 1)) - kb) * 4);
+  const rsrc_t ri = make_rsrc(a.row_idx + kb, bytes);
+  const rsrc_t rv = (ST == ST_F32) ? make_rsrc(a.val + kb, bytes) : make_rsrc(a.val16 + kb, bytes / 2);
+  int pi[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) pi[q] = uniform(plans[q < n ? q : 0]);
+  DecideLoads<NT> DL[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) decide_start<NT>(args[pi[q]], DL[q]);
+  const int4 wi = load_i4(make_rsrc(a.wg_cols, 16u * static_cast<uint32_t>(a.grid)), 16u * static_cast<uint32_t>(lw));
+  AdjStage<ST> A, B;
+  adj_issue(ri, rv, 0, A);
+  adj_issue(ri, rv, 1, B);
+  const int c0 = uniform(wi.x), c1 = uniform(wi.y);
+  int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
+  float csc = 1.0f;
+  if constexpr (coded(ST)) csc = a.col_scale[c < c1 ? c : 0];
+  auto bounds = [&]() {
+    lo = max(uniform(a.col_ptr[c]), k0w);
+    hi = min(uniform(a.col_ptr[c + 1]), k1w);
+    if constexpr (coded(ST)) csc = a.col_scale[c];
+  };
+  const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
+  rsrc_t rr[K];
+  float g[K][8];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    rr[q] = make_rsrc(q < n ? args[pi[q]].rbuf[0] : nullptr, q < n ? rbytes : 0u);
+    adj_gather(rr[q], A, g[q]);
+  }
+  bool need[K];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    need[q] = false;
+    if (q < n) {
+      const AdjArgs& aq = args[pi[q]];
+      decide<NT>(aq.fwd_partials, aq.fwd_parts, aq.step_partials, aq.step_parts, DL[q], dec[q], red);
+      if (sl.w == 0 && tid == 0) {
+        *aq.st_out = dec[q].st;
+        if (dec[q].accepted >= 0 && aq.trace != nullptr && dec[q].st.k - 1 < dec[q].st.trace_cap) {
+          TraceDev e;
+          e.k = dec[q].st.k;
+          e.backtracks = dec[q].backtracks;
+          e.lambda = dec[q].lam;
+          e.step_sq = dec[q].step_sq;
+          e.G = dec[q].st.G;
+          aq.trace[dec[q].st.k - 1] = e;
+        }
+      }
+      need[q] = dec[q].st.phase == PH_NEED_GRAD;
+      if (need[q] && dec[q].st.acc != 0) {
+        rr[q] = make_rsrc(select_buf(aq.rbuf, dec[q].st.acc), rbytes);
+        adj_gather(rr[q], A, g[q]);
+      }
+      if (!need[q]) rr[q] = make_rsrc(nullptr, 0u);
+      any = any || need[q];
+    }
+  }
+  if (!any) return;
+
+  double s[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) s[q] = 0.0;
+  auto close = [&]() {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      if (!need[q]) continue;
+      const AdjArgs& aq = args[pi[q]];
+      const double t = block_sum(s[q], red);
+      if (tid == 0) {
+        const int wlo = a.col_wlo[c], whi = a.col_whi[c];
+        if (wlo == whi) {
+          const double f = (ST == ST_F32) ? aq.scale : aq.scale * static_cast<double>(csc);
+          aq.out[c] = static_cast<float>(f * t);
+        } else {
+          if (c == c0) aq.pieces[2 * lw] = t;
+          if (c == c1 - 1) aq.pieces[2 * lw + 1] = t;
+          if (whi - wlo == 1 && aq.pieces_col != nullptr) aq.pieces_col[2 * c + (lw - wlo)] = t;
+        }
+      }
+      s[q] = 0.0;
+    }
+    ++c;
+    if (c < c1) bounds();
+  };
+  auto consume = [&](const AdjStage<ST>& cur, const float (&gv)[K][8], int round) {
+    const int base = kb + round * kAdjStep, end = base + kAdjStep;
+    while (c < c1 && lo < end) {
+      if (lo <= base && hi >= end) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+          if (need[q]) s[q] += adj_dot(cur, gv[q]);
+        if (hi == end) close();
+        break;
+      }
+      const int e0 = base + 256 * (tid >> 6) + (tid & 63);
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        if (need[q]) s[q] += adj_dot_masked(cur, gv[q], e0, lo, hi);
+      if (hi > end) break;
+      close();
+    }
+  };
+  int round = 0;
+  if (nrounds > 0) {
+    consume(A, g, 0);
+    round = 1;
+    auto step = [&](const AdjStage<ST>& cur, AdjStage<ST>& nxt) {
+      float gv[K][8];
+#pragma unroll
+      for (int q = 0; q < K; ++q) adj_gather(rr[q], cur, gv[q]);
+      if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+      consume(cur, gv, round);
+      ++round;
+      return round < nrounds;
+    };
+    while (round < nrounds) {
+      if (!step(B, A)) break;
+      if (!step(A, B)) break;
+    }
+  }
+  while (c < c1) close();
+}
+
+// Batched adjoint pass over groups of solves sharing a dose matrix:
+// slots[blockIdx.x] = (group << 16) | workgroup (or -1), groups[(K + 1) g]
+// = the group's size n, then its n plan indices.
+template <int NT, int ST, int K>
+__global__ __launch_bounds__(kThreads) void adj_multi_batch_kernel(const AdjArgs* __restrict__ args,
+                                                                   const int32_t* __restrict__ groups,
+                                                                   const int32_t* __restrict__ slots) {
+  const int sv = uniform(slots[blockIdx.x]);
+  if (sv < 0) return;
+  const int32_t* gr = groups + static_cast<size_t>(sv >> 16) * (K + 1);
+  const int n = uniform(gr[0]);
+  adj_multi_pass<NT, ST, K>(args, gr + 1, n, Slot{sv & 0xFFFF, args[uniform(gr[1])].grid});
+}
+
 // Columns shared by several adjoint workgroups (completion not folded): the
 // fixed-order sum of their pieces.  Runs after adj_kernel; in a solve only
 // when that pass computed a gradient (state after the decision in `st`).
@@ -1784,6 +1941,43 @@ int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t
   }
   if (rc) return rc;
   return check_launch("adj_batch_kernel");
+}
+
+template <int ST, int K>
+int launch_adjoint_multi_st(const AdjArgs* args, const int32_t* groups, const int32_t* slots, int nslots,
+                            int ntrials, hipStream_t s) {
+  const dim3 gd(nslots), bd(kThreads);
+  switch (ntrials) {
+    case 1: hipLaunchKernelGGL((adj_multi_batch_kernel<1, ST, K>), gd, bd, 0, s, args, groups, slots); break;
+    case 2: hipLaunchKernelGGL((adj_multi_batch_kernel<2, ST, K>), gd, bd, 0, s, args, groups, slots); break;
+    case 4: hipLaunchKernelGGL((adj_multi_batch_kernel<4, ST, K>), gd, bd, 0, s, args, groups, slots); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return IMRT_OK;
+}
+
+template <int K>
+int launch_adjoint_multi_k(const AdjArgs* args, const int32_t* groups, const int32_t* slots, int nslots,
+                           int ntrials, int storage, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: return launch_adjoint_multi_st<ST_F32, K>(args, groups, slots, nslots, ntrials, s);
+    case ST_BF16: return launch_adjoint_multi_st<ST_BF16, K>(args, groups, slots, nslots, ntrials, s);
+    case ST_F16: return launch_adjoint_multi_st<ST_F16, K>(args, groups, slots, nslots, ntrials, s);
+    default: return set_error(IMRT_EINVAL, "unknown storage");
+  }
+}
+
+int launch_adjoint_multi_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* groups, int group_k,
+                               const int32_t* slots, int nslots, int ntrials, int storage) {
+  if (nslots <= 0) return IMRT_OK;
+  int rc;
+  switch (group_k) {
+    case 2: rc = launch_adjoint_multi_k<2>(args, groups, slots, nslots, ntrials, storage, ctx->stream); break;
+    case 4: rc = launch_adjoint_multi_k<4>(args, groups, slots, nslots, ntrials, storage, ctx->stream); break;
+    default: return set_error(IMRT_EINVAL, "shared-matrix adjoint groups hold 2 or 4 solves");
+  }
+  if (rc) return rc;
+  return check_launch("adj_multi_batch_kernel");
 }
 
 int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, int ntrials, int grid,

@@ -115,7 +115,10 @@ struct imrt_server {
   AdjArgs* aargs = nullptr;
   int32_t* fslots = nullptr;
   int32_t* aslots = nullptr;
-  size_t fslot_cap = 0, aslot_cap = 0;
+  int32_t* gtab = nullptr;      // shared-matrix adjoint groups
+  size_t fslot_cap = 0, aslot_cap = 0, gtab_cap = 0;
+  int64_t shared_groups = 0;    // adjoint dispatch groups that served two or more solves at once
+  int64_t adj_groups = 0;       // adjoint dispatch groups in all
   std::vector<Live> live;       // index = batch slot of the plan
   std::vector<char> occupied;
   int64_t served = 0;
@@ -123,6 +126,8 @@ struct imrt_server {
 };
 
 namespace {
+
+constexpr size_t kShareMax = 4;   // solves per shared-matrix adjoint group
 
 int grow_slots(imrt_server* S, int32_t** p, size_t* cap, size_t need) {
   if (need <= *cap) return IMRT_OK;
@@ -297,7 +302,7 @@ void worker_main(imrt_server* S) {
   hipStream_t s = C->stream;
   const int K = std::max(1, S->ctx.tune.serve_groups);   // groups between polls: bounds a new request's wait
   std::vector<SolverState> seen(2 * static_cast<size_t>(S->max_live));
-  std::vector<int32_t> fs, as;
+  std::vector<int32_t> fs, as, gt;
   for (;;) {
     // admission, in arrival order, while a slot and memory are free
     std::vector<Pending> take;
@@ -354,6 +359,7 @@ void worker_main(imrt_server* S) {
     // slot tables of the live plans (each at a multiple of the die count)
     fs.clear();
     as.clear();
+    gt.clear();
     int storage = -1, fst = -1, nt = 1;
     size_t lds = 0;
     bool mixed = false;
@@ -368,22 +374,67 @@ void worker_main(imrt_server* S) {
       mixed = mixed || D->storage != storage || D->fwd_st != fst || L.nt != nt;
       while (fs.size() % kXcds) fs.push_back(-1);
       for (int w = 0; w < L.grid; ++w) fs.push_back((i << 16) | w);
-      while (as.size() % kXcds) as.push_back(-1);
-      for (int w = 0; w < D->adj_grid; ++w) as.push_back((i << 16) | w);
       lds = std::max(lds, forward_lds_bytes(D->nb, L.nt, L.plan->nstruct, true, D->fwd_st));
+    }
+    // Adjoint slots: the live solves on one resident matrix (re-plans of a
+    // patient) form groups of up to kShareMax that read the matrix once per
+    // pass (shared-matrix adjoint); without sharing every solve is its own
+    // group.  Each group takes the matrix's adjoint grid of slots.
+    std::vector<std::vector<int>> groups;
+    {
+      std::vector<const imrt_dose*> order;
+      std::map<const imrt_dose*, std::vector<int>> by_dose;
+      for (int i : active) {
+        const imrt_dose* D = S->live[i].plan->dose;
+        if (!S->ctx.tune.serve_shared_adj) {
+          groups.push_back({i});
+          continue;
+        }
+        if (!by_dose.count(D)) order.push_back(D);
+        by_dose[D].push_back(i);
+      }
+      for (const imrt_dose* D : order) {
+        const std::vector<int>& v = by_dose[D];
+        for (size_t j = 0; j < v.size(); j += kShareMax)
+          groups.emplace_back(v.begin() + j, v.begin() + std::min(v.size(), j + kShareMax));
+      }
+    }
+    size_t gmax = 1;
+    for (const auto& g : groups) gmax = std::max(gmax, g.size());
+    const int gk = gmax <= 1 ? 1 : (gmax <= 2 ? 2 : 4);
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const imrt_dose* D = S->live[groups[g][0]].plan->dose;
+      const int id = (gk == 1) ? groups[g][0] : static_cast<int>(g);
+      while (as.size() % kXcds) as.push_back(-1);
+      for (int w = 0; w < D->adj_grid; ++w) as.push_back((id << 16) | w);
+      if (gk > 1) {
+        gt.push_back(static_cast<int32_t>(groups[g].size()));
+        for (int q = 0; q < gk; ++q) gt.push_back(groups[g][std::min<size_t>(q, groups[g].size() - 1)]);
+      }
     }
     int rc = IMRT_OK;
     if (mixed) rc = set_error(IMRT_EINVAL, "live solves of one server must share storage, layout and trials_per_pass");
     if (!rc) rc = grow_slots(S, &S->fslots, &S->fslot_cap, fs.size());
     if (!rc) rc = grow_slots(S, &S->aslots, &S->aslot_cap, as.size());
+    if (!rc && gk > 1) rc = grow_slots(S, &S->gtab, &S->gtab_cap, gt.size());
     hipError_t e = hipSuccess;
     if (!rc) e = hipMemcpyAsync(S->fslots, fs.data(), sizeof(int32_t) * fs.size(), hipMemcpyHostToDevice, s);
     if (!rc && e == hipSuccess)
       e = hipMemcpyAsync(S->aslots, as.data(), sizeof(int32_t) * as.size(), hipMemcpyHostToDevice, s);
+    if (!rc && e == hipSuccess && gk > 1)
+      e = hipMemcpyAsync(S->gtab, gt.data(), sizeof(int32_t) * gt.size(), hipMemcpyHostToDevice, s);
     if (!rc && e != hipSuccess) rc = hip_error(e, "server slot upload");
     for (int k = 0; k < K && !rc; ++k) {
-      rc = launch_adjoint_batch(C, S->aargs, S->aslots, static_cast<int>(as.size()), nt, storage);
+      if (gk == 1) rc = launch_adjoint_batch(C, S->aargs, S->aslots, static_cast<int>(as.size()), nt, storage);
+      else
+        rc = launch_adjoint_multi_batch(C, S->aargs, S->gtab, gk, S->aslots, static_cast<int>(as.size()), nt,
+                                        storage);
       if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, lds);
+    }
+    if (!rc) {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->adj_groups += static_cast<int64_t>(K) * static_cast<int64_t>(groups.size());
+      for (const auto& grp : groups) S->shared_groups += (grp.size() > 1) ? K : 0;
     }
     if (!rc) {
       e = hipMemcpyAsync(seen.data(), S->st, sizeof(SolverState) * 2 * S->max_live, hipMemcpyDeviceToHost, s);
@@ -559,6 +610,14 @@ int imrt_server_stats(imrt_server* S, int64_t* used_bytes, int64_t* peak_bytes, 
   return IMRT_OK;
 }
 
+int imrt_server_adjoint_groups(imrt_server* S, int64_t* shared, int64_t* total) {
+  if (!S) return set_error(IMRT_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> g(S->mu);
+  if (shared) *shared = S->shared_groups;
+  if (total) *total = S->adj_groups;
+  return IMRT_OK;
+}
+
 int imrt_server_destroy(imrt_server* S) {
   if (!S) return IMRT_OK;
   {
@@ -572,7 +631,7 @@ int imrt_server_destroy(imrt_server* S) {
     if (S->occupied[i]) release(S, i);
   for (auto& kv : S->residents) (void)imrt_dose_destroy(kv.second.dose);
   for (void* p : {static_cast<void*>(S->st), static_cast<void*>(S->fargs), static_cast<void*>(S->aargs),
-                  static_cast<void*>(S->fslots), static_cast<void*>(S->aslots)})
+                  static_cast<void*>(S->fslots), static_cast<void*>(S->aslots), static_cast<void*>(S->gtab)})
     if (p) (void)hipFree(p);
   if (S->ctx.stream) (void)hipStreamDestroy(S->ctx.stream);
   delete S;

@@ -119,6 +119,7 @@ SIGNATURES = {
                                    C.POINTER(imrt_serve_times), C.c_int64]),
     "imrt_server_stats": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]),
+    "imrt_server_adjoint_groups": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "imrt_server_destroy": (C.c_int, [_vp]),
     "imrt_last_error": (C.c_char_p, []),
 }
@@ -286,6 +287,12 @@ def imrt_server_stats(server):
     v = [C.c_int64() for _ in range(4)]
     _check(load().imrt_server_stats(server, *[C.byref(x) for x in v]), "imrt_server_stats")
     return dict(zip(("used_bytes", "peak_bytes", "resident_matrices", "served"), (x.value for x in v)))
+
+
+def imrt_server_adjoint_groups(server):
+    shared, total = C.c_int64(), C.c_int64()
+    _check(load().imrt_server_adjoint_groups(server, C.byref(shared), C.byref(total)), "imrt_server_adjoint_groups")
+    return shared.value, total.value
 
 
 def imrt_server_destroy(server):
@@ -641,7 +648,9 @@ class Server:
         return res, times, x
 
     def stats(self):
-        return imrt_server_stats(self.handle)
+        st = imrt_server_stats(self.handle)
+        st["adjoint_groups_shared"], st["adjoint_groups"] = imrt_server_adjoint_groups(self.handle)
+        return st
 
     def close(self):
         if self.handle:

@@ -202,3 +202,45 @@ def test_served_against_oracle(ctx, storage):
         worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=1e-5, slack=slack)
         banner(f"ticket {tk}: {K} iterations (oracle {Ko}), worst G error {worst:.2e}")
     srv.close()
+
+
+def test_shared_matrix_adjoint_equals_alone():
+    """Four re-plans of one patient, two of another and a single new patient,
+    submitted together: the live solves on one resident matrix share each
+    adjoint pass (groups of four and two), and every plan equals the same
+    plan solved alone and served without sharing, bit for bit."""
+    from paper_0908_4421_amd.imrt import Context, Dose, Server
+    from workloads import replan_penalty_table
+    rng = np.random.default_rng(21)
+    reqs = [(30, SMALL, penalty_table(SMALL))] + [(30, SMALL, replan_penalty_table(SMALL, rng)) for _ in range(3)]
+    reqs += [(31, TINY, penalty_table(TINY)), (31, TINY, replan_penalty_table(TINY, rng))]
+    reqs += [(32, draw_batch_instance(1004), penalty_table(draw_batch_instance(1004)))]
+    ctx = Context(0)
+    part = (ctx.get_option("serve_adj_min_nnz"), ctx.get_option("serve_fwd_blocks_per_wave"))
+    doses = {}
+    for pat, sp, _ in reqs:
+        if pat not in doses:
+            d = Dose.from_geometry(ctx, sp)
+            d.repartition(*part)
+            doses[pat] = d
+    out = {}
+    for share in (1, 0):
+        c = Context(0, serve_shared_adjoint=share)
+        srv = Server(c, budget_bytes=8 << 30, max_live=16)
+        tickets = [srv.submit(p, sp, t, max_iter=1500) for p, sp, t in reqs]
+        out[share] = [srv.wait(tk, doses[p].nb) for tk, (p, _, _) in zip(tickets, reqs)]
+        st = srv.stats()
+        srv.close()
+        banner(f"shared adjoint {share}: {st['adjoint_groups_shared']} of {st['adjoint_groups']} adjoint groups "
+               f"shared, iterations {[g[0].iterations for g in out[share]]}")
+        if share:
+            assert st["adjoint_groups_shared"] > 0
+        else:
+            assert st["adjoint_groups_shared"] == 0
+    for (pat, sp, t), (res, times, x), (res0, _, x0) in zip(reqs, out[1], out[0]):
+        assert (res.iterations, res.status, res.G_final) == (res0.iterations, res0.status, res0.G_final)
+        assert np.array_equal(x, x0)
+        ref, xr = _alone(ctx, doses[pat], t, times.lambda0, max_iter=1500)
+        assert (res.iterations, res.status) == (ref.iterations, ref.status)
+        assert res.G_final == ref.G_final and res.G_initial == ref.G_initial
+        assert np.array_equal(x, xr)
