@@ -28,16 +28,22 @@ TRAFFIC_PROFILES = {
 }
 
 
-def forward_bytes(nv, nb, nnz):
+# The byte models count the rows that have nonzeros (nr): a voxel no beamlet
+# reaches needs no row pointer, structure id or residual in either pass (its
+# zero-dose penalty is a constant of the plan), and the wave forward skips
+# every run of 16 or more such rows.
+
+
+def forward_bytes(nr, nb, nnz):
     """Algorithmic bytes of one forward trial pass: CSR (int32 column, float32
     value, int32 row pointer), structure id, residual out, x_k and g_k in."""
-    return 8 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 8 * nb
+    return 8 * nnz + 4 * (nr + 1) + 1 * nr + 4 * nr + 8 * nb
 
 
-def forward_bytes_c16(nv, nb, nnz):
+def forward_bytes_c16(nr, nb, nnz):
     """The same when the forward reads 16-bit column indices beside the
     float32 values (float32 matrices with nb <= 65536, the default)."""
-    return 6 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 8 * nb
+    return 6 * nnz + 4 * (nr + 1) + 1 * nr + 4 * nr + 8 * nb
 
 
 def f32_forward(ctx, nb):
@@ -48,22 +54,33 @@ def f32_forward(ctx, nb):
     return 0, forward_bytes
 
 
-def adjoint_bytes(nv, nb, nnz):
+def adjoint_bytes(nr, nb, nnz):
     """Algorithmic bytes of one adjoint pass: CSC (int32 row, float32 value,
-    int32 column pointer), every residual once, gradient out."""
-    return 8 * nnz + 4 * (nb + 1) + 4 * nv + 4 * nb
+    int32 column pointer), every residual of a row with nonzeros once,
+    gradient out."""
+    return 8 * nnz + 4 * (nb + 1) + 4 * nr + 4 * nb
 
 
-def forward_bytes16(nv, nb, nnz):
+def forward_bytes16(nr, nb, nnz):
     """The same with 16-bit storage: 16-bit column index and code, plus the
     beamlet scales."""
-    return 4 * nnz + 4 * (nv + 1) + 1 * nv + 4 * nv + 12 * nb
+    return 4 * nnz + 4 * (nr + 1) + 1 * nr + 4 * nr + 12 * nb
 
 
-def adjoint_bytes16(nv, nb, nnz):
+def adjoint_bytes16(nr, nb, nnz):
     """The same with 16-bit storage: int32 row index and 16-bit code, plus the
     beamlet scales."""
-    return 6 * nnz + 4 * (nb + 1) + 4 * nv + 8 * nb
+    return 6 * nnz + 4 * (nb + 1) + 4 * nr + 8 * nb
+
+
+def nonempty_rows(dose):
+    """Rows of the dose matrix that hold at least one nonzero."""
+    import numpy as np
+
+    from paper_0908_4421_amd.imrt import imrt_dose_export
+    rp = np.empty(dose.nv + 1, np.int32)
+    imrt_dose_export(dose.handle, row_ptr=rp)
+    return int(np.count_nonzero(np.diff(rp)))
 
 
 def timed_plans(ctx, dose, spec, st, args, warmup, steps):
@@ -135,9 +152,9 @@ def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
     code = {"bf16": 1, "f16": 2}[storage]
     names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {code}>(",
              "adjoint": f"adj_kernel<{nt}, true, {code}>("}
-    nv, nb, nnz = dose.nv, dose.nb, dose.nnz
-    kern = kernel_table(runs, res, names, {"forward": forward_bytes16(nv, nb, nnz),
-                                           "adjoint": adjoint_bytes16(nv, nb, nnz)})
+    nr, nb, nnz = nonempty_rows(dose), dose.nb, dose.nnz
+    kern = kernel_table(runs, res, names, {"forward": forward_bytes16(nr, nb, nnz),
+                                           "adjoint": adjoint_bytes16(nr, nb, nnz)})
     d16 = torch.empty(nv, dtype=torch.float32, device="cuda")
     d32 = torch.empty(nv, dtype=torch.float32, device="cuda")
     G16 = pl.objective(x, d16)
@@ -241,8 +258,9 @@ def batch_form(ctx, args):
     batch_s = sorted(times)[len(times) // 2]
     same = all(a.iterations == b.iterations and a.G_final == b.G_final and torch.equal(xa, xb)
                for a, b, xa, xb in zip(rs, rb, x_solo, xs))
-    nbytes = sum(r.forward_passes * f32_forward(ctx, d.nb)[1](d.nv, d.nb, d.nnz) +
-                 r.adjoint_passes * adjoint_bytes(d.nv, d.nb, d.nnz) for r, d in zip(rb, doses))
+    nrs = [nonempty_rows(d) for d in doses]
+    nbytes = sum(r.forward_passes * f32_forward(ctx, d.nb)[1](nr, d.nb, d.nnz) +
+                 r.adjoint_passes * adjoint_bytes(nr, d.nb, d.nnz) for r, d, nr in zip(rb, doses, nrs))
     iters = sum(r.iterations for r in rb)
     print(f"[bench] batch of {len(specs)}: {iters} iterations, {batch_s * 1e3:.1f} ms batched, "
           f"{solo_default_s * 1e3:.1f} ms one by one", file=sys.stderr, flush=True)
@@ -339,8 +357,9 @@ def replan_form(ctx, plan, x, spec, st, args):
         warm[f"trials_per_pass_{nt}"] = {"ms": wt[-1], "iterations": rw.iterations, "status": rw.status,
                                          "forward_passes": rw.forward_passes, "G_final": rw.G_final,
                                          "target_voxels_within_3pct": float(np.mean(relw <= 0.03))}
-    nbytes = res.forward_passes * f32_forward(ctx, dose.nb)[1](dose.nv, dose.nb, dose.nnz) + \
-        res.adjoint_passes * adjoint_bytes(dose.nv, dose.nb, dose.nnz)
+    nr = nonempty_rows(dose)
+    nbytes = res.forward_passes * f32_forward(ctx, dose.nb)[1](nr, dose.nb, dose.nnz) + \
+        res.adjoint_passes * adjoint_bytes(nr, dose.nb, dose.nnz)
     print(f"[bench] re-plan on {day.name}: {res.iterations} iterations, {ms:.2f} ms", file=sys.stderr, flush=True)
     return {
         "workload": f"{day.name}: targets = original plan's dose (per voxel), x0 = {st.x0}",
@@ -385,18 +404,20 @@ def shape_form(ctx, args, spec=None, note=SCENARIO3_NOTE):
     ms, runs, x, pl = timed_plans(ctx, dose, spec, st, args, 1, max(1, min(args.steps, 3)))
     lam0, res = runs[-1]
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    nr = nonempty_rows(dose)
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
     names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {lay}>(",
              "adjoint": f"adj_kernel<{nt}, true, 0>("}
-    kern = kernel_table(runs, res, names, {"forward": fwd_model(nv, nb, nnz), "adjoint": adjoint_bytes(nv, nb, nnz)})
+    kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz), "adjoint": adjoint_bytes(nr, nb, nnz)})
     print(f"[bench] {spec.name}: {res.iterations} iterations, {ms:.2f} ms per plan, forward "
           f"{kern['forward']['frac_of_peak']:.2f} / adjoint {kern['adjoint']['frac_of_peak']:.2f} of peak",
           file=sys.stderr, flush=True)
     return {
         "workload": spec.name,
         "nv": nv, "nb": nb, "nnz": nnz,
-        "csr_csc_MB": (forward_bytes(nv, nb, nnz) + adjoint_bytes(nv, nb, nnz)) / 1e6,
+        "nonempty_rows": nr,
+        "csr_csc_MB": (forward_bytes(nr, nb, nnz) + adjoint_bytes(nr, nb, nnz)) / 1e6,
         "ms_per_plan": ms,
         "iterations": res.iterations,
         "status": res.status,
@@ -464,8 +485,9 @@ def shard_form(ctx, dose, spec, iters=100):
         x.fill_(1.0)
         res, _ = p.solve(x, **kw)
         tf, ta = 1e3 * res.forward_kernel_ms, 1e3 * res.adjoint_kernel_ms
-        bf = f32_forward(ctx, nb)[1](d.nv, nb, d.nnz)
-        ba = adjoint_bytes(d.nv, nb, d.nnz)
+        nr = nonempty_rows(d)
+        bf = f32_forward(ctx, nb)[1](nr, nb, d.nnz)
+        ba = adjoint_bytes(nr, nb, d.nnz)
         return {"rows": d.nv, "nnz": d.nnz, "forward_us": tf, "adjoint_us": ta,
                 "forward_GB_s": bf / (tf * 1e-6) / 1e9, "adjoint_GB_s": ba / (ta * 1e-6) / 1e9}
 
@@ -547,6 +569,8 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
 
     def pct(v):
         return {"n": len(v), "p50": _pct(v, 50), "p99": _pct(v, 99), "max": max(v) if v else None}
+    # (the server does not report a plan's rows with nonzeros: its voxel
+    # count stands in, which overstates the bytes of plans with empty rows)
     def fb(nv, nb, nnz):
         return f32_forward(ctx, nb)[1](nv, nb, nnz) if storage == "f32" else forward_bytes16(nv, nb, nnz)
     ab = adjoint_bytes if storage == "f32" else adjoint_bytes16
@@ -571,7 +595,7 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
         "iterations_total": sum(its),
         "iterations": {"p50": _pct(its, 50), "p99": _pct(its, 99), "max": its[-1]},
         "status_counts": status,
-        "GB_s": nbytes / span / 1e9,
+        "GB_s_voxel_count_bound": nbytes / span / 1e9,
         "peak_resident_GB": stats["peak_bytes"] / 1e9,
         "resident_matrices": stats["resident_matrices"],
     }
@@ -845,13 +869,14 @@ def main():
           flush=True)
 
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    nr = nonempty_rows(dose)
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
     names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {lay}>(" if wave else f"fwd_kernel<{nt}>(",
              "adjoint": f"adj_kernel<{nt}, true, 0>("}
-    kern = kernel_table(runs, res, names, {"forward": fwd_model(nv, nb, nnz),
-                                           "adjoint": adjoint_bytes(nv, nb, nnz)})
+    kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz),
+                                           "adjoint": adjoint_bytes(nr, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     probe = read_probe(ctx)
     roofline = {"bound": "hbm", "achieved": kern[dom]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -872,7 +897,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": spec.name, "nv": nv, "nb": nb, "nnz": nnz, "delta": st.delta,
+        "config": {"workload": spec.name, "nv": nv, "nonempty_rows": nr, "nb": nb, "nnz": nnz, "delta": st.delta,
                    "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
                    "trials_per_pass": args.trials_per_pass,
                    "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz",

@@ -151,40 +151,60 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   }
   for (int32_t b : blocks) block_k0.push_back(row_ptr[b]);
   // the same for one wave (at most wave_part_nnz nonzeros, which depends on
-  // the storage, and kWaveRowsMax rows)
+  // the storage, and kWaveRowsMax rows), except that a run of kGapRows or
+  // more rows without nonzeros lies between blocks instead of inside one:
+  // the wave forward never visits those rows (their penalty at zero dose is
+  // a constant of the plan, and their residual is never gathered)
   const int wave_part = wave_part_nnz(D->fwd_st);
-  std::vector<int32_t> wblocks, wblock_k0;
-  wblocks.push_back(0);
+  const int nv = D->nv;
+  std::vector<int32_t> run_end(static_cast<size_t>(nv) + 1);
+  run_end[nv] = nv;
+  for (int q = nv - 1; q >= 0; --q) run_end[q] = (row_ptr[q + 1] == row_ptr[q]) ? run_end[q + 1] : q;
+  auto long_gap = [&](int q) { return run_end[q] - q >= kGapRows; };
+  std::vector<std::pair<int32_t, int32_t>> wb;   // [first row, end row) of each block
+  std::vector<std::pair<int32_t, int32_t>> gaps;
   r = 0;
-  while (r < D->nv) {
+  while (r < nv) {
+    if (long_gap(r)) {
+      gaps.emplace_back(r, run_end[r]);
+      r = run_end[r];
+      continue;
+    }
     const int start = r;
     int64_t nz = 0;
-    while (r < D->nv && r - start < kWaveRowsMax) {
+    while (r < nv && r - start < kWaveRowsMax) {
+      if (r > start && long_gap(r)) break;
       const int64_t len = row_ptr[r + 1] - row_ptr[r];
       if (r > start && nz + len > wave_part) break;
       nz += len;
       ++r;
       if (nz > wave_part) break;
     }
-    wblocks.push_back(r);
+    wb.emplace_back(start, r);
+  }
+  if (wb.empty()) {
+    // no nonzeros at all: one block of rows anyway (every pass has work)
+    gaps.clear();
+    wb.emplace_back(0, std::min(nv, kWaveRowsMax));
+    for (int q = wb[0].second; q < nv; q += kWaveRowsMax) wb.emplace_back(q, std::min(nv, q + kWaveRowsMax));
   }
   // A wave's time is mostly a per-block latency, so every wave of the
   // default grid gets the same number of blocks: the blocks with the most
   // nonzeros are halved (by rows) until the count is a multiple of the waves.
   {
-    const int nwb = static_cast<int>(wblocks.size()) - 1;
+    const int nwb = static_cast<int>(wb.size());
     const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb, 1, D->fwd_bpw)) * forward_waves(1);
     const int64_t target = (nwb + waves - 1) / waves * waves;
     if (nwb > waves && target > nwb) {
       // max-heap of (nonzeros, block start row) over splittable blocks
       std::vector<std::pair<int64_t, int32_t>> heap;
-      for (int b = 0; b < nwb; ++b)
-        if (wblocks[b + 1] - wblocks[b] > 1)
-          heap.emplace_back(int64_t(row_ptr[wblocks[b + 1]]) - row_ptr[wblocks[b]], wblocks[b]);
+      std::vector<int32_t> end_of(static_cast<size_t>(nv) + 1, -1);
+      for (const auto& blk : wb) {
+        end_of[blk.first] = blk.second;
+        if (blk.second - blk.first > 1)
+          heap.emplace_back(int64_t(row_ptr[blk.second]) - row_ptr[blk.first], blk.first);
+      }
       std::make_heap(heap.begin(), heap.end());
-      std::vector<int32_t> cuts;
-      std::vector<int32_t> end_of(static_cast<size_t>(D->nv) + 1, -1);
-      for (int b = 0; b < nwb; ++b) end_of[wblocks[b]] = wblocks[b + 1];
       for (int64_t extra = target - nwb; extra > 0 && !heap.empty(); --extra) {
         std::pop_heap(heap.begin(), heap.end());
         const int32_t r0 = heap.back().second;
@@ -195,7 +215,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
         while (m < r1 - 1 && row_ptr[m] < half) ++m;
         end_of[r0] = m;
         end_of[m] = r1;
-        cuts.push_back(m);
+        wb.emplace_back(m, r1);
         if (m - r0 > 1) {
           heap.emplace_back(int64_t(row_ptr[m]) - row_ptr[r0], r0);
           std::push_heap(heap.begin(), heap.end());
@@ -205,11 +225,18 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
           std::push_heap(heap.begin(), heap.end());
         }
       }
-      wblocks.insert(wblocks.end(), cuts.begin(), cuts.end());
-      std::sort(wblocks.begin(), wblocks.end());
+      for (auto& blk : wb) blk.second = end_of[blk.first];
+      std::sort(wb.begin(), wb.end());
     }
   }
-  for (int32_t b : wblocks) wblock_k0.push_back(row_ptr[b]);
+  std::vector<int32_t> wblocks, wblock_k0, wblock_end;
+  for (const auto& blk : wb) {
+    wblocks.push_back(blk.first);
+    wblock_end.push_back(blk.second);
+    wblock_k0.push_back(row_ptr[blk.first]);
+  }
+  wblocks.push_back(nv);
+  wblock_k0.push_back(row_ptr[nv]);
 
   const int G = adjoint_grid_for(D->ctx, D->nnz, D->adj_min_nnz);
   const int64_t nnz = D->nnz;
@@ -251,10 +278,12 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   }
   D->nblocks = static_cast<int32_t>(blocks.size()) - 1;
   D->nwblocks = static_cast<int32_t>(wblocks.size()) - 1;
+  D->gaps.swap(gaps);
+  D->part_epoch += 1;
   D->adj_grid = G;
   // (a repartition replaces the previous tables)
-  for (int32_t** p : {&D->block_row, &D->block_k0, &D->wblock_row, &D->wblock_k0, &D->wg_cols, &D->col_wlo,
-                      &D->col_whi})
+  for (int32_t** p : {&D->block_row, &D->block_k0, &D->wblock_row, &D->wblock_k0, &D->wblock_end, &D->wg_cols,
+                      &D->col_wlo, &D->col_whi})
     dev_free(*p);
   dev_free(D->col_kind);
   dev_free(D->pieces);
@@ -262,6 +291,7 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   int rc;
   if ((rc = dev_alloc(&D->block_row, blocks.size())) || (rc = dev_alloc(&D->block_k0, block_k0.size())) ||
       (rc = dev_alloc(&D->wblock_row, wblocks.size())) || (rc = dev_alloc(&D->wblock_k0, wblock_k0.size())) ||
+      (rc = dev_alloc(&D->wblock_end, std::max<size_t>(wblock_end.size(), 1))) ||
       (rc = dev_alloc(&D->wg_cols, 4 * static_cast<size_t>(G))) ||
       (rc = dev_alloc(&D->col_wlo, static_cast<size_t>(D->nb))) ||
       (rc = dev_alloc(&D->col_whi, static_cast<size_t>(D->nb))) ||
@@ -273,6 +303,8 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   IMRT_HIP(hipMemcpyAsync(D->block_k0, block_k0.data(), sizeof(int32_t) * block_k0.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wblock_row, wblocks.data(), sizeof(int32_t) * wblocks.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wblock_k0, wblock_k0.data(), sizeof(int32_t) * wblock_k0.size(),
+                          hipMemcpyHostToDevice, s));
+  IMRT_HIP(hipMemcpyAsync(D->wblock_end, wblock_end.data(), sizeof(int32_t) * wblock_end.size(),
                           hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->wg_cols, wg_cols.data(), sizeof(int32_t) * wg_cols.size(), hipMemcpyHostToDevice, s));
   IMRT_HIP(hipMemcpyAsync(D->col_wlo, col_wlo.data(), sizeof(int32_t) * D->nb, hipMemcpyHostToDevice, s));
@@ -310,6 +342,7 @@ void free_dose(imrt_dose* D) {
   dev_free(D->block_k0);
   dev_free(D->wblock_row);
   dev_free(D->wblock_k0);
+  dev_free(D->wblock_end);
   dev_free(D->wg_cols);
   dev_free(D->col_wlo);
   dev_free(D->col_whi);
@@ -378,6 +411,48 @@ int plan_use(imrt_plan* P) {
   return rc ? rc : plan_fit(P);
 }
 
+// Objective of the voxels the wave forward skips (the runs of rows without
+// nonzeros between its blocks): at zero dose each contributes
+// F_j(0) = w_u min(-T_u, 0)^2 + w_o max(-T_o, 0)^2 (Eq. (1)), summed here in
+// float64 in row order, once per set of structures, penalties, targets and
+// partition.  The workgroup-wide forward visits every row: no constant then.
+double plan_skip_objective(imrt_plan* P) {
+  const imrt_dose* D = P->dose;
+  if (P->ctx->tune.fwd_wave == 0) return 0.0;
+  if (P->gskip_epoch == D->part_epoch) return P->G_skip;
+  // skipped rows per structure (kept until the structures or the partition change)
+  if (P->skip_hist_epoch != D->part_epoch) {
+    P->skip_hist.assign(kMaxStruct, 0);
+    for (const auto& gap : D->gaps)
+      for (int32_t j = gap.first; j < gap.second; ++j) ++P->skip_hist[P->sid_host[j]];
+    P->skip_hist_epoch = D->part_epoch;
+  }
+  auto F0 = [](double Tu, double To, double wu, double wo) {
+    const double under = std::fmin(0.0 - Tu, 0.0);
+    const double over = std::fmax(0.0 - To, 0.0);
+    const double a = wu * under * under;
+    const double b = wo * over * over;
+    return a + b;
+  };
+  double G = 0.0;
+  if (P->Tu_host.empty()) {
+    for (int st = 0; st < P->nstruct; ++st)
+      if (P->skip_hist[st] > 0) {
+        const PenaltyDev& t = P->table_host[st];
+        G += static_cast<double>(P->skip_hist[st]) * F0(t.T_u, t.T_o, t.w_u, t.w_o);
+      }
+  } else {
+    for (const auto& gap : D->gaps)
+      for (int32_t j = gap.first; j < gap.second; ++j) {
+        const PenaltyDev& t = P->table_host[P->sid_host[j]];
+        G += F0(static_cast<double>(P->Tu_host[j]), static_cast<double>(P->To_host[j]), t.w_u, t.w_o);
+      }
+  }
+  P->G_skip = G;
+  P->gskip_epoch = D->part_epoch;
+  return G;
+}
+
 Penalties plan_penalties(const imrt_plan* P) {
   return Penalties{P->sid, P->table, P->Tu_vox, P->To_vox};
 }
@@ -401,6 +476,7 @@ FwdArgs base_fwd(const imrt_dose* D) {
   a.nblocks = D->nblocks;
   a.wblock_row = D->wblock_row;
   a.wblock_k0 = D->wblock_k0;
+  a.wblock_end = D->wblock_end;
   a.nwblocks = D->nwblocks;
   a.nv = D->nv;
   a.nb = D->nb;
@@ -431,7 +507,7 @@ int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, in
   const int grid = std::min(forward_grid(P->ctx, D), P->fwd_cap);
   int rc = launch_forward(P->ctx, D, a, 1, grid);
   if (rc) return rc;
-  return launch_sum(P->ctx, P->fwd_partials, grid, P->misc + slot);
+  return launch_sum(P->ctx, P->fwd_partials, grid, P->misc + slot, plan_skip_objective(P));
 }
 
 AdjArgs base_adj(const imrt_dose* D) {
@@ -878,6 +954,8 @@ int imrt_dose_apply(const imrt_dose* D, const float* x_dev, float* d_dev) {
   a.x = x_dev;
   a.d_out = D->vox ? D->vscratch : d_dev;
   a.partials = D->partials;
+  // rows the wave blocks skip have no nonzeros: their dose is 0
+  if (!D->gaps.empty() && D->ctx->tune.fwd_wave && (rc = launch_zero(D->ctx, a.d_out, D->nv))) return rc;
   if ((rc = launch_forward(D->ctx, D, a, 1, std::min(forward_grid(D->ctx, D), D->fwd_cap)))) return rc;
   return D->vox ? launch_permute(D->ctx, D->vscratch, D->vox, D->nv, d_dev, true) : IMRT_OK;
 }
@@ -956,6 +1034,9 @@ int imrt_set_structures(imrt_plan* P, const uint8_t* voxel_struct, int32_t nstru
     present[ids[j]] = 1;
   }
   IMRT_HIP(hipMemcpy(P->sid, ids.data(), D->nv, hipMemcpyHostToDevice));
+  P->sid_host.swap(ids);
+  P->gskip_epoch = -1;
+  P->skip_hist_epoch = -1;
   P->nstruct = nstruct;
   P->have_struct = true;
   P->have_pen = false;  // the table must match the new structure count
@@ -985,6 +1066,8 @@ int imrt_set_penalties(imrt_plan* P, const imrt_penalty* table) {
   for (int s = 0; s < P->nstruct; ++s)
     if (present[s]) wmax = std::max(wmax, std::max(t[s].w_u, t[s].w_o));
   IMRT_HIP(hipMemcpy(P->table, t.data(), sizeof(PenaltyDev) * P->nstruct, hipMemcpyHostToDevice));
+  P->table_host.swap(t);
+  P->gskip_epoch = -1;
   P->w_max = wmax;
   P->have_pen = true;
   return IMRT_OK;
@@ -997,6 +1080,9 @@ int imrt_set_voxel_targets(imrt_plan* P, const float* T_under, const float* T_ov
   if (!T_under && !T_over) {
     dev_free(P->Tu_vox);
     dev_free(P->To_vox);
+    P->Tu_host.clear();
+    P->To_host.clear();
+    P->gskip_epoch = -1;
     return IMRT_OK;
   }
   if (!T_under || !T_over) return set_error(IMRT_EINVAL, "give both T_under and T_over, or neither");
@@ -1020,6 +1106,9 @@ int imrt_set_voxel_targets(imrt_plan* P, const float* T_under, const float* T_ov
   }
   IMRT_HIP(hipMemcpy(P->Tu_vox, T_under, sizeof(float) * nv, hipMemcpyHostToDevice));
   IMRT_HIP(hipMemcpy(P->To_vox, T_over, sizeof(float) * nv, hipMemcpyHostToDevice));
+  P->Tu_host.assign(T_under, T_under + nv);
+  P->To_host.assign(T_over, T_over + nv);
+  P->gskip_epoch = -1;
   return IMRT_OK;
 }
 
@@ -1029,7 +1118,10 @@ int imrt_evaluate_objective(imrt_plan* P, const float* x_dev, double* G_out, flo
   if (!x_dev || !G_out) return set_error(IMRT_EINVAL, "x or G_out is NULL");
   const imrt_dose* D = P->dose;
   float* d_int = (dose_dev && D->vox) ? P->vtmp : dose_dev;
-  if ((rc = use_device(P->ctx)) || (rc = eval_forward(P, x_dev, d_int, nullptr, 0))) return rc;
+  if ((rc = use_device(P->ctx))) return rc;
+  // rows the wave blocks skip have no nonzeros: their dose is 0
+  if (d_int && !D->gaps.empty() && P->ctx->tune.fwd_wave && (rc = launch_zero(P->ctx, d_int, D->nv))) return rc;
+  if ((rc = eval_forward(P, x_dev, d_int, nullptr, 0))) return rc;
   if (dose_dev && D->vox && (rc = launch_permute(P->ctx, P->vtmp, D->vox, D->nv, dose_dev, true))) return rc;
   if ((rc = fetch_misc(P, 1))) return rc;
   *G_out = P->misc_host[0];
@@ -1085,7 +1177,9 @@ int imrt_gradient_noalloc(imrt_plan* P, const float* x_dev, float* g_dev, double
   fa.x = x_dev;
   fa.r_out = r;
   fa.partials = parts;
-  if ((rc = launch_forward(P->ctx, D, fa, 1, grid)) || (rc = launch_sum(P->ctx, parts, grid, total))) return rc;
+  if ((rc = launch_forward(P->ctx, D, fa, 1, grid)) ||
+      (rc = launch_sum(P->ctx, parts, grid, total, plan_skip_objective(P))))
+    return rc;
   // adjoint pass: g = 2 D^T r (pieces written by the workgroups that share a column)
   AdjArgs aa = base_adj(D);
   aa.solve = 0;
@@ -1269,6 +1363,7 @@ void solve_args(imrt_plan* P, int nt, int grid, int cap, FwdArgs& fa, AdjArgs& a
   aa.step_partials = P->fwd_partials + static_cast<size_t>(nt) * grid;
   aa.step_parts = 1;
   aa.trace = cap > 0 ? P->trace : nullptr;
+  aa.G_skip = plan_skip_objective(P);
 }
 
 int imrt_solve(imrt_plan* P, const imrt_solve_params* prm, float* x_dev, imrt_solve_result* res) {

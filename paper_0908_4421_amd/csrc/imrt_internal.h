@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "imrt.h"
@@ -25,6 +26,7 @@ constexpr int kWavePartNnz = kWaveNnz - 4;
 constexpr int wave_nnz(int storage) { return storage == 0 ? kWaveNnz : storage == 3 ? 3 * kWaveNnz / 2 : 2 * kWaveNnz; }
 constexpr int wave_part_nnz(int storage) { return wave_nnz(storage) - 4; }
 constexpr int kWaveRowsMax = 256;      // rows of one wave's row block
+constexpr int kGapRows = 16;           // runs of at least this many empty rows lie between wave blocks
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;
 constexpr int kPad = 16;               // zeroed tail of every nonzero array (aligned vector loads)
@@ -100,8 +102,9 @@ struct FwdArgs {
   const int32_t* block_row;  // nblocks + 1 row boundaries
   const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
-  const int32_t* wblock_row; // per-wave row blocks (wave-granular forward)
-  const int32_t* wblock_k0;
+  const int32_t* wblock_row; // per-wave row blocks (wave-granular forward): first row,
+  const int32_t* wblock_k0;  // first nonzero (block b ends at wblock_k0[b + 1]),
+  const int32_t* wblock_end; // end row (runs of empty rows between blocks are skipped)
   int32_t nwblocks;
   int32_t grid;              // workgroups of this pass (read by the batched pass)
   int32_t nstruct;
@@ -160,6 +163,8 @@ struct AdjArgs {
   const SolverState* st_in;
   SolverState* st_out;
   TraceDev* trace;
+  double G_skip;             // objective of the voxels the wave forward skips (rows without
+                             // nonzeros between its blocks), added to every trial's G
 };
 
 // ---- host-side objects ------------------------------------------------------------
@@ -220,6 +225,12 @@ struct imrt_dose {
   int32_t nwblocks = 0;
   int32_t* wblock_row = nullptr;
   int32_t* wblock_k0 = nullptr;
+  int32_t* wblock_end = nullptr;
+  // runs of empty rows the wave blocks skip, [first, end) in internal row
+  // order, and a counter of partitions (a plan's constant for the skipped
+  // rows follows it)
+  std::vector<std::pair<int32_t, int32_t>> gaps;
+  int64_t part_epoch = 0;
   int32_t adj_grid = 0;        // workgroups of the adjoint partition
   int32_t* wg_cols = nullptr;
   int32_t* col_wlo = nullptr;
@@ -266,6 +277,15 @@ struct imrt_plan {
   int32_t trace_cap = 0;
   imrt::SolverState* st_host = nullptr;   // pinned, 2 slots
   double* misc_host = nullptr;            // pinned
+  // host copies (internal voxel order) for the objective of the voxels the
+  // wave forward skips: structure ids, penalty table, per-voxel targets
+  std::vector<uint8_t> sid_host;
+  std::vector<imrt::PenaltyDev> table_host;
+  std::vector<float> Tu_host, To_host;
+  double G_skip = 0.0;
+  int64_t gskip_epoch = -1;               // dose partition the constant was computed for (-1: stale)
+  std::vector<int64_t> skip_hist;         // skipped rows per structure id
+  int64_t skip_hist_epoch = -1;
 };
 
 namespace imrt {
@@ -319,7 +339,10 @@ int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t
 // group_k (K) is 2 or 4.
 int launch_adjoint_multi_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* groups, int group_k,
                                const int32_t* slots, int nslots, int ntrials, int storage);
-int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out);
+// out = (fixed-order sum of parts[0..n)) + add
+int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out, double add = 0.0);
+// p[0..n) = 0 with a kernel (usable under graph capture, unlike a memset node)
+int launch_zero(const imrt_ctx* ctx, float* p, int n);
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
                    float* x_out, double* s_out);
 int launch_normalize(const imrt_ctx* ctx, const float* w, int nb, float* v_out, double* norm_out);

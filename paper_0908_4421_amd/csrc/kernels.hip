@@ -298,7 +298,7 @@ __device__ __forceinline__ void decide_start(const AdjArgs& a, DecideLoads<NT>& 
 
 template <int NT>
 __device__ void decide(const double* partials, int nparts, const double* steps, int nsteps,
-                       const DecideLoads<NT>& L, Decision& dec, double* red) {
+                       const DecideLoads<NT>& L, Decision& dec, double* red, double G_add) {
 #pragma clang fp contract(off)
   __shared__ double Gq[NT];
   const int tid = threadIdx.x;
@@ -327,7 +327,7 @@ __device__ void decide(const double* partials, int nparts, const double* steps, 
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
     const double t = block_sum(s[q], red);
-    if (tid == 0) Gq[q] = t;
+    if (tid == 0) Gq[q] = t + G_add;
   }
   if (dec.st.phase == PH_DONE) return;
   const bool init = (dec.st.phase == PH_INIT);
@@ -1126,7 +1126,8 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   float* prod0 = xs + NT * nbp;
   int32_t* mrow = reinterpret_cast<int32_t*>(prod0 + WAVES * NT * NNZ + kWaveSlack);
   int32_t* mk0 = mrow + (kMetaChunk + 1);
-  double* gpart = reinterpret_cast<double*>(mk0 + (kMetaChunk + 1) + 2);   // 8-byte aligned
+  int32_t* mend = mk0 + (kMetaChunk + 1);
+  double* gpart = reinterpret_cast<double*>(mend + kMetaChunk + 2);   // 8-byte aligned
   const int wv = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   float* prod = prod0 + wv * (NT * NNZ);
   __shared__ double red[WAVES];
@@ -1145,14 +1146,6 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   const int lw = (G % kXcds == 0) ? (w % kXcds) * (G / kXcds) + w / kXcds : w;
   const int B0 = split_point(lw, a.nwblocks, G);
   const int B1 = split_point(lw + 1, a.nwblocks, G);
-  auto global_meta = [&](int b) {
-    WaveBlock m;
-    m.r0 = uniform(a.wblock_row[b]);
-    m.r1 = uniform(a.wblock_row[b + 1]);
-    m.k0 = uniform(a.wblock_k0[b]);
-    m.k1 = uniform(a.wblock_k0[b + 1]);
-    return m;
-  };
   // Loads in the order their results are needed, none of them in a branch:
   // the first block's bounds (lanes 0 and 1), the staging inputs (a solve's
   // trial inputs before the state is known), the state (one word per lane),
@@ -1162,7 +1155,8 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   const bool first = b < min(B1, B0 + kMetaChunk);
   const uint32_t meta_bytes = 4u * static_cast<uint32_t>(a.nwblocks + 1);
   const uint32_t moff = 4u * static_cast<uint32_t>(b + (lane & 1));
-  const int mrow0 = load_i32(make_rsrc(a.wblock_row, meta_bytes), moff);
+  const int mrow0 = load_i32(make_rsrc(a.wblock_row, meta_bytes), 4u * static_cast<uint32_t>(b));
+  const int mend0 = load_i32(make_rsrc(a.wblock_end, meta_bytes - 4u), 4u * static_cast<uint32_t>(b));
   const int mk00 = load_i32(make_rsrc(a.wblock_k0, meta_bytes), moff);
   TrialRegs<NT> TR;
   StageRegs<NT> SR;
@@ -1177,7 +1171,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   WaveBlock cur{0, 0, 0, 0};
   if (first) {
     cur.r0 = __builtin_amdgcn_readlane(mrow0, 0);
-    cur.r1 = __builtin_amdgcn_readlane(mrow0, 1);
+    cur.r1 = __builtin_amdgcn_readlane(mend0, 0);
     cur.k0 = __builtin_amdgcn_readlane(mk00, 0);
     cur.k1 = __builtin_amdgcn_readlane(mk00, 1);
   }
@@ -1222,6 +1216,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
     for (int i = tid; i <= c1 - c0; i += THREADS) {
       mrow[i] = a.wblock_row[c0 + i];
       mk0[i] = a.wblock_k0[c0 + i];
+      if (i < c1 - c0) mend[i] = a.wblock_end[c0 + i];
     }
     if (tid == 0) next_blk = c0 + WAVES;
     __syncthreads();
@@ -1229,7 +1224,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
       const int i = blk - c0;
       WaveBlock m;
       m.r0 = uniform(mrow[i]);
-      m.r1 = uniform(mrow[i + 1]);
+      m.r1 = uniform(mend[i]);
       m.k0 = uniform(mk0[i]);
       m.k1 = uniform(mk0[i + 1]);
       return m;
@@ -1492,7 +1487,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   adj_gather(rr, A, g);
   if (SOLVE) {
     // (a finished solve passes its state through unchanged and exits here)
-    decide<NT>(a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red);
+    decide<NT>(a.fwd_partials, a.fwd_parts, a.step_partials, a.step_parts, DL, dec, red, a.G_skip);
     if (sl.w == 0 && tid == 0) {
       *a.st_out = dec.st;
       if (dec.accepted >= 0 && a.trace != nullptr && dec.st.k - 1 < dec.st.trace_cap) {
@@ -1639,7 +1634,7 @@ __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args,
     need[q] = false;
     if (q < n) {
       const AdjArgs& aq = args[pi[q]];
-      decide<NT>(aq.fwd_partials, aq.fwd_parts, aq.step_partials, aq.step_parts, DL[q], dec[q], red);
+      decide<NT>(aq.fwd_partials, aq.fwd_parts, aq.step_partials, aq.step_parts, DL[q], dec[q], red, aq.G_skip);
       if (sl.w == 0 && tid == 0) {
         *aq.st_out = dec[q].st;
         if (dec[q].accepted >= 0 && aq.trace != nullptr && dec[q].st.k - 1 < dec[q].st.trace_cap) {
@@ -1758,12 +1753,16 @@ __global__ __launch_bounds__(kThreads) void adj_final_kernel(AdjArgs a, const So
 }
 
 // ---- small utility kernels ----------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void sum_kernel(const double* parts, int n, double* out) {
+__global__ __launch_bounds__(kThreads) void sum_kernel(const double* parts, int n, double* out, double add) {
   __shared__ double red[kWaves];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kThreads) s += parts[i];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) *out = s;
+  if (threadIdx.x == 0) *out = s + add;
+}
+
+__global__ __launch_bounds__(kThreads) void zero_kernel(float* p, int n) {
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) p[i] = 0.0f;
 }
 
 __global__ __launch_bounds__(kThreads) void project_kernel(const float* x, const float* g, double lam,
@@ -1834,7 +1833,8 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
   if (wave) {
     const size_t waves = static_cast<size_t>(forward_waves(ntrials));
     bytes += (waves * ntrials * wave_nnz(storage) + kWaveSlack) * sizeof(float);
-    bytes += (2 * (kMetaChunk + 1) + 2) * sizeof(int32_t) + static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
+    bytes += (2 * (kMetaChunk + 1) + kMetaChunk + 2) * sizeof(int32_t) +
+             static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
   } else {
     bytes += static_cast<size_t>(ntrials) * kFwdNnzMax * sizeof(float) +
              static_cast<size_t>(kFwdRowsMax + 1) * sizeof(int32_t) + kFwdRowsMax;
@@ -2053,10 +2053,18 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
   return rc;
 }
 
-int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out) {
+int launch_sum(const imrt_ctx* ctx, const double* parts, int n, double* out, double add) {
   clear_stale_error();
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, parts, n, out);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kThreads), 0, ctx->stream, parts, n, out, add);
   return check_launch("sum_kernel");
+}
+
+int launch_zero(const imrt_ctx* ctx, float* p, int n) {
+  if (n <= 0) return IMRT_OK;
+  clear_stale_error();
+  const int g = std::min((n + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(zero_kernel, dim3(g), dim3(kThreads), 0, ctx->stream, p, n);
+  return check_launch("zero_kernel");
 }
 
 int launch_project(const imrt_ctx* ctx, const float* x, const float* g, double lambda, int nb,
