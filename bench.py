@@ -232,7 +232,7 @@ def batch_form(ctx, args):
     torch.cuda.synchronize()
     t = time.perf_counter()
     part = Plan.autotune_batch(plans, xs, eps=st.eps, alpha=st.alpha, lambda0s=lams, delta=st.delta,
-                               tune_iters=args.tune_iters) if args.tune_iters > 0 else doses[0].partition()
+                               tune_iters=args.tune_iters, max_iter=st.max_iter) if args.tune_iters >= 0 else None
     tune_s = time.perf_counter() - t
 
     def batched():
@@ -283,8 +283,12 @@ def batch_form(ctx, args):
         "bit_identical_to_solo": same,
         "dose_build_s": build_s,
         "lambda0_s": lam_s,
-        "partition": {"adj_min_nnz": part[0], "fwd_blocks_per_wave": part[1], "autotune_s": tune_s},
-        "per_plan": [{"nnz": d.nnz, "iterations": r.iterations, "solo_ms": a, "solo_same_partition_ms": b}
+        "partition": {"adjoint_workgroups_per_plan": part[0] if part else None,
+                      "forward_workgroups_per_plan": part[1] if part else None, "autotune_s": tune_s,
+                      "autotune": "whole batch solved per candidate" if args.tune_iters == 0 else
+                                  f"{args.tune_iters} iterations per candidate"},
+        "per_plan": [{"nnz": d.nnz, "iterations": r.iterations, "solo_ms": a, "solo_same_partition_ms": b,
+                      "adj_min_nnz": d.partition()[0], "fwd_blocks_per_wave": d.partition()[1]}
                      for d, r, a, b in zip(doses, rb, solo_default_ms, solo_ms)],
         "note": "times exclude the dose-matrix builds, the lambda_0 estimates and the launch-shape search "
                 "(reported apart); "
@@ -792,8 +796,9 @@ def main():
     ap.add_argument("--batch", type=int, default=32, metavar="N",
                     help="also time the batched re-plan workload of N uneven instances (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--tune-iters", type=int, default=40,
-                    help="iterations per candidate of the batch's launch-shape search (0: default partition)")
+    ap.add_argument("--tune-iters", type=int, default=0,
+                    help="iterations per candidate of the batch's launch-shape search (0: the whole batch "
+                         "solved per candidate; negative: no search, the default partition)")
     ap.add_argument("--no-shard", action="store_true",
                     help="skip the timing of one GPU's row share of the plan")
     ap.add_argument("--no-coarse", action="store_true",

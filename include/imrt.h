@@ -371,15 +371,20 @@ IMRT_API int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_sol
 IMRT_API int imrt_dose_repartition(imrt_dose* dose, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave);
 IMRT_API int imrt_dose_partition(const imrt_dose* dose, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave);
 
-/* Launch-shape search for a batch: a few candidate partitions are applied to
- * every dose matrix of the batch in turn, and a short batched solve of
- * tune_iters fixed iterations (from copies of x_dev; params as for
- * imrt_solve_batch, their iteration settings overridden) is timed with
- * stream events; the fastest partition is left applied and returned
- * (nullable outputs).  Solving afterwards, alone or batched, uses it. */
+/* Launch-shape search for a batch.  A candidate is a pair of per-plan
+ * targets (ta adjoint workgroups, tf forward workgroups): every dose matrix
+ * of the batch gets nnz/ta nonzeros per adjoint workgroup (within
+ * [1024, 32768]) and nnz/(16 tf 512) row blocks per forward wave (within
+ * [1, 4]), so small plans keep enough workgroups to run fast once they run
+ * alone while large ones start few.  Each candidate is applied in turn and a
+ * batched solve from copies of x_dev (params as for imrt_solve_batch) is
+ * timed with stream events: tune_iters > 0 fixed iterations, or with
+ * tune_iters == 0 every plan to its own stopping rule (the whole batch).  The
+ * fastest candidate is left applied and its targets returned in ta_out and
+ * tf_out (nullable).  Solving afterwards, alone or batched, uses it. */
 IMRT_API int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
-                                 const float* const* x_dev, int32_t tune_iters, int32_t* adj_min_nnz_out,
-                                 int32_t* fwd_blocks_per_wave_out);
+                                 const float* const* x_dev, int32_t tune_iters, int32_t* ta_out,
+                                 int32_t* tf_out);
 
 IMRT_API int imrt_plan_destroy(imrt_plan* plan);
 

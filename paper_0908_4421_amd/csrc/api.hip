@@ -1905,10 +1905,9 @@ int imrt_dose_partition(const imrt_dose* D, int32_t* adj_min_nnz, int32_t* fwd_b
 // iterations from the given x, on copies) is timed by stream events; the
 // fastest candidate is left applied.
 int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_params* params,
-                        const float* const* x_dev, int32_t tune_iters, int32_t* adj_min_nnz_out,
-                        int32_t* fwd_blocks_per_wave_out) {
-  if (n <= 0 || !plans || !params || !x_dev || tune_iters <= 0)
-    return set_error(IMRT_EINVAL, "n and tune_iters must be positive; plans, params and x must not be NULL");
+                        const float* const* x_dev, int32_t tune_iters, int32_t* ta_out, int32_t* tf_out) {
+  if (n <= 0 || !plans || !params || !x_dev || tune_iters < 0)
+    return set_error(IMRT_EINVAL, "n must be positive, tune_iters >= 0; plans, params and x must not be NULL");
   for (int i = 0; i < n; ++i)
     if (!plans[i] || !plans[i]->dose) return set_error(IMRT_EINVAL, "a plan is NULL or has no dose matrix");
   std::vector<imrt_dose*> doses;
@@ -1931,47 +1930,67 @@ int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_par
   }
   std::vector<imrt_solve_params> prm(params, params + n);
   for (auto& p : prm) {
-    p.max_iter = tune_iters;
-    p.fixed_iters = 1;
+    if (tune_iters > 0) {
+      p.max_iter = tune_iters;
+      p.fixed_iters = 1;
+    }
     p.trace = nullptr;
     p.profile = 0;
   }
   std::vector<imrt_solve_result> res(n);
-  const int32_t adj_candidates[] = {2048, 8192, 32768};
-  const int32_t bpw_candidates[] = {1, 4};
+  // Candidates are per-plan targets: about `ta` adjoint workgroups and `tf`
+  // forward workgroups per plan, i.e. for a matrix of nnz nonzeros
+  // nnz / ta nonzeros per adjoint workgroup (within [1024, 32768]) and
+  // nnz / (16 tf kWaveNnz) row blocks per forward wave (within [1, 4]).  Few
+  // workgroups per plan spend less on their starts while many plans share a
+  // dispatch; many keep a plan fast once it runs alone.
+  struct Cand {
+    int32_t ta, tf;
+  };
+  const Cand cands[] = {{32, 8}, {128, 16}, {128, 64}, {512, 32}, {512, 128}, {2048, 256}};
+  auto part_of = [](const imrt_dose* d, const Cand& c, int32_t* a, int32_t* b) {
+    const int64_t nnz = std::max<int64_t>(d->nnz, 1);
+    *a = static_cast<int32_t>(std::min<int64_t>(32768, std::max<int64_t>(1024, (nnz + c.ta - 1) / c.ta)));
+    const int64_t blocks = nnz / kWaveNnz + 1;
+    *b = static_cast<int32_t>(std::min<int64_t>(4, std::max<int64_t>(1, blocks / (16 * int64_t(c.tf)))));
+  };
   double best = -1.0;
-  int32_t best_adj = doses[0]->adj_min_nnz, best_bpw = doses[0]->fwd_bpw;
+  Cand best_c = cands[0];
   hipStream_t s = plans[0]->ctx->stream;
-  for (int32_t a : adj_candidates)
-    for (int32_t b : bpw_candidates) {
-      for (imrt_dose* d : doses)
-        if ((rc = imrt_dose_repartition(d, a, b))) {
-          release();
-          return rc;
-        }
-      for (int i = 0; i < n; ++i) {
-        const hipError_t e = hipMemcpyAsync(xs[i], x_dev[i], sizeof(float) * plans[i]->dose->nb,
-                                            hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) {
-          release();
-          return hip_error(e, "autotune copy");
-        }
-      }
-      if ((rc = imrt_solve_batch(n, plans, prm.data(), xs.data(), res.data()))) {
+  for (const Cand& c : cands) {
+    for (imrt_dose* d : doses) {
+      int32_t a = 0, b = 0;
+      part_of(d, c, &a, &b);
+      if ((rc = imrt_dose_repartition(d, a, b))) {
         release();
         return rc;
       }
-      const double ms = res[0].device_ms;
-      if (best < 0.0 || ms < best) {
-        best = ms;
-        best_adj = a;
-        best_bpw = b;
+    }
+    for (int i = 0; i < n; ++i) {
+      const hipError_t e = hipMemcpyAsync(xs[i], x_dev[i], sizeof(float) * plans[i]->dose->nb,
+                                          hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) {
+        release();
+        return hip_error(e, "autotune copy");
       }
     }
+    if ((rc = imrt_solve_batch(n, plans, prm.data(), xs.data(), res.data()))) {
+      release();
+      return rc;
+    }
+    const double ms = res[0].device_ms;
+    if (best < 0.0 || ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
   release();
-  for (imrt_dose* d : doses)
-    if ((rc = imrt_dose_repartition(d, best_adj, best_bpw))) return rc;
-  if (adj_min_nnz_out) *adj_min_nnz_out = best_adj;
-  if (fwd_blocks_per_wave_out) *fwd_blocks_per_wave_out = best_bpw;
+  for (imrt_dose* d : doses) {
+    int32_t a = 0, b = 0;
+    part_of(d, best_c, &a, &b);
+    if ((rc = imrt_dose_repartition(d, a, b))) return rc;
+  }
+  if (ta_out) *ta_out = best_c.ta;
+  if (tf_out) *tf_out = best_c.tf;
   return IMRT_OK;
 }

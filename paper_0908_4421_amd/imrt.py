@@ -560,11 +560,15 @@ class Plan:
 
     @staticmethod
     def autotune_batch(plans, xs, *, eps, alpha, lambda0s, delta=1e-5, max_backtracks=60, trials_per_pass=1,
-                       tune_iters=40):
-        """imrt_batch_autotune: returns the (adj_min_nnz, fwd_blocks_per_wave) left applied."""
+                       tune_iters=40, max_iter=20000):
+        """imrt_batch_autotune: returns the per-plan targets (adjoint
+        workgroups, forward workgroups) of the partition left applied.
+        tune_iters > 0 times that many fixed iterations per candidate, 0 the
+        whole batch solved to the stopping rule (max_iter cap)."""
         n = len(plans)
+        it, fixed = (tune_iters, 1) if tune_iters > 0 else (max_iter, 0)
         params = (imrt_solve_params * n)(*[
-            imrt_solve_params(eps, alpha, lam, delta, tune_iters, max_backtracks, 1, trials_per_pass, 0, 0, None)
+            imrt_solve_params(eps, alpha, lam, delta, it, max_backtracks, fixed, trials_per_pass, 0, 0, None)
             for lam in lambda0s])
         handles = (_vp * n)(*[p.handle for p in plans])
         xptr = (_vp * n)(*[x.data_ptr() for x in xs])

@@ -138,10 +138,13 @@ def test_repartition_and_autotune(ctx):
     plans = [_plan(ctx, dz, penalty_table(s)) for dz, s in zip(doses, specs)]
     lams = [_lambda0(p, dz, s.seed) for p, dz, s in zip(plans, doses, specs)]
     xs = [to_dev(np.full(dz.nb, ST.x0, np.float32)) for dz in doses]
-    adj, bpw = Plan.autotune_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=lams, tune_iters=20)
-    banner(f"autotune chose adj_min_nnz {adj}, blocks per wave {bpw}")
-    assert adj in (2048, 8192, 32768) and bpw in (1, 4)
-    assert all(dz.partition() == (adj, bpw) for dz in doses)
+    ta, tf = Plan.autotune_batch(plans, xs, eps=ST.eps, alpha=ST.alpha, lambda0s=lams, tune_iters=20)
+    banner(f"autotune chose {ta} adjoint and {tf} forward workgroups per plan")
+    assert (ta, tf) in ((32, 8), (128, 16), (128, 64), (512, 32), (512, 128), (2048, 256))
+    for dz in doses:   # each matrix carries its own partition from the chosen per-plan targets
+        a = min(32768, max(1024, -(-dz.nnz // ta)))
+        b = min(4, max(1, (dz.nnz // 512 + 1) // (16 * tf)))
+        assert dz.partition() == (a, b), (dz.nnz, dz.partition(), (a, b))
     # the start points were not modified by the search
     assert all(np.all(to_host(x0) == ST.x0) for x0 in xs)
     _solo_then_batch(plans, doses, lams, delta=ST.delta, max_iter=2000)
