@@ -195,9 +195,10 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    API are in grid order either way.
  *   "fwd_blocks_per_wave"  fewest forward row blocks per wave (1..1024,
  *                    default 1) of dose matrices created afterwards
- *   "serve_adj_min_nnz", "serve_fwd_blocks_per_wave"  the same two for the
- *                    matrices of servers created afterwards (defaults 32768
- *                    and 4)
+ *   "serve_adjoint_workgroups", "serve_forward_workgroups"  per-plan
+ *                    partition targets of the matrices servers created
+ *                    afterwards build (defaults 128 and 16; see
+ *                    imrt_dose_repartition_targets)
  *   "serve_groups_per_poll"  (adjoint, forward) dispatch groups a server
  *                    created afterwards runs between polls (1..4096,
  *                    default 16): more groups poll less often, fewer admit
@@ -370,6 +371,12 @@ IMRT_API int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_sol
  * [1, 1024], else IMRT_EINVAL. */
 IMRT_API int imrt_dose_repartition(imrt_dose* dose, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave);
 IMRT_API int imrt_dose_partition(const imrt_dose* dose, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave);
+/* imrt_dose_repartition with the partition of the per-plan targets that
+ * imrt_batch_autotune and the server use: about adj_workgroups adjoint and
+ * fwd_workgroups forward workgroups (>= 1 each), i.e. nnz/adj_workgroups
+ * nonzeros per adjoint workgroup within [1024, 32768] and
+ * (nnz/512 + 1)/(16 fwd_workgroups) row blocks per forward wave within [1, 4]. */
+IMRT_API int imrt_dose_repartition_targets(imrt_dose* dose, int32_t adj_workgroups, int32_t fwd_workgroups);
 
 /* Launch-shape search for a batch.  A candidate is a pair of per-plan
  * targets (ta adjoint workgroups, tf forward workgroups): every dose matrix
@@ -401,10 +408,10 @@ IMRT_API int imrt_plan_destroy(imrt_plan* plan);
  * One dispatch holds one storage, forward layout and trials_per_pass: a
  * request that differs from the live solves in these waits until they have
  * finished (requests keep their arrival order).  Matrices the
- * server builds take the context's "serve_adj_min_nnz" and
- * "serve_fwd_blocks_per_wave" partition (read at server creation), coarser
- * than a lone plan's since every dispatch holds several plans; a result
- * equals imrt_solve's on a matrix with that partition. */
+ * server builds take the partition of the context's per-plan targets
+ * "serve_adjoint_workgroups" and "serve_forward_workgroups" (read at server
+ * creation; imrt_dose_repartition_targets); a result equals imrt_solve's on
+ * a matrix with that partition. */
 typedef struct imrt_server imrt_server;
 
 typedef struct {

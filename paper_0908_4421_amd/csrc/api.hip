@@ -128,6 +128,20 @@ int alloc_nonzeros(imrt_dose* D) {
   return IMRT_OK;
 }
 
+void partition_for_targets(int64_t nnz, int ta, int tf, int32_t* adj_min_nnz, int32_t* fwd_bpw) {
+  nnz = std::max<int64_t>(nnz, 1);
+  ta = std::max(ta, 1);
+  tf = std::max(tf, 1);
+  *adj_min_nnz = static_cast<int32_t>(std::min<int64_t>(32768, std::max<int64_t>(1024, (nnz + ta - 1) / ta)));
+  const int64_t blocks = nnz / kWaveNnz + 1;
+  *fwd_bpw = static_cast<int32_t>(std::min<int64_t>(4, std::max<int64_t>(1, blocks / (16 * int64_t(tf)))));
+}
+
+void apply_partition_targets(const imrt_ctx* ctx, imrt_dose* D) {
+  if (ctx->tune.part_adj_wgs > 0 && ctx->tune.part_fwd_wgs > 0)
+    partition_for_targets(D->nnz, ctx->tune.part_adj_wgs, ctx->tune.part_fwd_wgs, &D->adj_min_nnz, &D->fwd_bpw);
+}
+
 // Row blocks for the forward pass (at most kFwdPartNnz nonzeros and
 // kFwdRowsMax rows each, or one longer row alone), and the adjoint partition:
 // workgroup w of G owns nonzeros [w*nnz/G, (w+1)*nnz/G) of the CSC arrays.
@@ -617,11 +631,8 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.fwd_col16;
   }
-  if (n == "serve_adj_min_nnz") {
-    *lo = 16;
-    return &ctx->tune.serve_adj_min_nnz;
-  }
-  if (n == "serve_fwd_blocks_per_wave") return &ctx->tune.serve_fwd_bpw;
+  if (n == "serve_adjoint_workgroups") return &ctx->tune.serve_adj_wgs;
+  if (n == "serve_forward_workgroups") return &ctx->tune.serve_fwd_wgs;
   if (n == "serve_groups_per_poll") return &ctx->tune.serve_groups;
   if (n == "serve_shared_adjoint") {
     *lo = 0;
@@ -649,7 +660,8 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
                       nm == "serve_shared_adjoint")
                          ? 1
                      : (nm == "fwd_wg_per_cu" || nm == "adj_wg_per_cu")         ? 64
-                     : (nm == "fwd_blocks_per_wave" || nm == "serve_fwd_blocks_per_wave") ? 1024
+                     : (nm == "fwd_blocks_per_wave")                                         ? 1024
+                     : (nm == "serve_adjoint_workgroups" || nm == "serve_forward_workgroups") ? 65536
                      : (nm == "serve_groups_per_poll")                                      ? 4096
                                                                                  : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
@@ -770,6 +782,7 @@ int imrt_dose_from_csr(imrt_ctx* ctx, int32_t nv, int32_t nb, int64_t nnz, const
       free_dose(D);
       return hip_error(e, "upload of D");
     }
+    apply_partition_targets(ctx, D);
     rc = finish_dose(D, rp, cp);
     if (rc == IMRT_OK) rc = store16(D, storage);
   } catch (const std::bad_alloc&) {
@@ -1892,6 +1905,14 @@ int imrt_dose_repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_
   }
 }
 
+int imrt_dose_repartition_targets(imrt_dose* D, int32_t adj_workgroups, int32_t fwd_workgroups) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  if (adj_workgroups < 1 || fwd_workgroups < 1) return set_error(IMRT_EINVAL, "workgroup targets must be >= 1");
+  int32_t a = 0, b = 0;
+  partition_for_targets(D->nnz, adj_workgroups, fwd_workgroups, &a, &b);
+  return imrt_dose_repartition(D, a, b);
+}
+
 int imrt_dose_partition(const imrt_dose* D, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave) {
   if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
   if (adj_min_nnz) *adj_min_nnz = D->adj_min_nnz;
@@ -1949,10 +1970,7 @@ int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_par
   };
   const Cand cands[] = {{32, 8}, {128, 16}, {128, 64}, {512, 32}, {512, 128}, {2048, 256}};
   auto part_of = [](const imrt_dose* d, const Cand& c, int32_t* a, int32_t* b) {
-    const int64_t nnz = std::max<int64_t>(d->nnz, 1);
-    *a = static_cast<int32_t>(std::min<int64_t>(32768, std::max<int64_t>(1024, (nnz + c.ta - 1) / c.ta)));
-    const int64_t blocks = nnz / kWaveNnz + 1;
-    *b = static_cast<int32_t>(std::min<int64_t>(4, std::max<int64_t>(1, blocks / (16 * int64_t(c.tf)))));
+    partition_for_targets(d->nnz, c.ta, c.tf, a, b);
   };
   double best = -1.0;
   Cand best_c = cands[0];

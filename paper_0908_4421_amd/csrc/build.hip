@@ -583,6 +583,7 @@ int build_phantom(imrt_ctx* ctx, const imrt_geometry* G, imrt_dose* D) {
                      D->val, 1);
   IMRT_HIP(hipGetLastError());
   IMRT_HIP(hipStreamSynchronize(s));
+  apply_partition_targets(ctx, D);
   return finish_dose(D, row_ptr, col_ptr);
 }
 

@@ -178,8 +178,10 @@ struct Tuning {
   int fwd_wave = 1;            // forward rows blocks per wave (1) or per workgroup (0)
   int fwd_bpw = 1;             // fewest row blocks per forward wave (new dose matrices)
   int fwd_col16 = 1;           // float32 matrices with nb <= 65536: 16-bit CSR columns for the forward
-  int serve_adj_min_nnz = 32768;   // the same two for matrices a server builds, which
-  int serve_fwd_bpw = 4;           // share every dispatch with other live plans
+  int part_adj_wgs = 0;            // > 0: new matrices take the per-plan partition targets
+  int part_fwd_wgs = 0;            // (adjoint / forward workgroups) instead of the two above
+  int serve_adj_wgs = 128;         // the targets of the matrices a server builds, which
+  int serve_fwd_wgs = 16;          // share their dispatches with the other live plans
   int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
   int serve_shared_adj = 1;        // live solves on one resident matrix share its adjoint pass
 };
@@ -353,6 +355,12 @@ int store16(imrt_dose* D, int storage);
 
 // phantom builder (build.hip)
 int build_phantom(imrt_ctx* ctx, const imrt_geometry* g, imrt_dose* D);
+// Partition of a matrix of nnz nonzeros for about `ta` adjoint and `tf`
+// forward workgroups: nonzeros per adjoint workgroup in [1024, 32768], row
+// blocks per forward wave in [1, 4].
+void partition_for_targets(int64_t nnz, int ta, int tf, int32_t* adj_min_nnz, int32_t* fwd_bpw);
+// The context's per-plan targets (if set) fixed as D's partition, once nnz is known.
+void apply_partition_targets(const imrt_ctx* ctx, imrt_dose* D);
 
 // host preprocessing (api.hip)
 int alloc_nonzeros(imrt_dose* D);

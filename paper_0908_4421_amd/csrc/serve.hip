@@ -510,9 +510,11 @@ int imrt_server_create(imrt_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_live
   S->user = ctx;
   S->ctx = *ctx;
   S->ctx.stream = nullptr;
-  // matrices the server builds take the partition meant for shared dispatches
-  S->ctx.tune.adj_min_nnz = ctx->tune.serve_adj_min_nnz;
-  S->ctx.tune.fwd_bpw = ctx->tune.serve_fwd_bpw;
+  // matrices the server builds take per-plan partition targets: few
+  // workgroups for a large plan sharing its dispatches, enough for a small
+  // one to run fast when it is (nearly) alone
+  S->ctx.tune.part_adj_wgs = ctx->tune.serve_adj_wgs;
+  S->ctx.tune.part_fwd_wgs = ctx->tune.serve_fwd_wgs;
   S->budget = hbm_budget_bytes;
   S->reserve = std::min<int64_t>(hbm_budget_bytes / 2, int64_t(1) << 28);
   S->max_live = max_live;

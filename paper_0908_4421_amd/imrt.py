@@ -110,6 +110,7 @@ SIGNATURES = {
                                    C.POINTER(imrt_solve_result)]),
     "imrt_dose_repartition": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "imrt_dose_partition": (C.c_int, [_vp, _i32p, _i32p]),
+    "imrt_dose_repartition_targets": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "imrt_batch_autotune": (C.c_int, [C.c_int32, C.POINTER(_vp), C.POINTER(imrt_solve_params), C.POINTER(_vp),
                                       C.c_int32, _i32p, _i32p]),
     "imrt_plan_destroy": (C.c_int, [_vp]),
@@ -255,6 +256,11 @@ def imrt_dose_partition(dose):
     a, b = C.c_int32(), C.c_int32()
     _check(load().imrt_dose_partition(dose, C.byref(a), C.byref(b)), "imrt_dose_partition")
     return a.value, b.value
+
+
+def imrt_dose_repartition_targets(dose, adj_workgroups: int, fwd_workgroups: int):
+    return _check(load().imrt_dose_repartition_targets(dose, int(adj_workgroups), int(fwd_workgroups)),
+                  "imrt_dose_repartition_targets")
 
 
 def imrt_batch_autotune(n: int, plans, params, x_devs, tune_iters: int):
@@ -440,6 +446,10 @@ class Dose:
 
     def partition(self):
         return imrt_dose_partition(self.handle)
+
+    def repartition_targets(self, adj_workgroups: int, fwd_workgroups: int):
+        """Per-plan partition targets (the batch search's and the server's rule)."""
+        imrt_dose_repartition_targets(self.handle, adj_workgroups, fwd_workgroups)
 
     def export_codes(self):
         """16-bit storage: codes in CSR and CSC order and the beamlet scales."""
