@@ -152,7 +152,8 @@ def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
     code = {"bf16": 1, "f16": 2}[storage]
     names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt == 1 else 8}, {code}>(",
              "adjoint": f"adj_kernel<{nt}, true, {code}>("}
-    nr, nb, nnz = nonempty_rows(dose), dose.nb, dose.nnz
+    nv, nb, nnz = dose.nv, dose.nb, dose.nnz
+    nr = nonempty_rows(dose)
     kern = kernel_table(runs, res, names, {"forward": forward_bytes16(nr, nb, nnz),
                                            "adjoint": adjoint_bytes16(nr, nb, nnz)})
     d16 = torch.empty(nv, dtype=torch.float32, device="cuda")
