@@ -659,20 +659,28 @@ struct TrialRegs {
   double tab;
 };
 
+// Buffer loads bounded by nb: the slots of a thread past the last beamlet
+// read zeros and send no request to memory.
 template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<NT>& R) {
-  const int nb = a.nb;
+  const uint32_t nb = static_cast<uint32_t>(a.nb);
+  rsrc_t rx[NT + 1];
+#pragma unroll
+  for (int j = 0; j <= NT; ++j) rx[j] = make_rsrc(a.xbuf[j], 4u * nb);
+  const rsrc_t rg = make_rsrc(a.g, 4u * nb);
+  const rsrc_t rp = make_rsrc(a.pieces_col, a.pieces_col ? 16u * nb : 0u);
+  const rsrc_t rk = make_rsrc(a.col_kind, nb);
+  const rsrc_t rs = make_rsrc(a.col_scale, (coded(ST) && a.col_scale) ? 4u * nb : 0u);
 #pragma unroll
   for (int u = 0; u < kTrialU; ++u) {
-    const int i = i0 + u * THREADS;
-    const int ii = i < nb ? i : 0;
+    const uint32_t i = static_cast<uint32_t>(i0 + u * THREADS);
 #pragma unroll
-    for (int j = 0; j <= NT; ++j) R.xc[j][u] = a.xbuf[j][ii];
-    R.g[u] = a.g[ii];
-    R.p0[u] = a.pieces_col[2 * ii];
-    R.p1[u] = a.pieces_col[2 * ii + 1];
-    R.kind[u] = a.col_kind[ii];
-    if constexpr (coded(ST)) R.sc[u] = a.col_scale[ii];
+    for (int j = 0; j <= NT; ++j) R.xc[j][u] = load_f32(rx[j], 4u * i);
+    R.g[u] = load_f32(rg, 4u * i);
+    R.p0[u] = load_f64(rp, 16u * i);
+    R.p1[u] = load_f64(rp, 16u * i + 8u);
+    R.kind[u] = load_u8(rk, i);
+    if constexpr (coded(ST)) R.sc[u] = load_f32(rs, 4u * i);
   }
 }
 
@@ -1084,7 +1092,17 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
       float acc[NT];
 #pragma unroll
       for (int q = 0; q < NT; ++q) acc[q] = 0.f;
-      for (int k = S.rlo[p] - a0 + sub; k < s1; k += 4 * L) {
+      // rounds of four products per lane: whole rounds first, then at most
+      // one round that runs past the row's end (its tail slots read as zero)
+      int k = S.rlo[p] - a0 + sub;
+      for (; k + 3 * L < s1; k += 4 * L) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+          const float* pq = prod + q * NNZ + k;
+          acc[q] += (pq[0] + pq[L]) + (pq[2 * L] + pq[3 * L]);
+        }
+      }
+      if (k < s1) {
         const int left = s1 - k;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
@@ -1158,6 +1176,15 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   const int mrow0 = load_i32(make_rsrc(a.wblock_row, meta_bytes), 4u * static_cast<uint32_t>(b));
   const int mend0 = load_i32(make_rsrc(a.wblock_end, meta_bytes - 4u), 4u * static_cast<uint32_t>(b));
   const int mk00 = load_i32(make_rsrc(a.wblock_k0, meta_bytes), moff);
+  // the first chunk's block bounds (thread i loads entry B0 + i), stored to
+  // LDS before the staging barrier, so that no round trip and no barrier of
+  // their own stand between the staging and the first block
+  static_assert(THREADS > kMetaChunk, "one thread per bound of the first chunk");
+  const int cfirst = min(B1, B0 + kMetaChunk) - B0;
+  const uint32_t mi = 4u * static_cast<uint32_t>(B0 + tid);
+  const int pre_row = load_i32(make_rsrc(a.wblock_row, meta_bytes), mi);
+  const int pre_k0 = load_i32(make_rsrc(a.wblock_k0, meta_bytes), mi);
+  const int pre_end = load_i32(make_rsrc(a.wblock_end, meta_bytes - 4u), mi);
   TrialRegs<NT> TR;
   StageRegs<NT> SR;
   int32_t sw = 0;
@@ -1205,6 +1232,13 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
 #pragma unroll
     for (int q = 0; q < NT; ++q) rout[q] = make_rsrc(a.rbuf[q], vbytes);
   }
+  if (tid <= cfirst) {
+    mrow[tid] = pre_row;
+    mk0[tid] = pre_k0;
+    if (tid < cfirst) mend[tid] = pre_end;
+  }
+  if (tid == 0) next_blk = B0 + WAVES;
+  // (both stagings end with a barrier)
   if (solve) trial_finish<NT, THREADS, ST>(a, TR, T, lam, tab, xs, red, sl.G);
   else stage_finish<NT, THREADS, ST>(a, a.x, want_sid, SR, tab, xs);
 
@@ -1213,13 +1247,15 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   for (int q = 0; q < NT; ++q) gsum[q] = 0.0;
   for (int c0 = B0; c0 < B1; c0 += kMetaChunk) {
     const int c1 = min(c0 + kMetaChunk, B1);
-    for (int i = tid; i <= c1 - c0; i += THREADS) {
-      mrow[i] = a.wblock_row[c0 + i];
-      mk0[i] = a.wblock_k0[c0 + i];
-      if (i < c1 - c0) mend[i] = a.wblock_end[c0 + i];
+    if (c0 != B0) {
+      for (int i = tid; i <= c1 - c0; i += THREADS) {
+        mrow[i] = a.wblock_row[c0 + i];
+        mk0[i] = a.wblock_k0[c0 + i];
+        if (i < c1 - c0) mend[i] = a.wblock_end[c0 + i];
+      }
+      if (tid == 0) next_blk = c0 + WAVES;
+      __syncthreads();
     }
-    if (tid == 0) next_blk = c0 + WAVES;
-    __syncthreads();
     auto meta = [&](int blk) {
       const int i = blk - c0;
       WaveBlock m;
@@ -1231,10 +1267,8 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
     };
     if (c0 != B0) {
       b = c0 + wv;
-      if (b < c1) {
-        cur = meta(b);
-        if (cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
-      }
+      cur = (b < c1) ? meta(b) : WaveBlock{0, 0, 0, 0};
+      wave_issue<MODE, true, ST>(a, (b < c1 && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
     }
     while (b < c1) {
       // the block after this one (taken now, its loads issued once this
@@ -1277,7 +1311,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
           const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
           row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pb, rout, dout, ntr);
         }
-        if (more && cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
+        wave_issue<MODE, true, ST>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
       } else {
         // products of this block into the wave's LDS region (lanes past the
         // block hold zeros and write slots that no row reads)
@@ -1300,7 +1334,10 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const WaveStage<ST> R = S;   // this block's row pointers and ids (loads already waited on)
-        if (more && cur.k1 - cur.k0 <= PART) wave_issue<MODE, false, ST>(a, cur, lane, S);
+        // issued whether or not a next block follows (an empty block reads
+        // zeros and touches no memory), so the loads land in the registers
+        // the next products read, with no copies to merge two paths
+        wave_issue<MODE, true, ST>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
         switch (log2_lanes(blk.r1 - blk.r0)) {
           case 0: wave_rows<1, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
           case 1: wave_rows<2, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
