@@ -25,7 +25,12 @@ constexpr int kWavePartNnz = kWaveNnz - 4;
 // and 16-bit column indices it holds 1.5 times as many (6 bytes each).
 constexpr int wave_nnz(int storage) { return storage == 0 ? kWaveNnz : storage == 3 ? 3 * kWaveNnz / 2 : 2 * kWaveNnz; }
 constexpr int wave_part_nnz(int storage) { return wave_nnz(storage) - 4; }
-constexpr int kWaveRowsMax = 256;      // rows of one wave's row block
+// Rows of one wave's row block, and the passes of one lane per row over it.
+// Every pass's row loads are issued for every block (out-of-range rows read
+// zeros), and they cost address cycles even then: fewer passes make the
+// blocks of long-row matrices cheaper.
+constexpr int kWaveRowsMax = 128;
+constexpr int kWavePasses = kWaveRowsMax / 64;
 constexpr int kGapRows = 16;           // runs of at least this many empty rows lie between wave blocks
 constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;

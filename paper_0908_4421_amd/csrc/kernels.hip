@@ -962,8 +962,8 @@ template <int ST>
 struct WaveStage {
   ColGroup<ST> c[wave_groups<ST>()];
   ValGroup<ST> v[wave_groups<ST>()];
-  int rlo[4], rhi[4];
-  uint32_t sid[4];
+  int rlo[kWavePasses], rhi[kWavePasses];
+  uint32_t sid[kWavePasses];
 };
 
 // Loads of the entries base + 4 lane + 256 j + u (u < 4, j < the group count)
@@ -1028,7 +1028,7 @@ __device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m,
   const rsrc_t rp = make_rsrc(a.row_ptr + m.r0, static_cast<uint32_t>(nr + 1) * 4);
   const rsrc_t rs = make_rsrc(a.pen.sid + m.r0, static_cast<uint32_t>(nr));
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < kWavePasses; ++p) {
     S.rlo[p] = S.rhi[p] = 0;
     S.sid[p] = 0;
     if (UNCOND) {
@@ -1085,7 +1085,7 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
   const int passes = (nr * L + 63) / 64;
   const int sub = lane & (L - 1);
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
+  for (int p = 0; p < kWavePasses; ++p) {
     if (p < passes) {
       const int row = p * kRowsPerPass + lane / L;
       const int s1 = S.rhi[p] - a0;
