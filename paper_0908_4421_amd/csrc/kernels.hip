@@ -577,19 +577,21 @@ struct StageRegs {
 template <int NT, int THREADS = kThreads, int ST = ST_F32>
 __device__ __forceinline__ void stage_start(const FwdArgs& a, const float* src, bool want_sid, StageRegs<NT>& R) {
   const int tid = threadIdx.x, nb = a.nb, nbp = pad4(nb);
+  // (slots wholly past the last entry for this wave issue no loads)
+  const int wave0 = uniform(tid - (tid & 63));
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int i = tid + u * THREADS;
-      R.v[q][u] = src[q * nbp + (i < nb ? i : 0)];
+      R.v[q][u] = (wave0 + u * THREADS < nb) ? src[q * nbp + (i < nb ? i : 0)] : 0.0f;
     }
   }
   if constexpr (coded(ST)) {
 #pragma unroll
     for (int u = 0; u < kStageU; ++u) {
       const int i = tid + u * THREADS;
-      R.sc[u] = a.col_scale[i < nb ? i : 0];
+      R.sc[u] = (wave0 + u * THREADS < nb) ? a.col_scale[i < nb ? i : 0] : 0.0f;
     }
   }
   // first THREADS doubles of the table (4 per structure); the rest in stage_finish
@@ -671,16 +673,28 @@ __device__ __forceinline__ void trial_load(const FwdArgs& a, int i0, TrialRegs<N
   const rsrc_t rp = make_rsrc(a.pieces_col, a.pieces_col ? 16u * nb : 0u);
   const rsrc_t rk = make_rsrc(a.col_kind, nb);
   const rsrc_t rs = make_rsrc(a.col_scale, (coded(ST) && a.col_scale) ? 4u * nb : 0u);
+  // a slot wholly past the last beamlet for this wave issues no loads at
+  // all (out-of-range lanes cost address cycles even when they read zeros)
+  const int wave0 = uniform(i0 - static_cast<int>(threadIdx.x & 63));
 #pragma unroll
   for (int u = 0; u < kTrialU; ++u) {
     const uint32_t i = static_cast<uint32_t>(i0 + u * THREADS);
+    if (wave0 + u * THREADS < a.nb) {
 #pragma unroll
-    for (int j = 0; j <= NT; ++j) R.xc[j][u] = load_f32(rx[j], 4u * i);
-    R.g[u] = load_f32(rg, 4u * i);
-    R.p0[u] = load_f64(rp, 16u * i);
-    R.p1[u] = load_f64(rp, 16u * i + 8u);
-    R.kind[u] = load_u8(rk, i);
-    if constexpr (coded(ST)) R.sc[u] = load_f32(rs, 4u * i);
+      for (int j = 0; j <= NT; ++j) R.xc[j][u] = load_f32(rx[j], 4u * i);
+      R.g[u] = load_f32(rg, 4u * i);
+      R.p0[u] = load_f64(rp, 16u * i);
+      R.p1[u] = load_f64(rp, 16u * i + 8u);
+      R.kind[u] = load_u8(rk, i);
+      if constexpr (coded(ST)) R.sc[u] = load_f32(rs, 4u * i);
+    } else {
+#pragma unroll
+      for (int j = 0; j <= NT; ++j) R.xc[j][u] = 0.0f;
+      R.g[u] = 0.0f;
+      R.p0[u] = R.p1[u] = 0.0;
+      R.kind[u] = 0;
+      R.sc[u] = 0.0f;
+    }
   }
 }
 
