@@ -179,10 +179,11 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 
 /* Launch-shape settings of a context, by name:
  *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (1..64; default
- *                    1).  A "fwd_wave" workgroup has 16 waves (8 when a pass
- *                    tries four step sizes) that take row blocks from a
- *                    shared counter; otherwise the value is scaled by four
- *                    workgroups of 4 waves.
+ *                    3).  A "fwd_wave" workgroup has 8 waves that take row
+ *                    blocks from a shared counter (three fit a compute unit
+ *                    with one or two trials per pass, so that one's start
+ *                    overlaps the others' streams); otherwise the value is
+ *                    scaled by four workgroups of 4 waves.
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (1..64)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
  *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die,
@@ -197,7 +198,7 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    default 1) of dose matrices created afterwards
  *   "serve_adjoint_workgroups", "serve_forward_workgroups"  per-plan
  *                    partition targets of the matrices servers created
- *                    afterwards build (defaults 128 and 16; see
+ *                    afterwards build (defaults 128 and 32; see
  *                    imrt_dose_repartition_targets)
  *   "serve_groups_per_poll"  (adjoint, forward) dispatch groups a server
  *                    created afterwards runs between polls (1..4096,
@@ -381,7 +382,7 @@ IMRT_API int imrt_dose_repartition_targets(imrt_dose* dose, int32_t adj_workgrou
 /* Launch-shape search for a batch.  A candidate is a pair of per-plan
  * targets (ta adjoint workgroups, tf forward workgroups): every dose matrix
  * of the batch gets nnz/ta nonzeros per adjoint workgroup (within
- * [1024, 32768]) and nnz/(16 tf 512) row blocks per forward wave (within
+ * [1024, 32768]) and nnz/(8 tf 512) row blocks per forward wave (within
  * [1, 4]), so small plans keep enough workgroups to run fast once they run
  * alone while large ones start few.  Each candidate is applied in turn and a
  * batched solve from copies of x_dev (params as for imrt_solve_batch) is

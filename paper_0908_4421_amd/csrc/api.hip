@@ -134,7 +134,8 @@ void partition_for_targets(int64_t nnz, int ta, int tf, int32_t* adj_min_nnz, in
   tf = std::max(tf, 1);
   *adj_min_nnz = static_cast<int32_t>(std::min<int64_t>(32768, std::max<int64_t>(1024, (nnz + ta - 1) / ta)));
   const int64_t blocks = nnz / kWaveNnz + 1;
-  *fwd_bpw = static_cast<int32_t>(std::min<int64_t>(4, std::max<int64_t>(1, blocks / (16 * int64_t(tf)))));
+  *fwd_bpw = static_cast<int32_t>(
+      std::min<int64_t>(4, std::max<int64_t>(1, blocks / (int64_t(forward_waves(1)) * tf))));
 }
 
 void apply_partition_targets(const imrt_ctx* ctx, imrt_dose* D) {
@@ -1962,13 +1963,14 @@ int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_par
   // Candidates are per-plan targets: about `ta` adjoint workgroups and `tf`
   // forward workgroups per plan, i.e. for a matrix of nnz nonzeros
   // nnz / ta nonzeros per adjoint workgroup (within [1024, 32768]) and
-  // nnz / (16 tf kWaveNnz) row blocks per forward wave (within [1, 4]).  Few
+  // nnz / (8 tf kWaveNnz) row blocks per forward wave (8-wave workgroups;
+  // within [1, 4]).  Few
   // workgroups per plan spend less on their starts while many plans share a
   // dispatch; many keep a plan fast once it runs alone.
   struct Cand {
     int32_t ta, tf;
   };
-  const Cand cands[] = {{32, 8}, {128, 16}, {128, 64}, {512, 32}, {512, 128}, {2048, 256}};
+  const Cand cands[] = {{32, 16}, {128, 32}, {128, 128}, {512, 64}, {512, 256}, {2048, 512}};
   auto part_of = [](const imrt_dose* d, const Cand& c, int32_t* a, int32_t* b) {
     partition_for_targets(d->nnz, c.ta, c.tf, a, b);
   };

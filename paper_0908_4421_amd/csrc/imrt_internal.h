@@ -174,7 +174,7 @@ struct AdjArgs {
 
 // ---- host-side objects ------------------------------------------------------------
 struct Tuning {
-  int fwd_grid_per_cu = 1;
+  int fwd_grid_per_cu = 3;
   int adj_grid_per_cu = 4;
   int adj_min_nnz = 1024;      // nonzeros per adjoint workgroup at least (small matrices)
   int batch_iters = 32;        // iterations enqueued between host polls
@@ -186,7 +186,7 @@ struct Tuning {
   int part_adj_wgs = 0;            // > 0: new matrices take the per-plan partition targets
   int part_fwd_wgs = 0;            // (adjoint / forward workgroups) instead of the two above
   int serve_adj_wgs = 128;         // the targets of the matrices a server builds, which
-  int serve_fwd_wgs = 16;          // share their dispatches with the other live plans
+  int serve_fwd_wgs = 32;          // share their dispatches with the other live plans
   int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
   int serve_shared_adj = 1;        // live solves on one resident matrix share its adjoint pass
 };

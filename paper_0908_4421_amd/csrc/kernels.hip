@@ -1138,12 +1138,13 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
   }
 }
 
-// Waves of a wave-granular forward workgroup: sixteen (one workgroup per
-// compute unit) for one or two trials, eight for four (registers).
+// Waves of a wave-granular forward workgroup: eight, with three workgroups
+// per compute unit by default, so that one workgroup's staging (the start of
+// every workgroup, and of every plan's workgroups in a batched pass)
+// overlaps the others' streams.  One and two trials per pass keep within 80
+// and 128 registers per lane (six and four waves per SIMD).
 template <int NT>
-struct FwdWaves {
-  static constexpr int value = (NT <= 2) ? 16 : 8;
-};
+constexpr int fwd_min_waves_per_simd() { return NT == 1 ? 6 : NT == 2 ? 4 : 1; }
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
 template <int NT, int MODE, int WAVES, int ST>
@@ -1392,7 +1393,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
 }
 
 template <int NT, int MODE, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
+__global__ __launch_bounds__(WAVES * 64, fwd_min_waves_per_simd<NT>()) void fwd_wave_kernel(FwdArgs a) {
   fwd_wave_pass<NT, MODE, WAVES, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
 }
 
@@ -1400,7 +1401,7 @@ __global__ __launch_bounds__(WAVES * 64) void fwd_wave_kernel(FwdArgs a) {
 // plan's pass, or -1 for an idle slot (plans start at multiples of the die
 // count, so each plan keeps its workgroups' die placement).
 template <int NT, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
+__global__ __launch_bounds__(WAVES * 64, fwd_min_waves_per_simd<NT>()) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
                                                                     const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
@@ -1893,7 +1894,10 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
   return bytes;
 }
 
-int forward_waves(int ntrials) { return ntrials <= 2 ? 16 : 8; }
+int forward_waves(int ntrials) {
+  (void)ntrials;
+  return 8;
+}
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials) {
   if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials, D->fwd_bpw);
@@ -1919,20 +1923,20 @@ int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz) {
 template <int ST>
 int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipStream_t s, hipEvent_t before,
                         hipEvent_t after) {
-  const dim3 bd16(16 * 64), bd8(8 * 64);
+  const dim3 bd8(8 * 64);
   if (a.mode == FWD_SOLVE) {
     switch (ntrials) {
-      case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a); break;
-      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a); break;
+      case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
+      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
       case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
       default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
     }
   } else if (ntrials != 1) {
     return set_error(IMRT_EINVAL, "evaluation passes take one trial");
   } else if (a.mode == FWD_EVAL) {
-    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
   } else {
-    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
   }
   return IMRT_OK;
 }
@@ -1944,8 +1948,8 @@ int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslot
                             hipStream_t s) {
   const dim3 gd(nslots);
   switch (ntrials) {
-    case 1: hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots); break;
-    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots); break;
+    case 1: hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
     case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }

@@ -103,7 +103,7 @@ def test_full_solve_trajectory_block_forward(built, fx):
 
 
 def test_full_solve_trajectory_two_trials(built, fx):
-    """The same with two trial steps per forward pass (16-wave workgroups):
+    """The same with two trial steps per forward pass:
     the trajectory does not depend on how the trials are grouped."""
     banner("paper-scale solve, two trials per pass")
     _check_full_solve(built, fx, nt=2)
