@@ -150,7 +150,7 @@ def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
           flush=True)
     nt = args.trials_per_pass
     code = {"bf16": 1, "f16": 2}[storage]
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, 8, {code}>(",
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {code}>(",
              "adjoint": f"adj_kernel<{nt}, true, {code}>("}
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     nr = nonempty_rows(dose)
@@ -412,7 +412,7 @@ def shape_form(ctx, args, spec=None, note=SCENARIO3_NOTE):
     nr = nonempty_rows(dose)
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, 8, {lay}>(",
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}>(",
              "adjoint": f"adj_kernel<{nt}, true, 0>("}
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz), "adjoint": adjoint_bytes(nr, nb, nnz)})
     print(f"[bench] {spec.name}: {res.iterations} iterations, {ms:.2f} ms per plan, forward "
@@ -879,7 +879,7 @@ def main():
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, 8, {lay}>(" if wave else f"fwd_kernel<{nt}>(",
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}>(" if wave else f"fwd_kernel<{nt}>(",
              "adjoint": f"adj_kernel<{nt}, true, 0>("}
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz),
                                            "adjoint": adjoint_bytes(nr, nb, nnz)})

@@ -179,11 +179,15 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
 
 /* Launch-shape settings of a context, by name:
  *   "fwd_wg_per_cu"  forward-pass workgroups per compute unit (1..64; default
- *                    3).  A "fwd_wave" workgroup has 8 waves that take row
- *                    blocks from a shared counter (three fit a compute unit
- *                    with one or two trials per pass, so that one's start
- *                    overlaps the others' streams); otherwise the value is
- *                    scaled by four workgroups of 4 waves.
+ *                    3).  A "fwd_wave" workgroup has 16 waves, or 8 on a
+ *                    matrix partitioned by per-plan targets
+ *                    (imrt_dose_repartition_targets), that take row blocks
+ *                    from a shared counter; the grid never holds more per
+ *                    compute unit than fit side by side (one of 16 waves;
+ *                    three of 8 with one trial per pass, two with more;
+ *                    fewer when the staged vectors of a large nb fill the
+ *                    LDS).  Otherwise the value is scaled by four
+ *                    workgroups of 4 waves.
  *   "adj_wg_per_cu"  adjoint-pass workgroups per compute unit (1..64)
  *   "adj_min_nnz"    fewest nonzeros per adjoint workgroup (>= 16)
  *   "adj_xcd"        1: consecutive adjoint ranges on the same accelerator die,
@@ -376,7 +380,12 @@ IMRT_API int imrt_dose_partition(const imrt_dose* dose, int32_t* adj_min_nnz, in
  * imrt_batch_autotune and the server use: about adj_workgroups adjoint and
  * fwd_workgroups forward workgroups (>= 1 each), i.e. nnz/adj_workgroups
  * nonzeros per adjoint workgroup within [1024, 32768] and
- * (nnz/512 + 1)/(16 fwd_workgroups) row blocks per forward wave within [1, 4]. */
+ * (nnz/512 + 1)/(8 fwd_workgroups) row blocks per forward wave within [1, 4].
+ * Such a matrix's forward workgroups have 8 waves (several side by side on a
+ * compute unit, so that the starts of one plan's workgroups overlap the
+ * others' streams in shared dispatches); a new matrix's have 16 (one per
+ * compute unit), which imrt_dose_repartition keeps.  One batched solve needs
+ * matrices with the same forward workgroup size (else IMRT_EINVAL). */
 IMRT_API int imrt_dose_repartition_targets(imrt_dose* dose, int32_t adj_workgroups, int32_t fwd_workgroups);
 
 /* Launch-shape search for a batch.  A candidate is a pair of per-plan

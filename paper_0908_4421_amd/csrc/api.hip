@@ -135,12 +135,14 @@ void partition_for_targets(int64_t nnz, int ta, int tf, int32_t* adj_min_nnz, in
   *adj_min_nnz = static_cast<int32_t>(std::min<int64_t>(32768, std::max<int64_t>(1024, (nnz + ta - 1) / ta)));
   const int64_t blocks = nnz / kWaveNnz + 1;
   *fwd_bpw = static_cast<int32_t>(
-      std::min<int64_t>(4, std::max<int64_t>(1, blocks / (int64_t(forward_waves(1)) * tf))));
+      std::min<int64_t>(4, std::max<int64_t>(1, blocks / (int64_t(forward_waves(1, 8)) * tf))));
 }
 
 void apply_partition_targets(const imrt_ctx* ctx, imrt_dose* D) {
-  if (ctx->tune.part_adj_wgs > 0 && ctx->tune.part_fwd_wgs > 0)
+  if (ctx->tune.part_adj_wgs > 0 && ctx->tune.part_fwd_wgs > 0) {
     partition_for_targets(D->nnz, ctx->tune.part_adj_wgs, ctx->tune.part_fwd_wgs, &D->adj_min_nnz, &D->fwd_bpw);
+    D->fwd_waves = 8;
+  }
 }
 
 // Row blocks for the forward pass (at most kFwdPartNnz nonzeros and
@@ -208,7 +210,9 @@ int finish_dose(imrt_dose* D, const std::vector<int32_t>& row_ptr, const std::ve
   // nonzeros are halved (by rows) until the count is a multiple of the waves.
   {
     const int nwb = static_cast<int>(wb.size());
-    const int64_t waves = static_cast<int64_t>(wave_grid(D->ctx, nwb, 1, D->fwd_bpw)) * forward_waves(1);
+    const int64_t waves =
+        static_cast<int64_t>(wave_grid(D->ctx, nwb, 1, D->fwd_bpw, D->nb, D->fwd_st, D->fwd_waves)) *
+        forward_waves(1, D->fwd_waves);
     const int64_t target = (nwb + waves - 1) / waves * waves;
     if (nwb > waves && target > nwb) {
       // max-heap of (nonzeros, block start row) over splittable blocks
@@ -486,6 +490,7 @@ FwdArgs base_fwd(const imrt_dose* D) {
   a.val16 = D->val16;
   a.col_scale = D->col_scale;
   a.storage = D->fwd_st;
+  a.waves = D->fwd_waves;
   a.block_row = D->block_row;
   a.block_k0 = D->block_k0;
   a.nblocks = D->nblocks;
@@ -579,11 +584,13 @@ int imrt_ctx_create(int device, void* hip_stream, imrt_ctx** out) {
   auto* c = new (std::nothrow) imrt_ctx();
   if (!c) return set_error(IMRT_ENOMEM, "host allocation failed");
   c->device = device;
-  int ncu = 0, lds = 0;
+  int ncu = 0, lds = 0, culds = 0;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
   (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+  (void)hipDeviceGetAttribute(&culds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device);
   if (ncu > 0) c->num_cu = ncu;
   if (lds > 0) c->max_lds = static_cast<size_t>(lds);
+  c->cu_lds = std::max(c->max_lds, culds > 0 ? static_cast<size_t>(culds) : c->max_lds);
   c->tune.fwd_grid_per_cu = std::min(64, env_int("IMRT_FWD_WG_PER_CU", c->tune.fwd_grid_per_cu));
   c->tune.adj_grid_per_cu = std::min(64, env_int("IMRT_ADJ_WG_PER_CU", c->tune.adj_grid_per_cu));
   c->tune.batch_iters = env_int("IMRT_BATCH_ITERS", c->tune.batch_iters);
@@ -1298,7 +1305,7 @@ int solve_prepare(imrt_plan* P, const imrt_solve_params* prm, const float* x_dev
   const imrt_dose* D = P->dose;
   imrt_ctx* C = P->ctx;
   hipStream_t s = C->stream;
-  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0, D->fwd_st) > C->max_lds)
+  if (forward_lds_bytes(D->nb, nt, P->nstruct, C->tune.fwd_wave != 0, D->fwd_st, D->fwd_waves) > C->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "nb * trials_per_pass exceeds the LDS budget of the forward pass");
 
   // x_1 >= 0 and finite (initialisation of the method)
@@ -1666,8 +1673,11 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   for (int i = 0; i < n; ++i) {
     if (plans[i]->ctx != C) return set_error(IMRT_EINVAL, "all plans of a batch must share one context");
     if (plans[i]->dose && (plans[i]->dose->storage != plans[0]->dose->storage ||
-                           plans[i]->dose->fwd_st != plans[0]->dose->fwd_st))
-      return set_error(IMRT_EINVAL, "all dose matrices of a batch must have the same storage and layout");
+                           plans[i]->dose->fwd_st != plans[0]->dose->fwd_st ||
+                           plans[i]->dose->fwd_waves != plans[0]->dose->fwd_waves))
+      return set_error(IMRT_EINVAL,
+                       "all dose matrices of a batch must have the same storage, layout and forward workgroup size "
+                       "(partition them alike, e.g. with imrt_dose_repartition_targets)");
   }
   if (C->tune.fwd_wave == 0) return set_error(IMRT_EUNSUPPORTED, "the batched solve needs fwd_wave = 1");
   std::vector<int> nt(n), cap(n), fgrid(n), agrid(n);
@@ -1678,7 +1688,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     if (nt[i] != nt[0]) return set_error(IMRT_EINVAL, "all plans of a batch must use the same trials_per_pass");
     if (plans[i]->dose->adj_grid >= 65536) return set_error(IMRT_EUNSUPPORTED, "adjoint grid too large for a batch");
   }
-  const int storage = plans[0]->dose->storage, fst = plans[0]->dose->fwd_st;
+  const int storage = plans[0]->dose->storage, fst = plans[0]->dose->fwd_st, fwv = plans[0]->dose->fwd_waves;
   BatchBuffers B;
   // The batch runs on a stream of its own (a graph cannot be captured on the
   // null stream), ordered after the work already on the context's stream;
@@ -1711,7 +1721,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     imrt_plan* P = plans[i];
     fgrid[i] = std::min(forward_grid(C, P->dose, nt[i]), P->fwd_cap);
     agrid[i] = P->dose->adj_grid;
-    lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, fst));
+    lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, fst, fwv));
   }
   if (dev_alloc(&B.st, 2 * static_cast<size_t>(n)) || dev_alloc(&B.fargs, n) || dev_alloc(&B.aargs, n))
     return IMRT_ENOMEM;
@@ -1748,7 +1758,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   if (e != hipSuccess) return hip_error(e, "batch setup");
 
   // initial evaluation G(x_1) of every plan
-  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, lds))) {
+  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds))) {
     (void)hipStreamSynchronize(s);
     return rc;
   }
@@ -1769,7 +1779,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     for (long long k = 0; k < K && lrc == IMRT_OK; ++k) {
       lrc = launch_adjoint_batch(C, B.aargs, B.aslots, static_cast<int>(as.size()), nt[0], storage);
       if (lrc == IMRT_OK)
-        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, lds);
+        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds);
     }
     r = hipStreamEndCapture(s, &B.graph);
     if (lrc) return lrc;
@@ -1885,7 +1895,9 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   return IMRT_OK;
 }
 
-int imrt_dose_repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave) {
+namespace {
+// A new work partition (and forward workgroup size) for a dose matrix.
+int repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave, int32_t fwd_waves) {
   if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
   if (adj_min_nnz < 16 || fwd_blocks_per_wave < 1 || fwd_blocks_per_wave > 1024)
     return set_error(IMRT_EINVAL, "adj_min_nnz must be >= 16 and fwd_blocks_per_wave in [1, 1024]");
@@ -1893,25 +1905,34 @@ int imrt_dose_repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_
   if (rc) return rc;
   hipStream_t s = D->ctx->stream;
   IMRT_HIP(hipStreamSynchronize(s));
-  if (adj_min_nnz == D->adj_min_nnz && fwd_blocks_per_wave == D->fwd_bpw) return IMRT_OK;
+  if (adj_min_nnz == D->adj_min_nnz && fwd_blocks_per_wave == D->fwd_bpw && fwd_waves == D->fwd_waves) return IMRT_OK;
   try {
     std::vector<int32_t> rp(static_cast<size_t>(D->nv) + 1), cp(static_cast<size_t>(D->nb) + 1);
     IMRT_HIP(hipMemcpy(rp.data(), D->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
     IMRT_HIP(hipMemcpy(cp.data(), D->col_ptr, sizeof(int32_t) * cp.size(), hipMemcpyDeviceToHost));
     D->adj_min_nnz = adj_min_nnz;
     D->fwd_bpw = fwd_blocks_per_wave;
+    D->fwd_waves = fwd_waves;
     return finish_dose(D, rp, cp);
   } catch (const std::bad_alloc&) {
     return set_error(IMRT_ENOMEM, "host allocation failed");
   }
 }
+}  // namespace
 
+int imrt_dose_repartition(imrt_dose* D, int32_t adj_min_nnz, int32_t fwd_blocks_per_wave) {
+  if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
+  return repartition(D, adj_min_nnz, fwd_blocks_per_wave, D->fwd_waves);
+}
+
+// Per-plan targets serve dispatches that several plans share: their forward
+// workgroups have 8 waves (see partition_for_targets).
 int imrt_dose_repartition_targets(imrt_dose* D, int32_t adj_workgroups, int32_t fwd_workgroups) {
   if (!D) return set_error(IMRT_EINVAL, "dose is NULL");
   if (adj_workgroups < 1 || fwd_workgroups < 1) return set_error(IMRT_EINVAL, "workgroup targets must be >= 1");
   int32_t a = 0, b = 0;
   partition_for_targets(D->nnz, adj_workgroups, fwd_workgroups, &a, &b);
-  return imrt_dose_repartition(D, a, b);
+  return repartition(D, a, b, 8);
 }
 
 int imrt_dose_partition(const imrt_dose* D, int32_t* adj_min_nnz, int32_t* fwd_blocks_per_wave) {
@@ -1981,7 +2002,7 @@ int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_par
     for (imrt_dose* d : doses) {
       int32_t a = 0, b = 0;
       part_of(d, c, &a, &b);
-      if ((rc = imrt_dose_repartition(d, a, b))) {
+      if ((rc = repartition(d, a, b, 8))) {
         release();
         return rc;
       }
@@ -2008,7 +2029,7 @@ int imrt_batch_autotune(int32_t n, imrt_plan* const* plans, const imrt_solve_par
   for (imrt_dose* d : doses) {
     int32_t a = 0, b = 0;
     part_of(d, best_c, &a, &b);
-    if ((rc = imrt_dose_repartition(d, a, b))) return rc;
+    if ((rc = repartition(d, a, b, 8))) return rc;
   }
   if (ta_out) *ta_out = best_c.ta;
   if (tf_out) *tf_out = best_c.tf;

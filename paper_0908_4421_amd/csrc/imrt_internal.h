@@ -104,6 +104,7 @@ struct FwdArgs {
   const uint16_t* val16;     // 16-bit storage: codes
   const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
   int32_t storage;
+  int32_t waves;             // waves of a wave-granular forward workgroup (8 or 16; 8 with four trials)
   const int32_t* block_row;  // nblocks + 1 row boundaries
   const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
@@ -198,6 +199,7 @@ struct imrt_ctx {
   hipStream_t stream = nullptr;
   int num_cu = 256;
   size_t max_lds = 65536;
+  size_t cu_lds = 65536;   // LDS of one compute unit (workgroups that fit side by side)
   imrt::Tuning tune;
 };
 
@@ -225,6 +227,10 @@ struct imrt_dose {
   // per forward wave (from the context's options when created; changed by
   // imrt_dose_repartition)
   int32_t adj_min_nnz = 1024, fwd_bpw = 1;
+  // Waves of a forward workgroup with one or two trials per pass: 16 (one
+  // workgroup per compute unit) for a matrix solved alone, 8 (three side by
+  // side) once per-plan targets are applied for shared dispatches.
+  int32_t fwd_waves = 16;
   // forward row blocks and adjoint chunks
   int32_t nblocks = 0;
   int32_t* block_row = nullptr;
@@ -311,10 +317,11 @@ int hip_error(hipError_t e, const char* what);
 // forward grid: wave-granular pass, fwd_grid_per_cu workgroups of 16 waves
 // (8 for several trials) per CU; workgroup-granular pass, 4x as many of 4 waves
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials = 1);
-int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials = 1, int blocks_per_wave = 1);
-int forward_waves(int ntrials);
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials, int blocks_per_wave, int nb, int storage,
+              int dose_waves);
+int forward_waves(int ntrials, int dose_waves);
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz);
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage = 0);
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage, int dose_waves);
 __host__ __device__ inline int pad4(int n) { return (n + 3) & ~3; }
 
 // CSC nonzero k is stored at slot csc_slot(k): within every aligned tile of
@@ -338,7 +345,7 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
 // Batched solve passes over a slot table (device arrays of per-plan arguments
 // and of (plan << 16 | workgroup) slots, -1 for an idle slot).
 int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage, size_t lds);
+                         int storage, int dose_waves, size_t lds);
 int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
                          int storage);
 // Adjoint passes of groups of solves sharing a dose matrix: groups[(K + 1) g]

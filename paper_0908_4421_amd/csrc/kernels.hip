@@ -1138,13 +1138,16 @@ __device__ __forceinline__ void wave_rows(const FwdArgs& a, const float* prod, i
   }
 }
 
-// Waves of a wave-granular forward workgroup: eight, with three workgroups
-// per compute unit by default, so that one workgroup's staging (the start of
-// every workgroup, and of every plan's workgroups in a batched pass)
-// overlaps the others' streams.  One and two trials per pass keep within 80
-// and 128 registers per lane (six and four waves per SIMD).
-template <int NT>
-constexpr int fwd_min_waves_per_simd() { return NT == 1 ? 6 : NT == 2 ? 4 : 1; }
+// Waves of a wave-granular forward workgroup: sixteen, one workgroup per
+// compute unit, for a matrix solved alone; eight, up to three side by side,
+// once per-plan targets are applied for dispatches that several plans share
+// (one workgroup's staging -- the start of every workgroup, and of every
+// plan's workgroups in a batched pass -- then overlaps the others'
+// streams).  Launch bounds: 8-wave workgroups with one and two trials per
+// pass keep within 80 and 128 registers per lane (six and four waves per
+// SIMD); four trials take 8-wave workgroups with no such bound.
+template <int NT, int WAVES>
+constexpr int fwd_min_waves_per_simd() { return WAVES == 16 ? 4 : NT == 1 ? 6 : NT == 2 ? 4 : 1; }
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
 template <int NT, int MODE, int WAVES, int ST>
@@ -1393,7 +1396,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
 }
 
 template <int NT, int MODE, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64, fwd_min_waves_per_simd<NT>()) void fwd_wave_kernel(FwdArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (fwd_min_waves_per_simd<NT, WAVES>())) void fwd_wave_kernel(FwdArgs a) {
   fwd_wave_pass<NT, MODE, WAVES, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
 }
 
@@ -1401,7 +1404,7 @@ __global__ __launch_bounds__(WAVES * 64, fwd_min_waves_per_simd<NT>()) void fwd_
 // plan's pass, or -1 for an idle slot (plans start at multiples of the die
 // count, so each plan keeps its workgroups' die placement).
 template <int NT, int WAVES, int ST>
-__global__ __launch_bounds__(WAVES * 64, fwd_min_waves_per_simd<NT>()) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
+__global__ __launch_bounds__(WAVES * 64, (fwd_min_waves_per_simd<NT, WAVES>())) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
                                                                     const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
@@ -1878,12 +1881,12 @@ int grid_for(int items, int cap) {
 
 }  // namespace
 
-size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage) {
+size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storage, int dose_waves) {
   const size_t nbp = static_cast<size_t>(pad4(nb));
   size_t bytes = static_cast<size_t>(nstruct) * sizeof(PenaltyDev) +
                  static_cast<size_t>(ntrials) * nbp * sizeof(float);
   if (wave) {
-    const size_t waves = static_cast<size_t>(forward_waves(ntrials));
+    const size_t waves = static_cast<size_t>(forward_waves(ntrials, dose_waves));
     bytes += (waves * ntrials * wave_nnz(storage) + kWaveSlack) * sizeof(float);
     bytes += (2 * (kMetaChunk + 1) + kMetaChunk + 2) * sizeof(int32_t) +
              static_cast<size_t>(ntrials) * kMetaChunk * sizeof(double);
@@ -1894,19 +1897,27 @@ size_t forward_lds_bytes(int nb, int ntrials, int nstruct, bool wave, int storag
   return bytes;
 }
 
-int forward_waves(int ntrials) {
-  (void)ntrials;
-  return 8;
-}
+int forward_waves(int ntrials, int dose_waves) { return (ntrials <= 2 && dose_waves == 16) ? 16 : 8; }
 
 int forward_grid(const imrt_ctx* ctx, const imrt_dose* D, int ntrials) {
-  if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials, D->fwd_bpw);
+  if (ctx->tune.fwd_wave) return wave_grid(ctx, D->nwblocks, ntrials, D->fwd_bpw, D->nb, D->fwd_st, D->fwd_waves);
   return grid_for(D->nblocks, kWaves * ctx->tune.fwd_grid_per_cu * ctx->num_cu);
 }
 
-int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials, int blocks_per_wave) {
-  const int64_t per = static_cast<int64_t>(forward_waves(ntrials)) * std::max(blocks_per_wave, 1);
-  return grid_for(static_cast<int>((nwblocks + per - 1) / per), ctx->tune.fwd_grid_per_cu * ctx->num_cu);
+// Forward workgroups per compute unit: the setting, but no more than fit
+// side by side -- by registers (one 16-wave workgroup; three 8-wave ones with
+// one trial per pass, two with more) and by LDS (the staged vectors grow with
+// nb; a structure table of 16 entries assumed) -- since a workgroup that does
+// not fit would only start once another has finished.
+int wave_grid(const imrt_ctx* ctx, int nwblocks, int ntrials, int blocks_per_wave, int nb, int storage,
+              int dose_waves) {
+  const int waves = forward_waves(ntrials, dose_waves);
+  const int64_t per = static_cast<int64_t>(waves) * std::max(blocks_per_wave, 1);
+  const size_t lds = forward_lds_bytes(nb, ntrials, 16, true, storage, dose_waves);
+  const int by_lds = static_cast<int>(std::max<size_t>(1, ctx->cu_lds / std::max<size_t>(lds, 1)));
+  const int by_regs = (waves == 16) ? 1 : (ntrials == 1) ? 3 : 2;
+  const int per_cu = std::max(1, std::min({ctx->tune.fwd_grid_per_cu, by_regs, by_lds}));
+  return grid_for(static_cast<int>((nwblocks + per - 1) / per), per_cu * ctx->num_cu);
 }
 
 int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz) {
@@ -1923,33 +1934,49 @@ int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz) {
 template <int ST>
 int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipStream_t s, hipEvent_t before,
                         hipEvent_t after) {
-  const dim3 bd8(8 * 64);
+  const dim3 bd16(16 * 64), bd8(8 * 64);
+  const bool w16 = forward_waves(ntrials, a.waves) == 16;
   if (a.mode == FWD_SOLVE) {
     switch (ntrials) {
-      case 1: hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
-      case 2: hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
+      case 1:
+        if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+        else hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
+        break;
+      case 2:
+        if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+        else hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
+        break;
       case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
       default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
     }
   } else if (ntrials != 1) {
     return set_error(IMRT_EINVAL, "evaluation passes take one trial");
   } else if (a.mode == FWD_EVAL) {
-    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
+    if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+    else hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_EVAL, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
   } else {
-    hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
+    if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
+    else hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_PLAIN, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
   }
   return IMRT_OK;
 }
 
 // Batched solve passes: one dispatch over the slot table of several plans
-// (all with the same storage and trials per pass).
+// (all with the same storage, forward workgroup size and trials per pass).
 template <int ST>
-int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslots, int ntrials, size_t lds,
-                            hipStream_t s) {
+int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslots, int ntrials, int dose_waves,
+                            size_t lds, hipStream_t s) {
   const dim3 gd(nslots);
+  const bool w16 = forward_waves(ntrials, dose_waves) == 16;
   switch (ntrials) {
-    case 1: hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
-    case 2: hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    case 1:
+      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots);
+      else hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots);
+      break;
+    case 2:
+      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots);
+      else hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots);
+      break;
     case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
@@ -1957,15 +1984,17 @@ int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslot
 }
 
 int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage, size_t lds) {
+                         int storage, int dose_waves, size_t lds) {
   if (nslots <= 0) return IMRT_OK;
   if (lds > ctx->max_lds) return set_error(IMRT_EUNSUPPORTED, "batched forward pass: LDS budget exceeded");
   int rc;
+  const int w = dose_waves;
+  hipStream_t s = ctx->stream;
   switch (storage) {
-    case ST_F32: rc = launch_forward_batch_st<ST_F32>(args, slots, nslots, ntrials, lds, ctx->stream); break;
-    case ST_BF16: rc = launch_forward_batch_st<ST_BF16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
-    case ST_F16: rc = launch_forward_batch_st<ST_F16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
-    case ST_F32C16: rc = launch_forward_batch_st<ST_F32C16>(args, slots, nslots, ntrials, lds, ctx->stream); break;
+    case ST_F32: rc = launch_forward_batch_st<ST_F32>(args, slots, nslots, ntrials, w, lds, s); break;
+    case ST_BF16: rc = launch_forward_batch_st<ST_BF16>(args, slots, nslots, ntrials, w, lds, s); break;
+    case ST_F16: rc = launch_forward_batch_st<ST_F16>(args, slots, nslots, ntrials, w, lds, s); break;
+    case ST_F32C16: rc = launch_forward_batch_st<ST_F32C16>(args, slots, nslots, ntrials, w, lds, s); break;
     default: return set_error(IMRT_EINVAL, "unknown storage");
   }
   if (rc) return rc;
@@ -2040,7 +2069,7 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   (void)D;
   clear_stale_error();
   const bool wave = ctx->tune.fwd_wave != 0;
-  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave, a.storage);
+  const size_t lds = forward_lds_bytes(a.nb, ntrials, a.nstruct, wave, a.storage, a.waves);
   if (lds > ctx->max_lds)
     return set_error(IMRT_EUNSUPPORTED, "forward pass: nb * trials exceeds the LDS budget");
   const dim3 gd(grid), bd(kThreads);

@@ -206,7 +206,8 @@ bool admit(imrt_server* S, Pending& p, int slot) {
   for (int i = 0; i < S->max_live; ++i) {
     if (!S->occupied[i]) continue;
     const imrt_dose* LD = S->live[i].plan->dose;
-    if (LD->storage != D->storage || LD->fwd_st != D->fwd_st || S->live[i].nt != nt) return false;
+    if (LD->storage != D->storage || LD->fwd_st != D->fwd_st || LD->fwd_waves != D->fwd_waves || S->live[i].nt != nt)
+      return false;
   }
   const int64_t pb = plan_bytes(D, nt) + (p.params.trace ? static_cast<int64_t>(sizeof(imrt_trace_entry)) *
                                                               std::max(0, p.params.max_iter) : 0);
@@ -360,7 +361,7 @@ void worker_main(imrt_server* S) {
     fs.clear();
     as.clear();
     gt.clear();
-    int storage = -1, fst = -1, nt = 1;
+    int storage = -1, fst = -1, fwv = 16, nt = 1;
     size_t lds = 0;
     bool mixed = false;
     for (int i : active) {
@@ -369,12 +370,13 @@ void worker_main(imrt_server* S) {
       if (storage < 0) {
         storage = D->storage;
         fst = D->fwd_st;
+        fwv = D->fwd_waves;
         nt = L.nt;
       }
-      mixed = mixed || D->storage != storage || D->fwd_st != fst || L.nt != nt;
+      mixed = mixed || D->storage != storage || D->fwd_st != fst || D->fwd_waves != fwv || L.nt != nt;
       while (fs.size() % kXcds) fs.push_back(-1);
       for (int w = 0; w < L.grid; ++w) fs.push_back((i << 16) | w);
-      lds = std::max(lds, forward_lds_bytes(D->nb, L.nt, L.plan->nstruct, true, D->fwd_st));
+      lds = std::max(lds, forward_lds_bytes(D->nb, L.nt, L.plan->nstruct, true, D->fwd_st, D->fwd_waves));
     }
     // Adjoint slots: the live solves on one resident matrix (re-plans of a
     // patient) form groups of up to kShareMax that read the matrix once per
@@ -429,7 +431,7 @@ void worker_main(imrt_server* S) {
       else
         rc = launch_adjoint_multi_batch(C, S->aargs, S->gtab, gk, S->aslots, static_cast<int>(as.size()), nt,
                                         storage);
-      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, lds);
+      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, fwv, lds);
     }
     if (!rc) {
       std::lock_guard<std::mutex> g(S->mu);

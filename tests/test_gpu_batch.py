@@ -108,6 +108,14 @@ def test_batch_argument_checks(ctx):
         Plan.solve_batch([p], [to_dev(-np.ones(d.nb, np.float32))], eps=1e-4, alpha=2.0, lambda0s=[2.0 ** -7],
                          max_iter=5)
     assert e.value.code == imrt.IMRT_EINVAL
+    # per-plan targets give a matrix 8-wave forward workgroups, a new matrix
+    # 16-wave ones: one batched dispatch cannot hold both
+    d2 = Dose.from_geometry(ctx, TINY)
+    p2 = _plan(ctx, d2, penalty_table(TINY))
+    d2.repartition_targets(128, 32)
+    with pytest.raises(imrt.ImrtError) as e:
+        Plan.solve_batch([p, p2], [x, y], eps=1e-4, alpha=2.0, lambda0s=[2.0 ** -7] * 2, max_iter=5)
+    assert e.value.code == imrt.IMRT_EINVAL and "workgroup size" in str(e.value)
 
 
 def test_repartition_and_autotune(ctx):
