@@ -541,6 +541,7 @@ AdjArgs base_adj(const imrt_dose* D) {
   a.wg_cols = D->wg_cols;
   a.col_wlo = D->col_wlo;
   a.col_whi = D->col_whi;
+  a.col_kind = D->col_kind;
   a.nnz = D->nnz;
   a.nv = D->nv;
   a.nb = D->nb;

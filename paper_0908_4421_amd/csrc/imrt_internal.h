@@ -151,6 +151,7 @@ struct AdjArgs {
   const int32_t* wg_cols;
   const int32_t* col_wlo;
   const int32_t* col_whi;
+  const uint8_t* col_kind;   // 0: one adjoint workgroup, 1: two, 2: more
   int64_t nnz;
   int32_t nv, nb, grid;
   int32_t xcd_map;           // workgroup ranges contiguous per accelerator die (else dispatch order)

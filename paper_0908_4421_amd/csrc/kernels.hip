@@ -1493,6 +1493,81 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage<ST>& S, const fl
   return s;
 }
 
+// ---- an adjoint workgroup's columns ----------------------------------------------
+// A workgroup walks its columns c0..c1-1 in order, kColChunk at a time: lane
+// j of every wave holds column cb + j's entries of col_ptr (and its kind and
+// 16-bit scale), so moving on to the next column reads a register.  Closing a
+// column sums it over each wave and parks the wave's sum in lane j; when the
+// chunk is full, and at the end, the waves' sums meet in LDS and wave 0 adds
+// them in wave order (block_sum's order) and stores the chunk's gradient
+// entries and pieces.  No workgroup barrier and no dependent global load sits
+// between one column and the next.
+constexpr int kColChunk = 64;
+
+template <int ST>
+struct ColChunk {
+  int cb;          // first column of the chunk (uniform)
+  int p0, p1;      // lane j: col_ptr[cb + j], col_ptr[cb + j + 1]
+  uint32_t kind;   // lane j: col_kind[cb + j]
+  float csc;       // lane j: 16-bit storage scale of column cb + j
+};
+
+template <int ST>
+__device__ __forceinline__ void col_chunk_load(const AdjArgs& a, int cb, ColChunk<ST>& K) {
+  const uint32_t nb = static_cast<uint32_t>(a.nb);
+  const uint32_t j = static_cast<uint32_t>(cb + (threadIdx.x & 63));
+  const rsrc_t rp = make_rsrc(a.col_ptr, 4u * (nb + 1));
+  K.cb = cb;
+  K.p0 = load_i32(rp, 4u * j);
+  K.p1 = load_i32(rp, 4u * j + 4u);
+  K.kind = load_u8(make_rsrc(a.col_kind, nb), j);
+  K.csc = coded(ST) ? load_f32(make_rsrc(a.col_scale, 4u * nb), 4u * j) : 1.0f;
+}
+
+// Loads of a chunk after the first one: wait for them at once (vmcnt 0).
+// Without this wait, the compiler cannot tell at the next column whether a
+// reload is still in flight, and every column's register read would wait
+// for all loads issued since, the next round's prefetch included.
+constexpr int kWaitVmcnt0 = 0x0F70;   // vmcnt 0, expcnt and lgkmcnt unchecked
+
+template <int ST>
+__device__ __forceinline__ void col_chunk_reload(const AdjArgs& a, int cb, ColChunk<ST>& K) {
+  col_chunk_load(a, cb, K);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+}
+
+// Column c's entries inside the workgroup's range [k0w, k1w).
+template <int ST>
+__device__ __forceinline__ void col_bounds(const ColChunk<ST>& K, int c, int k0w, int k1w, int& lo, int& hi) {
+  lo = max(__builtin_amdgcn_readlane(K.p0, c - K.cb), k0w);
+  hi = min(__builtin_amdgcn_readlane(K.p1, c - K.cb), k1w);
+}
+
+// The wave's sum of v, parked in lane j of h.
+__device__ __forceinline__ void col_park(double v, int j, double& h) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, wave_sum(v));
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b), 63));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63));
+  if ((threadIdx.x & 63) == j) h = __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// Lane j of wave 0, column c = cb + j closed with workgroup sum t: the
+// gradient entry of a column inside the range, else the workgroup's piece.
+template <int ST>
+__device__ __forceinline__ void col_store(const AdjArgs& aq, const ColChunk<ST>& K, int c0, int c1, int lw, int k0w,
+                                          int k1w, double t) {
+  const int c = K.cb + (threadIdx.x & 63);
+  if (K.p0 >= k0w && K.p1 <= k1w) {
+    const double f = (ST == ST_F32) ? aq.scale : aq.scale * static_cast<double>(K.csc);
+    aq.out[c] = static_cast<float>(f * t);
+  } else {
+    if (c == c0) aq.pieces[2 * lw] = t;
+    if (c == c1 - 1) aq.pieces[2 * lw + 1] = t;
+    // a column shared by two workgroups also keeps its pieces side by side
+    if (K.kind == 1 && aq.pieces_col != nullptr) aq.pieces_col[2 * c + (K.p0 < k0w ? 1 : 0)] = t;
+  }
+}
+
 // Adjoint pass: in a solve, the decision on the preceding forward pass
 // (every workgroup identically; workgroup 0 stores the new state and trace
 // entry), and g = scale * D^T r over this workgroup's share of the nonzeros.
@@ -1503,6 +1578,7 @@ __device__ __forceinline__ double adj_dot_masked(const AdjStage<ST>& S, const fl
 template <int NT, bool SOLVE, int ST>
 __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   __shared__ double red[kWaves];
+  __shared__ double colsh[kWaves * kColChunk];
   __shared__ Decision dec;
   const int tid = threadIdx.x;
   const int lw = logical_wg(sl, a.xcd_map != 0);
@@ -1526,14 +1602,8 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   adj_issue(ri, rv, 1, B);
   const int c0 = uniform(wi.x), c1 = uniform(wi.y);
   int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
-  // 16-bit storage: the column's scale, loaded with its bounds
-  float csc = 1.0f;
-  if constexpr (coded(ST)) csc = a.col_scale[c < c1 ? c : 0];
-  auto bounds = [&]() {
-    lo = max(uniform(a.col_ptr[c]), k0w);
-    hi = min(uniform(a.col_ptr[c + 1]), k1w);
-    if constexpr (coded(ST)) csc = a.col_scale[c];
-  };
+  ColChunk<ST> CK;
+  col_chunk_load(a, c0, CK);
   // a solve gathers the residual of the first trial: the accepted one
   // unless a later trial wins
   const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
@@ -1562,24 +1632,30 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
     }
   }
 
-  double s = 0.0;
-  auto close = [&]() {
-    const double t = block_sum(s, red);
-    if (tid == 0) {
-      const int wlo = a.col_wlo[c], whi = a.col_whi[c];
-      if (wlo == whi) {
-        const double f = (ST == ST_F32) ? a.scale : a.scale * static_cast<double>(csc);
-        a.out[c] = static_cast<float>(f * t);
-      } else {
-        if (c == c0) a.pieces[2 * lw] = t;
-        if (c == c1 - 1) a.pieces[2 * lw + 1] = t;
-        // a column shared by two workgroups also keeps its pieces side by side
-        if (whi - wlo == 1 && a.pieces_col != nullptr) a.pieces_col[2 * c + (lw - wlo)] = t;
-      }
+  double s = 0.0, h = 0.0;
+  // the chunk's closed columns: the waves' sums in wave order, then stored
+  auto flush = [&]() {
+    colsh[(tid >> 6) * kColChunk + (tid & 63)] = h;
+    __syncthreads();
+    if (tid < c - CK.cb) {
+      double t = colsh[tid];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) t += colsh[w * kColChunk + tid];
+      col_store(a, CK, c0, c1, lw, k0w, k1w, t);
     }
+  };
+  auto close = [&]() {
+    col_park(s, c - CK.cb, h);
     s = 0.0;
     ++c;
-    if (c < c1) bounds();
+    if (c < c1) {
+      if (c - CK.cb == kColChunk) {
+        flush();
+        __syncthreads();   // LDS slots reused by the next chunk
+        col_chunk_reload(a, c, CK);
+      }
+      col_bounds(CK, c, k0w, k1w, lo, hi);
+    }
   };
   // distribute one round's products over the columns it meets
   auto consume = [&](const AdjStage<ST>& cur, const float (&gv)[8], int round) {
@@ -1604,7 +1680,12 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
     auto step = [&](const AdjStage<ST>& cur, AdjStage<ST>& nxt) {
       float gv[8];
       adj_gather(rr, cur, gv);
-      if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+      // The next round's loads go out after this round's gathers and also
+      // past the last round (zeros out of bounds): loads complete in issue
+      // order, so either a branch here or loads moved ahead of the gathers
+      // would make the wait for the gathers wait for these loads as well.
+      __builtin_amdgcn_sched_barrier(0);
+      adj_issue(ri, rv, round + 1, nxt);
       consume(cur, gv, round);
       ++round;
       return round < nrounds;
@@ -1616,6 +1697,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   }
   // empty columns at the end of the range
   while (c < c1) close();
+  if (c1 > c0) flush();
 }
 
 template <int NT, bool SOLVE, int ST>
@@ -1644,6 +1726,7 @@ template <int NT, int ST, int K>
 __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args, const int32_t* plans, int n,
                                                const Slot sl) {
   __shared__ double red[kWaves];
+  __shared__ double colsh[K][kWaves * kColChunk];
   __shared__ Decision dec[K];
   const AdjArgs& a = args[uniform(plans[0])];   // the shared matrix and partition
   const int tid = threadIdx.x;
@@ -1667,13 +1750,8 @@ __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args,
   adj_issue(ri, rv, 1, B);
   const int c0 = uniform(wi.x), c1 = uniform(wi.y);
   int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
-  float csc = 1.0f;
-  if constexpr (coded(ST)) csc = a.col_scale[c < c1 ? c : 0];
-  auto bounds = [&]() {
-    lo = max(uniform(a.col_ptr[c]), k0w);
-    hi = min(uniform(a.col_ptr[c + 1]), k1w);
-    if constexpr (coded(ST)) csc = a.col_scale[c];
-  };
+  ColChunk<ST> CK;
+  col_chunk_load(a, c0, CK);
   const uint32_t rbytes = 4u * static_cast<uint32_t>(a.nv);
   rsrc_t rr[K];
   float g[K][8];
@@ -1713,30 +1791,41 @@ __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args,
   }
   if (!any) return;
 
-  double s[K];
+  double s[K], h[K];
 #pragma unroll
-  for (int q = 0; q < K; ++q) s[q] = 0.0;
+  for (int q = 0; q < K; ++q) s[q] = h[q] = 0.0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      if (need[q]) colsh[q][(tid >> 6) * kColChunk + (tid & 63)] = h[q];
+    __syncthreads();
+    if (tid < c - CK.cb) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        if (!need[q]) continue;
+        double t = colsh[q][tid];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) t += colsh[q][w * kColChunk + tid];
+        col_store(args[pi[q]], CK, c0, c1, lw, k0w, k1w, t);
+      }
+    }
+  };
   auto close = [&]() {
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       if (!need[q]) continue;
-      const AdjArgs& aq = args[pi[q]];
-      const double t = block_sum(s[q], red);
-      if (tid == 0) {
-        const int wlo = a.col_wlo[c], whi = a.col_whi[c];
-        if (wlo == whi) {
-          const double f = (ST == ST_F32) ? aq.scale : aq.scale * static_cast<double>(csc);
-          aq.out[c] = static_cast<float>(f * t);
-        } else {
-          if (c == c0) aq.pieces[2 * lw] = t;
-          if (c == c1 - 1) aq.pieces[2 * lw + 1] = t;
-          if (whi - wlo == 1 && aq.pieces_col != nullptr) aq.pieces_col[2 * c + (lw - wlo)] = t;
-        }
-      }
+      col_park(s[q], c - CK.cb, h[q]);
       s[q] = 0.0;
     }
     ++c;
-    if (c < c1) bounds();
+    if (c < c1) {
+      if (c - CK.cb == kColChunk) {
+        flush();
+        __syncthreads();   // LDS slots reused by the next chunk
+        col_chunk_reload(a, c, CK);
+      }
+      col_bounds(CK, c, k0w, k1w, lo, hi);
+    }
   };
   auto consume = [&](const AdjStage<ST>& cur, const float (&gv)[K][8], int round) {
     const int base = kb + round * kAdjStep, end = base + kAdjStep;
@@ -1764,7 +1853,12 @@ __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args,
       float gv[K][8];
 #pragma unroll
       for (int q = 0; q < K; ++q) adj_gather(rr[q], cur, gv[q]);
-      if (round + 1 < nrounds) adj_issue(ri, rv, round + 1, nxt);
+      // The next round's loads go out after this round's gathers and also
+      // past the last round (zeros out of bounds): loads complete in issue
+      // order, so either a branch here or loads moved ahead of the gathers
+      // would make the wait for the gathers wait for these loads as well.
+      __builtin_amdgcn_sched_barrier(0);
+      adj_issue(ri, rv, round + 1, nxt);
       consume(cur, gv, round);
       ++round;
       return round < nrounds;
@@ -1775,6 +1869,7 @@ __device__ __forceinline__ void adj_multi_pass(const AdjArgs* __restrict__ args,
     }
   }
   while (c < c1) close();
+  if (c1 > c0) flush();
 }
 
 // Batched adjoint pass over groups of solves sharing a dose matrix:
