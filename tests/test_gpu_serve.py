@@ -204,18 +204,22 @@ def test_served_against_oracle(ctx, storage):
     srv.close()
 
 
-def test_shared_matrix_adjoint_equals_alone():
+@pytest.mark.parametrize("adj_wgs", [0, 2], ids=["default_targets", "two_adjoint_workgroups"])
+def test_shared_matrix_adjoint_equals_alone(adj_wgs):
     """Four re-plans of one patient, two of another and a single new patient,
     submitted together: the live solves on one resident matrix share each
     adjoint pass (groups of four and two), and every plan equals the same
-    plan solved alone and served without sharing, bit for bit."""
+    plan solved alone and served without sharing, bit for bit.  With two
+    adjoint workgroups per plan each workgroup walks 80 to 240 columns, so
+    the shared pass reloads its column chunk (64 at a time) mid-range."""
     from paper_0908_4421_amd.imrt import Context, Dose, Server
     from workloads import replan_penalty_table
     rng = np.random.default_rng(21)
     reqs = [(30, SMALL, penalty_table(SMALL))] + [(30, SMALL, replan_penalty_table(SMALL, rng)) for _ in range(3)]
     reqs += [(31, TINY, penalty_table(TINY)), (31, TINY, replan_penalty_table(TINY, rng))]
     reqs += [(32, draw_batch_instance(1004), penalty_table(draw_batch_instance(1004)))]
-    ctx = Context(0)
+    opts = {"serve_adjoint_workgroups": adj_wgs} if adj_wgs else {}
+    ctx = Context(0, **opts)
     part = (ctx.get_option("serve_adjoint_workgroups"), ctx.get_option("serve_forward_workgroups"))
     doses = {}
     for pat, sp, _ in reqs:
@@ -225,7 +229,7 @@ def test_shared_matrix_adjoint_equals_alone():
             doses[pat] = d
     out = {}
     for share in (1, 0):
-        c = Context(0, serve_shared_adjoint=share)
+        c = Context(0, serve_shared_adjoint=share, **opts)
         srv = Server(c, budget_bytes=8 << 30, max_live=16)
         tickets = [srv.submit(p, sp, t, max_iter=1500) for p, sp, t in reqs]
         out[share] = [srv.wait(tk, doses[p].nb) for tk, (p, _, _) in zip(tickets, reqs)]

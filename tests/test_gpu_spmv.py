@@ -19,6 +19,9 @@ CASES = {
     "single": (1, 1, 1.0, 5, 0.0, 0, 0),
     "one_row": (1, 300, 200.0, 6, 0.0, 0, 0),
     "one_col": (4097, 1, 1.0, 7, 0.3, 0, 0),
+    # thousands of mostly empty columns per adjoint workgroup: its column
+    # bounds are reloaded 64 at a time many times over
+    "many_cols": (2000, 20000, 3.0, 8, 0.3, 0, 0),
 }
 
 
