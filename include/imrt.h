@@ -208,11 +208,14 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    created afterwards runs between polls (1..4096,
  *                    default 16): more groups poll less often, fewer admit
  *                    and retire sooner
- *   "serve_shared_adjoint"  1 (default): live solves of a server created
- *                    afterwards that share a resident dose matrix (re-plans
- *                    of one patient) take their gradients from one pass over
- *                    its CSC, up to four solves per pass, each solve's
- *                    arithmetic unchanged; 0: one pass per solve
+ *   "serve_shared_adjoint"  1: live solves of a server created afterwards
+ *                    that share a resident dose matrix (re-plans of one
+ *                    patient) take their gradients from one pass over its
+ *                    CSC, up to four solves per pass, each solve's
+ *                    arithmetic unchanged; 0 (default): one pass per solve.
+ *                    Sharing saves the matrix's reads but puts several
+ *                    solves' work in each workgroup: for matrices that stay
+ *                    in the last-level cache one pass per solve is faster
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "fwd_col16"      1 (default): float32 matrices with nb <= 65536 created

@@ -190,7 +190,7 @@ struct Tuning {
   int serve_adj_wgs = 128;         // the targets of the matrices a server builds, which
   int serve_fwd_wgs = 32;          // share their dispatches with the other live plans
   int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
-  int serve_shared_adj = 1;        // live solves on one resident matrix share its adjoint pass
+  int serve_shared_adj = 0;        // live solves on one resident matrix share its adjoint pass
 };
 
 }  // namespace imrt

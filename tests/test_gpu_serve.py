@@ -157,10 +157,12 @@ def test_served_workload_mix_equals_alone(ctx):
         assert res.G_final == ref.G_final
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_served_against_oracle(ctx, storage):
+@pytest.mark.parametrize("storage,share", [("f32", 0), ("bf16", 1)], ids=["f32", "bf16_shared_adjoint"])
+def test_served_against_oracle(storage, share):
     """Requests served together (new patients and a re-plan of a resident
-    one, continuous batching) against the FP64 oracle: every served plan's
+    one, continuous batching; in bfloat16 with the shared-matrix adjoint, so
+    the re-plan and its patient's first plan share adjoint passes while both
+    are live) against the FP64 oracle: every served plan's
     trajectory (traced by the server) has the oracle's steps and backtracks,
     G within 1e-6 relative plus the float32 dose-rounding bound at every index
     and at the served stop index (a plan that runs to the 3000-iteration cap
@@ -192,8 +194,9 @@ def test_served_against_oracle(ctx, storage):
                      [(e.k, e.lam, e.backtracks, e.step_sq, e.G) for e in ext.trace],
                      dose_rounding_slack(pen)))
         lams.append(lam)
-    srv = Server(ctx, budget_bytes=8 << 30, max_live=16)
-    banner(f"served against the oracle ({storage}): {len(reqs)} requests")
+    from paper_0908_4421_amd.imrt import Context
+    srv = Server(Context(0, serve_shared_adjoint=share), budget_bytes=8 << 30, max_live=16)
+    banner(f"served against the oracle ({storage}, shared adjoint {share}): {len(reqs)} requests")
     tickets = [srv.submit(p, sp, t, storage=storage, lambda0=lam, max_iter=3000, trace=True)
                for (p, sp, t), lam in zip(reqs, lams)]
     for (pat, sp, t), tk, (stop, G0, ref, slack) in zip(reqs, tickets, refs):
@@ -201,6 +204,8 @@ def test_served_against_oracle(ctx, storage):
         tr = srv.trace_of(tk, res.iterations)
         worst, K, Ko = check_trajectory(tr, res, ref, G0, stop, delta=1e-5, slack=slack)
         banner(f"ticket {tk}: {K} iterations (oracle {Ko}), worst G error {worst:.2e}")
+    st = srv.stats()
+    assert (st["adjoint_groups_shared"] > 0) == bool(share)
     srv.close()
 
 
