@@ -551,13 +551,18 @@ def serve_stream(ctx, reqs, budget, paced, st, storage):
               max_backtracks=st.max_backtracks)
     t0 = time.perf_counter()
     tickets, sub = [], []
-    for r in reqs:
+    last = t0
+    for i, r in enumerate(reqs):
         if paced:
             dt = t0 + r.arrival_s - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
         sub.append((time.perf_counter() - t0) * 1e3)
         tickets.append(srv.submit(r.patient, r.spec, r.table, **kw))
+        if time.perf_counter() - last > 30.0:   # long streams report as they go
+            last = time.perf_counter()
+            print(f"[bench] serve: {i + 1} of {len(reqs)} requests submitted after {last - t0:.0f} s",
+                  file=sys.stderr, flush=True)
     got = [srv.wait(tk) for tk in tickets]
     span = time.perf_counter() - t0
     stats = srv.stats()
