@@ -2,6 +2,7 @@
 (new patients and re-plans of resident patients with new thresholds) each
 end exactly as the same plan solved alone; a small HBM budget serialises
 admissions and evicts unused matrices; a failed request fails alone."""
+import time
 import numpy as np
 import pytest
 
@@ -111,8 +112,11 @@ def test_storage_change_waits_for_the_live_mix(ctx):
     part = (ctx.get_option("serve_adjoint_workgroups"), ctx.get_option("serve_forward_workgroups"))
     reqs = [(20, TINY, "f32"), (21, SMALL, "bf16"), (22, draw_batch_instance(1003), "f32")]
     srv = Server(ctx, budget_bytes=4 << 30, max_live=8)
-    tickets = [srv.submit(pt, sp, penalty_table(sp), storage=st, max_iter=400, fixed_iters=True)
-               for pt, sp, st in reqs]
+    tables = [penalty_table(sp) for _, sp, _ in reqs]
+    tickets, sub_s = [], []
+    for (pt, sp, st), tab in zip(reqs, tables):
+        sub_s.append(time.perf_counter())
+        tickets.append(srv.submit(pt, sp, tab, storage=st, max_iter=400, fixed_iters=True))
     got = []
     for tk in tickets:
         got.append(srv.wait(tk, 0))
@@ -124,11 +128,13 @@ def test_storage_change_waits_for_the_live_mix(ctx):
         ref, _ = _alone(ctx, d, penalty_table(sp), times.lambda0, max_iter=400, fixed=True)
         assert res.iterations == ref.iterations == 400
         assert res.G_final == ref.G_final
-    # admitted one after the other (the three arrivals lie within a few
-    # milliseconds: submission only queues the request)
-    gap = 5.0
-    assert got[1][1].queue_ms >= got[0][1].plan_ms - gap
-    assert got[2][1].queue_ms >= got[1][1].plan_ms - gap
+    # admitted one after the other: request i+1 waits from its submission
+    # until request i is done, so its queue time is at least request i's
+    # time to plan less the time between the two submissions (measured here,
+    # plus 1 ms for the server's own clock reads)
+    for i in (0, 1):
+        gap = 1e3 * (sub_s[i + 1] - sub_s[i]) + 1.0
+        assert got[i + 1][1].queue_ms >= got[i][1].plan_ms - gap
 
 
 def test_served_workload_mix_equals_alone(ctx):
