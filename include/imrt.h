@@ -458,7 +458,9 @@ IMRT_API int imrt_server_submit(imrt_server* server, const imrt_request* request
  * IMRT_ETIMEDOUT and the ticket stays pending (it may be waited on again);
  * the device work of the live solves is not affected.  A ticket's result is
  * handed out once (IMRT_EINVAL for an unknown ticket, for a ticket already
- * handed out, or while another thread waits on it). */
+ * handed out, or while another thread waits on it).  An x_out whose nb
+ * differs from the plan's beamlet count is IMRT_EINVAL and leaves the
+ * result pending for a later wait. */
 IMRT_API int imrt_server_wait(imrt_server* server, int64_t ticket, float* x_out, int32_t nb,
                               imrt_solve_result* result, imrt_serve_times* times, int64_t timeout_ms);
 IMRT_API int imrt_server_stats(imrt_server* server, int64_t* used_bytes, int64_t* peak_bytes,

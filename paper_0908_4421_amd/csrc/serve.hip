@@ -588,14 +588,16 @@ int imrt_server_wait(imrt_server* S, int64_t ticket, float* x_out, int32_t nb, i
       return set_error(IMRT_ETIMEDOUT, "ticket " + std::to_string(ticket) + " not finished after " +
                                            std::to_string(timeout_ms) + " ms");
     }
-    f = std::move(S->finished[ticket]);
+    Finished& done = S->finished[ticket];
+    if (x_out && done.rc == IMRT_OK && nb != static_cast<int32_t>(done.x.size())) {
+      S->delivered.erase(ticket);  // the result stays for a wait with the right length
+      return set_error(IMRT_EINVAL, "x_out length differs from nb");
+    }
+    f = std::move(done);
     S->finished.erase(ticket);
   }
   if (f.rc) return set_error(f.rc, f.error);
-  if (x_out) {
-    if (nb != static_cast<int32_t>(f.x.size())) return set_error(IMRT_EINVAL, "x_out length differs from nb");
-    std::memcpy(x_out, f.x.data(), sizeof(float) * f.x.size());
-  }
+  if (x_out) std::memcpy(x_out, f.x.data(), sizeof(float) * f.x.size());
   if (result) *result = f.result;
   if (times) *times = f.times;
   if (f.trace_dst && !f.trace.empty())

@@ -87,16 +87,23 @@ def test_small_budget_evicts_and_serialises(ctx):
 
 
 def test_failed_request_fails_alone(ctx):
+    """A request that cannot be served fails alone; an x_out of the wrong
+    length is refused without losing the result; a ticket is handed out once."""
     from paper_0908_4421_amd import imrt
-    from paper_0908_4421_amd.imrt import Server
+    from paper_0908_4421_amd.imrt import Dose, Server
+    nb_tiny = Dose.from_geometry(ctx, TINY).nb
     srv = Server(ctx, budget_bytes=1 << 30, max_live=4)
     bad = srv.submit(99, None, penalty_table(TINY))          # not resident, no geometry
     good = srv.submit(1, TINY, penalty_table(TINY), max_iter=50, fixed_iters=True)
     with pytest.raises(imrt.ImrtError) as e:
         srv.wait(bad)
     assert e.value.code == imrt.IMRT_EINVAL
-    res, times, _ = srv.wait(good)
-    assert res.iterations == 50
+    # an x_out of the wrong length is refused and leaves the result pending
+    with pytest.raises(imrt.ImrtError) as e:
+        srv.wait(good, nb_tiny + 1)
+    assert e.value.code == imrt.IMRT_EINVAL
+    res, times, x = srv.wait(good, nb_tiny)
+    assert res.iterations == 50 and x.shape == (nb_tiny,) and np.all(np.isfinite(x))
     for tk in (good, 0, 999):     # waited on already, never issued
         with pytest.raises(imrt.ImrtError) as e:
             srv.wait(tk)
