@@ -126,7 +126,10 @@ def kernel_table(runs, res, names, nbytes):
         ms = sum((r.forward_kernel_ms if name == "forward" else r.adjoint_kernel_ms) for _, r in runs) / len(runs)
         n = res.forward_passes if name == "forward" else res.adjoint_passes
         gbs = nbytes[name] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-        kern[name] = {"kernel": names[name], "avg_ms": ms, "launches": n, "bytes_per_launch": nbytes[name],
+        # (a name ending in ", " leaves out the last template argument, the
+        # matrix streams' cache policy, which the library picks per matrix)
+        label = names[name] + "*>" if names[name].endswith(", ") else names[name]
+        kern[name] = {"kernel": label, "avg_ms": ms, "launches": n, "bytes_per_launch": nbytes[name],
                       "GB_s": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "total_ms": ms * n}
     return kern
 
@@ -150,8 +153,8 @@ def storage_form(ctx, spec, st, args, storage, plan32, res32, ms32):
           flush=True)
     nt = args.trials_per_pass
     code = {"bf16": 1, "f16": 2}[storage]
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {code}>(",
-             "adjoint": f"adj_kernel<{nt}, true, {code}>("}
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {code}, ",
+             "adjoint": f"adj_kernel<{nt}, true, {code}, "}
     nv, nb, nnz = dose.nv, dose.nb, dose.nnz
     nr = nonempty_rows(dose)
     kern = kernel_table(runs, res, names, {"forward": forward_bytes16(nr, nb, nnz),
@@ -412,8 +415,8 @@ def shape_form(ctx, args, spec=None, note=SCENARIO3_NOTE):
     nr = nonempty_rows(dose)
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}>(",
-             "adjoint": f"adj_kernel<{nt}, true, 0>("}
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}, ",
+             "adjoint": f"adj_kernel<{nt}, true, 0, "}
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz), "adjoint": adjoint_bytes(nr, nb, nnz)})
     print(f"[bench] {spec.name}: {res.iterations} iterations, {ms:.2f} ms per plan, forward "
           f"{kern['forward']['frac_of_peak']:.2f} / adjoint {kern['adjoint']['frac_of_peak']:.2f} of peak",
@@ -884,8 +887,8 @@ def main():
     wave = ctx.get_option("fwd_wave")
     nt = args.trials_per_pass
     lay, fwd_model = f32_forward(ctx, nb)
-    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}>(" if wave else f"fwd_kernel<{nt}>(",
-             "adjoint": f"adj_kernel<{nt}, true, 0>("}
+    names = {"forward": f"fwd_wave_kernel<{nt}, 0, {16 if nt <= 2 else 8}, {lay}, " if wave else f"fwd_kernel<{nt}>(",
+             "adjoint": f"adj_kernel<{nt}, true, 0, "}
     kern = kernel_table(runs, res, names, {"forward": fwd_model(nr, nb, nnz),
                                            "adjoint": adjoint_bytes(nr, nb, nnz)})
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
@@ -912,7 +915,8 @@ def main():
                    "x0": st.x0, "eps": st.eps, "alpha": st.alpha, "lambda0": lam0,
                    "trials_per_pass": args.trials_per_pass,
                    "launch": {k: ctx.get_option(k) for k in ("fwd_wg_per_cu", "adj_wg_per_cu", "adj_min_nnz",
-                                                             "fwd_col16", "batch_iters", "fwd_wave", "adj_xcd")}},
+                                                             "fwd_col16", "batch_iters", "fwd_wave", "adj_xcd",
+                                                             "stream_nt")}},
         "iterations": res.iterations,
         "iters_per_s": res.iterations / (ms_per_step / 1e3),
         "forward_passes": res.forward_passes,

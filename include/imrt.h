@@ -216,6 +216,13 @@ IMRT_API int imrt_ctx_stream(const imrt_ctx* ctx, void** hip_stream_out);
  *                    Sharing saves the matrix's reads but puts several
  *                    solves' work in each workgroup: for matrices that stay
  *                    in the last-level cache one pass per solve is faster
+ *   "stream_nt"      cache policy of the matrix streams in the passes of
+ *                    imrt_solve and imrt_solve_batch: 0 default policy, 1
+ *                    non-temporal, 2 (default) non-temporal when the CSR and
+ *                    CSC bytes one iteration reads (a batch: its unfinished
+ *                    plans' distinct matrices together) exceed the 256 MB
+ *                    last-level cache.  Results are the same under every
+ *                    policy; a server's passes keep the default policy
  *   "fwd_wave"       1: each wave of a forward workgroup streams its own row
  *                    blocks; 0: the whole workgroup shares each row block
  *   "fwd_col16"      1 (default): float32 matrices with nb <= 65536 created

@@ -481,8 +481,24 @@ void set_plan_penalties(FwdArgs& a, const imrt_plan* P) {
   a.nstruct = P->nstruct;
 }
 
+// Bytes of the matrix streams one iteration reads: the forward layout's
+// column index and value per nonzero, and the CSC's row index and value.
+int64_t stream_bytes(const imrt_dose* D) {
+  const int64_t fwd = (D->fwd_st == ST_F32) ? 8 : (D->fwd_st == ST_F32C16) ? 6 : 4;
+  const int64_t adj = (D->storage == ST_F32) ? 8 : 6;
+  return static_cast<int64_t>(D->nnz) * (fwd + adj);
+}
+
+// Cache policy of a solve pass's matrix streams (0 default, 2 non-temporal)
+// under the context's stream_nt option.
+int stream_policy(const imrt_ctx* ctx, int64_t bytes) {
+  const int opt = ctx->tune.stream_nt;
+  return (opt == 1 || (opt == 2 && bytes > kLlcBytes)) ? 2 : 0;
+}
+
 FwdArgs base_fwd(const imrt_dose* D) {
   FwdArgs a{};
+  a.stream_cp = stream_policy(D->ctx, stream_bytes(D));
   a.row_ptr = D->row_ptr;
   a.col_idx = D->col_idx;
   a.val = D->val;
@@ -532,6 +548,7 @@ int eval_forward(imrt_plan* P, const float* x, float* dose_out, float* r_out, in
 
 AdjArgs base_adj(const imrt_dose* D) {
   AdjArgs a{};
+  a.stream_cp = stream_policy(D->ctx, stream_bytes(D));
   a.row_idx = D->row_idx;
   a.val = D->cval;
   a.val16 = D->cval16;
@@ -655,6 +672,10 @@ int* option_slot(imrt_ctx* ctx, const char* name, int64_t* lo) {
     *lo = 0;
     return &ctx->tune.voxel_tiles;
   }
+  if (n == "stream_nt") {
+    *lo = 0;
+    return &ctx->tune.stream_nt;
+  }
   return nullptr;
 }
 }  // namespace
@@ -672,6 +693,7 @@ int imrt_ctx_set_option(imrt_ctx* ctx, const char* name, int64_t value) {
                      : (nm == "fwd_blocks_per_wave")                                         ? 1024
                      : (nm == "serve_adjoint_workgroups" || nm == "serve_forward_workgroups") ? 65536
                      : (nm == "serve_groups_per_poll")                                      ? 4096
+                     : (nm == "stream_nt")                                                  ? 2
                                                                                  : (int64_t(1) << 30);
   if (value < lo || value > hi) return set_error(IMRT_EINVAL, std::string("value out of range for ") + name);
   *slot = static_cast<int>(value);
@@ -1724,6 +1746,20 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     agrid[i] = P->dose->adj_grid;
     lds = std::max(lds, forward_lds_bytes(P->dose->nb, nt[i], P->nstruct, true, fst, fwv));
   }
+  // the live plans' matrix streams share the last-level cache: their policy
+  // follows the bytes of the distinct matrices of the unfinished plans
+  // together, taken again whenever plans drop out
+  auto live_policy = [&](const std::vector<int>& live) {
+    std::vector<const imrt_dose*> seen;
+    int64_t bytes = 0;
+    for (int i : live)
+      if (std::find(seen.begin(), seen.end(), plans[i]->dose) == seen.end()) {
+        seen.push_back(plans[i]->dose);
+        bytes += stream_bytes(plans[i]->dose);
+      }
+    return stream_policy(C, bytes);
+  };
+  int batch_cp = 0;
   if (dev_alloc(&B.st, 2 * static_cast<size_t>(n)) || dev_alloc(&B.fargs, n) || dev_alloc(&B.aargs, n))
     return IMRT_ENOMEM;
   for (int i = 0; i < n; ++i) {
@@ -1735,6 +1771,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   }
   std::vector<int> active(n);
   for (int i = 0; i < n; ++i) active[i] = i;
+  batch_cp = live_policy(active);
   std::vector<int32_t> fs, as;
   batch_slots(active, fgrid, fs);
   batch_slots(active, agrid, as);
@@ -1759,7 +1796,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   if (e != hipSuccess) return hip_error(e, "batch setup");
 
   // initial evaluation G(x_1) of every plan
-  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds))) {
+  if ((rc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds, batch_cp))) {
     (void)hipStreamSynchronize(s);
     return rc;
   }
@@ -1769,6 +1806,7 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
   // from the slot tables (stream-ordered uploads, then a new capture).
   const long long K = C->tune.batch_iters;
   auto capture = [&]() -> int {
+    batch_cp = live_policy(active);
     // the previous graph may still have a launch queued: keep it until the end
     if (B.exec) B.old_exec.push_back(B.exec);
     if (B.graph) B.old_graph.push_back(B.graph);
@@ -1778,9 +1816,9 @@ int imrt_solve_batch(int32_t n, imrt_plan* const* plans, const imrt_solve_params
     if (r != hipSuccess) return hip_error(r, "hipStreamBeginCapture");
     int lrc = IMRT_OK;
     for (long long k = 0; k < K && lrc == IMRT_OK; ++k) {
-      lrc = launch_adjoint_batch(C, B.aargs, B.aslots, static_cast<int>(as.size()), nt[0], storage);
+      lrc = launch_adjoint_batch(C, B.aargs, B.aslots, static_cast<int>(as.size()), nt[0], storage, batch_cp);
       if (lrc == IMRT_OK)
-        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds);
+        lrc = launch_forward_batch(C, B.fargs, B.fslots, static_cast<int>(fs.size()), nt[0], fst, fwv, lds, batch_cp);
     }
     r = hipStreamEndCapture(s, &B.graph);
     if (lrc) return lrc;

@@ -36,6 +36,7 @@ constexpr int kMaxTrials = 4;          // trial step sizes per forward pass
 constexpr int kMaxStruct = 256;
 constexpr int kPad = 16;               // zeroed tail of every nonzero array (aligned vector loads)
 constexpr int kXcds = 8;               // MI355X: 8 accelerator dies, workgroups dealt round-robin
+constexpr int64_t kLlcBytes = int64_t(256) << 20;   // MI355X: last-level (Infinity) cache
 
 // ---- device-resident solver state -------------------------------------------
 // Phases of the device-side state machine.  Only one workgroup at a time (a
@@ -105,6 +106,7 @@ struct FwdArgs {
   const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
   int32_t storage;
   int32_t waves;             // waves of a wave-granular forward workgroup (8 or 16; 8 with four trials)
+  int32_t stream_cp;         // host side: cache policy of a solve pass's matrix streams (0 or 2)
   const int32_t* block_row;  // nblocks + 1 row boundaries
   const int32_t* block_k0;   // nblocks + 1 nonzero offsets of the blocks
   int32_t nblocks, nv, nb, mode;
@@ -147,6 +149,7 @@ struct AdjArgs {
   const uint16_t* val16;     // 16-bit storage: codes (CSC slot order)
   const float* col_scale;    // 16-bit storage: per-beamlet scale (else null)
   int32_t storage;
+  int32_t stream_cp;         // host side: cache policy of a solve pass's matrix streams (0 or 2)
   const int32_t* col_ptr;
   const int32_t* wg_cols;
   const int32_t* col_wlo;
@@ -191,6 +194,8 @@ struct Tuning {
   int serve_fwd_wgs = 32;          // share their dispatches with the other live plans
   int serve_groups = 16;           // (adjoint, forward) groups a server runs between polls
   int serve_shared_adj = 0;        // live solves on one resident matrix share its adjoint pass
+  int stream_nt = 2;               // solve passes read the matrix streams non-temporally: 0 never,
+                                   // 1 always, 2 when they exceed the last-level cache
 };
 
 }  // namespace imrt
@@ -345,10 +350,11 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
                    hipEvent_t before = nullptr, hipEvent_t after = nullptr);
 // Batched solve passes over a slot table (device arrays of per-plan arguments
 // and of (plan << 16 | workgroup) slots, -1 for an idle slot).
+// stream_cp: cache policy of the matrix streams (0 default, 2 non-temporal).
 int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage, int dose_waves, size_t lds);
+                         int storage, int dose_waves, size_t lds, int stream_cp);
 int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage);
+                         int storage, int stream_cp);
 // Adjoint passes of groups of solves sharing a dose matrix: groups[(K + 1) g]
 // = n <= K, then n plan indices into args; slots = (group << 16) | workgroup.
 // group_k (K) is 2 or 4.

@@ -128,9 +128,6 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
 __device__ __forceinline__ int4 load_i4(rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
-__device__ __forceinline__ float4 load_f4(rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
 __device__ __forceinline__ int load_i32(rsrc_t r, uint32_t off) {
   return static_cast<int>(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
@@ -140,11 +137,24 @@ __device__ __forceinline__ float load_f32(rsrc_t r, uint32_t off) {
 __device__ __forceinline__ double load_f64(rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
-__device__ __forceinline__ uint2 load_u2(rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
 __device__ __forceinline__ uint32_t load_u8(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+// Loads of the matrix streams with cache policy CP: 0 the default, 2 the
+// non-temporal policy, for matrices larger than the last-level cache (a
+// pass's stream would otherwise evict the vectors and tables the passes
+// reuse; the values read are the same either way).
+template <int CP>
+__device__ __forceinline__ int4 load_i4s(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP));
+}
+template <int CP>
+__device__ __forceinline__ float4 load_f4s(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP));
+}
+template <int CP>
+__device__ __forceinline__ uint2 load_u2s(rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP));
 }
 __device__ __forceinline__ void store_f32(rsrc_t r, uint32_t off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
@@ -984,7 +994,7 @@ struct WaveStage {
 // of the CSR index and value arrays; base is a multiple of 4 and the arrays
 // carry a zeroed tail, so whole groups stay in bounds and entries past k1
 // read zeros.
-template <int ST>
+template <int ST, int CP = 0>
 __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, int lane,
                                           ColGroup<ST> (&c)[wave_groups<ST>()],
                                           ValGroup<ST> (&v)[wave_groups<ST>()]) {
@@ -995,8 +1005,8 @@ __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, in
     const rsrc_t rv = make_rsrc(a.val + base, bytes);
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-      c[j] = load_i4(rc, 16 * lane + 1024 * j);
-      v[j] = load_f4(rv, 16 * lane + 1024 * j);
+      c[j] = load_i4s<CP>(rc, 16 * lane + 1024 * j);
+      v[j] = load_f4s<CP>(rv, 16 * lane + 1024 * j);
     }
   } else if constexpr (ST == ST_F32C16) {
     const uint32_t n = static_cast<uint32_t>(k1 - base);
@@ -1004,8 +1014,8 @@ __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, in
     const rsrc_t rv = make_rsrc(a.val + base, (n * 4 + 15) & ~15u);
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-      c[j] = load_u2(rc, 8 * lane + 512 * j);
-      v[j] = load_f4(rv, 16 * lane + 1024 * j);
+      c[j] = load_u2s<CP>(rc, 8 * lane + 512 * j);
+      v[j] = load_f4s<CP>(rv, 16 * lane + 1024 * j);
     }
   } else {
     const uint32_t bytes = static_cast<uint32_t>((k1 - base) * 2 + 7) & ~7u;
@@ -1013,8 +1023,8 @@ __device__ __forceinline__ void csr_issue(const FwdArgs& a, int base, int k1, in
     const rsrc_t rv = make_rsrc(a.val16 + base, bytes);
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-      c[j] = load_u2(rc, 8 * lane + 512 * j);
-      v[j] = load_u2(rv, 8 * lane + 512 * j);
+      c[j] = load_u2s<CP>(rc, 8 * lane + 512 * j);
+      v[j] = load_u2s<CP>(rv, 8 * lane + 512 * j);
     }
   }
 }
@@ -1033,9 +1043,9 @@ __device__ __forceinline__ int log2_lanes(int nr) {
 // UNCOND: every row load is issued (rows past the block read zeros out of
 // bounds), so that no load of the block sits in a branch and a later wait
 // for an earlier load can count exactly how many were issued after it.
-template <int MODE, bool UNCOND = false, int ST = ST_F32>
+template <int MODE, bool UNCOND = false, int ST = ST_F32, int CP = 0>
 __device__ __forceinline__ void wave_issue(const FwdArgs& a, const WaveBlock& m, int lane, WaveStage<ST>& S) {
-  csr_issue<ST>(a, m.k0 & ~3, m.k1, lane, S.c, S.v);
+  csr_issue<ST, CP>(a, m.k0 & ~3, m.k1, lane, S.c, S.v);
   const int nr = m.r1 - m.r0;
   const int e = log2_lanes(nr);
   const int passes = ((nr << e) + 63) >> 6;
@@ -1150,7 +1160,7 @@ template <int NT, int WAVES>
 constexpr int fwd_min_waves_per_simd() { return WAVES == 16 ? 4 : NT == 1 ? 6 : NT == 2 ? 4 : 1; }
 constexpr int kMetaChunk = 256;   // row blocks whose bounds are staged in LDS at a time
 
-template <int NT, int MODE, int WAVES, int ST>
+template <int NT, int MODE, int WAVES, int ST, int CP = 0>
 __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   constexpr int THREADS = WAVES * 64;
   constexpr int NNZ = wave_nnz(ST), PART = wave_part_nnz(ST), NG = wave_groups<ST>();
@@ -1223,7 +1233,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   // a row longer than a wave block is streamed in the loop instead
   const bool short_first = cur.k1 - cur.k0 <= PART;
   WaveStage<ST> S;
-  wave_issue<MODE, true, ST>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+  wave_issue<MODE, true, ST, CP>(a, short_first ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
 
   int ntr = 1;
   rsrc_t rout[NT];
@@ -1286,7 +1296,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
     if (c0 != B0) {
       b = c0 + wv;
       cur = (b < c1) ? meta(b) : WaveBlock{0, 0, 0, 0};
-      wave_issue<MODE, true, ST>(a, (b < c1 && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+      wave_issue<MODE, true, ST, CP>(a, (b < c1 && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
     }
     while (b < c1) {
       // the block after this one (taken now, its loads issued once this
@@ -1308,7 +1318,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
         for (int base = blk.k0 & ~3; base < blk.k1; base += NNZ) {
           ColGroup<ST> cg[NG];
           ValGroup<ST> vg[NG];
-          csr_issue<ST>(a, base, blk.k1, lane, cg, vg);
+          csr_issue<ST, CP>(a, base, blk.k1, lane, cg, vg);
 #pragma unroll
           for (int j = 0; j < NG; ++j) {
             const int e0 = base + 4 * lane + 256 * j;
@@ -1329,7 +1339,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
           const uint32_t sid = want_sid ? a.pen.sid[blk.r0] : 0;
           row_finish<NT, MODE>(a, blk.r0, sid, tab, d, pb, rout, dout, ntr);
         }
-        wave_issue<MODE, true, ST>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+        wave_issue<MODE, true, ST, CP>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
       } else {
         // products of this block into the wave's LDS region (lanes past the
         // block hold zeros and write slots that no row reads)
@@ -1355,7 +1365,7 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
         // issued whether or not a next block follows (an empty block reads
         // zeros and touches no memory), so the loads land in the registers
         // the next products read, with no copies to merge two paths
-        wave_issue<MODE, true, ST>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
+        wave_issue<MODE, true, ST, CP>(a, (more && cur.k1 - cur.k0 <= PART) ? cur : WaveBlock{0, 0, 0, 0}, lane, S);
         switch (log2_lanes(blk.r1 - blk.r0)) {
           case 0: wave_rows<1, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
           case 1: wave_rows<2, NT, MODE, NNZ>(a, prod, lane, blk, R, tab, pb, rout, dout, ntr); break;
@@ -1395,21 +1405,21 @@ __device__ __forceinline__ void fwd_wave_pass(const FwdArgs& a, const Slot sl) {
   }
 }
 
-template <int NT, int MODE, int WAVES, int ST>
+template <int NT, int MODE, int WAVES, int ST, int CP = 0>
 __global__ __launch_bounds__(WAVES * 64, (fwd_min_waves_per_simd<NT, WAVES>())) void fwd_wave_kernel(FwdArgs a) {
-  fwd_wave_pass<NT, MODE, WAVES, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
+  fwd_wave_pass<NT, MODE, WAVES, ST, CP>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
 }
 
 // Batched solve pass: slots[blockIdx.x] = (plan << 16) | workgroup of that
 // plan's pass, or -1 for an idle slot (plans start at multiples of the die
 // count, so each plan keeps its workgroups' die placement).
-template <int NT, int WAVES, int ST>
+template <int NT, int WAVES, int ST, int CP = 0>
 __global__ __launch_bounds__(WAVES * 64, (fwd_min_waves_per_simd<NT, WAVES>())) void fwd_wave_batch_kernel(const FwdArgs* __restrict__ args,
                                                                     const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
   const FwdArgs& a = args[sv >> 16];
-  fwd_wave_pass<NT, FWD_SOLVE, WAVES, ST>(a, Slot{sv & 0xFFFF, a.grid});
+  fwd_wave_pass<NT, FWD_SOLVE, WAVES, ST, CP>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
 // ---- adjoint pass ----------------------------------------------------------------
@@ -1441,16 +1451,16 @@ __device__ __forceinline__ int logical_wg(const Slot sl, bool xcd_map) {
 
 // rv covers the value array from the same entry as ri: float32 values in
 // the index slots' order, or 16-bit codes in that order at half the width.
-template <int ST>
+template <int ST, int CP = 0>
 __device__ __forceinline__ void adj_issue(rsrc_t ri, rsrc_t rv, int round, AdjStage<ST>& S) {
   const uint32_t t = 16u * threadIdx.x;
   const uint32_t base = static_cast<uint32_t>(round) * (kAdjStep * 4u);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) S.c[j] = load_i4(ri, base + t + 4096u * j);
+  for (int j = 0; j < 2; ++j) S.c[j] = load_i4s<CP>(ri, base + t + 4096u * j);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if constexpr (ST == ST_F32) S.v[j] = load_f4(rv, base + t + 4096u * j);
-    else S.v[j] = load_u2(rv, base / 2 + t / 2 + 2048u * j);
+    if constexpr (ST == ST_F32) S.v[j] = load_f4s<CP>(rv, base + t + 4096u * j);
+    else S.v[j] = load_u2s<CP>(rv, base / 2 + t / 2 + 2048u * j);
   }
 }
 
@@ -1575,7 +1585,7 @@ __device__ __forceinline__ void col_store(const AdjArgs& aq, const ColChunk<ST>&
 // residual gathers before the decision is known, from the residual buffer of
 // the pass's first trial (the one an accepted step of a single-trial pass
 // always lands in); if another trial is accepted they are issued again.
-template <int NT, bool SOLVE, int ST>
+template <int NT, bool SOLVE, int ST, int CP = 0>
 __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   __shared__ double red[kWaves];
   __shared__ double colsh[kWaves * kColChunk];
@@ -1598,8 +1608,8 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   if (SOLVE) decide_start<NT>(a, DL);
   const int4 wi = load_i4(make_rsrc(a.wg_cols, 16u * static_cast<uint32_t>(a.grid)), 16u * static_cast<uint32_t>(lw));
   AdjStage<ST> A, B;
-  adj_issue(ri, rv, 0, A);
-  adj_issue(ri, rv, 1, B);
+  adj_issue<ST, CP>(ri, rv, 0, A);
+  adj_issue<ST, CP>(ri, rv, 1, B);
   const int c0 = uniform(wi.x), c1 = uniform(wi.y);
   int c = c0, lo = uniform(wi.z), hi = uniform(wi.w);
   ColChunk<ST> CK;
@@ -1685,7 +1695,7 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
       // order, so either a branch here or loads moved ahead of the gathers
       // would make the wait for the gathers wait for these loads as well.
       __builtin_amdgcn_sched_barrier(0);
-      adj_issue(ri, rv, round + 1, nxt);
+      adj_issue<ST, CP>(ri, rv, round + 1, nxt);
       consume(cur, gv, round);
       ++round;
       return round < nrounds;
@@ -1700,20 +1710,20 @@ __device__ __forceinline__ void adj_pass(const AdjArgs& a, const Slot sl) {
   if (c1 > c0) flush();
 }
 
-template <int NT, bool SOLVE, int ST>
+template <int NT, bool SOLVE, int ST, int CP = 0>
 __global__ __launch_bounds__(kThreads) void adj_kernel(AdjArgs a) {
-  adj_pass<NT, SOLVE, ST>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
+  adj_pass<NT, SOLVE, ST, CP>(a, Slot{static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)});
 }
 
 // Batched solve pass (slots as for fwd_wave_batch_kernel).
-template <int NT, int ST>
+template <int NT, int ST, int CP = 0>
 __global__ __launch_bounds__(kThreads) void adj_batch_kernel(const AdjArgs* __restrict__ args,
                                                              const int32_t* __restrict__ slots) {
   const int sv = uniform(slots[blockIdx.x]);
   if (sv < 0) return;
   // read in place (uniform, read-only): a local copy would live in scratch
   const AdjArgs& a = args[sv >> 16];
-  adj_pass<NT, true, ST>(a, Slot{sv & 0xFFFF, a.grid});
+  adj_pass<NT, true, ST, CP>(a, Slot{sv & 0xFFFF, a.grid});
 }
 
 // Adjoint pass of n <= K solves that share one dose matrix (the same CSC
@@ -2026,24 +2036,33 @@ int adjoint_grid_for(const imrt_ctx* ctx, int64_t nnz, int min_nnz) {
 // Launches take optional start/stop events, recorded by the dispatch itself
 // around the kernel (hipExtLaunchKernelGGL), so their elapsed time is the
 // kernel's own duration.
+template <int ST, int CP>
+int launch_wave_solve(const FwdArgs& a, int ntrials, bool w16, dim3 gd, size_t lds, hipStream_t s, hipEvent_t before,
+                      hipEvent_t after) {
+  const dim3 bd16(16 * 64), bd8(8 * 64);
+  switch (ntrials) {
+    case 1:
+      if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST, CP>), gd, bd16, lds, s, before, after, 0, a);
+      else hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 8, ST, CP>), gd, bd8, lds, s, before, after, 0, a);
+      break;
+    case 2:
+      if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 16, ST, CP>), gd, bd16, lds, s, before, after, 0, a);
+      else hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST, CP>), gd, bd8, lds, s, before, after, 0, a);
+      break;
+    case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST, CP>), gd, bd8, lds, s, before, after, 0, a); break;
+    default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
+  }
+  return IMRT_OK;
+}
+
 template <int ST>
 int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipStream_t s, hipEvent_t before,
                         hipEvent_t after) {
   const dim3 bd16(16 * 64), bd8(8 * 64);
   const bool w16 = forward_waves(ntrials, a.waves) == 16;
   if (a.mode == FWD_SOLVE) {
-    switch (ntrials) {
-      case 1:
-        if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
-        else hipExtLaunchKernelGGL((fwd_wave_kernel<1, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
-        break;
-      case 2:
-        if (w16) hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 16, ST>), gd, bd16, lds, s, before, after, 0, a);
-        else hipExtLaunchKernelGGL((fwd_wave_kernel<2, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a);
-        break;
-      case 4: hipExtLaunchKernelGGL((fwd_wave_kernel<4, FWD_SOLVE, 8, ST>), gd, bd8, lds, s, before, after, 0, a); break;
-      default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
-    }
+    return a.stream_cp ? launch_wave_solve<ST, 2>(a, ntrials, w16, gd, lds, s, before, after)
+                       : launch_wave_solve<ST, 0>(a, ntrials, w16, gd, lds, s, before, after);
   } else if (ntrials != 1) {
     return set_error(IMRT_EINVAL, "evaluation passes take one trial");
   } else if (a.mode == FWD_EVAL) {
@@ -2058,64 +2077,85 @@ int launch_wave_forward(const FwdArgs& a, int ntrials, dim3 gd, size_t lds, hipS
 
 // Batched solve passes: one dispatch over the slot table of several plans
 // (all with the same storage, forward workgroup size and trials per pass).
-template <int ST>
+template <int ST, int CP>
 int launch_forward_batch_st(const FwdArgs* args, const int32_t* slots, int nslots, int ntrials, int dose_waves,
                             size_t lds, hipStream_t s) {
   const dim3 gd(nslots);
   const bool w16 = forward_waves(ntrials, dose_waves) == 16;
   switch (ntrials) {
     case 1:
-      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots);
-      else hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots);
+      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 16, ST, CP>), gd, dim3(16 * 64), lds, s, args, slots);
+      else hipLaunchKernelGGL((fwd_wave_batch_kernel<1, 8, ST, CP>), gd, dim3(8 * 64), lds, s, args, slots);
       break;
     case 2:
-      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 16, ST>), gd, dim3(16 * 64), lds, s, args, slots);
-      else hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots);
+      if (w16) hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 16, ST, CP>), gd, dim3(16 * 64), lds, s, args, slots);
+      else hipLaunchKernelGGL((fwd_wave_batch_kernel<2, 8, ST, CP>), gd, dim3(8 * 64), lds, s, args, slots);
       break;
-    case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST>), gd, dim3(8 * 64), lds, s, args, slots); break;
+    case 4: hipLaunchKernelGGL((fwd_wave_batch_kernel<4, 8, ST, CP>), gd, dim3(8 * 64), lds, s, args, slots); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
   return IMRT_OK;
 }
 
 int launch_forward_batch(const imrt_ctx* ctx, const FwdArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage, int dose_waves, size_t lds) {
+                         int storage, int dose_waves, size_t lds, int stream_cp) {
   if (nslots <= 0) return IMRT_OK;
   if (lds > ctx->max_lds) return set_error(IMRT_EUNSUPPORTED, "batched forward pass: LDS budget exceeded");
   int rc;
   const int w = dose_waves;
   hipStream_t s = ctx->stream;
   switch (storage) {
-    case ST_F32: rc = launch_forward_batch_st<ST_F32>(args, slots, nslots, ntrials, w, lds, s); break;
-    case ST_BF16: rc = launch_forward_batch_st<ST_BF16>(args, slots, nslots, ntrials, w, lds, s); break;
-    case ST_F16: rc = launch_forward_batch_st<ST_F16>(args, slots, nslots, ntrials, w, lds, s); break;
-    case ST_F32C16: rc = launch_forward_batch_st<ST_F32C16>(args, slots, nslots, ntrials, w, lds, s); break;
+    case ST_F32:
+      rc = stream_cp ? launch_forward_batch_st<ST_F32, 2>(args, slots, nslots, ntrials, w, lds, s)
+                     : launch_forward_batch_st<ST_F32, 0>(args, slots, nslots, ntrials, w, lds, s);
+      break;
+    case ST_BF16:
+      rc = stream_cp ? launch_forward_batch_st<ST_BF16, 2>(args, slots, nslots, ntrials, w, lds, s)
+                     : launch_forward_batch_st<ST_BF16, 0>(args, slots, nslots, ntrials, w, lds, s);
+      break;
+    case ST_F16:
+      rc = stream_cp ? launch_forward_batch_st<ST_F16, 2>(args, slots, nslots, ntrials, w, lds, s)
+                     : launch_forward_batch_st<ST_F16, 0>(args, slots, nslots, ntrials, w, lds, s);
+      break;
+    case ST_F32C16:
+      rc = stream_cp ? launch_forward_batch_st<ST_F32C16, 2>(args, slots, nslots, ntrials, w, lds, s)
+                     : launch_forward_batch_st<ST_F32C16, 0>(args, slots, nslots, ntrials, w, lds, s);
+      break;
     default: return set_error(IMRT_EINVAL, "unknown storage");
   }
   if (rc) return rc;
   return check_launch("fwd_wave_batch_kernel");
 }
 
-template <int ST>
+template <int ST, int CP>
 int launch_adjoint_batch_st(const AdjArgs* args, const int32_t* slots, int nslots, int ntrials, hipStream_t s) {
   const dim3 gd(nslots), bd(kThreads);
   switch (ntrials) {
-    case 1: hipLaunchKernelGGL((adj_batch_kernel<1, ST>), gd, bd, 0, s, args, slots); break;
-    case 2: hipLaunchKernelGGL((adj_batch_kernel<2, ST>), gd, bd, 0, s, args, slots); break;
-    case 4: hipLaunchKernelGGL((adj_batch_kernel<4, ST>), gd, bd, 0, s, args, slots); break;
+    case 1: hipLaunchKernelGGL((adj_batch_kernel<1, ST, CP>), gd, bd, 0, s, args, slots); break;
+    case 2: hipLaunchKernelGGL((adj_batch_kernel<2, ST, CP>), gd, bd, 0, s, args, slots); break;
+    case 4: hipLaunchKernelGGL((adj_batch_kernel<4, ST, CP>), gd, bd, 0, s, args, slots); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
   return IMRT_OK;
 }
 
 int launch_adjoint_batch(const imrt_ctx* ctx, const AdjArgs* args, const int32_t* slots, int nslots, int ntrials,
-                         int storage) {
+                         int storage, int stream_cp) {
   if (nslots <= 0) return IMRT_OK;
   int rc;
   switch (storage) {
-    case ST_F32: rc = launch_adjoint_batch_st<ST_F32>(args, slots, nslots, ntrials, ctx->stream); break;
-    case ST_BF16: rc = launch_adjoint_batch_st<ST_BF16>(args, slots, nslots, ntrials, ctx->stream); break;
-    case ST_F16: rc = launch_adjoint_batch_st<ST_F16>(args, slots, nslots, ntrials, ctx->stream); break;
+    case ST_F32:
+      rc = stream_cp ? launch_adjoint_batch_st<ST_F32, 2>(args, slots, nslots, ntrials, ctx->stream)
+                     : launch_adjoint_batch_st<ST_F32, 0>(args, slots, nslots, ntrials, ctx->stream);
+      break;
+    case ST_BF16:
+      rc = stream_cp ? launch_adjoint_batch_st<ST_BF16, 2>(args, slots, nslots, ntrials, ctx->stream)
+                     : launch_adjoint_batch_st<ST_BF16, 0>(args, slots, nslots, ntrials, ctx->stream);
+      break;
+    case ST_F16:
+      rc = stream_cp ? launch_adjoint_batch_st<ST_F16, 2>(args, slots, nslots, ntrials, ctx->stream)
+                     : launch_adjoint_batch_st<ST_F16, 0>(args, slots, nslots, ntrials, ctx->stream);
+      break;
     default: return set_error(IMRT_EINVAL, "unknown storage");
   }
   if (rc) return rc;
@@ -2192,14 +2232,14 @@ int launch_forward(const imrt_ctx* ctx, const imrt_dose* D, const FwdArgs& a, in
   return check_launch("fwd_kernel");
 }
 
-template <int ST>
+template <int ST, int CP>
 int launch_adjoint_kernel(const AdjArgs& a, int ntrials, dim3 gd, dim3 bd, hipStream_t s, hipEvent_t before,
                           hipEvent_t after) {
   switch (a.solve ? ntrials : 0) {
     case 0: hipExtLaunchKernelGGL((adj_kernel<1, false, ST>), gd, bd, 0, s, before, after, 0, a); break;
-    case 1: hipExtLaunchKernelGGL((adj_kernel<1, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
-    case 2: hipExtLaunchKernelGGL((adj_kernel<2, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
-    case 4: hipExtLaunchKernelGGL((adj_kernel<4, true, ST>), gd, bd, 0, s, before, after, 0, a); break;
+    case 1: hipExtLaunchKernelGGL((adj_kernel<1, true, ST, CP>), gd, bd, 0, s, before, after, 0, a); break;
+    case 2: hipExtLaunchKernelGGL((adj_kernel<2, true, ST, CP>), gd, bd, 0, s, before, after, 0, a); break;
+    case 4: hipExtLaunchKernelGGL((adj_kernel<4, true, ST, CP>), gd, bd, 0, s, before, after, 0, a); break;
     default: return set_error(IMRT_EINVAL, "trials per pass must be 1, 2 or 4");
   }
   return IMRT_OK;
@@ -2213,9 +2253,18 @@ int launch_adjoint(const imrt_ctx* ctx, const imrt_dose* D, const AdjArgs& a, in
   if (!a.solve && ntrials != 1) return set_error(IMRT_EINVAL, "a plain adjoint pass takes one vector");
   int rc = IMRT_OK;
   switch (a.storage) {
-    case ST_F32: rc = launch_adjoint_kernel<ST_F32>(a, ntrials, gd, bd, s, before, after); break;
-    case ST_BF16: rc = launch_adjoint_kernel<ST_BF16>(a, ntrials, gd, bd, s, before, after); break;
-    case ST_F16: rc = launch_adjoint_kernel<ST_F16>(a, ntrials, gd, bd, s, before, after); break;
+    case ST_F32:
+      rc = (a.solve && a.stream_cp) ? launch_adjoint_kernel<ST_F32, 2>(a, ntrials, gd, bd, s, before, after)
+                                    : launch_adjoint_kernel<ST_F32, 0>(a, ntrials, gd, bd, s, before, after);
+      break;
+    case ST_BF16:
+      rc = (a.solve && a.stream_cp) ? launch_adjoint_kernel<ST_BF16, 2>(a, ntrials, gd, bd, s, before, after)
+                                    : launch_adjoint_kernel<ST_BF16, 0>(a, ntrials, gd, bd, s, before, after);
+      break;
+    case ST_F16:
+      rc = (a.solve && a.stream_cp) ? launch_adjoint_kernel<ST_F16, 2>(a, ntrials, gd, bd, s, before, after)
+                                    : launch_adjoint_kernel<ST_F16, 0>(a, ntrials, gd, bd, s, before, after);
+      break;
     default: return set_error(IMRT_EINVAL, "unknown storage");
   }
   if (rc) return rc;

@@ -427,11 +427,11 @@ void worker_main(imrt_server* S) {
       e = hipMemcpyAsync(S->gtab, gt.data(), sizeof(int32_t) * gt.size(), hipMemcpyHostToDevice, s);
     if (!rc && e != hipSuccess) rc = hip_error(e, "server slot upload");
     for (int k = 0; k < K && !rc; ++k) {
-      if (gk == 1) rc = launch_adjoint_batch(C, S->aargs, S->aslots, static_cast<int>(as.size()), nt, storage);
+      if (gk == 1) rc = launch_adjoint_batch(C, S->aargs, S->aslots, static_cast<int>(as.size()), nt, storage, 0);
       else
         rc = launch_adjoint_multi_batch(C, S->aargs, S->gtab, gk, S->aslots, static_cast<int>(as.size()), nt,
                                         storage);
-      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, fwv, lds);
+      if (!rc) rc = launch_forward_batch(C, S->fargs, S->fslots, static_cast<int>(fs.size()), nt, fst, fwv, lds, 0);
     }
     if (!rc) {
       std::lock_guard<std::mutex> g(S->mu);
